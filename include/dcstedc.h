@@ -1,0 +1,204 @@
+/*
+ * dcstedc.h -- C ABI of the MI355X (gfx950) structured divide-and-conquer
+ * symmetric tridiagonal eigensolver.
+ *
+ * The method is that of Liao, Li, Lu and Roman, "A parallel structured
+ * divide-and-conquer algorithm for symmetric tridiagonal eigenvalue problems"
+ * (IEEE TPDS 2020): Cuppen's divide and conquer (Algorithm 1) whose merge
+ * step forms the eigenvectors as Q_new = diag(Q1, Q2) U (eq. updateV), with U
+ * the Cauchy-like eigenvector matrix of the rank-one modified diagonal
+ * problem (eq. Q_Cauchy), built from its generators and optionally replaced
+ * off the diagonal by structured low-rank approximations (section "SRRSC
+ * low-rank approximation"; Algorithm 2 step 3(b)-(c); Algorithm 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - FP64 throughout.  Every array argument is a DEVICE pointer owned by the
+ *    caller unless stated otherwise; the library never frees caller memory.
+ *  - Matrices are column-major with a leading dimension (LAPACK layout), so
+ *    eigenvector j is the contiguous column j.
+ *  - Calls are asynchronous on the caller's stream.  Argument errors are
+ *    detected synchronously on the host: the call returns -i for the i-th
+ *    (1-based) invalid argument and launches nothing.  Errors the device
+ *    detects are written to a device status word:
+ *        0        success
+ *        j > 0    secular root / leaf block j (1-based) did not converge
+ *        -1000    a non-finite value in the input
+ *    The short forms keep that word in library-owned memory per stream
+ *    (read it with dc_last_info after synchronising); the _ex forms write it
+ *    to the caller's info_dev.
+ *  - A positive return value is a HIP runtime error code.
+ *  - The short forms allocate stream-ordered workspace; only the _ex forms
+ *    with caller workspace allocate nothing and may be captured in a graph.
+ */
+#ifndef DCSTEDC_H
+#define DCSTEDC_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Tuning and path options.  A NULL dc_opts* means the defaults below. */
+typedef struct dc_opts {
+    int leaf;        /* largest block solved directly by tridiagonal QR
+                        (Algorithm 1, "size of T is small enough");
+                        1..64, default 32 */
+    double lr_tol;   /* absolute tolerance of the structured low-rank merge
+                        (0 = plain merge, the default) */
+    int lr_block;    /* block size b of the low-rank merge (default 1024) */
+    int lr_min_k;    /* use the low-rank merge only when the deflated size K
+                        reaches this (Algorithm 3's "size of M is large");
+                        default 4096 */
+    int max_iter;    /* secular iteration cap (default 64) */
+    int gemm_tile;   /* merge-product tile variant, 0 = automatic */
+} dc_opts;
+
+void dc_opts_default(dc_opts* opt);
+
+/*
+ * dc_stedc -- all eigenpairs of the symmetric tridiagonal T(d, e),
+ * T[i][i] = d[i], T[i][i+1] = T[i+1][i] = e[i] (section "Preliminaries",
+ * eq. t; Algorithm 1's input and output).
+ *   n    order, n >= 0 (n == 0: nothing happens)
+ *   d    in: diagonal (n); out: eigenvalues in ascending order
+ *   e    in: off-diagonal (n-1); left unchanged
+ *   Q    out: ldq x n, column j the unit eigenvector of d[j]
+ *   ldq  >= max(1, n)
+ * Returns 0, -i for a bad argument i, or a HIP error.
+ */
+int dc_stedc(int n, double* d, double* e, double* Q, int ldq, hipStream_t stream);
+
+/* Workspace in bytes that dc_stedc_ex needs for order n. */
+size_t dc_stedc_workspace(int n, const dc_opts* opt);
+
+/*
+ * dc_stedc_ex -- dc_stedc with caller workspace and status word.
+ *   work, lwork  device workspace of at least dc_stedc_workspace(n, opt)
+ *                bytes, 256-byte aligned
+ *   info_dev     device int; receives the status (see above)
+ * Allocates nothing and performs no host synchronisation: graph-capturable.
+ */
+int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void* work,
+                size_t lwork, int* info_dev, const dc_opts* opt,
+                hipStream_t stream);
+
+/*
+ * dc_stedc_batched -- many independent problems of uneven size, solved
+ * together: every tree level of every problem runs as one launch per phase.
+ *   count           number of problems
+ *   n_host, ldq_host  HOST arrays (count) of orders and leading dimensions
+ *   d, e, Q         HOST arrays (count) of DEVICE pointers, as in dc_stedc
+ *   work, lwork     device workspace >= dc_stedc_batched_workspace(...)
+ *   info_dev        DEVICE int array (count), one status per problem
+ * The level schedule is captured into a HIP graph on first use for a given
+ * (count, sizes, options, pointers) signature and replayed afterwards.
+ */
+size_t dc_stedc_batched_workspace(int count, const int* n_host, const dc_opts* opt);
+int dc_stedc_batched(int count, const int* n_host, double* const* d,
+                     double* const* e, double* const* Q, const int* ldq_host,
+                     void* work, size_t lwork, int* info_dev,
+                     const dc_opts* opt, hipStream_t stream);
+
+/*
+ * dc_secular -- the rank-one modified diagonal eigenproblem
+ * M = diag(D) + rho z z^T (eq. rankone) on its deflated generators.
+ *   K        size, K >= 1
+ *   Dbar     poles, strictly increasing (K)
+ *   zbar     weights, all non-zero (K); rho > 0
+ *   org      out: origin pole of root j (K, int): lam_j = Dbar[org_j] + tau_j
+ *   tau      out: offset of root j from its origin (K) (eq. secular with
+ *            Remark 3's stable differences, eq. d-lambda)
+ *   zhat     out: Loewner-recomputed weights (K) (Gu-Eisenstat)
+ *   scale    out: column normalisers s_j (K) (eq. Q_Cauchy)
+ *   info_dev device int status, or NULL
+ */
+int dc_secular(int K, const double* Dbar, const double* zbar, double rho,
+               int* org, double* tau, double* zhat, double* scale,
+               int* info_dev, int max_iter, hipStream_t stream);
+
+/*
+ * dc_merge_update -- the merge-step eigenvector update C = Qnd * U
+ * (eq. updateV, eq. evect) with U generated from its generators and never
+ * stored: U_ij = zhat_i scale_j / ((Dbar_i - Dbar_{org_j}) - tau_j)
+ * (eq. Q_Cauchy with Remark 3's differences).  With org == NULL the column
+ * nodes are tau itself: U_ij = zhat_i scale_j / (Dbar_i - tau_j) (general
+ * Cauchy-like generators as in the paper's Examples 0 and 1).
+ *   m, K         Qnd is m x K (ldq >= m), U is K x K, C is m x K (ldc >= m)
+ *   lr_tol       0: plain product.  > 0: off-diagonal lr_block x lr_block
+ *                blocks of U are replaced by SRRSC approximations with
+ *                absolute entry error <= lr_tol (eq. sid; Algorithm 2 step
+ *                3(b)-(c)); diagonal blocks stay exact.
+ *   lr_block     block size for lr_tol > 0 (<= 0: default 1024)
+ * Allocates stream-ordered workspace when lr_tol > 0.
+ */
+int dc_merge_update(int m, int K, const double* Qnd, int ldq,
+                    const double* Dbar, const int* org, const double* tau,
+                    const double* zhat, const double* scale, double* C,
+                    int ldc, double lr_tol, int lr_block, hipStream_t stream);
+
+/*
+ * dc_merge_lowrank_ranks -- ranks the low-rank merge would use: for the
+ * generators of dc_merge_update, writes nb*nb ints to ranks_host (HOST),
+ * nb = ceil(K / lr_block), -1 on the diagonal.  Synchronises the stream.
+ */
+int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
+                           const double* tau, const double* zhat,
+                           const double* scale, double lr_tol, int lr_block,
+                           int* ranks_host, hipStream_t stream);
+
+/*
+ * dc_stedc_backward -- reverse-mode gradient of (lam, Q) = eig(T(d, e)).
+ * With M = diag(lam_bar) + F o (Q^T Q_bar), F_ij = 1/(lam_j - lam_i)
+ * (i != j, 0 on the diagonal), A_bar = Q M Q^T and
+ *   d_bar_i = A_bar[i][i],  e_bar_i = A_bar[i][i+1] + A_bar[i+1][i].
+ * Only the band of A_bar is formed.
+ *   lam, Q     the forward result (Q ldq x n, column-major)
+ *   lam_bar    cotangent of lam (n) or NULL (= 0)
+ *   Q_bar      cotangent of Q (ldqb x n) or NULL (= 0)
+ *   d_bar      out (n);  e_bar  out (n-1)
+ * Equal eigenvalues make F undefined: such pairs get F_ij = 0 and the status
+ * word is set to -2000 (read with dc_last_info).
+ */
+int dc_stedc_backward(int n, const double* lam, const double* Q, int ldq,
+                      const double* lam_bar, const double* Q_bar, int ldqb,
+                      double* d_bar, double* e_bar, hipStream_t stream);
+
+/*
+ * dc_stedc_backward_rank1 -- the same gradient when Q_bar = u g^T has rank
+ * one (for instance a loss sum_i c_i (u^T q_i)^2, where g_i = 2 c_i u^T q_i).
+ * Then F o (Q^T Q_bar) is itself Cauchy-like, (Q^T u)_i g_j / (lam_j -
+ * lam_i), and the product Q M runs through the generated-tile merge kernel.
+ *   u (n), g (n) device vectors; lam_bar may be NULL.
+ */
+int dc_stedc_backward_rank1(int n, const double* lam, const double* Q, int ldq,
+                            const double* lam_bar, const double* u,
+                            const double* g, double* d_bar, double* e_bar,
+                            hipStream_t stream);
+
+/* Status word of the last short-form call on `stream`; synchronises it. */
+int dc_last_info(hipStream_t stream);
+
+/* Human-readable text for a return or status code. */
+const char* dc_strerror(int code);
+
+/*
+ * dc_stats -- per-merge record of the last dc_stedc / dc_stedc_ex call on
+ * the calling host thread (copied back synchronously when requested):
+ * order m, deflated size K, number of pair rotations, path (0 plain,
+ * 1 low-rank), and the product's algorithmic flop count.
+ */
+typedef struct dc_merge_stat {
+    int level, m, K, nrot, path;
+    double flops;
+} dc_merge_stat;
+
+/* Copies up to cap records into out (HOST); returns the number available. */
+int dc_last_stats(dc_merge_stat* out, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCSTEDC_H */

@@ -1,0 +1,81 @@
+// Shared device helpers and plain-old-data descriptors of the HIP path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dcstedc.h"
+
+#define DC_STATUS_NONFINITE (-1000)
+#define DC_STATUS_EQUAL_EIG (-2000)
+
+typedef double dc_double4 __attribute__((ext_vector_type(4)));
+
+// Reciprocal to full double precision: hardware estimate plus two
+// Newton-Raphson corrections r <- r + r (1 - x r).
+__device__ __forceinline__ double dc_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return r;
+}
+
+__device__ __forceinline__ double dc_wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double dc_wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Record a device-detected failure: the first non-convergence code wins;
+// a non-finite input overrides any other code (later phases test for it).
+__device__ __forceinline__ void dc_set_info(int* info, int code) {
+    if (!info) return;
+    if (code == DC_STATUS_NONFINITE) atomicExch(info, code);
+    else atomicCAS(info, 0, code);
+}
+
+// One product C[rows, cols] (=|+=) A[rows, klist] * B[klist, cols] in which
+// B is a Cauchy-like matrix generated on the fly:
+//   B_kj = rz[g_k] * cs[j] / ((rD[g_k] - cbase[j]) - coff[j]),  g_k = klist[k].
+// A's column for generator g is acol[g] (identity when acol is null).
+struct GemmTask {
+    const double* A;      // row 0 of this task inside A
+    long long lda;
+    const int* acol;      // A column of generator g, or null (= g)
+    const int* klist;     // generator of k-entry, or null (= k)
+    const int* klen_p;    // device number of k-entries, or null (= klen)
+    int klen;
+    int rows;             // rows of the task
+    const double* rD;     // row nodes, indexed by generator
+    const double* rz;     // row weights, indexed by generator
+    const double* cbase;  // column node bases
+    const int* corg;      // if set, column node base j is rD[corg[j]] (cbase unused)
+    const double* coff;   // column node offsets, or null (= 0)
+    const double* cs;     // column scales
+    const int* ncol_p;    // device number of columns, or null (= ncol)
+    int ncol;
+    double* C;            // row 0 of this task inside C
+    long long ldc;
+    const int* cpos;      // output column of column j, or null (= j)
+    int tiles_m, tiles_n; // worst-case tile grid of the task
+    int beta;             // 0: overwrite, 1: accumulate
+    int pad_;
+};
+
+// Host-side launcher of the generated-Cauchy product over a task list.
+// tasks_dev / tile_start_dev live in device memory; tile_start has ntasks+1
+// entries (exclusive prefix sum of tiles_m * tiles_n).  variant selects the
+// tile shape (0 = default).
+hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
+                                 int ntasks, int total_tiles, int variant,
+                                 hipStream_t stream);
+int dc_gemm_tile_m(int variant);
+int dc_gemm_tile_n(int variant);

@@ -1,0 +1,90 @@
+// Descriptors shared by the tree driver and its kernels.
+//
+// A plan describes the divide-and-conquer tree of one or many problems with
+// pointer-free records (offsets and sizes only), uploaded once.  Per call the
+// caller's pointers reach the device through kernel arguments (the Prob table
+// is written by a kernel whose arguments carry it), so a captured graph holds
+// no pointer to host memory.
+#pragma once
+#include "secular.hpp"
+
+#define DC_MAX_LEAF 64
+
+struct Prob {
+    double* d;          // in: diagonal; out: eigenvalues (also the level's lam array)
+    const double* e;    // off-diagonal (n - 1)
+    double* Q;          // output eigenvectors, column-major
+    long long ldq;
+    double* B1;         // ping-pong partner of Q inside the workspace
+    long long ld1;
+    int n;
+    int row0;           // first row of this problem in the concatenated row space
+    int* info;          // status word
+    int pad_;
+};
+
+// A tree node: a merge (n2 > 0) or a leaf (n2 == 0, size n1).
+struct Node {
+    int prob;
+    int off;            // first row inside its problem
+    int n1, n2;
+    int depth;          // 0 at the root; parity selects Q (even) or B1 (odd)
+    int slot;           // merge index across the plan (per-merge scalars)
+};
+
+// Per-merge counters, one record per merge slot.
+struct MergeCnt {
+    int K;              // deflated size (secular problem order)
+    int nrot;           // pair rotations
+    int ndefl;          // deflated eigenpairs
+    int ntop;           // survivors with non-zeros in the top rows
+    int nbot;           // survivors with non-zeros in the bottom rows
+    int pad_[3];
+};
+
+// Per-row scratch (indexed by prob.row0 + node.off + local index) and
+// per-merge records, all inside the caller's workspace.
+struct Scratch {
+    double *Ds, *zs;            // sorted poles / weights (m)
+    double *Dbar, *zbar;        // survivors (K)
+    double *tau, *cbase, *lamr, *zhat, *scale;   // roots and eigenvector generators (K)
+    double *Dd;                 // deflated eigenvalues, ascending (m - K)
+    double *rc, *rs;            // rotation cosines / sines
+    int *perm;                  // sorted position -> local column
+    int *surv, *stype;          // survivor -> local column, row-type bits
+    int *org;                   // root origin (K)
+    int *dcol, *dtype;          // deflated -> local column, row-type bits
+    int *rp, *ri, *rt;          // rotation column pair and row-type bits (p | i << 2)
+    int *ktop, *kbot;           // generator lists of the top and bottom row halves
+    int *pos_root, *pos_defl;   // output column of each root / deflated pair
+    MergeCnt* cnt;              // per merge slot
+    double* rho2;               // per merge slot: 2 |e_k|
+    Prob* probs;
+    GemmTask* gtask;            // two per merge slot
+    SecTask* stask;             // one per merge slot
+};
+
+__host__ __device__ inline double* node_buf(const Prob& P, int depth, long long& ld) {
+    if (depth & 1) { ld = P.ld1; return P.B1; }
+    ld = P.ldq;
+    return P.Q;
+}
+
+// Kernel launchers (deflate.hip / leaf.hip).
+hipError_t dc_launch_leaf(const Node* leaves, int nleaves, Scratch S, hipStream_t s);
+hipError_t dc_launch_build(const Node* merges, int nmerges, int bm, int bn, Scratch S,
+                           hipStream_t s);
+hipError_t dc_launch_deflate(const Node* merges, int nm, Scratch S, hipStream_t s);
+hipError_t dc_launch_rotate(const Node* merges, const int* blk_start, int nm, int nblk,
+                            Scratch S, hipStream_t s);
+hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, int nblk,
+                              Scratch S, hipStream_t s);
+hipError_t dc_launch_copy_deflated(const Node* merges, const int* blk_start, int nm,
+                                   int nblk, Scratch S, hipStream_t s);
+hipError_t dc_launch_set_probs(const Prob* host_probs, int count, Prob* dev, hipStream_t s);
+
+// Rows handled per block by the rotation and assembly kernels, and columns
+// per block of the deflated-column copy.
+#define DC_ROWS_PER_BLOCK 256
+#define DC_COLS_PER_BLOCK 4
+#define DC_ROOTS_PER_BLOCK 64

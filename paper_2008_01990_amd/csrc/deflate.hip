@@ -1,0 +1,458 @@
+// Merge set-up and clean-up kernels of the divide-and-conquer tree:
+// rank-one vector and deflation (eq. T3, eq. T3-def), Givens rotations of
+// the basis, final eigenvalue order and deflated-column copy (eq. evect).
+//
+// For a merge of children with (Lambda_1, Q_1) rows [0, n1) and
+// (Lambda_2, Q_2) rows [n1, m) of its diagonal block:
+//   z = [last row of Q_1, sigma * first row of Q_2] / sqrt(2),  rho' = 2 |e_k|
+//   D = [Lambda_1; Lambda_2] sorted by a merge of the two ascending lists.
+// Deflation (tol = 8 eps max(max|D|, rho')): z-negligible entries become
+// eigenpairs as they are; neighbouring survivors p < i with
+// |(D_i - D_p) c s| <= tol for the Givens pair that zeroes z_p are rotated
+// and p deflated.  The walk over survivors is inherently sequential (each
+// test involves the last survivor), so one lane performs it while the
+// workgroup stages the sorted arrays through LDS in chunks.
+//
+// Every column of the merge block carries row-type bits: 1 if it may be
+// non-zero in the top rows [0, n1), 2 in the bottom rows [n1, m).  Columns of
+// Q_1 start as 1, of Q_2 as 2; a rotation of two columns gives both the union.
+// Memory outside a column's type is never read (it holds stale data of other
+// tree levels), and the product then runs separately on the top rows (k over
+// survivors of type 1|3) and on the bottom rows (type 2|3): the structural
+// zeros of diag(Q_1, Q_2) cost no flops.
+#include "dc_internal.hpp"
+
+namespace {
+
+constexpr double EPS = 2.220446049250313e-16;
+constexpr int NT = 1024;
+constexpr int CH = 2048;       // scan chunk staged through LDS
+
+__device__ __forceinline__ int block_of(const int* blk_start, int nm, int b) {
+    int lo = 0, hi = nm - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (blk_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Number of entries of the ascending a[0..n) strictly below x / at most x.
+__device__ __forceinline__ int count_lt(const double* a, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int count_le(const double* a, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Writes up to 8 Prob records carried in the kernel arguments.
+struct ProbPack { Prob p[8]; };
+__global__ void k_write_probs(Prob* dst, int first, int count, ProbPack pack) {
+    const int i = threadIdx.x;
+    if (i < count) dst[first + i] = pack.p[i];
+}
+
+// Build the product and secular task records of every merge (per call: they
+// hold the caller's pointers).
+__global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn, Scratch S) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nm) return;
+    const Node N = merges[g];
+    const Prob P = S.probs[N.prob];
+    const int m = N.n1 + N.n2;
+    const long long base = (long long)P.row0 + N.off;
+    long long ldi, ldo;
+    double* Qi = node_buf(P, N.depth + 1, ldi);
+    double* Qo = node_buf(P, N.depth, ldo);
+    const int slot = N.slot;
+    MergeCnt* cnt = S.cnt + slot;
+    const int tn = (m + bn - 1) / bn;   // worst-case column tiles
+    for (int half = 0; half < 2; ++half) {
+        GemmTask T;
+        const int r0 = half ? N.n1 : 0;
+        T.A = Qi + (long long)N.off * ldi + N.off + r0;
+        T.lda = ldi;
+        T.acol = S.surv + base;
+        T.klist = (half ? S.kbot : S.ktop) + base;
+        T.klen_p = half ? &cnt->nbot : &cnt->ntop;
+        T.klen = 0;
+        T.rows = half ? N.n2 : N.n1;
+        T.rD = S.Dbar + base;
+        T.rz = S.zhat + base;
+        T.cbase = S.cbase + base;
+        T.corg = nullptr;
+        T.coff = S.tau + base;
+        T.cs = S.scale + base;
+        T.ncol_p = &cnt->K;
+        T.ncol = 0;
+        T.C = Qo + (long long)N.off * ldo + N.off + r0;
+        T.ldc = ldo;
+        T.cpos = S.pos_root + base;
+        T.tiles_m = (T.rows + bm - 1) / bm;
+        T.tiles_n = tn;
+        T.beta = 0;
+        T.pad_ = 0;
+        S.gtask[2 * slot + half] = T;
+    }
+    SecTask Q;
+    Q.D = S.Dbar + base;
+    Q.z = S.zbar + base;
+    Q.K_p = &cnt->K;
+    Q.K = 0;
+    Q.pad_ = 0;
+    Q.rho_p = S.rho2 + slot;
+    Q.rho = 0.0;
+    Q.org = S.org + base;
+    Q.tau = S.tau + base;
+    Q.cbase = S.cbase + base;
+    Q.lam = S.lamr + base;
+    Q.zhat = S.zhat + base;
+    Q.scale = S.scale + base;
+    Q.info = P.info;
+    S.stask[slot] = Q;
+}
+
+// One workgroup per merge: z, sort, deflation walk, generator lists.
+__global__ __launch_bounds__(NT)
+void k_deflate(const Node* __restrict__ merges, Scratch S) {
+    __shared__ double sD[CH];
+    __shared__ double sz[CH];
+    __shared__ int sp[CH];
+    __shared__ int wsum[NT / 64];
+    __shared__ int s_K;
+
+    const Node N = merges[blockIdx.x];
+    const Prob P = S.probs[N.prob];
+    const int n1 = N.n1, n2 = N.n2, m = n1 + n2;
+    const long long base = (long long)P.row0 + N.off;
+    long long ldi;
+    const double* Qi = node_buf(P, N.depth + 1, ldi);
+    const double* L1 = P.d + N.off;          // Lambda_1 ascending
+    const double* L2 = P.d + N.off + n1;     // Lambda_2 ascending
+    const double ek = P.e[N.off + n1 - 1];
+    const double rho2 = 2.0 * fabs(ek);
+    const double sigma = ek < 0.0 ? -1.0 : 1.0;
+    const double rs2 = 0.70710678118654752440;
+    const int tid = threadIdx.x;
+
+    // A problem with non-finite input (flagged by the leaf phase) cannot be
+    // ordered: every pair becomes a deflated identity column with a NaN
+    // eigenvalue, which keeps every later index in range.
+    if (*P.info == DC_STATUS_NONFINITE) {
+        for (int k = tid; k < m; k += NT) {
+            S.Dd[base + k] = NAN;
+            S.dcol[base + k] = k;
+            S.dtype[base + k] = k < n1 ? 1 : 2;
+        }
+        if (tid == 0) {
+            MergeCnt* cnt = S.cnt + N.slot;
+            cnt->K = 0;
+            cnt->nrot = 0;
+            cnt->ndefl = m;
+            cnt->ntop = 0;
+            cnt->nbot = 0;
+            S.rho2[N.slot] = 0.0;
+        }
+        return;
+    }
+
+    // z, merge of the two sorted lists, scatter to sorted order.
+    for (int i = tid; i < m; i += NT) {
+        double Dv, zv;
+        int pos;
+        if (i < n1) {
+            Dv = L1[i];
+            zv = Qi[(long long)(N.off + i) * ldi + N.off + n1 - 1] * rs2;
+            pos = i + count_lt(L2, n2, Dv);
+        } else {
+            Dv = L2[i - n1];
+            zv = sigma * Qi[(long long)(N.off + i) * ldi + N.off + n1] * rs2;
+            pos = (i - n1) + count_le(L1, n1, Dv);
+        }
+        S.Ds[base + pos] = Dv;
+        S.zs[base + pos] = zv;
+        S.perm[base + pos] = i;
+    }
+    const double dmax = fmax(fmax(fabs(L1[0]), fabs(L1[n1 - 1])),
+                             fmax(fabs(L2[0]), fabs(L2[n2 - 1])));
+    const double tol = 8.0 * EPS * fmax(dmax, rho2);
+    __syncthreads();
+
+    // Sequential deflation walk (lane 0), chunks staged through LDS.
+    int K = 0, nrot = 0, nd = 0;
+    int p = -1, colp = 0, typp = 0;
+    double Dp = 0.0, zp = 0.0, lastd = -INFINITY;
+    auto emit_deflated = [&](double v, int col, int typ) {
+        // keep Dd ascending: insertion from the back (rarely moves)
+        int k = nd;
+        if (v < lastd) {
+            while (k > 0 && S.Dd[base + k - 1] > v) {
+                S.Dd[base + k] = S.Dd[base + k - 1];
+                S.dcol[base + k] = S.dcol[base + k - 1];
+                S.dtype[base + k] = S.dtype[base + k - 1];
+                --k;
+            }
+        } else {
+            lastd = v;
+        }
+        S.Dd[base + k] = v;
+        S.dcol[base + k] = col;
+        S.dtype[base + k] = typ;
+        ++nd;
+    };
+    for (int c0 = 0; c0 < m; c0 += CH) {
+        const int cn = min(CH, m - c0);
+        for (int i = tid; i < cn; i += NT) {
+            sD[i] = S.Ds[base + c0 + i];
+            sz[i] = S.zs[base + c0 + i];
+            sp[i] = S.perm[base + c0 + i];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int ii = 0; ii < cn; ++ii) {
+                const double Di = sD[ii];
+                const double zi = sz[ii];
+                // every position is written by the merge path above; the clamp
+                // only guards the column range against a broken ordering
+                const int coli = min(max(sp[ii], 0), m - 1);
+                const int typi = coli < n1 ? 1 : 2;
+                if (rho2 * fabs(zi) <= tol) {
+                    emit_deflated(Di, coli, typi);
+                    continue;
+                }
+                if (p < 0) {
+                    p = c0 + ii; Dp = Di; zp = zi; colp = coli; typp = typi;
+                    continue;
+                }
+                const double r = hypot(zp, zi);
+                const double c = zi / r;
+                const double s = zp / r;
+                if (fabs((Di - Dp) * c * s) <= tol) {
+                    S.rp[base + nrot] = colp;
+                    S.ri[base + nrot] = coli;
+                    S.rc[base + nrot] = c;
+                    S.rs[base + nrot] = s;
+                    S.rt[base + nrot] = typp | (typi << 2);
+                    ++nrot;
+                    const int tu = typp | typi;
+                    emit_deflated(c * c * Dp + s * s * Di, colp, tu);
+                    Dp = s * s * Dp + c * c * Di;
+                    zp = r;
+                    colp = coli;
+                    typp = tu;
+                    p = c0 + ii;
+                } else {
+                    S.Dbar[base + K] = Dp;
+                    S.zbar[base + K] = zp;
+                    S.surv[base + K] = colp;
+                    S.stype[base + K] = typp;
+                    ++K;
+                    p = c0 + ii; Dp = Di; zp = zi; colp = coli; typp = typi;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (p >= 0) {
+            S.Dbar[base + K] = Dp;
+            S.zbar[base + K] = zp;
+            S.surv[base + K] = colp;
+            S.stype[base + K] = typp;
+            ++K;
+        }
+        MergeCnt* cnt = S.cnt + N.slot;
+        cnt->K = K;
+        cnt->nrot = nrot;
+        cnt->ndefl = nd;
+        S.rho2[N.slot] = rho2;
+        s_K = K;
+    }
+    __syncthreads();
+    K = s_K;
+
+    // Order-preserving lists of survivors touching the top / bottom rows.
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int half = 0; half < 2; ++half) {
+        const int bit = half ? 2 : 1;
+        int* out = (half ? S.kbot : S.ktop) + base;
+        int running = 0;
+        for (int c0 = 0; c0 < K; c0 += NT) {
+            const int j = c0 + tid;
+            const bool f = j < K && (S.stype[base + j] & bit);
+            const unsigned long long bal = __ballot(f);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wsum[wv] = __popcll(bal);
+            __syncthreads();
+            int woff = 0;
+            for (int q = 0; q < wv; ++q) woff += wsum[q];
+            int tot = 0;
+            for (int q = 0; q < NT / 64; ++q) tot += wsum[q];
+            if (f) out[running + woff + before] = j;
+            running += tot;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            MergeCnt* cnt = S.cnt + N.slot;
+            if (half) cnt->nbot = running; else cnt->ntop = running;
+        }
+    }
+}
+
+// Apply the pair rotations of each merge to its basis, in order.  Thread r
+// owns row r of the merge block; entries outside a column's row type are
+// structural zeros.
+__global__ __launch_bounds__(DC_ROWS_PER_BLOCK)
+void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
+              Scratch S) {
+    const int mi = block_of(blk_start, nm, blockIdx.x);
+    const Node N = merges[mi];
+    const int nrot = S.cnt[N.slot].nrot;
+    if (nrot == 0) return;
+    const int r = (blockIdx.x - blk_start[mi]) * DC_ROWS_PER_BLOCK + threadIdx.x;
+    const int m = N.n1 + N.n2;
+    if (r >= m) return;
+    const Prob P = S.probs[N.prob];
+    const long long base = (long long)P.row0 + N.off;
+    long long ld;
+    double* Qi = node_buf(P, N.depth + 1, ld);
+    double* row = Qi + (long long)N.off * ld + N.off + r;
+    const int rbit = r < N.n1 ? 1 : 2;
+    for (int t = 0; t < nrot; ++t) {
+        const int cp = S.rp[base + t];
+        const int ci = S.ri[base + t];
+        const double c = S.rc[base + t];
+        const double s = S.rs[base + t];
+        const int ty = S.rt[base + t];
+        const bool inp = (ty & rbit) != 0;
+        const bool ini = ((ty >> 2) & rbit) != 0;
+        if (!(inp || ini)) continue;
+        double* ap = row + (long long)cp * ld;
+        double* ai = row + (long long)ci * ld;
+        const double qp = inp ? *ap : 0.0;
+        const double qi = ini ? *ai : 0.0;
+        *ap = c * qp - s * qi;
+        *ai = s * qp + c * qi;
+    }
+}
+
+// Final ascending order of the merged eigenvalues: roots (ascending by
+// interlacing) and deflated values (ascending) meet by a merge path; ties
+// place the root first.  Writes the eigenvalues into the lam array.
+__global__ __launch_bounds__(DC_ROWS_PER_BLOCK)
+void k_assemble(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
+                Scratch S) {
+    const int mi = block_of(blk_start, nm, blockIdx.x);
+    const Node N = merges[mi];
+    const int x = (blockIdx.x - blk_start[mi]) * DC_ROWS_PER_BLOCK + threadIdx.x;
+    const int m = N.n1 + N.n2;
+    if (x >= m) return;
+    const MergeCnt C = S.cnt[N.slot];
+    const Prob P = S.probs[N.prob];
+    const long long base = (long long)P.row0 + N.off;
+    const double* lr = S.lamr + base;
+    const double* dd = S.Dd + base;
+    if (x < C.K) {
+        const double v = lr[x];
+        const int pos = x + count_lt(dd, C.ndefl, v);
+        S.pos_root[base + x] = pos;
+        P.d[N.off + pos] = v;
+    } else {
+        const int k = x - C.K;
+        const double v = dd[k];
+        const int pos = k + count_le(lr, C.K, v);
+        S.pos_defl[base + k] = pos;
+        P.d[N.off + pos] = v;
+    }
+}
+
+// Deflated eigenvectors: the (rotated) basis column itself, zero-filled
+// outside its row type, written to its final position.
+__global__ __launch_bounds__(256)
+void k_copy_deflated(const Node* __restrict__ merges, const int* __restrict__ blk_start,
+                     int nm, Scratch S) {
+    const int mi = block_of(blk_start, nm, blockIdx.x);
+    const Node N = merges[mi];
+    const MergeCnt C = S.cnt[N.slot];
+    const int k0 = (blockIdx.x - blk_start[mi]) * DC_COLS_PER_BLOCK;
+    if (k0 >= C.ndefl) return;
+    const Prob P = S.probs[N.prob];
+    const long long base = (long long)P.row0 + N.off;
+    const int m = N.n1 + N.n2;
+    long long ldi, ldo;
+    const double* Qi = node_buf(P, N.depth + 1, ldi);
+    double* Qo = node_buf(P, N.depth, ldo);
+    for (int k = k0; k < min(C.ndefl, k0 + DC_COLS_PER_BLOCK); ++k) {
+        const int src = S.dcol[base + k];
+        const int ty = S.dtype[base + k];
+        const int dst = S.pos_defl[base + k];
+        const double* a = Qi + (long long)(N.off + src) * ldi + N.off;
+        double* o = Qo + (long long)(N.off + dst) * ldo + N.off;
+        for (int r = threadIdx.x; r < m; r += 256) {
+            const int rbit = r < N.n1 ? 1 : 2;
+            o[r] = (ty & rbit) ? a[r] : 0.0;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t dc_launch_set_probs(const Prob* host_probs, int count, Prob* dev, hipStream_t s) {
+    for (int first = 0; first < count; first += 8) {
+        ProbPack pk;
+        const int c = count - first < 8 ? count - first : 8;
+        for (int i = 0; i < c; ++i) pk.p[i] = host_probs[first + i];
+        hipLaunchKernelGGL(k_write_probs, dim3(1), dim3(64), 0, s, dev, first, c, pk);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+hipError_t dc_launch_build(const Node* merges, int nm, int bm, int bn, Scratch S,
+                           hipStream_t s) {
+    if (nm <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build, dim3((nm + 127) / 128), dim3(128), 0, s, merges, nm, bm, bn,
+                       S);
+    return hipGetLastError();
+}
+
+hipError_t dc_launch_deflate(const Node* merges, int nm, Scratch S, hipStream_t s) {
+    if (nm <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(NT), 0, s, merges, S);
+    return hipGetLastError();
+}
+
+hipError_t dc_launch_rotate(const Node* merges, const int* blk_start, int nm, int nblk,
+                            Scratch S, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rotate, dim3(nblk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
+                       blk_start, nm, S);
+    return hipGetLastError();
+}
+
+hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, int nblk,
+                              Scratch S, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_assemble, dim3(nblk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
+                       blk_start, nm, S);
+    return hipGetLastError();
+}
+
+hipError_t dc_launch_copy_deflated(const Node* merges, const int* blk_start, int nm,
+                                   int nblk, Scratch S, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_deflated, dim3(nblk), dim3(256), 0, s, merges, blk_start, nm,
+                       S);
+    return hipGetLastError();
+}

@@ -1,0 +1,488 @@
+// Divide-and-conquer tree driver (Algorithm 1, with Algorithm 3's choice of
+// merge product) and the dc_stedc family of entry points.
+//
+// Plan: every problem is split at k = m / 2 until a block has at most
+// `leaf` rows.  Merges are grouped by tree depth; all merges of one depth
+// (of every problem of a batch) form one level, processed as one launch per
+// phase:
+//   deflate -> rotate -> secular roots / Loewner / scales -> assemble
+//   -> generated-Cauchy product (top and bottom row halves) -> deflated copy.
+// Leaves run first, all in one launch.  A node's eigenvectors live in the
+// caller's Q when its depth is even and in the workspace partner B1 when it
+// is odd, so each merge reads its children from one buffer and writes the
+// other, and the root lands in Q.
+//
+// Nothing here synchronises with the device after the plan exists: the
+// level loop only launches kernels, with data-dependent sizes (the deflated
+// K of each merge) read by the kernels from device memory and grids sized
+// for the worst case.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "dc_internal.hpp"
+#include "driver.hpp"
+
+namespace {
+
+struct Level {
+    int first;          // first merge (slot) of the level
+    int nm;
+    int tiles;          // worst-case product tiles
+    int sec_blocks, row_blocks, copy_blocks;
+    int off_tile, off_sec, off_row, off_copy;   // offsets into the prefix array
+};
+
+struct Plan {
+    std::vector<int> sizes;
+    int leaf, bm, bn;
+    std::vector<Node> leaves, merges;   // merges ordered by level, deepest first
+    std::vector<Level> levels;
+    std::vector<int> prefix;            // all per-level prefix sums
+    std::vector<long long> row0, buf_off;
+    long long rows = 0;                 // sum of n
+    long long buf_elems = 0;            // sum of n^2 (odd-depth buffers)
+    Node* d_nodes = nullptr;            // leaves then merges
+    int* d_prefix = nullptr;
+    int device = -1;
+    ~Plan() {
+        if (d_nodes) hipFree(d_nodes);
+        if (d_prefix) hipFree(d_prefix);
+    }
+};
+
+void split(std::vector<std::vector<Node>>& by_depth, std::vector<Node>& leaves, int prob,
+           int off, int m, int depth, int leaf) {
+    if (m <= leaf) {
+        leaves.push_back(Node{prob, off, m, 0, depth, -1});
+        return;
+    }
+    const int k = m / 2;
+    split(by_depth, leaves, prob, off, k, depth + 1, leaf);
+    split(by_depth, leaves, prob, off + k, m - k, depth + 1, leaf);
+    if ((int)by_depth.size() <= depth) by_depth.resize(depth + 1);
+    by_depth[depth].push_back(Node{prob, off, k, m - k, depth, -1});
+}
+
+std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int bm, int bn) {
+    auto P = std::make_unique<Plan>();
+    P->sizes = sizes;
+    P->leaf = leaf;
+    P->bm = bm;
+    P->bn = bn;
+    std::vector<std::vector<Node>> by_depth;
+    for (size_t p = 0; p < sizes.size(); ++p) {
+        P->row0.push_back(P->rows);
+        P->buf_off.push_back(P->buf_elems);
+        P->rows += sizes[p];
+        P->buf_elems += (long long)sizes[p] * sizes[p];
+        if (sizes[p] > 0) split(by_depth, P->leaves, (int)p, 0, sizes[p], 0, leaf);
+    }
+    for (int dep = (int)by_depth.size() - 1; dep >= 0; --dep) {
+        Level L{};
+        L.first = (int)P->merges.size();
+        for (Node N : by_depth[dep]) {
+            N.slot = (int)P->merges.size();
+            P->merges.push_back(N);
+        }
+        L.nm = (int)P->merges.size() - L.first;
+        if (L.nm == 0) continue;
+        auto& pre = P->prefix;
+        L.off_tile = (int)pre.size();
+        int acc = 0;
+        for (int i = 0; i < L.nm; ++i) {
+            const Node& N = P->merges[L.first + i];
+            const int m = N.n1 + N.n2;
+            const int tn = (m + bn - 1) / bn;
+            pre.push_back(acc);
+            acc += ((N.n1 + bm - 1) / bm) * tn;
+            pre.push_back(acc);
+            acc += ((N.n2 + bm - 1) / bm) * tn;
+        }
+        pre.push_back(acc);
+        L.tiles = acc;
+        auto add = [&](int per, int& off, int& total) {
+            off = (int)pre.size();
+            int a = 0;
+            for (int i = 0; i < L.nm; ++i) {
+                const Node& N = P->merges[L.first + i];
+                pre.push_back(a);
+                a += (N.n1 + N.n2 + per - 1) / per;
+            }
+            pre.push_back(a);
+            total = a;
+        };
+        add(DC_ROOTS_PER_BLOCK, L.off_sec, L.sec_blocks);
+        add(DC_ROWS_PER_BLOCK, L.off_row, L.row_blocks);
+        add(DC_COLS_PER_BLOCK, L.off_copy, L.copy_blocks);
+        P->levels.push_back(L);
+    }
+    return P;
+}
+
+hipError_t upload(Plan& P) {
+    hipError_t err = hipGetDevice(&P.device);
+    if (err != hipSuccess) return err;
+    std::vector<Node> all(P.leaves);
+    all.insert(all.end(), P.merges.begin(), P.merges.end());
+    if (!all.empty()) {
+        err = hipMalloc(&P.d_nodes, all.size() * sizeof(Node));
+        if (err != hipSuccess) return err;
+        err = hipMemcpy(P.d_nodes, all.data(), all.size() * sizeof(Node), hipMemcpyHostToDevice);
+        if (err != hipSuccess) return err;
+    }
+    if (!P.prefix.empty()) {
+        err = hipMalloc(&P.d_prefix, P.prefix.size() * sizeof(int));
+        if (err != hipSuccess) return err;
+        err = hipMemcpy(P.d_prefix, P.prefix.data(), P.prefix.size() * sizeof(int),
+                        hipMemcpyHostToDevice);
+    }
+    return err;
+}
+
+std::mutex g_plan_mu;
+std::map<std::vector<int>, std::unique_ptr<Plan>> g_plans;
+
+// Plans are keyed by (device, leaf, tile shape, sizes).
+hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan** out) {
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    const int bm = dc_gemm_tile_m(variant), bn = dc_gemm_tile_n(variant);
+    std::vector<int> key{dev, leaf, bm, bn};
+    key.insert(key.end(), sizes.begin(), sizes.end());
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        *out = it->second.get();
+        return hipSuccess;
+    }
+    auto P = make_plan(sizes, leaf, bm, bn);
+    err = upload(*P);
+    if (err != hipSuccess) return err;
+    *out = P.get();
+    g_plans[key] = std::move(P);
+    return hipSuccess;
+}
+
+// Workspace layout.
+struct Layout {
+    size_t bytes = 0;
+    size_t probs, gtask, stask, cnt, rho2, dbl, ints, bufs;
+    int nd = 12, ni = 13;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout(const Plan& P) {
+    Layout L;
+    size_t o = 0;
+    const size_t nm = std::max<size_t>(P.merges.size(), 1);
+    const size_t R = std::max<long long>(P.rows, 1);
+    L.probs = o; o = align256(o + P.sizes.size() * sizeof(Prob));
+    L.gtask = o; o = align256(o + 2 * nm * sizeof(GemmTask));
+    L.stask = o; o = align256(o + nm * sizeof(SecTask));
+    L.cnt = o; o = align256(o + nm * sizeof(MergeCnt));
+    L.rho2 = o; o = align256(o + nm * sizeof(double));
+    L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
+    L.ints = o; o = align256(o + L.ni * R * sizeof(int));
+    L.bufs = o; o = align256(o + P.buf_elems * sizeof(double));
+    L.bytes = o;
+    return L;
+}
+
+Scratch carve(const Plan& P, const Layout& L, char* w) {
+    Scratch S;
+    const size_t R = std::max<long long>(P.rows, 1);
+    double* db = reinterpret_cast<double*>(w + L.dbl);
+    double** dp[] = {&S.Ds, &S.zs, &S.Dbar, &S.zbar, &S.tau, &S.cbase, &S.lamr, &S.zhat,
+                     &S.scale, &S.Dd, &S.rc, &S.rs};
+    for (int i = 0; i < L.nd; ++i) *dp[i] = db + i * R;
+    int* ib = reinterpret_cast<int*>(w + L.ints);
+    int** ip[] = {&S.perm, &S.surv, &S.stype, &S.org, &S.dcol, &S.dtype, &S.rp, &S.ri,
+                  &S.rt, &S.ktop, &S.kbot, &S.pos_root, &S.pos_defl};
+    for (int i = 0; i < L.ni; ++i) *ip[i] = ib + i * R;
+    S.cnt = reinterpret_cast<MergeCnt*>(w + L.cnt);
+    S.rho2 = reinterpret_cast<double*>(w + L.rho2);
+    S.probs = reinterpret_cast<Prob*>(w + L.probs);
+    S.gtask = reinterpret_cast<GemmTask*>(w + L.gtask);
+    S.stask = reinterpret_cast<SecTask*>(w + L.stask);
+    return S;
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
+                    const dc_opts& o, hipStream_t s) {
+    const Layout L = layout(P);
+    Scratch S = carve(P, L, work);
+    hipError_t err = dc_launch_set_probs(probs.data(), (int)probs.size(), S.probs, s);
+    if (err != hipSuccess) return err;
+    const Node* d_leaves = P.d_nodes;
+    const Node* d_merges = P.d_nodes + P.leaves.size();
+    err = dc_launch_build(d_merges, (int)P.merges.size(), P.bm, P.bn, S, s);
+    if (err != hipSuccess) return err;
+    err = dc_launch_leaf(d_leaves, (int)P.leaves.size(), S, s);
+    if (err != hipSuccess) return err;
+    for (const Level& Lv : P.levels) {
+        const Node* mg = d_merges + Lv.first;
+        err = dc_launch_deflate(mg, Lv.nm, S, s);
+        if (err != hipSuccess) return err;
+        err = dc_launch_rotate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s);
+        if (err != hipSuccess) return err;
+        err = dc_launch_secular(S.stask + Lv.first, P.d_prefix + Lv.off_sec, Lv.nm,
+                                Lv.sec_blocks, o.max_iter, s);
+        if (err != hipSuccess) return err;
+        err = dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s);
+        if (err != hipSuccess) return err;
+        err = dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
+                                    2 * Lv.nm, Lv.tiles, o.gemm_tile, s);
+        if (err != hipSuccess) return err;
+        err = dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks, S,
+                                      s);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+thread_local const Plan* t_last_plan = nullptr;
+thread_local char* t_last_work = nullptr;
+
+}  // namespace
+
+dc_opts dc_resolve_opts(const dc_opts* opt) {
+    dc_opts o;
+    dc_opts_default(&o);
+    if (opt) {
+        if (opt->leaf > 0) o.leaf = opt->leaf;
+        o.lr_tol = opt->lr_tol;
+        if (opt->lr_block > 0) o.lr_block = opt->lr_block;
+        if (opt->lr_min_k > 0) o.lr_min_k = opt->lr_min_k;
+        if (opt->max_iter > 0) o.max_iter = opt->max_iter;
+        o.gemm_tile = opt->gemm_tile;
+    }
+    return o;
+}
+
+hipError_t dc_fill_int(int* p, int n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+extern "C" void dc_opts_default(dc_opts* o) {
+    if (!o) return;
+    o->leaf = 32;
+    o->lr_tol = 0.0;
+    o->lr_block = 1024;
+    o->lr_min_k = 4096;
+    o->max_iter = 64;
+    o->gemm_tile = 0;
+}
+
+static int check_opts(const dc_opts& o) {
+    if (o.leaf < 1 || o.leaf > DC_MAX_LEAF) return 1;
+    if (!(o.lr_tol >= 0.0)) return 1;
+    return 0;
+}
+
+extern "C" size_t dc_stedc_workspace(int n, const dc_opts* opt) {
+    if (n < 0) return 0;
+    const dc_opts o = dc_resolve_opts(opt);
+    if (check_opts(o)) return 0;
+    Plan* P = nullptr;
+    if (get_plan({n}, o.leaf, o.gemm_tile, &P) != hipSuccess) return 0;
+    return layout(*P).bytes;
+}
+
+extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void* work,
+                           size_t lwork, int* info_dev, const dc_opts* opt,
+                           hipStream_t stream) {
+    if (n < 0) return -1;
+    if (n > 0 && !d) return -2;
+    if (n > 1 && !e) return -3;
+    if (n > 0 && !Q) return -4;
+    if (ldq < std::max(1, n)) return -5;
+    const dc_opts o = dc_resolve_opts(opt);
+    if (check_opts(o)) return -9;
+    if (!info_dev) return -8;
+    Plan* P = nullptr;
+    hipError_t err = get_plan({n}, o.leaf, o.gemm_tile, &P);
+    if (err != hipSuccess) return (int)err;
+    const Layout L = layout(*P);
+    if (!work || lwork < L.bytes) return -7;
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -6;
+    err = (hipError_t)dc_fill_int(info_dev, 1, 0, stream);
+    if (err != hipSuccess) return (int)err;
+    if (n == 0) return 0;
+    char* w = static_cast<char*>(work);
+    Prob pr{};
+    pr.d = d;
+    pr.e = e;
+    pr.Q = Q;
+    pr.ldq = ldq;
+    pr.B1 = reinterpret_cast<double*>(w + L.bufs);
+    pr.ld1 = n;
+    pr.n = n;
+    pr.row0 = 0;
+    pr.info = info_dev;
+    err = run_plan(*P, {pr}, w, o, stream);
+    t_last_plan = P;
+    t_last_work = w;
+    return (int)err;
+}
+
+extern "C" size_t dc_stedc_batched_workspace(int count, const int* n_host, const dc_opts* opt) {
+    if (count < 0 || (count > 0 && !n_host)) return 0;
+    const dc_opts o = dc_resolve_opts(opt);
+    if (check_opts(o)) return 0;
+    std::vector<int> sizes(n_host, n_host + count);
+    for (int v : sizes)
+        if (v < 0) return 0;
+    Plan* P = nullptr;
+    if (get_plan(sizes, o.leaf, o.gemm_tile, &P) != hipSuccess) return 0;
+    return layout(*P).bytes;
+}
+
+// Batched solve; the graph cache lives in graph.cpp-equivalent code below.
+int dc_batched_impl(int count, const int* n_host, double* const* d, double* const* e,
+                    double* const* Q, const int* ldq_host, void* work, size_t lwork,
+                    int* info_dev, const dc_opts* opt, hipStream_t stream, bool use_graph);
+
+namespace {
+struct GraphEntry {
+    std::vector<Prob> probs;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::map<std::vector<uintptr_t>, std::unique_ptr<GraphEntry>> g_graphs;
+}  // namespace
+
+int dc_batched_impl(int count, const int* n_host, double* const* d, double* const* e,
+                    double* const* Q, const int* ldq_host, void* work, size_t lwork,
+                    int* info_dev, const dc_opts* opt, hipStream_t stream, bool use_graph) {
+    if (count < 0) return -1;
+    if (count > 0 && (!n_host || !d || !e || !Q || !ldq_host)) return -2;
+    const dc_opts o = dc_resolve_opts(opt);
+    if (check_opts(o)) return -10;
+    if (!info_dev) return -9;
+    std::vector<int> sizes(n_host, n_host + count);
+    for (int p = 0; p < count; ++p) {
+        if (sizes[p] < 0) return -2;
+        if (sizes[p] > 0 && (!d[p] || !Q[p])) return -3;
+        if (sizes[p] > 1 && !e[p]) return -4;
+        if (ldq_host[p] < std::max(1, sizes[p])) return -6;
+    }
+    Plan* P = nullptr;
+    hipError_t err = get_plan(sizes, o.leaf, o.gemm_tile, &P);
+    if (err != hipSuccess) return (int)err;
+    const Layout L = layout(*P);
+    if (!work || lwork < L.bytes) return -8;
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -7;
+    char* w = static_cast<char*>(work);
+    std::vector<Prob> probs(count);
+    for (int p = 0; p < count; ++p) {
+        Prob& pr = probs[p];
+        pr.d = d[p];
+        pr.e = e[p];
+        pr.Q = Q[p];
+        pr.ldq = ldq_host[p];
+        pr.B1 = reinterpret_cast<double*>(w + L.bufs) + P->buf_off[p];
+        pr.ld1 = std::max(1, sizes[p]);
+        pr.n = sizes[p];
+        pr.row0 = (int)P->row0[p];
+        pr.info = info_dev + p;
+        pr.pad_ = 0;
+    }
+    if (!use_graph) {
+        err = (hipError_t)dc_fill_int(info_dev, count, 0, stream);
+        if (err != hipSuccess) return (int)err;
+        return (int)run_plan(*P, probs, w, o, stream);
+    }
+    // Graph path: capture the whole level schedule once per signature.
+    std::vector<uintptr_t> key{(uintptr_t)P, (uintptr_t)work, (uintptr_t)info_dev,
+                               (uintptr_t)o.max_iter};
+    for (int p = 0; p < count; ++p) {
+        key.push_back((uintptr_t)d[p]);
+        key.push_back((uintptr_t)e[p]);
+        key.push_back((uintptr_t)Q[p]);
+        key.push_back((uintptr_t)ldq_host[p]);
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        auto G = std::make_unique<GraphEntry>();
+        G->probs = probs;
+        hipStream_t cap;
+        err = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (err != hipSuccess) return (int)err;
+        err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            hipError_t e1 = dc_fill_int(info_dev, count, 0, cap);
+            if (e1 == hipSuccess) e1 = run_plan(*P, G->probs, w, o, cap);
+            hipGraph_t graph = nullptr;
+            err = hipStreamEndCapture(cap, &graph);
+            if (e1 != hipSuccess) err = e1;
+            if (err == hipSuccess) err = hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0);
+            if (graph) hipGraphDestroy(graph);
+        }
+        hipStreamDestroy(cap);
+        if (err != hipSuccess) return (int)err;
+        it = g_graphs.emplace(key, std::move(G)).first;
+    }
+    return (int)hipGraphLaunch(it->second->exec, stream);
+}
+
+extern "C" int dc_stedc_batched(int count, const int* n_host, double* const* d,
+                                double* const* e, double* const* Q, const int* ldq_host,
+                                void* work, size_t lwork, int* info_dev, const dc_opts* opt,
+                                hipStream_t stream) {
+    return dc_batched_impl(count, n_host, d, e, Q, ldq_host, work, lwork, info_dev, opt,
+                           stream, true);
+}
+
+extern "C" int dc_stedc_batched_eager(int count, const int* n_host, double* const* d,
+                                      double* const* e, double* const* Q, const int* ldq_host,
+                                      void* work, size_t lwork, int* info_dev,
+                                      const dc_opts* opt, hipStream_t stream) {
+    return dc_batched_impl(count, n_host, d, e, Q, ldq_host, work, lwork, info_dev, opt,
+                           stream, false);
+}
+
+extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
+    const Plan* P = t_last_plan;
+    if (!P || !t_last_work) return 0;
+    const Layout L = layout(*P);
+    std::vector<MergeCnt> cnt(P->merges.size());
+    if (!cnt.empty() &&
+        hipMemcpy(cnt.data(), t_last_work + L.cnt, cnt.size() * sizeof(MergeCnt),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return 0;
+    const int nmr = (int)P->merges.size();
+    int li = 0;
+    for (int lv = 0; lv < (int)P->levels.size(); ++lv) {
+        const Level& Lv = P->levels[lv];
+        for (int i = 0; i < Lv.nm; ++i) {
+            const int g = Lv.first + i;
+            if (out && g < cap) {
+                const Node& N = P->merges[g];
+                dc_merge_stat& r = out[g];
+                r.level = (int)P->levels.size() - 1 - lv;
+                r.m = N.n1 + N.n2;
+                r.K = cnt[g].K;
+                r.nrot = cnt[g].nrot;
+                r.path = 0;
+                r.flops = 2.0 * ((double)N.n1 * cnt[g].ntop + (double)N.n2 * cnt[g].nbot) *
+                          cnt[g].K;
+            }
+            ++li;
+        }
+    }
+    return nmr;
+}

@@ -1,0 +1,308 @@
+// Secular roots, Loewner recomputation and column scales of one or many
+// rank-one modified diagonal problems M = diag(D) + rho z z^T (eq. rankone).
+//
+// Roots (eq. secular, summation restored): f(lam) = 1 + rho sum z_i^2/(D_i - lam)
+// has one root in each (D_j, D_{j+1}) and one in (D_K, D_K + rho ||z||^2].
+// Root j is kept as (origin o_j, offset tau_j), o_j the nearer pole, so every
+// D_i - lam_j is formed as (D_i - D_{o_j}) - tau_j (Remark 3, eq. d-lambda).
+// The iteration is the rational-interpolation scheme of Bunch-Nielsen-Sorensen
+// in R.-C. Li's "middle way" form: the pole sums left and right of the root
+// are each modelled by a constant plus one pole fitted to value and slope,
+// and the quadratic of the model gives the step; a bisection safeguard keeps
+// each iterate inside a sign-change bracket.
+//
+// Loewner (Gu-Eisenstat): zhat_i^2 = (lam_K - D_i)/rho
+//     * prod_{j<i} (lam_j - D_i)/(D_j - D_i) * prod_{i<=j<K-1} (lam_j - D_i)/(D_{j+1} - D_i).
+// Column scales: s_j = (sum_i zhat_i^2 / (D_i - lam_j)^2)^(-1/2) (eq. Q_Cauchy).
+//
+// Mapping: a workgroup of four waves owns 64 roots (or 64 poles for the
+// Loewner product); lane r of every wave works on root r, and wave w sweeps
+// one quarter of the K poles, read with wave-uniform addresses; the four
+// partial sums meet in LDS.  All O(K^2) work is FP64 VALU with one
+// reciprocal per term; HBM traffic is O(K).
+#include "secular.hpp"
+
+namespace {
+
+constexpr double EPS = 2.220446049250313e-16;
+constexpr int NW = 4;           // waves per workgroup
+constexpr int NR = 64;          // roots per workgroup
+
+__device__ __forceinline__ int task_of(const int* block_start, int ntasks, int b) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (block_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct Sums {
+    double psi, dpsi, phi, dphi, aabs;
+};
+
+// Partial sums over this wave's pole range for a root with origin pole Do,
+// offset tau and interval index j (poles i <= j are "left").
+__device__ __forceinline__ Sums pole_sums(const double* __restrict__ D,
+                                          const double* __restrict__ z, int i0, int i1,
+                                          double Do, double tau, int j) {
+    Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = i0; i < i1; ++i) {
+        const double Di = D[i];
+        const double zi = z[i];
+        const double t = (Di - Do) - tau;
+        const double r = dc_rcp(t);
+        const double term = zi * zi * r;
+        const double dterm = term * r;
+        if (i <= j) {
+            s.psi += term;
+            s.dpsi += dterm;
+        } else {
+            s.phi += term;
+            s.dphi += dterm;
+        }
+        s.aabs += fabs(term);
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(NW * 64)
+void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
+                     int ntasks, int max_iter) {
+    __shared__ double red[5][NW][NR];
+    __shared__ double s_tau[NR];
+    __shared__ double s_do[NR];
+    __shared__ int s_org[NR];
+    __shared__ int s_live;
+
+    const int ti = task_of(block_start, ntasks, blockIdx.x);
+    const SecTask& T = tasks[ti];
+    const int K = T.K_p ? *T.K_p : T.K;
+    const int j0 = (blockIdx.x - block_start[ti]) * NR;
+    if (j0 >= K) return;
+    const double rho = T.rho_p ? *T.rho_p : T.rho;
+    const double* __restrict__ D = T.D;
+    const double* __restrict__ z = T.z;
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int per = (K + NW - 1) / NW;
+    const int i0 = min(K, w * per);
+    const int i1 = min(K, i0 + per);
+    const int j = j0 + lane;
+    const bool valid = j < K;
+    const bool last = j == K - 1;
+
+    // Wave 0 owns the per-root state.
+    double lo = 0.0, hi = 0.0, tau = 0.0, dlo = 0.0, dhi = 0.0;
+    double Dj = 0.0, Dj1 = 0.0;
+    int org = 0;
+    bool done = !valid;
+    int iters = 0;
+    if (w == 0 && valid) {
+        Dj = D[j];
+        Dj1 = last ? 0.0 : D[j + 1];
+        if (last) {
+            // rho ||z||^2 bounds the last root; widen by a few ulps.
+            double zz = 0.0;
+            for (int i = 0; i < K; ++i) zz += z[i] * z[i];
+            hi = rho * zz * (1.0 + 8.0 * EPS);
+            tau = 0.5 * hi;
+        } else {
+            tau = 0.5 * (Dj1 - Dj);     // midpoint, origin j frame
+        }
+        org = j;
+    }
+    if (w == 0) {
+        s_tau[lane] = tau;
+        s_do[lane] = valid ? D[j] : 0.0;
+        s_org[lane] = org;
+    }
+    __syncthreads();
+
+    for (int it = 0;; ++it) {
+        // Every wave: partial sums at the current iterate of root `lane`.
+        Sums p{0.0, 0.0, 0.0, 0.0, 0.0};
+        if (valid) p = pole_sums(D, z, i0, i1, s_do[lane], s_tau[lane], j);
+        red[0][w][lane] = p.psi;
+        red[1][w][lane] = p.dpsi;
+        red[2][w][lane] = p.phi;
+        red[3][w][lane] = p.dphi;
+        red[4][w][lane] = p.aabs;
+        __syncthreads();
+        if (w == 0) {
+            double psi = 0, dpsi = 0, phi = 0, dphi = 0, aabs = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                psi += red[0][q][lane];
+                dpsi += red[1][q][lane];
+                phi += red[2][q][lane];
+                dphi += red[3][q][lane];
+                aabs += red[4][q][lane];
+            }
+            const double g = 1.0 / rho + psi + phi;
+            if (!done) {
+                ++iters;
+                if (it == 0 && !last) {
+                    // Origin choice from the sign at the midpoint.
+                    const double h = 0.5 * (Dj1 - Dj);
+                    if (g > 0.0) {          // root left of the midpoint
+                        org = j; lo = 0.0; hi = h;
+                    } else {                // root right of it: re-frame at D_{j+1}
+                        org = j + 1; lo = -h; hi = 0.0; tau = -h;
+                    }
+                    dlo = Dj - (org == j ? Dj : Dj1);
+                    dhi = Dj1 - (org == j ? Dj : Dj1);
+                    if (g == 0.0) done = true;
+                } else {
+                    if (it == 0) { dlo = 0.0; dhi = 0.0; }
+                    if (g > 0.0) hi = tau; else lo = tau;
+                    const bool conv = fabs(g) <= 8.0 * EPS * (1.0 / rho + aabs) ||
+                                      (hi - lo) <= 4.0 * EPS * fmax(fabs(lo), fabs(hi));
+                    if (conv) done = true;
+                }
+                if (!done) {
+                    if (iters > max_iter) {
+                        done = true;
+                        dc_set_info(T.info, j + 1);
+                    } else {
+                        // Middle-way model step from tau.
+                        const double d1 = dlo - tau;
+                        const double d2 = dhi - tau;
+                        const double s1 = dpsi * d1 * d1;
+                        double nt;
+                        if (last) {
+                            const double c = 1.0 / rho + (psi - dpsi * d1);
+                            nt = tau + (d1 + s1 / c);
+                        } else {
+                            const double s2 = dphi * d2 * d2;
+                            const double c = 1.0 / rho + (psi - dpsi * d1) + (phi - dphi * d2);
+                            const double B = c * (d1 + d2) + s1 + s2;
+                            const double C = c * d1 * d2 + s1 * d2 + s2 * d1;
+                            const double disc = fmax(B * B - 4.0 * c * C, 0.0);
+                            const double q = 0.5 * (B + copysign(sqrt(disc), B));
+                            const double r1 = q / c;
+                            const double r2 = C / q;
+                            const double eta = (r1 > d1 && r1 < d2) ? r1 : r2;
+                            nt = tau + eta;
+                        }
+                        if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
+                        tau = nt;
+                    }
+                }
+            }
+            s_tau[lane] = tau;
+            if (valid) s_do[lane] = (org == j) ? Dj : Dj1;
+            s_org[lane] = org;
+            const unsigned long long live = __ballot(!done);
+            if (lane == 0) s_live = live != 0ull;
+        }
+        __syncthreads();
+        if (!s_live) break;
+    }
+    if (w == 0 && valid) {
+        T.org[j] = org;
+        T.tau[j] = tau;
+        const double base = (org == j) ? Dj : Dj1;
+        if (T.cbase) T.cbase[j] = base;
+        if (T.lam) T.lam[j] = base + tau;
+    }
+}
+
+// zhat_i: lane r of each wave owns pole i = i0 + r; wave w multiplies the
+// factors of one quarter of the roots.
+__global__ __launch_bounds__(NW * 64)
+void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
+               int ntasks) {
+    __shared__ double part[NW][NR];
+    const int ti = task_of(block_start, ntasks, blockIdx.x);
+    const SecTask& T = tasks[ti];
+    const int K = T.K_p ? *T.K_p : T.K;
+    const int p0 = (blockIdx.x - block_start[ti]) * NR;
+    if (p0 >= K) return;
+    const double rho = T.rho_p ? *T.rho_p : T.rho;
+    const double* __restrict__ D = T.D;
+    const double* __restrict__ cb = T.cbase;
+    const double* __restrict__ tau = T.tau;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = p0 + lane;
+    const bool valid = i < K;
+    const double Di = valid ? D[i] : 0.0;
+    const int per = (K + NW - 1) / NW;
+    const int j0 = min(K, w * per);
+    const int j1 = min(K, j0 + per);
+    double prod = 1.0;
+    if (valid) {
+        for (int j = j0; j < j1; ++j) {
+            const double lmd = (cb[j] - Di) + tau[j];      // lam_j - D_i
+            double den;
+            if (j == K - 1) den = rho;
+            else den = (j < i ? D[j] : D[j + 1]) - Di;
+            prod *= lmd * dc_rcp(den);
+        }
+    }
+    part[w][lane] = prod;
+    __syncthreads();
+    if (w == 0 && valid) {
+        double p = part[0][lane];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) p *= part[q][lane];
+        T.zhat[i] = copysign(sqrt(p), T.z[i]);
+    }
+}
+
+__global__ __launch_bounds__(NW * 64)
+void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
+                int ntasks) {
+    __shared__ double part[NW][NR];
+    const int ti = task_of(block_start, ntasks, blockIdx.x);
+    const SecTask& T = tasks[ti];
+    const int K = T.K_p ? *T.K_p : T.K;
+    const int j0 = (blockIdx.x - block_start[ti]) * NR;
+    if (j0 >= K) return;
+    const double* __restrict__ D = T.D;
+    const double* __restrict__ zh = T.zhat;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = j0 + lane;
+    const bool valid = j < K;
+    const double base = valid ? T.cbase[j] : 0.0;
+    const double tj = valid ? T.tau[j] : 0.0;
+    const int per = (K + NW - 1) / NW;
+    const int i0 = min(K, w * per);
+    const int i1 = min(K, i0 + per);
+    double s = 0.0;
+    if (valid) {
+        for (int i = i0; i < i1; ++i) {
+            const double q = zh[i] * dc_rcp((D[i] - base) - tj);
+            s += q * q;
+        }
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && valid) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) t += part[q][lane];
+        T.scale[j] = 1.0 / sqrt(t);
+    }
+}
+
+}  // namespace
+
+hipError_t dc_launch_secular(const SecTask* tasks, const int* block_start, int ntasks,
+                             int total_blocks, int max_iter, hipStream_t s) {
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_secular_roots, dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
+                       block_start, ntasks, max_iter);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_loewner, dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
+                       block_start, ntasks);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_colscale, dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
+                       block_start, ntasks);
+    return hipGetLastError();
+}

@@ -1,0 +1,26 @@
+// Descriptors of the secular / Loewner / column-scale kernels.
+#pragma once
+#include "common.hpp"
+
+// One rank-one modified diagonal problem diag(D) + rho z z^T.
+struct SecTask {
+    const double* D;      // poles, strictly increasing
+    const double* z;      // weights
+    const int* K_p;       // device size, or null (= K)
+    int K;
+    int pad_;
+    const double* rho_p;  // device rho, or null (= rho)
+    double rho;
+    int* org;             // out: origin pole of each root
+    double* tau;          // out: offset from the origin pole
+    double* cbase;        // out: D[org_j]
+    double* lam;          // out (optional): D[org_j] + tau_j
+    double* zhat;         // out: Loewner weights
+    double* scale;        // out: column scales
+    int* info;            // status word, or null
+};
+
+// block_start: exclusive prefix sum (ntasks + 1 entries, device) of
+// ceil(Kmax / 64) per task; the three kernels run in sequence.
+hipError_t dc_launch_secular(const SecTask* tasks, const int* block_start, int ntasks,
+                             int total_blocks, int max_iter, hipStream_t s);

@@ -1,0 +1,235 @@
+"""Python binding of libdcstedc.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors to device pointers and leading dimensions, calls the C ABI on the
+current torch stream and raises on a non-zero return code.  There is no CPU
+fallback: if the library is missing, importing the handle fails loudly.
+
+Matrices cross the boundary column-major (LAPACK layout).  A torch tensor X
+of shape (m, n) is passed as the storage of X.T.contiguous(), and results
+come back as the transpose of a row-major (n, ld) buffer.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcstedc.so")
+
+c_int = ctypes.c_int
+c_double = ctypes.c_double
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+P = ctypes.c_void_p
+
+
+class DcOpts(ctypes.Structure):
+    _fields_ = [("leaf", c_int), ("lr_tol", c_double), ("lr_block", c_int),
+                ("lr_min_k", c_int), ("max_iter", c_int), ("gemm_tile", c_int)]
+
+
+class MergeStat(ctypes.Structure):
+    _fields_ = [("level", c_int), ("m", c_int), ("K", c_int), ("nrot", c_int),
+                ("path", c_int), ("flops", c_double)]
+
+
+# (name, restype, argtypes) of every exported entry point.
+SIGNATURES = [
+    ("dc_opts_default", None, [ctypes.POINTER(DcOpts)]),
+    ("dc_stedc", c_int, [c_int, P, P, P, c_int, P]),
+    ("dc_stedc_workspace", c_size_t, [c_int, ctypes.POINTER(DcOpts)]),
+    ("dc_stedc_ex", c_int, [c_int, P, P, P, c_int, P, c_size_t, P,
+                            ctypes.POINTER(DcOpts), P]),
+    ("dc_stedc_batched_workspace", c_size_t, [c_int, P, ctypes.POINTER(DcOpts)]),
+    ("dc_stedc_batched", c_int, [c_int, P, P, P, P, P, P, c_size_t, P,
+                                 ctypes.POINTER(DcOpts), P]),
+    ("dc_secular", c_int, [c_int, P, P, c_double, P, P, P, P, P, c_int, P]),
+    ("dc_merge_update", c_int, [c_int, c_int, P, c_int, P, P, P, P, P, P, c_int,
+                                c_double, c_int, P]),
+    ("dc_merge_lowrank_ranks", c_int, [c_int, P, P, P, P, P, c_double, c_int, P, P]),
+    ("dc_stedc_backward", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P]),
+    ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
+    ("dc_last_info", c_int, [P]),
+    ("dc_strerror", ctypes.c_char_p, [c_int]),
+    ("dc_last_stats", c_int, [ctypes.POINTER(MergeStat), c_int]),
+]
+
+# Extra (non-header) hooks used by tests and the benchmark.
+EXTRA = [
+    ("dc_stedc_batched_eager", c_int, [c_int, P, P, P, P, P, P, c_size_t, P,
+                                       ctypes.POINTER(DcOpts), P]),
+    ("dc_merge_update_variant", c_int, [c_int, c_int, P, c_int, P, P, P, P, P, P,
+                                        c_int, c_int, P]),
+]
+
+_lib = None
+
+
+def load():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2008_01990_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES + EXTRA:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class DcError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = load().dc_strerror(rc).decode()
+        raise DcError(f"{what} returned {rc}: {msg}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype=torch.float64):
+    t = torch.as_tensor(t)
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def opts(leaf=32, lr_tol=0.0, lr_block=1024, lr_min_k=4096, max_iter=64, gemm_tile=0):
+    o = DcOpts()
+    load().dc_opts_default(ctypes.byref(o))
+    o.leaf, o.lr_tol, o.lr_block = leaf, lr_tol, lr_block
+    o.lr_min_k, o.max_iter, o.gemm_tile = lr_min_k, max_iter, gemm_tile
+    return o
+
+
+def to_colmajor(X):
+    """(m, n) tensor -> contiguous storage of its column-major layout."""
+    return X.t().contiguous()
+
+
+def from_colmajor(buf, m):
+    """Row-major (n, ld) buffer holding a column-major m x n matrix -> (m, n) view."""
+    return buf[:, :m].t()
+
+
+class Solver:
+    """Reusable workspace for repeated solves of one order n."""
+
+    def __init__(self, n, **kw):
+        self.n = n
+        self.o = opts(**kw)
+        lib = load()
+        self.lwork = lib.dc_stedc_workspace(n, ctypes.byref(self.o))
+        if self.lwork == 0 and n > 0:
+            raise DcError("dc_stedc_workspace failed")
+        self.work = torch.empty(max(self.lwork, 256) // 8 + 32, dtype=torch.float64,
+                                device="cuda")
+        self.info = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def _wptr(self):
+        addr = self.work.data_ptr()
+        return ctypes.c_void_p((addr + 255) & ~255)
+
+    def solve_into(self, d, e, Qbuf):
+        """In place: d -> eigenvalues, Qbuf (n, n) row-major = Q column-major."""
+        n = self.n
+        rc = load().dc_stedc_ex(n, _ptr(d), _ptr(e), _ptr(Qbuf), n, self._wptr(),
+                                self.lwork, _ptr(self.info), ctypes.byref(self.o),
+                                _stream())
+        _check(rc, "dc_stedc_ex")
+
+    def __call__(self, d, e):
+        d = _dev(d).clone()
+        e = _dev(e).clone() if self.n > 1 else torch.zeros(1, dtype=torch.float64,
+                                                            device="cuda")
+        Qbuf = torch.empty(max(self.n, 1), max(self.n, 1), dtype=torch.float64,
+                           device="cuda")
+        self.solve_into(d, e, Qbuf)
+        return d, from_colmajor(Qbuf, self.n)
+
+    def status(self):
+        return int(self.info.item())
+
+
+def stedc(d, e, **kw):
+    """(lam ascending, Q) of T(d, e) on the GPU; Q is an (n, n) view."""
+    n = int(torch.as_tensor(d).numel())
+    s = Solver(n, **kw)
+    lam, Q = s(d, e)
+    st = s.status()
+    if st != 0:
+        raise DcError(f"device status {st}: {load().dc_strerror(st).decode()}")
+    return lam, Q
+
+
+def stedc_short(d, e):
+    """The short form dc_stedc (library-allocated workspace)."""
+    n = int(torch.as_tensor(d).numel())
+    d = _dev(d).clone()
+    e = _dev(e).clone() if n > 1 else torch.zeros(1, dtype=torch.float64, device="cuda")
+    Qbuf = torch.empty(max(n, 1), max(n, 1), dtype=torch.float64, device="cuda")
+    _check(load().dc_stedc(n, _ptr(d), _ptr(e), _ptr(Qbuf), max(n, 1), _stream()),
+           "dc_stedc")
+    st = load().dc_last_info(_stream())
+    return d, from_colmajor(Qbuf, n), st
+
+
+def last_stats():
+    lib = load()
+    cnt = lib.dc_last_stats(None, 0)
+    arr = (MergeStat * max(cnt, 1))()
+    lib.dc_last_stats(arr, cnt)
+    return [dict(level=r.level, m=r.m, K=r.K, nrot=r.nrot, path=r.path, flops=r.flops)
+            for r in arr[:cnt]]
+
+
+def secular(D, z, rho, max_iter=64):
+    """(org, tau, zhat, scale) of diag(D) + rho z z^T."""
+    D = _dev(D)
+    z = _dev(z)
+    K = D.numel()
+    org = torch.empty(K, dtype=torch.int32, device="cuda")
+    tau = torch.empty(K, dtype=torch.float64, device="cuda")
+    zhat = torch.empty_like(tau)
+    scale = torch.empty_like(tau)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _check(load().dc_secular(K, _ptr(D), _ptr(z), float(rho), _ptr(org), _ptr(tau),
+                             _ptr(zhat), _ptr(scale), _ptr(info), max_iter, _stream()),
+           "dc_secular")
+    st = int(info.item())
+    if st != 0:
+        raise DcError(f"dc_secular device status {st}")
+    return org, tau, zhat, scale
+
+
+def merge_update(Qnd_cm, m, K, Dbar, org, tau, zhat, scale, lr_tol=0.0, lr_block=0,
+                 ldq=None, out=None, variant=None):
+    """C = Qnd U with U generated from (Dbar, org, tau, zhat, scale).
+
+    Qnd_cm is the column-major storage of Qnd: a tensor of shape (K, ldq).
+    Returns the column-major storage of C, shape (K, m).
+    """
+    ldq = ldq if ldq is not None else Qnd_cm.shape[1]
+    C = out if out is not None else torch.empty(K, m, dtype=torch.float64, device="cuda")
+    args = (m, K, _ptr(Qnd_cm), ldq, _ptr(Dbar), _ptr(org), _ptr(tau), _ptr(zhat),
+            _ptr(scale), _ptr(C), C.shape[1])
+    if variant is not None:
+        _check(load().dc_merge_update_variant(*args, variant, _stream()),
+               "dc_merge_update_variant")
+    else:
+        _check(load().dc_merge_update(*args, float(lr_tol), int(lr_block), _stream()),
+               "dc_merge_update")
+    return C

@@ -1,0 +1,55 @@
+"""CPU checks of the C-ABI library: it loads and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcstedc.h")
+LIB = os.path.join(ROOT, "paper_2008_01990_amd", "libdcstedc.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(dc_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dc_stedc", "dc_stedc_ex", "dc_stedc_workspace", "dc_stedc_batched",
+                     "dc_merge_update", "dc_stedc_backward", "dc_secular",
+                     "dc_last_info", "dc_strerror"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_signatures_cover_the_header():
+    from paper_2008_01990_amd import dcstedc
+    bound = {s[0] for s in dcstedc.SIGNATURES}
+    assert set(declared_functions()) <= bound
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_side_argument_checks_need_no_gpu():
+    # Bad arguments are rejected on the host before anything touches a device.
+    from paper_2008_01990_amd import dcstedc
+    lib = dcstedc.load()
+    assert lib.dc_stedc(-1, None, None, None, 1, None) == -1
+    assert lib.dc_stedc(4, None, None, None, 4, None) == -2
+    assert lib.dc_merge_update(-1, 1, None, 1, None, None, None, None, None, None, 1,
+                               0.0, 0, None) == -1
+    assert lib.dc_secular(0, None, None, 1.0, None, None, None, None, None, 0, None) == -1
+    assert lib.dc_strerror(0) == b"success"
+    o = dcstedc.DcOpts()
+    lib.dc_opts_default(ctypes.byref(o))
+    assert o.leaf == 32 and o.lr_tol == 0.0

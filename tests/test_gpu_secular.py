@@ -1,0 +1,39 @@
+"""GPU parity of the secular solver, Loewner weights and column scales.
+
+Roots are compared on the offset scale: two correct solvers may differ in
+the last bits of tau (several last-bit answers are all correct), so the bound
+is a few ulps of max(|tau|, spacing).  Loewner weights and scales are smooth
+functions of the roots and agree to ~1e-13 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import secular
+from paper_2008_01990_amd import workloads as W
+from tests.gpu_util import announce, cuda, host
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+@pytest.mark.parametrize("K,seed,cluster", [(1, 0, False), (2, 1, False), (63, 2, False),
+                                            (700, 3, False), (300, 4, True)])
+def test_secular_matches_oracle(lib, K, seed, cluster):
+    announce(f"secular K={K} seed={seed} cluster={cluster}")
+    D, z, rho = W.random_secular(K, seed=seed, cluster=cluster)
+    o_org, o_tau, o_zhat, o_s = secular.solve_rank_one(D, z, rho)
+    g_org, g_tau, g_zhat, g_s = [host(t) for t in lib.secular(D, z, rho)]
+    g_org = g_org.astype(np.int64)
+    # same root, possibly different frame: (D[og] - D[oo]) + (tg - to)
+    diff = (D[g_org] - D[o_org]) + (g_tau - o_tau)
+    scale = np.maximum(np.abs(o_tau), np.abs(g_tau))
+    # each solver stops at |f| <= 8 eps sum|terms|, i.e. within ~8-16 ulps of
+    # the offset; two correct answers may differ by the sum of both
+    assert np.all(np.abs(diff) <= 64 * EPS * scale + 4 * EPS * np.abs(D[g_org] - D[o_org]))
+    lam = D[g_org] + g_tau
+    assert np.all(lam[:-1] > D[:-1]) and np.all(lam[:-1] < D[1:])
+    assert np.allclose(g_zhat, o_zhat, rtol=1e-12, atol=0)
+    assert np.allclose(g_s, o_s, rtol=1e-12, atol=0)
+    U = secular.cauchy_matrix(D, g_org, g_tau, g_zhat, g_s)
+    assert np.abs(U.T @ U - np.eye(K)).max() <= 1e-13

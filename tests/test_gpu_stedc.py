@@ -1,0 +1,105 @@
+"""GPU parity of the whole divide-and-conquer solve (dc_stedc_ex).
+
+Bars: eigenvalue error <= 1e-13 ||T||, ||TQ - Q Lambda||_F / (n ||T||) <=
+1e-14 and max |Q^T Q - I| <= 1e-12; eigenvalues against the oracle within
+1e-13 ||T||; eigenvectors against the oracle column by column up to sign,
+within c eps ||T|| / gap_j (eigenvectors are only defined to that accuracy).
+"""
+import numpy as np
+import pytest
+
+from oracle import dc, metrics
+from paper_2008_01990_amd import workloads as W
+from tests.gpu_util import announce, cuda, host
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+def _solve(lib, d, e, **kw):
+    lam, Q = lib.stedc(cuda(d), cuda(e), **kw)
+    return host(lam), host(Q)
+
+
+def _check_against_oracle(d, e, lam, Q, leaf):
+    n = d.shape[0]
+    lo, Qo = dc.eigh_tridiagonal(d, e, leaf=leaf)
+    tn = max(np.abs(lo).max(), 1e-300)
+    assert np.abs(lam - lo).max() <= 1e-13 * tn
+    assert metrics.orthogonality(Q) <= 1e-12
+    assert metrics.residual(d, e, lam, Q) <= 1e-14
+    gap = np.full(n, np.inf)
+    if n > 1:
+        g = np.diff(lo)
+        gap[:-1] = np.minimum(gap[:-1], g)
+        gap[1:] = np.minimum(gap[1:], g)
+    tolv = np.minimum(1.0, 1e3 * EPS * tn / gap + 1e-12)
+    dots = np.abs((Q * Qo).sum(axis=0))
+    assert np.all(np.abs(dots - 1.0) <= tolv)
+
+
+@pytest.mark.parametrize("n,leaf", [(1024, 32), (777, 16), (200, 64), (65, 32)])
+def test_toeplitz_and_ragged_sizes(lib, n, leaf):
+    announce(f"stedc toeplitz n={n} leaf={leaf}")
+    d, e = W.toeplitz(n)
+    lam, Q = _solve(lib, d, e, leaf=leaf)
+    k = np.arange(1, n + 1)
+    assert metrics.eig_error(lam, 2 - 2 * np.cos(k * np.pi / (n + 1))) <= 1e-13
+    _check_against_oracle(d, e, lam, Q, leaf)
+
+
+def test_toeplitz_sine_vectors_n1024(lib):
+    n = 1024
+    announce("stedc toeplitz sine vectors n=1024")
+    d, e = W.toeplitz(n)
+    lam, Q = _solve(lib, d, e, leaf=32)
+    k = np.arange(1, n + 1)
+    i = np.arange(1, n + 1)[:, None]
+    S = np.sqrt(2.0 / (n + 1)) * np.sin(i * k[None, :] * np.pi / (n + 1))
+    assert np.abs(np.abs((S * Q).sum(axis=0)) - 1.0).max() <= 1e-10
+
+
+def test_clement(lib):
+    n = 640
+    announce(f"stedc clement n={n}")
+    d, e = W.clement(n)
+    lam, Q = _solve(lib, d, e, leaf=64)
+    assert metrics.eig_error(lam, np.arange(-(n - 1), n, 2, dtype=float)) <= 1e-13
+    _check_against_oracle(d, e, lam, Q, 64)
+
+
+@pytest.mark.parametrize("n,seed,leaf", [(500, 0, 32), (129, 1, 8), (2, 2, 1), (1, 3, 32),
+                                         (37, 4, 64)])
+def test_random(lib, n, seed, leaf):
+    announce(f"stedc random n={n} seed={seed} leaf={leaf}")
+    rng = np.random.default_rng(seed)
+    d, e = W.random_tridiag(n, rng)
+    lam, Q = _solve(lib, d, e, leaf=leaf)
+    _check_against_oracle(d, e, lam, Q, leaf)
+
+
+def test_zero_coupling_everything_deflates(lib):
+    announce("stedc zero coupling")
+    d = np.array([4.0, -2.0, 7.0, 1.0, 1.0, 0.0, -3.0, 5.0] * 8)
+    e = np.zeros(63)
+    lam, Q = _solve(lib, d, e, leaf=4)
+    assert np.array_equal(lam, np.sort(d))
+    assert metrics.orthogonality(Q) == 0.0
+
+
+def test_short_form_and_status(lib):
+    announce("stedc short form")
+    d, e = W.toeplitz(300)
+    lam, Q, st = lib.stedc_short(cuda(d), cuda(e))
+    assert st == 0
+    k = np.arange(1, 301)
+    assert metrics.eig_error(host(lam), 2 - 2 * np.cos(k * np.pi / 301)) <= 1e-13
+
+
+def test_nonfinite_input_sets_status(lib):
+    announce("stedc nan input")
+    d, e = W.toeplitz(100)
+    d[17] = np.nan
+    s = lib.Solver(100, leaf=16)
+    s(cuda(d), cuda(e))
+    assert s.status() == -1000
