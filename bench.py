@@ -1,0 +1,207 @@
+"""Benchmark: the full divide-and-conquer eigensolve on one MI355X.
+
+One step = one dc_stedc_ex solve (every leaf, every merge level: deflation,
+secular roots, Loewner weights, scales, eigenvalue order, generated-Cauchy
+merge product, deflated copy) of the n = 32768 Clement-type matrix
+(d_i = 0, e_i = sqrt(i (n - i))), leaf 64, inputs resident in HBM.
+
+Printed: one JSON line with the eigensolve seconds (the metric), the
+roofline of the dominant kernel (the merge product of the root level, HIP
+events on the solver's stream), per-level product rates, the optional
+low-rank comparison, accuracy of the last solve and the CPU oracle baseline.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "n=32768 eigensolve sec; merge Q·U % FP64-MFMA peak; low-rank vs plain"
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--family", default="clement", choices=["clement", "toeplitz"])
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--gemm-tile", type=int, default=0)
+    ap.add_argument("--lowrank-tol", type=float, default=0.0,
+                    help="also time the low-rank path at this tolerance (0: skip)")
+    ap.add_argument("--lowrank-block", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=4096)
+    return ap.parse_args()
+
+
+def inputs(family, n):
+    from paper_2008_01990_amd import workloads as W
+    return W.clement(n) if family == "clement" else W.toeplitz(n)
+
+
+def closed_form(family, n):
+    import numpy as np
+    if family == "clement":
+        return np.arange(-(n - 1), n, 2, dtype=np.float64)
+    k = np.arange(1, n + 1)
+    return 2.0 - 2.0 * np.cos(k * np.pi / (n + 1))
+
+
+def gpu_accuracy(d, e, lam, Qbuf, family):
+    """Eigenvalue error, residual and orthogonality of the last solve (GPU,
+    plain torch ops independent of the solver's kernels)."""
+    import numpy as np
+    import torch
+    n = d.numel()
+    ref = torch.tensor(closed_form(family, n), device="cuda")
+    tn = ref.abs().max()
+    eig = float(((lam - ref).abs().max() / tn).item())
+    Q = Qbuf.t()                                   # (n, n) view, Q[:, j] eigvec j
+    TQ = d[:, None] * Q
+    TQ[:-1] += e[:, None] * Q[1:]
+    TQ[1:] += e[:, None] * Q[:-1]
+    R = TQ - Q * lam[None, :]
+    res = float((torch.linalg.norm(R) / (n * tn)).item())
+    del TQ, R
+    G = Qbuf @ Qbuf.t()                            # = Q^T Q
+    G.diagonal().sub_(1.0)
+    orth = float(G.abs().max().item())
+    del G
+    return {"eig_err_rel": eig, "residual": res, "orthogonality": orth}
+
+
+def cpu_baseline(family, n_full, n_sample, leaf):
+    """The oracle on the host cores: a full solve at n_sample, scaled by the
+    cubic flop ratio of divide and conquer to the benchmark's order."""
+    from threadpoolctl import threadpool_info
+    from oracle import dc
+    d, e = inputs(family, n_sample)
+    t0 = time.perf_counter()
+    dc.eigh_tridiagonal(d, e, leaf=leaf)
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    scale = (n_full / n_sample) ** 3
+    return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"full oracle solve of the {family} matrix at n={n_sample} "
+                      f"(leaf {leaf}) took {dt:.2f} s; scaled by (n/{n_sample})^3 = "
+                      f"{scale:.0f} to n={n_full}",
+            "sample_seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU row-sharded merge is a design, not a measured path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2008_01990_amd import dcstedc as L
+
+    torch.cuda.set_device(0)
+    n = args.n
+    d0, e0 = inputs(args.family, n)
+    d_in = torch.tensor(d0, device="cuda")
+    e = torch.tensor(e0, device="cuda")
+    d = torch.empty_like(d_in)
+    Qbuf = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    solver = L.Solver(n, leaf=args.leaf, gemm_tile=args.gemm_tile)
+
+    def step():
+        d.copy_(d_in)
+        solver.solve_into(d, e, Qbuf)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if solver.status() != 0:
+        raise RuntimeError(f"device status {solver.status()}")
+
+    L.profile_enable(True)
+    prof = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        prof.append(L.profile_read())          # waits on this step's events
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    stats = L.last_stats()
+
+    # Per-level merge-product rates (algorithmic flops of the launch over its
+    # event-timed duration, averaged over the timed steps).
+    nlev = len(prof[0])
+    flops_lvl = [0.0] * nlev
+    for r in stats:
+        flops_lvl[nlev - 1 - r["level"]] += r["flops"]
+    levels = []
+    for li in range(nlev):
+        t_ms = sum(p[li]["product"] for p in prof) / len(prof)
+        phase = {k: sum(p[li][k] for p in prof) / len(prof) for k in L.PHASES}
+        levels.append({"level_from_root": nlev - 1 - li, "product_ms": t_ms,
+                       "product_tflops": flops_lvl[li] / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0,
+                       "phase_ms": phase})
+    top = levels[-1]
+    achieved = top["product_tflops"]
+    total_prod_ms = sum(l["product_ms"] for l in levels)
+    total_flops = sum(flops_lvl)
+    sec_ms = sum(l["phase_ms"]["secular"] for l in levels)
+    Ks = [r["K"] for r in stats]
+    sec_bytes = sum(48.0 * k for k in Ks)
+
+    out = {
+        "metric": METRIC,
+        "value": ms / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.family}_n{n}_leaf{args.leaf}_plain", "n": n,
+                   "family": args.family, "leaf": args.leaf, "path": "plain"},
+        "roofline": {"bound": "mfma", "achieved": achieved,
+                     "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
+                     "kernel": "k_cauchy_gemm (root-level merge product)",
+                     "flops_per_launch": flops_lvl[-1],
+                     "launch_ms": top["product_ms"]},
+        "merge_product": {"total_ms": total_prod_ms, "total_flops": total_flops,
+                          "tflops": total_flops / (total_prod_ms * 1e-3) / 1e12,
+                          "frac_peak": total_flops / (total_prod_ms * 1e-3) / 1e12
+                          / PEAK_FP64_MFMA_TFLOPS},
+        "secular_phase": {"total_ms": sec_ms,
+                          "hbm_gbs_algorithmic": sec_bytes / (sec_ms * 1e-3) / 1e9
+                          if sec_ms > 0 else 0.0},
+        "levels": levels,
+        "merges_top": [dict(m=r["m"], K=r["K"], nrot=r["nrot"]) for r in stats
+                       if r["level"] <= 1],
+    }
+    if not args.no_accuracy:
+        out["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
+    del Qbuf
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.family, n, args.cpu_n, args.leaf)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

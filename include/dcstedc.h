@@ -198,6 +198,18 @@ typedef struct dc_merge_stat {
 /* Copies up to cap records into out (HOST); returns the number available. */
 int dc_last_stats(dc_merge_stat* out, int cap);
 
+/*
+ * Instrumentation.  dc_profile_enable(1) makes later dc_stedc / dc_stedc_ex
+ * calls record HIP events on the caller's stream at the phase boundaries of
+ * every tree level; dc_profile_read waits for them and writes, for each
+ * level from the deepest to the root, six durations in milliseconds
+ * (deflation, rotations, secular/Loewner/scale, eigenvalue order, merge
+ * product, deflated-column copy) into ms (HOST, 6 per level, up to cap
+ * values); it returns the number of levels.  Not for use under graph capture.
+ */
+int dc_profile_enable(int on);
+int dc_profile_read(double* ms, int cap);
+
 #ifdef __cplusplus
 }
 #endif

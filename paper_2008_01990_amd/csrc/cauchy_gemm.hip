@@ -8,12 +8,18 @@
 // instead of receiving it (the paper's "main observation").  On one GPU the
 // observation is taken to its end: no tile of U ever leaves LDS.
 //
-// Layout: A and C column-major; a workgroup owns a BM x BN tile of C and
-// streams k in chunks of BK.  Per chunk each thread prefetches into registers
-// the A entries and the row generators it will place in LDS, overlapping the
-// global loads with the previous chunk's MFMA work; it then writes its A
-// entries and the U entries it generates (one reciprocal per entry) to LDS.
-// Each wave computes a 64 x 64 sub-tile with v_mfma_f64_16x16x4_f64.
+// A (the deflated basis panel) is a plain column-major matrix: the driver
+// gathers the survivor columns into a contiguous panel before the product,
+// so a tile load is one coalesced column segment per k and no index chases
+// sit in front of the MFMA pipe.
+//
+// Pipeline: a workgroup owns a BM x BN tile of C and walks k in chunks of BK
+// through two LDS buffers.  While the waves run the MFMAs of chunk c from one
+// buffer, each thread holds the global loads of chunk c+1 in registers and
+// writes them (A as loaded, U generated with one reciprocal per entry) into
+// the other buffer in slices placed between the MFMA groups, so the matrix
+// cores stay fed; one barrier per chunk.  Each wave owns a WTM x WTN
+// sub-tile of v_mfma_f64_16x16x4_f64 blocks.
 //
 // Work distribution: one flat grid over the tiles of every task (every merge
 // half of a tree level).  Workgroup b runs on XCD b % 8; the flat id is
@@ -37,15 +43,16 @@ struct Cfg {
     static constexpr int PADB = 2;
     static constexpr int LDA_S = BM + PADA;
     static constexpr int LDB_S = BN + PADB;
-    // per-thread share of the A tile and of the U tile
-    static constexpr int A_PER = BM * BK / NT;
-    static constexpr int B_PER = BN * BK / NT;
-    static_assert(BM * BK % NT == 0, "A tile split");
-    static_assert(BN * BK % NT == 0, "B tile split");
-    static_assert(NT % BM == 0, "A rows per pass");
-    static_assert(NT % BN == 0, "B cols per pass");
-    static constexpr int A_KSTEP = NT / BM;     // k advance per A pass
+    static constexpr int A_PER = BM * BK / NT;  // A entries per thread per chunk
+    static constexpr int B_PER = BN * BK / NT;  // U entries per thread per chunk
+    static constexpr int A_KSTEP = NT / BM;
     static constexpr int B_KSTEP = NT / BN;
+    static constexpr int KSTEPS = BK / 4;       // MFMA k-steps per chunk
+    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile split");
+    static_assert(NT % BM == 0 && NT % BN == 0, "rows per pass");
+    static_assert(A_PER % KSTEPS == 0 && B_PER % KSTEPS == 0, "store slices");
+    static constexpr int A_SLICE = A_PER / KSTEPS;
+    static constexpr int B_SLICE = B_PER / KSTEPS;
 };
 
 __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int t) {
@@ -62,8 +69,8 @@ __global__ __launch_bounds__(WGM * WGN * 64)
 void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
                    int ntasks, int total_tiles) {
     using C_ = Cfg<BM, BN, BK, WGM, WGN>;
-    __shared__ double As[BK * C_::LDA_S];
-    __shared__ double Bs[BK * C_::LDB_S];
+    __shared__ double As[2][BK * C_::LDA_S];
+    __shared__ double Bs[2][BK * C_::LDB_S];
 
     // XCD-aware flat id (grid size is a multiple of 8).
     const int nb = gridDim.x;
@@ -92,15 +99,18 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     const int bk0 = tid / BN;
     const int gcol = col0 + bj;
     const bool col_ok = gcol < ncol;
-    const double cb = col_ok ? (T.corg ? T.rD[T.corg[gcol]] : T.cbase[gcol]) : 0.0;
+    const double* __restrict__ rD = T.rD;
+    const double* __restrict__ rz = T.rz;
+    const double cb = col_ok ? (T.corg ? rD[T.corg[gcol]] : T.cbase[gcol]) : 0.0;
     const double co = (col_ok && T.coff) ? T.coff[gcol] : 0.0;
     const double csj = col_ok ? T.cs[gcol] : 0.0;
 
-    // A entries this thread loads: row ar, k = ak0 + i * A_KSTEP.
+    // A entries this thread moves: row ar, k = ak0 + i * A_KSTEP.
     const int ar = tid % BM;
     const int ak0 = tid / BM;
-    const int grow = row0 + ar;
-    const bool row_ok = grow < T.rows;
+    const bool row_ok = row0 + ar < T.rows;
+    const double* __restrict__ Acol = T.A + row0 + ar;
+    const long long lda = T.lda;
 
     dc_double4 acc[C_::FM][C_::FN];
 #pragma unroll
@@ -112,63 +122,66 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     double d_reg[C_::B_PER];
     double z_reg[C_::B_PER];
 
-    auto prefetch = [&](int kb) {
+    auto load = [&](int kb) {
 #pragma unroll
         for (int i = 0; i < C_::A_PER; ++i) {
             const int k = kb + ak0 + i * C_::A_KSTEP;
-            double v = 0.0;
-            if (k < klen && row_ok) {
-                const int g = T.klist ? T.klist[k] : k;
-                const int c = T.acol ? T.acol[g] : g;
-                v = T.A[(long long)c * T.lda + grow];
-            }
-            a_reg[i] = v;
+            a_reg[i] = (k < klen && row_ok) ? Acol[(long long)k * lda] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < C_::B_PER; ++i) {
             const int k = kb + bk0 + i * C_::B_KSTEP;
-            double dv = 0.0, zv = 0.0;
-            if (k < klen) {
-                const int g = T.klist ? T.klist[k] : k;
-                dv = T.rD[g];
-                zv = T.rz[g];
-            }
-            d_reg[i] = dv;
-            z_reg[i] = zv;
+            const bool ok = k < klen;
+            d_reg[i] = ok ? rD[k] : 0.0;
+            z_reg[i] = ok ? rz[k] : 0.0;
         }
     };
-
-    prefetch(0);
-    for (int kb = 0; kb < klen; kb += BK) {
-        // Registers -> LDS: A as loaded, U generated.
+    // Store slice s of the registers into LDS buffer `buf` (U generated).
+    auto store_slice = [&](int buf, int kb, int s) {
 #pragma unroll
-        for (int i = 0; i < C_::A_PER; ++i)
-            As[(ak0 + i * C_::A_KSTEP) * C_::LDA_S + ar] = a_reg[i];
+        for (int q = 0; q < C_::A_SLICE; ++q) {
+            const int i = s * C_::A_SLICE + q;
+            As[buf][(ak0 + i * C_::A_KSTEP) * C_::LDA_S + ar] = a_reg[i];
+        }
 #pragma unroll
-        for (int i = 0; i < C_::B_PER; ++i) {
+        for (int q = 0; q < C_::B_SLICE; ++q) {
+            const int i = s * C_::B_SLICE + q;
             const int kk = bk0 + i * C_::B_KSTEP;
             const double den = (d_reg[i] - cb) - co;
             double v = z_reg[i] * csj * dc_rcp(den);
             v = (kb + kk < klen && col_ok) ? v : 0.0;
-            Bs[kk * C_::LDB_S + bj] = v;
+            Bs[buf][kk * C_::LDB_S + bj] = v;
         }
-        __syncthreads();
-        if (kb + BK < klen) prefetch(kb + BK);
+    };
+
+    const int nchunks = (klen + BK - 1) / BK;
+    load(0);
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
+    for (int s = 0; s < C_::KSTEPS; ++s) store_slice(0, 0, s);
+    __syncthreads();
+
+    for (int c = 0; c < nchunks; ++c) {
+        const int cur = c & 1;
+        const bool more = c + 1 < nchunks;
+        const int kb_next = (c + 1) * BK;
+        if (more) load(kb_next);
+#pragma unroll
+        for (int ks = 0; ks < C_::KSTEPS; ++ks) {
             double af[C_::FM], bf[C_::FN];
-            const int kr = kk + (lane >> 4);
+            const int kr = ks * 4 + (lane >> 4);
 #pragma unroll
             for (int i = 0; i < C_::FM; ++i)
-                af[i] = As[kr * C_::LDA_S + wm * C_::WTM + i * 16 + (lane & 15)];
+                af[i] = As[cur][kr * C_::LDA_S + wm * C_::WTM + i * 16 + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < C_::FN; ++j)
-                bf[j] = Bs[kr * C_::LDB_S + wn * C_::WTN + j * 16 + (lane & 15)];
+                bf[j] = Bs[cur][kr * C_::LDB_S + wn * C_::WTN + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < C_::FM; ++i)
 #pragma unroll
                 for (int j = 0; j < C_::FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j],
+                                                                     0, 0, 0);
+            if (more) store_slice(cur ^ 1, kb_next, ks);
         }
         __syncthreads();
     }
@@ -207,10 +220,14 @@ hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int 
 
 }  // namespace
 
+// Tile variants: 0 (default) 256 x 128, BK 16, 4 x 2 waves (two waves per
+// SIMD); 1: 128 x 128, BK 16, 2 x 2 waves; 2: 64 x 64, BK 16, one wave;
+// 3: 128 x 128, BK 32, 2 x 2 waves.
 int dc_gemm_tile_m(int variant) {
     switch (variant) {
+        case 1: case 3: return 128;
         case 2: return 64;
-        default: return 128;
+        default: return 256;
     }
 }
 
@@ -224,8 +241,9 @@ int dc_gemm_tile_n(int variant) {
 hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
                                  int total, int variant, hipStream_t s) {
     switch (variant) {
-        case 2: return launch<64, 64, 32, 1, 1>(tasks, tile_start, ntasks, total, s);
+        case 1: return launch<128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
+        case 2: return launch<64, 64, 16, 1, 1>(tasks, tile_start, ntasks, total, s);
         case 3: return launch<128, 128, 32, 2, 2>(tasks, tile_start, ntasks, total, s);
-        default: return launch<128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
+        default: return launch<256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
     }
 }

@@ -42,20 +42,17 @@ __device__ __forceinline__ void dc_set_info(int* info, int code) {
     else atomicCAS(info, 0, code);
 }
 
-// One product C[rows, cols] (=|+=) A[rows, klist] * B[klist, cols] in which
+// One product C[rows, cols] (=|+=) A[rows, 0:klen] * B[0:klen, cols] in which
 // B is a Cauchy-like matrix generated on the fly:
-//   B_kj = rz[g_k] * cs[j] / ((rD[g_k] - cbase[j]) - coff[j]),  g_k = klist[k].
-// A's column for generator g is acol[g] (identity when acol is null).
+//   B_kj = rz[k] * cs[j] / ((rD[k] - cbase[j]) - coff[j]).
 struct GemmTask {
-    const double* A;      // row 0 of this task inside A
+    const double* A;      // row 0 of this task inside A (column-major, lda)
     long long lda;
-    const int* acol;      // A column of generator g, or null (= g)
-    const int* klist;     // generator of k-entry, or null (= k)
     const int* klen_p;    // device number of k-entries, or null (= klen)
     int klen;
     int rows;             // rows of the task
-    const double* rD;     // row nodes, indexed by generator
-    const double* rz;     // row weights, indexed by generator
+    const double* rD;     // row nodes
+    const double* rz;     // row weights
     const double* cbase;  // column node bases
     const int* corg;      // if set, column node base j is rD[corg[j]] (cbase unused)
     const double* coff;   // column node offsets, or null (= 0)

@@ -17,6 +17,8 @@ struct Prob {
     long long ldq;
     double* B1;         // ping-pong partner of Q inside the workspace
     long long ld1;
+    double* B2;         // packed survivor panels of the merge products
+    long long ld2;
     int n;
     int row0;           // first row of this problem in the concatenated row space
     int* info;          // status word
@@ -49,6 +51,8 @@ struct Scratch {
     double *Dbar, *zbar;        // survivors (K)
     double *tau, *cbase, *lamr, *zhat, *scale;   // roots and eigenvector generators (K)
     double *Dd;                 // deflated eigenvalues, ascending (m - K)
+    double *gDt, *gzt;          // row generators of the top-half product (ntop)
+    double *gDb, *gzb;          // row generators of the bottom-half product (nbot)
     double *rc, *rs;            // rotation cosines / sines
     int *perm;                  // sorted position -> local column
     int *surv, *stype;          // survivor -> local column, row-type bits
@@ -79,6 +83,8 @@ hipError_t dc_launch_rotate(const Node* merges, const int* blk_start, int nm, in
                             Scratch S, hipStream_t s);
 hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, int nblk,
                               Scratch S, hipStream_t s);
+hipError_t dc_launch_gather(const Node* merges, const int* blk_start, int nm, int nblk,
+                            Scratch S, hipStream_t s);
 hipError_t dc_launch_copy_deflated(const Node* merges, const int* blk_start, int nm,
                                    int nblk, Scratch S, hipStream_t s);
 hipError_t dc_launch_set_probs(const Prob* host_probs, int count, Prob* dev, hipStream_t s);
@@ -87,4 +93,5 @@ hipError_t dc_launch_set_probs(const Prob* host_probs, int count, Prob* dev, hip
 // per block of the deflated-column copy.
 #define DC_ROWS_PER_BLOCK 256
 #define DC_COLS_PER_BLOCK 4
+#define DC_GATHER_COLS 4
 #define DC_ROOTS_PER_BLOCK 64

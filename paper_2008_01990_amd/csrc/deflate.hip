@@ -71,8 +71,7 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
     const Prob P = S.probs[N.prob];
     const int m = N.n1 + N.n2;
     const long long base = (long long)P.row0 + N.off;
-    long long ldi, ldo;
-    double* Qi = node_buf(P, N.depth + 1, ldi);
+    long long ldo;
     double* Qo = node_buf(P, N.depth, ldo);
     const int slot = N.slot;
     MergeCnt* cnt = S.cnt + slot;
@@ -80,15 +79,13 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
     for (int half = 0; half < 2; ++half) {
         GemmTask T;
         const int r0 = half ? N.n1 : 0;
-        T.A = Qi + (long long)N.off * ldi + N.off + r0;
-        T.lda = ldi;
-        T.acol = S.surv + base;
-        T.klist = (half ? S.kbot : S.ktop) + base;
+        T.A = P.B2 + (long long)N.off * P.ld2 + N.off + r0;
+        T.lda = P.ld2;
         T.klen_p = half ? &cnt->nbot : &cnt->ntop;
         T.klen = 0;
         T.rows = half ? N.n2 : N.n1;
-        T.rD = S.Dbar + base;
-        T.rz = S.zhat + base;
+        T.rD = (half ? S.gDb : S.gDt) + base;
+        T.rz = (half ? S.gzb : S.gzt) + base;
         T.cbase = S.cbase + base;
         T.corg = nullptr;
         T.coff = S.tau + base;
@@ -362,6 +359,17 @@ void k_assemble(const Node* __restrict__ merges, const int* __restrict__ blk_sta
     const long long base = (long long)P.row0 + N.off;
     const double* lr = S.lamr + base;
     const double* dd = S.Dd + base;
+    // Row generators of the two half products, packed in k order.
+    if (x < C.ntop) {
+        const int g = S.ktop[base + x];
+        S.gDt[base + x] = S.Dbar[base + g];
+        S.gzt[base + x] = S.zhat[base + g];
+    }
+    if (x < C.nbot) {
+        const int g = S.kbot[base + x];
+        S.gDb[base + x] = S.Dbar[base + g];
+        S.gzb[base + x] = S.zhat[base + g];
+    }
     if (x < C.K) {
         const double v = lr[x];
         const int pos = x + count_lt(dd, C.ndefl, v);
@@ -373,6 +381,39 @@ void k_assemble(const Node* __restrict__ merges, const int* __restrict__ blk_sta
         const int pos = k + count_le(lr, C.K, v);
         S.pos_defl[base + k] = pos;
         P.d[N.off + pos] = v;
+    }
+}
+
+// Pack the survivor columns of each merge into the product panel: column t
+// of the top panel is rows [0, n1) of the basis column of top-list entry t,
+// column t of the bottom panel rows [n1, m) of bottom-list entry t.
+__global__ __launch_bounds__(256)
+void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
+              Scratch S) {
+    const int mi = block_of(blk_start, nm, blockIdx.x);
+    const Node N = merges[mi];
+    const MergeCnt C = S.cnt[N.slot];
+    const int t0 = (blockIdx.x - blk_start[mi]) * DC_GATHER_COLS;
+    if (t0 >= max(C.ntop, C.nbot)) return;
+    const Prob P = S.probs[N.prob];
+    const long long base = (long long)P.row0 + N.off;
+    long long ldi;
+    const double* Qi = node_buf(P, N.depth + 1, ldi);
+    const double* blk = Qi + (long long)N.off * ldi + N.off;
+    double* G = P.B2 + (long long)N.off * P.ld2 + N.off;
+    for (int t = t0; t < t0 + DC_GATHER_COLS; ++t) {
+        if (t < C.ntop) {
+            const int src = S.surv[base + S.ktop[base + t]];
+            const double* a = blk + (long long)src * ldi;
+            double* o = G + (long long)t * P.ld2;
+            for (int r = threadIdx.x; r < N.n1; r += 256) o[r] = a[r];
+        }
+        if (t < C.nbot) {
+            const int src = S.surv[base + S.kbot[base + t]];
+            const double* a = blk + (long long)src * ldi + N.n1;
+            double* o = G + (long long)t * P.ld2 + N.n1;
+            for (int r = threadIdx.x; r < N.n2; r += 256) o[r] = a[r];
+        }
     }
 }
 
@@ -446,6 +487,13 @@ hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, 
     if (nblk <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_assemble, dim3(nblk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
                        blk_start, nm, S);
+    return hipGetLastError();
+}
+
+hipError_t dc_launch_gather(const Node* merges, const int* blk_start, int nm, int nblk,
+                            Scratch S, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(nblk), dim3(256), 0, s, merges, blk_start, nm, S);
     return hipGetLastError();
 }
 

@@ -32,8 +32,8 @@ struct Level {
     int first;          // first merge (slot) of the level
     int nm;
     int tiles;          // worst-case product tiles
-    int sec_blocks, row_blocks, copy_blocks;
-    int off_tile, off_sec, off_row, off_copy;   // offsets into the prefix array
+    int sec_blocks, row_blocks, copy_blocks, gather_blocks;
+    int off_tile, off_sec, off_row, off_copy, off_gather;   // offsets into the prefix array
 };
 
 struct Plan {
@@ -118,6 +118,7 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int bm,
         add(DC_ROOTS_PER_BLOCK, L.off_sec, L.sec_blocks);
         add(DC_ROWS_PER_BLOCK, L.off_row, L.row_blocks);
         add(DC_COLS_PER_BLOCK, L.off_copy, L.copy_blocks);
+        add(DC_GATHER_COLS, L.off_gather, L.gather_blocks);
         P->levels.push_back(L);
     }
     return P;
@@ -172,7 +173,7 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 struct Layout {
     size_t bytes = 0;
     size_t probs, gtask, stask, cnt, rho2, dbl, ints, bufs;
-    int nd = 12, ni = 13;
+    int nd = 16, ni = 13;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -189,7 +190,7 @@ Layout layout(const Plan& P) {
     L.rho2 = o; o = align256(o + nm * sizeof(double));
     L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
     L.ints = o; o = align256(o + L.ni * R * sizeof(int));
-    L.bufs = o; o = align256(o + P.buf_elems * sizeof(double));
+    L.bufs = o; o = align256(o + 2 * P.buf_elems * sizeof(double));
     L.bytes = o;
     return L;
 }
@@ -199,7 +200,7 @@ Scratch carve(const Plan& P, const Layout& L, char* w) {
     const size_t R = std::max<long long>(P.rows, 1);
     double* db = reinterpret_cast<double*>(w + L.dbl);
     double** dp[] = {&S.Ds, &S.zs, &S.Dbar, &S.zbar, &S.tau, &S.cbase, &S.lamr, &S.zhat,
-                     &S.scale, &S.Dd, &S.rc, &S.rs};
+                     &S.scale, &S.Dd, &S.rc, &S.rs, &S.gDt, &S.gzt, &S.gDb, &S.gzb};
     for (int i = 0; i < L.nd; ++i) *dp[i] = db + i * R;
     int* ib = reinterpret_cast<int*>(w + L.ints);
     int** ip[] = {&S.perm, &S.surv, &S.stype, &S.org, &S.dcol, &S.dtype, &S.rp, &S.ri,
@@ -218,6 +219,26 @@ __global__ void k_fill_int(int* p, int n, int v) {
     if (i < n) p[i] = v;
 }
 
+// Optional instrumentation: HIP events on the caller's stream at the phase
+// boundaries of every level (deflate, rotate, secular, assemble, product,
+// deflated copy).  Off by default; never enabled under graph capture.
+constexpr int NPHASE = 6;
+bool g_prof = false;
+std::vector<hipEvent_t> g_ev;
+int g_ev_levels = 0;
+
+hipError_t prof_mark(int level, int phase, hipStream_t s) {
+    if (!g_prof) return hipSuccess;
+    const size_t idx = (size_t)level * (NPHASE + 1) + phase;
+    while (g_ev.size() <= idx) {
+        hipEvent_t ev;
+        hipError_t err = hipEventCreate(&ev);
+        if (err != hipSuccess) return err;
+        g_ev.push_back(ev);
+    }
+    return hipEventRecord(g_ev[idx], s);
+}
+
 hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
                     const dc_opts& o, hipStream_t s) {
     const Layout L = layout(P);
@@ -230,23 +251,30 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
     if (err != hipSuccess) return err;
     err = dc_launch_leaf(d_leaves, (int)P.leaves.size(), S, s);
     if (err != hipSuccess) return err;
-    for (const Level& Lv : P.levels) {
+    g_ev_levels = (int)P.levels.size();
+    for (int li = 0; li < (int)P.levels.size(); ++li) {
+        const Level& Lv = P.levels[li];
         const Node* mg = d_merges + Lv.first;
-        err = dc_launch_deflate(mg, Lv.nm, S, s);
-        if (err != hipSuccess) return err;
-        err = dc_launch_rotate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s);
-        if (err != hipSuccess) return err;
-        err = dc_launch_secular(S.stask + Lv.first, P.d_prefix + Lv.off_sec, Lv.nm,
-                                Lv.sec_blocks, o.max_iter, s);
-        if (err != hipSuccess) return err;
-        err = dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s);
-        if (err != hipSuccess) return err;
-        err = dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
-                                    2 * Lv.nm, Lv.tiles, o.gemm_tile, s);
-        if (err != hipSuccess) return err;
-        err = dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks, S,
-                                      s);
-        if (err != hipSuccess) return err;
+#define DC_TRY(x) do { err = (x); if (err != hipSuccess) return err; } while (0)
+        DC_TRY(prof_mark(li, 0, s));
+        DC_TRY(dc_launch_deflate(mg, Lv.nm, S, s));
+        DC_TRY(prof_mark(li, 1, s));
+        DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
+        DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks, S,
+                                s));
+        DC_TRY(prof_mark(li, 2, s));
+        DC_TRY(dc_launch_secular(S.stask + Lv.first, P.d_prefix + Lv.off_sec, Lv.nm,
+                                 Lv.sec_blocks, o.max_iter, s));
+        DC_TRY(prof_mark(li, 3, s));
+        DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
+        DC_TRY(prof_mark(li, 4, s));
+        DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
+                                     2 * Lv.nm, Lv.tiles, o.gemm_tile, s));
+        DC_TRY(prof_mark(li, 5, s));
+        DC_TRY(dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks,
+                                       S, s));
+        DC_TRY(prof_mark(li, 6, s));
+#undef DC_TRY
     }
     return hipSuccess;
 }
@@ -329,6 +357,8 @@ extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void
     pr.ldq = ldq;
     pr.B1 = reinterpret_cast<double*>(w + L.bufs);
     pr.ld1 = n;
+    pr.B2 = reinterpret_cast<double*>(w + L.bufs) + (size_t)n * n;
+    pr.ld2 = n;
     pr.n = n;
     pr.row0 = 0;
     pr.info = info_dev;
@@ -395,6 +425,8 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
         pr.ldq = ldq_host[p];
         pr.B1 = reinterpret_cast<double*>(w + L.bufs) + P->buf_off[p];
         pr.ld1 = std::max(1, sizes[p]);
+        pr.B2 = reinterpret_cast<double*>(w + L.bufs) + P->buf_elems + P->buf_off[p];
+        pr.ld2 = std::max(1, sizes[p]);
         pr.n = sizes[p];
         pr.row0 = (int)P->row0[p];
         pr.info = info_dev + p;
@@ -485,4 +517,27 @@ extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
         }
     }
     return nmr;
+}
+
+extern "C" int dc_profile_enable(int on) {
+    g_prof = on != 0;
+    return 0;
+}
+
+extern "C" int dc_profile_read(double* ms, int cap) {
+    if (!g_prof) return 0;
+    const int nl = g_ev_levels;
+    for (int li = 0; li < nl; ++li) {
+        for (int ph = 0; ph < NPHASE; ++ph) {
+            const int k = li * NPHASE + ph;
+            if (!ms || k >= cap) continue;
+            float t = 0.0f;
+            const size_t a = (size_t)li * (NPHASE + 1) + ph;
+            if (hipEventSynchronize(g_ev[a + 1]) != hipSuccess ||
+                hipEventElapsedTime(&t, g_ev[a], g_ev[a + 1]) != hipSuccess)
+                t = -1.0f;
+            ms[k] = t;
+        }
+    }
+    return nl;
 }

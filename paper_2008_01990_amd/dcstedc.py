@@ -54,6 +54,8 @@ SIGNATURES = [
     ("dc_last_info", c_int, [P]),
     ("dc_strerror", ctypes.c_char_p, [c_int]),
     ("dc_last_stats", c_int, [ctypes.POINTER(MergeStat), c_int]),
+    ("dc_profile_enable", c_int, [c_int]),
+    ("dc_profile_read", c_int, [P, c_int]),
 ]
 
 # Extra (non-header) hooks used by tests and the benchmark.
@@ -194,6 +196,22 @@ def last_stats():
     lib.dc_last_stats(arr, cnt)
     return [dict(level=r.level, m=r.m, K=r.K, nrot=r.nrot, path=r.path, flops=r.flops)
             for r in arr[:cnt]]
+
+
+PHASES = ("deflate", "rotate", "secular", "assemble", "product", "copy")
+
+
+def profile_enable(on=True):
+    load().dc_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """Per level (deepest first): dict of phase -> milliseconds."""
+    lib = load()
+    nl = lib.dc_profile_read(None, 0)
+    buf = (ctypes.c_double * max(6 * nl, 1))()
+    lib.dc_profile_read(ctypes.cast(buf, ctypes.c_void_p), 6 * nl)
+    return [dict(zip(PHASES, buf[6 * i:6 * i + 6])) for i in range(nl)]
 
 
 def secular(D, z, rho, max_iter=64):

@@ -41,7 +41,7 @@ def test_plain_merge_update_matches_oracle(lib, m, K, seed):
     assert np.all(np.abs(got - ref) <= _bound(Qnd, U))
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_tile_variants_agree(lib, variant):
     m, K = 300, 260
     announce(f"merge_update variant={variant}")
