@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--lowrank-tol", type=float, default=0.0,
                     help="also time the low-rank path at this tolerance (0: skip)")
     ap.add_argument("--lowrank-block", type=int, default=1024)
+    ap.add_argument("--lowrank-min-k", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096)
@@ -196,6 +197,42 @@ def main():
     }
     if not args.no_accuracy:
         out["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
+    if args.lowrank_tol > 0.0:
+        lr = L.Solver(n, leaf=args.leaf, gemm_tile=args.gemm_tile, lr_tol=args.lowrank_tol,
+                      lr_block=args.lowrank_block, lr_min_k=args.lowrank_min_k)
+        del solver
+        torch.cuda.empty_cache()
+
+        def lr_step():
+            d.copy_(d_in)
+            lr.solve_into(d, e, Qbuf)
+
+        for _ in range(args.warmup):
+            lr_step()
+        L.profile_enable(True)
+        lprof = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lr_step()
+            lprof.append(L.profile_read())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.profile_enable(False)
+        lms = (t1 - t0) * 1e3 / args.steps
+        lstats = L.last_stats()
+        lr_top_ms = sum(p[-1]["product"] for p in lprof) / len(lprof)
+        out["lowrank"] = {
+            "tol": args.lowrank_tol, "block": args.lowrank_block,
+            "min_k": args.lowrank_min_k, "seconds": lms / 1e3,
+            "speedup_vs_plain": ms / lms,
+            "root_product_ms": lr_top_ms,
+            "root_product_speedup_vs_plain": top["product_ms"] / lr_top_ms,
+            "merges": [dict(m=r["m"], K=r["K"], path=r["path"], flops=r["flops"])
+                       for r in lstats if r["path"] == 1],
+        }
+        if not args.no_accuracy:
+            out["lowrank"]["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
     del Qbuf
     torch.cuda.empty_cache()
     if not args.no_cpu:

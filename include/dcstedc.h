@@ -79,7 +79,13 @@ size_t dc_stedc_workspace(int n, const dc_opts* opt);
  *   work, lwork  device workspace of at least dc_stedc_workspace(n, opt)
  *                bytes, 256-byte aligned
  *   info_dev     device int; receives the status (see above)
- * Allocates nothing and performs no host synchronisation: graph-capturable.
+ * With opt->lr_tol == 0 it allocates nothing and performs no host
+ * synchronisation (graph-capturable).  With lr_tol > 0, each merge that takes
+ * the low-rank product reads its sizes and ranks on the host and allocates
+ * stream-ordered temporaries: not graph-capturable.
+ * The first call for a given (n, options) builds and uploads the tree plan
+ * synchronously; call dc_stedc_workspace first (it builds the plan) before
+ * capturing.
  */
 int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void* work,
                 size_t lwork, int* info_dev, const dc_opts* opt,

@@ -64,7 +64,7 @@ __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int 
     return lo;
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int KIND, int BM, int BN, int BK, int WGM, int WGN>
 __global__ __launch_bounds__(WGM * WGN * 64)
 void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
                    int ntasks, int total_tiles) {
@@ -94,16 +94,20 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     const int wm = wave / WGN;
     const int wn = wave - wm * WGN;
 
-    // Column generators of the U entries this thread produces (fixed column).
+    // Column generators of the B entries this thread produces (fixed column).
     const int bj = tid % BN;
     const int bk0 = tid / BN;
-    const int gcol = col0 + bj;
-    const bool col_ok = gcol < ncol;
+    const int lcol = col0 + bj;
+    const bool col_ok = lcol < ncol;
+    const int gcol = col_ok ? (T.ccol ? T.ccol[lcol] : T.col_off + lcol) : 0;
     const double* __restrict__ rD = T.rD;
     const double* __restrict__ rz = T.rz;
-    const double cb = col_ok ? (T.corg ? rD[T.corg[gcol]] : T.cbase[gcol]) : 0.0;
-    const double co = (col_ok && T.coff) ? T.coff[gcol] : 0.0;
-    const double csj = col_ok ? T.cs[gcol] : 0.0;
+    double cb = 0.0, co = 0.0, csj = 0.0;
+    if (col_ok) {
+        cb = (KIND == 0 && T.corg) ? rD[T.corg[gcol]] : T.cbase[gcol];
+        co = T.coff ? T.coff[gcol] : 0.0;
+        if (KIND == 0) csj = T.cs[gcol];
+    }
 
     // A entries this thread moves: row ar, k = ak0 + i * A_KSTEP.
     const int ar = tid % BM;
@@ -119,8 +123,10 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int j = 0; j < C_::FN; ++j) acc[i][j] = dc_double4{0.0, 0.0, 0.0, 0.0};
 
     double a_reg[C_::A_PER];
-    double d_reg[C_::B_PER];
-    double z_reg[C_::B_PER];
+    double d_reg[C_::B_PER];    // kind 0: row node; kind 1: y * vk
+    double z_reg[C_::B_PER];    // kind 0: row weight; kind 1: skeleton node base
+    double o_reg[KIND == 1 ? C_::B_PER : 1];   // kind 1: skeleton node offset
+    int s_reg[KIND == 1 ? C_::B_PER : 1];      // kind 1: skeleton column (generator)
 
     auto load = [&](int kb) {
 #pragma unroll
@@ -132,11 +138,19 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int i = 0; i < C_::B_PER; ++i) {
             const int k = kb + bk0 + i * C_::B_KSTEP;
             const bool ok = k < klen;
-            d_reg[i] = ok ? rD[k] : 0.0;
-            z_reg[i] = ok ? rz[k] : 0.0;
+            if (KIND == 0) {
+                d_reg[i] = ok ? rD[k] : 0.0;
+                z_reg[i] = ok ? rz[k] : 0.0;
+            } else {
+                const int h = ok ? T.rgen[k] : 0;
+                d_reg[i] = (ok && col_ok) ? T.ry[k] * T.vk[T.rvo[k] + lcol] : 0.0;
+                z_reg[i] = ok ? T.cbase[h] : 0.0;
+                o_reg[i] = (ok && T.coff) ? T.coff[h] : 0.0;
+                s_reg[i] = ok ? h : -1;
+            }
         }
     };
-    // Store slice s of the registers into LDS buffer `buf` (U generated).
+    // Store slice s of the registers into LDS buffer `buf` (B generated).
     auto store_slice = [&](int buf, int kb, int s) {
 #pragma unroll
         for (int q = 0; q < C_::A_SLICE; ++q) {
@@ -147,8 +161,14 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int q = 0; q < C_::B_SLICE; ++q) {
             const int i = s * C_::B_SLICE + q;
             const int kk = bk0 + i * C_::B_KSTEP;
-            const double den = (d_reg[i] - cb) - co;
-            double v = z_reg[i] * csj * dc_rcp(den);
+            double v;
+            if (KIND == 0) {
+                const double den = (d_reg[i] - cb) - co;
+                v = z_reg[i] * csj * dc_rcp(den);
+            } else {
+                const double den = (z_reg[i] - cb) + (o_reg[i] - co);
+                v = (s_reg[i] == gcol) ? 1.0 : d_reg[i] * dc_rcp(den);
+            }
             v = (kb + kk < klen && col_ok) ? v : 0.0;
             Bs[buf][kk * C_::LDB_S + bj] = v;
         }
@@ -192,7 +212,8 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     for (int j = 0; j < C_::FN; ++j) {
         const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
         if (c >= ncol) continue;
-        const int oc = T.cpos ? T.cpos[c] : c;
+        const int g = T.ccol ? T.ccol[c] : T.col_off + c;
+        const int oc = T.cpos ? T.cpos[T.ccol ? c : g] : g - T.out_off;
         double* Ccol = T.C + (long long)oc * T.ldc;
 #pragma unroll
         for (int i = 0; i < C_::FM; ++i) {
@@ -208,14 +229,25 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int KIND, int BM, int BN, int BK, int WGM, int WGN>
 hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
                   hipStream_t s) {
     int grid = (total + 7) & ~7;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cauchy_gemm<BM, BN, BK, WGM, WGN>), dim3(grid),
+    hipLaunchKernelGGL((k_cauchy_gemm<KIND, BM, BN, BK, WGM, WGN>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
     return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_variant(const GemmTask* tasks, const int* tile_start, int ntasks,
+                          int total, int variant, hipStream_t s) {
+    switch (variant) {
+        case 1: return launch<KIND, 128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
+        case 2: return launch<KIND, 64, 64, 16, 1, 1>(tasks, tile_start, ntasks, total, s);
+        case 3: return launch<KIND, 128, 128, 32, 2, 2>(tasks, tile_start, ntasks, total, s);
+        default: return launch<KIND, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+    }
 }
 
 }  // namespace
@@ -240,10 +272,10 @@ int dc_gemm_tile_n(int variant) {
 
 hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
                                  int total, int variant, hipStream_t s) {
-    switch (variant) {
-        case 1: return launch<128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
-        case 2: return launch<64, 64, 16, 1, 1>(tasks, tile_start, ntasks, total, s);
-        case 3: return launch<128, 128, 32, 2, 2>(tasks, tile_start, ntasks, total, s);
-        default: return launch<256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
-    }
+    return launch_variant<0>(tasks, tile_start, ntasks, total, variant, s);
+}
+
+hipError_t dc_launch_interp_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
+                                 int total, int variant, hipStream_t s) {
+    return launch_variant<1>(tasks, tile_start, ntasks, total, variant, s);
 }

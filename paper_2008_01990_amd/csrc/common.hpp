@@ -43,28 +43,43 @@ __device__ __forceinline__ void dc_set_info(int* info, int code) {
 }
 
 // One product C[rows, cols] (=|+=) A[rows, 0:klen] * B[0:klen, cols] in which
-// B is a Cauchy-like matrix generated on the fly:
-//   B_kj = rz[k] * cs[j] / ((rD[k] - cbase[j]) - coff[j]).
+// B is generated on the fly, one of two kinds:
+//  kind 0 (Cauchy-like eigenvector block, eq. Q_Cauchy):
+//    B_kc = rz[k] * cs[g] / ((rD[k] - cbase[g]) - coff[g]),
+//  kind 1 (interpolation rows [I Z] P^T of a compressed block, eq. sid /
+//  eq. geneZ): row k belongs to the skeleton column h = rgen[k] of its block,
+//    B_kc = 1                                        if g == h
+//    B_kc = ry[k] * vk[rvo[k] + c] / ((cbase[h] - cbase[g]) + (coff[h] - coff[g]))
+//  where g = ccol[c] if ccol is set, else col_off + c, is the generator index
+//  of output column c.  The output column of C is cpos[c] when both ccol and
+//  cpos are set, cpos[g] when only cpos is, and g - out_off otherwise.
 struct GemmTask {
     const double* A;      // row 0 of this task inside A (column-major, lda)
     long long lda;
     const int* klen_p;    // device number of k-entries, or null (= klen)
     int klen;
     int rows;             // rows of the task
-    const double* rD;     // row nodes
-    const double* rz;     // row weights
-    const double* cbase;  // column node bases
-    const int* corg;      // if set, column node base j is rD[corg[j]] (cbase unused)
+    const double* rD;     // kind 0: row nodes
+    const double* rz;     // kind 0: row weights
+    const double* cbase;  // column node bases (by generator index)
+    const int* corg;      // kind 0: if set, node base of g is rD[corg[g]] (cbase unused)
     const double* coff;   // column node offsets, or null (= 0)
-    const double* cs;     // column scales
+    const double* cs;     // kind 0: column scales
     const int* ncol_p;    // device number of columns, or null (= ncol)
     int ncol;
+    int col_off;          // generator index of column 0 when ccol is null
+    const int* ccol;      // generator index of column c, or null
     double* C;            // row 0 of this task inside C
     long long ldc;
-    const int* cpos;      // output column of column j, or null (= j)
+    const int* cpos;      // output column of generator g, or null (= g - out_off)
+    int out_off;          // subtracted from g when cpos is null
     int tiles_m, tiles_n; // worst-case tile grid of the task
     int beta;             // 0: overwrite, 1: accumulate
-    int pad_;
+    // kind 1 row data
+    const double* ry;
+    const int* rgen;
+    const long long* rvo;
+    const double* vk;
 };
 
 // Host-side launcher of the generated-Cauchy product over a task list.
@@ -72,6 +87,10 @@ struct GemmTask {
 // entries (exclusive prefix sum of tiles_m * tiles_n).  variant selects the
 // tile shape (0 = default).
 hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
+                                 int ntasks, int total_tiles, int variant,
+                                 hipStream_t stream);
+// Same for kind-1 (interpolation) tasks.
+hipError_t dc_launch_interp_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
                                  int ntasks, int total_tiles, int variant,
                                  hipStream_t stream);
 int dc_gemm_tile_m(int variant);

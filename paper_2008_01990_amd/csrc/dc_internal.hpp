@@ -41,7 +41,7 @@ struct MergeCnt {
     int ndefl;          // deflated eigenpairs
     int ntop;           // survivors with non-zeros in the top rows
     int nbot;           // survivors with non-zeros in the bottom rows
-    int pad_[3];
+    int pad_[3];        // pad_[0] stays 0: a disabled product task points here
 };
 
 // Per-row scratch (indexed by prob.row0 + node.off + local index) and

@@ -78,6 +78,7 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
     const int tn = (m + bn - 1) / bn;   // worst-case column tiles
     for (int half = 0; half < 2; ++half) {
         GemmTask T;
+        memset(&T, 0, sizeof(T));
         const int r0 = half ? N.n1 : 0;
         T.A = P.B2 + (long long)N.off * P.ld2 + N.off + r0;
         T.lda = P.ld2;
@@ -98,7 +99,6 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
         T.tiles_m = (T.rows + bm - 1) / bm;
         T.tiles_n = tn;
         T.beta = 0;
-        T.pad_ = 0;
         S.gtask[2 * slot + half] = T;
     }
     SecTask Q;
@@ -158,6 +158,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
             cnt->ndefl = m;
             cnt->ntop = 0;
             cnt->nbot = 0;
+            cnt->pad_[0] = 0;
             S.rho2[N.slot] = 0.0;
         }
         return;
@@ -272,6 +273,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         cnt->K = K;
         cnt->nrot = nrot;
         cnt->ndefl = nd;
+        cnt->pad_[0] = 0;
         S.rho2[N.slot] = rho2;
         s_K = K;
     }

@@ -25,6 +25,7 @@
 
 #include "dc_internal.hpp"
 #include "driver.hpp"
+#include "lowrank.hpp"
 
 namespace {
 
@@ -33,6 +34,7 @@ struct Level {
     int nm;
     int tiles;          // worst-case product tiles
     int sec_blocks, row_blocks, copy_blocks, gather_blocks;
+    int max_m;          // largest merge of the level
     int off_tile, off_sec, off_row, off_copy, off_gather;   // offsets into the prefix array
 };
 
@@ -90,6 +92,9 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int bm,
         }
         L.nm = (int)P->merges.size() - L.first;
         if (L.nm == 0) continue;
+        L.max_m = 0;
+        for (int i = 0; i < L.nm; ++i)
+            L.max_m = std::max(L.max_m, P->merges[L.first + i].n1 + P->merges[L.first + i].n2);
         auto& pre = P->prefix;
         L.off_tile = (int)pre.size();
         int acc = 0;
@@ -239,8 +244,70 @@ hipError_t prof_mark(int level, int phase, hipStream_t s) {
     return hipEventRecord(g_ev[idx], s);
 }
 
+// Per-merge product record of the last solve on this host thread:
+// path (0 plain, 1 low rank) and executed flops of low-rank merges.
+thread_local std::vector<int> t_path;
+thread_local std::vector<double> t_lr_flops;
+
+// Algorithm 3's switch: every merge of the level whose deflated size reaches
+// lr_min_k (and exceeds one block) gets the structured low-rank product; its
+// plain product tasks are then disabled.  Reads the level's sizes on the host.
+hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Scratch& S,
+                         int first, int nm, const dc_opts& o, hipStream_t s) {
+    std::vector<MergeCnt> cnt(nm);
+    hipError_t err = hipMemcpyAsync(cnt.data(), S.cnt + first, nm * sizeof(MergeCnt),
+                                    hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    const int b = std::min(o.lr_block, 2048);
+    for (int i = 0; i < nm; ++i) {
+        const Node& N = P.merges[first + i];
+        const MergeCnt& C = cnt[i];
+        if (C.K < o.lr_min_k || C.K <= b) continue;
+        const Prob& pr = probs[N.prob];
+        const long long base = (long long)pr.row0 + N.off;
+        long long ldo;
+        double* Qo = node_buf(pr, N.depth, ldo);
+        std::vector<LrHalf> halves(2);
+        for (int h = 0; h < 2; ++h) {
+            LrHalf& H = halves[h];
+            const int r0 = h ? N.n1 : 0;
+            const int cntk = h ? C.nbot : C.ntop;
+            H.klist.resize(cntk);
+            if (cntk > 0) {
+                err = hipMemcpyAsync(H.klist.data(), (h ? S.kbot : S.ktop) + base,
+                                     cntk * sizeof(int), hipMemcpyDeviceToHost, s);
+                if (err != hipSuccess) return err;
+            }
+            H.A = pr.B2 + (long long)N.off * pr.ld2 + N.off + r0;
+            H.lda = pr.ld2;
+            H.rows = h ? N.n2 : N.n1;
+            H.gD = (h ? S.gDb : S.gDt) + base;
+            H.gz = (h ? S.gzb : S.gzt) + base;
+            H.C = Qo + (long long)N.off * ldo + N.off + r0;
+            H.ldc = ldo;
+            H.cpos = S.pos_root + base;
+            H.w_row0 = r0;
+        }
+        err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return err;
+        double flops = 0.0;
+        err = dc_lowrank_product(C.K, b, o.lr_tol, S.Dbar + base, S.zhat + base,
+                                 S.cbase + base, S.tau + base, S.scale + base, halves,
+                                 N.n1 + N.n2, o.gemm_tile, s, &flops);
+        if (err != hipSuccess) return err;
+        err = dc_disable_tasks(S.gtask + 2 * N.slot, 2, &S.cnt[N.slot].pad_[0], s);
+        if (err != hipSuccess) return err;
+        t_path[N.slot] = 1;
+        t_lr_flops[N.slot] = flops;
+    }
+    return hipSuccess;
+}
+
 hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
                     const dc_opts& o, hipStream_t s) {
+    t_path.assign(P.merges.size(), 0);
+    t_lr_flops.assign(P.merges.size(), 0.0);
     const Layout L = layout(P);
     Scratch S = carve(P, L, work);
     hipError_t err = dc_launch_set_probs(probs.data(), (int)probs.size(), S.probs, s);
@@ -268,6 +335,8 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         DC_TRY(prof_mark(li, 3, s));
         DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
         DC_TRY(prof_mark(li, 4, s));
+        if (o.lr_tol > 0.0 && Lv.max_m > o.lr_min_k)
+            DC_TRY(lowrank_level(P, probs, S, Lv.first, Lv.nm, o, s));
         DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
                                      2 * Lv.nm, Lv.tiles, o.gemm_tile, s));
         DC_TRY(prof_mark(li, 5, s));
@@ -317,6 +386,7 @@ extern "C" void dc_opts_default(dc_opts* o) {
 static int check_opts(const dc_opts& o) {
     if (o.leaf < 1 || o.leaf > DC_MAX_LEAF) return 1;
     if (!(o.lr_tol >= 0.0)) return 1;
+    if (o.lr_block < 16 || o.lr_block > 2048) return 1;
     return 0;
 }
 
@@ -509,9 +579,11 @@ extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
                 r.m = N.n1 + N.n2;
                 r.K = cnt[g].K;
                 r.nrot = cnt[g].nrot;
-                r.path = 0;
-                r.flops = 2.0 * ((double)N.n1 * cnt[g].ntop + (double)N.n2 * cnt[g].nbot) *
-                          cnt[g].K;
+                const bool lr = g < (int)t_path.size() && t_path[g] == 1;
+                r.path = lr ? 1 : 0;
+                r.flops = lr ? t_lr_flops[g]
+                             : 2.0 * ((double)N.n1 * cnt[g].ntop + (double)N.n2 * cnt[g].nbot) *
+                                   cnt[g].K;
             }
             ++li;
         }

@@ -1,14 +1,518 @@
-// Structured low-rank merge product: placeholder until the SRRSC kernels land.
+// Structured low-rank merge product: SRRSC compression of the off-diagonal
+// blocks of U from their Cauchy generators, then two generated products.
+//
+// Compression (section "SRRSC low-rank approximation"): U is cut into
+// contiguous b x b blocks of the sorted order (block data distribution, which
+// keeps the off-diagonal low-rank property; section "Storage form affects the
+// off-diagonally low-rank property").  One workgroup per off-diagonal block
+// runs Schur-complement elimination on the generators alone (Theorem 1): with
+// the pivot (row node d_k, column node w_k) the generators update as
+//     u_l <- u_l (d_l - d_k) / (d_l - w_k),   v_l <- v_l (w_l - w_k) / (w_l - d_k),
+// which also zeroes the pivot row and column, so the next complete-pivoting
+// search simply scans the whole block again.  Elimination stops when every
+// Schur-complement entry is at most tol.  The pivot columns are the skeleton
+// T, and the interpolation matrix Z = A11^{-1} A12 is Cauchy-like with row
+// generator y (eq. yk) and column generator v^(r) (Theorem 2, eq. geneZ).
+// A block whose rank would exceed rmax is kept dense.
+//
+// Products (Algorithm 2 step 3(c), C += (A U_B) V_B, restated for one GPU):
+//   1a  C(:, J) = A(:, J) U_JJ                      diagonal blocks, exact
+//   1b  W(:, T_IJ) = A(:, I) U_I,T_IJ                skeleton columns, all J != I
+//   2   C(:, J) += [W(:, T_IJ)]_I [I Z_IJ]_I P^T      interpolation rows generated
+// A block kept dense is carried as a block whose skeleton is every column
+// (identity interpolation rows), so step 2 still owns each output block J
+// through exactly one task and no two tasks of a launch write the same
+// column.  W is laid out by output block J, so step 2 reads one contiguous
+// column range of W per J.  Every product is the generated-tile MFMA kernel; U, Z
+// and W's factors never exist as matrices except W itself (m x sum of ranks).
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <vector>
+
+#include "dc_internal.hpp"
+#include "driver.hpp"
 #include "lowrank.hpp"
 
-hipError_t dc_lowrank_update(int, int, const double*, long long, const double*, const int*,
-                             const double*, const double*, const double*, double*, long long,
-                             double, int, hipStream_t) {
-    return hipErrorNotSupported;
+namespace {
+
+constexpr int NT = 1024;
+constexpr int MAX_B = 2048;
+constexpr int MAX_R = 128;
+
+struct SrrscOut {
+    int* rank;        // p*p: rank, -1 on the diagonal, -2 kept dense
+    int* prow;        // p*p*rmax, local pivot rows
+    int* pcol;        // p*p*rmax, local skeleton columns
+    double* y;        // p*p*rmax
+    double* vk;       // p*p*b: v^(r) of the block's columns (0 on skeletons)
+};
+
+__global__ __launch_bounds__(NT)
+void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __restrict__ u0,
+             const double* __restrict__ cbase, const double* __restrict__ coff,
+             const double* __restrict__ v0, double tol, int rmax, SrrscOut O) {
+    __shared__ double sd[MAX_B], su[MAX_B], swb[MAX_B], swo[MAX_B], sv[MAX_B];
+    __shared__ double wv[NT / 64];
+    __shared__ int wi[NT / 64];
+    __shared__ int spr[MAX_R], spc[MAX_R];
+    __shared__ double s_max;
+    __shared__ int s_piv;
+
+    const int pair = blockIdx.x;
+    const int I = pair / p, J = pair - (pair / p) * p;
+    const int tid = threadIdx.x;
+    if (I == J) {
+        if (tid == 0) O.rank[pair] = -1;
+        return;
+    }
+    const int r0 = I * b, c0 = J * b;
+    const int bi = min(b, K - r0), bj = min(b, K - c0);
+    for (int i = tid; i < bi; i += NT) {
+        sd[i] = D[r0 + i];
+        su[i] = u0[r0 + i];
+    }
+    for (int j = tid; j < bj; j += NT) {
+        swb[j] = cbase[c0 + j];
+        swo[j] = coff ? coff[c0 + j] : 0.0;
+        sv[j] = v0[c0 + j];
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int nflat = bi * bj;
+    int k = 0;
+    bool dense = false;
+    for (;;) {
+        // Complete pivoting: largest |A^(k)_ij| = |u_i v_j / (d_i - w_j)|,
+        // ties to the smallest row-major position.
+        double best = -1.0;
+        int bf = INT_MAX;
+        for (int f = tid; f < nflat; f += NT) {
+            const int i = f / bj;
+            const int j = f - i * bj;
+            const double val = fabs(su[i] * sv[j] * dc_rcp((sd[i] - swb[j]) - swo[j]));
+            if (val > best) { best = val; bf = f; }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(best, off, 64);
+            const int of = __shfl_xor(bf, off, 64);
+            if (ov > best || (ov == best && of < bf)) { best = ov; bf = of; }
+        }
+        if (lane == 0) { wv[w] = best; wi[w] = bf; }
+        __syncthreads();
+        if (tid == 0) {
+            double bb = wv[0];
+            int bbf = wi[0];
+            for (int q = 1; q < NT / 64; ++q)
+                if (wv[q] > bb || (wv[q] == bb && wi[q] < bbf)) { bb = wv[q]; bbf = wi[q]; }
+            s_max = bb;
+            s_piv = bbf;
+        }
+        __syncthreads();
+        if (!(s_max > tol)) break;
+        if (k == rmax) { dense = true; break; }
+        const int pi = s_piv / bj;
+        const int pj = s_piv - pi * bj;
+        if (tid == 0) { spr[k] = pi; spc[k] = pj; }
+        const double dk = sd[pi], wbk = swb[pj], wok = swo[pj];
+        // Theorem 1 generator updates (the pivot row and column become 0).
+        for (int i = tid; i < bi; i += NT)
+            su[i] *= (sd[i] - dk) * dc_rcp((sd[i] - wbk) - wok);
+        for (int j = tid; j < bj; j += NT)
+            sv[j] *= ((swb[j] - wbk) + (swo[j] - wok)) * dc_rcp((swb[j] - dk) + swo[j]);
+        ++k;
+        __syncthreads();
+    }
+    if (tid == 0) O.rank[pair] = dense ? -2 : k;
+    if (dense) {
+        // every column becomes a skeleton column: v^(r) = 0 throughout
+        for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = 0.0;
+        return;
+    }
+    const long long pb = (long long)pair * rmax;
+    // Theorem 2, eq. yk: y_a = prod_{c != a} (d_c - w_a)/(w_c - w_a) * (d_a - w_a)/v0_a.
+    for (int a = tid; a < k; a += NT) {
+        const int ja = spc[a];
+        const double wba = swb[ja], woa = swo[ja];
+        double y = 1.0;
+        for (int c = 0; c < k; ++c) {
+            if (c == a) continue;
+            const double num = (sd[spr[c]] - wba) - woa;
+            const double den = (swb[spc[c]] - wba) + (swo[spc[c]] - woa);
+            y *= num * dc_rcp(den);
+        }
+        y *= ((sd[spr[a]] - wba) - woa) * dc_rcp(v0[c0 + ja]);
+        O.y[pb + a] = y;
+        O.prow[pb + a] = spr[a];
+        O.pcol[pb + a] = ja;
+    }
+    for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = sv[j];
 }
 
-extern "C" int dc_merge_lowrank_ranks(int, const double*, const int*, const double*,
-                                      const double*, const double*, double, int, int*,
-                                      hipStream_t) {
-    return (int)hipErrorNotSupported;
+__global__ void k_nodes(int K, const double* D, const int* org, const double* tau,
+                        double* cbase, double* coff) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K) return;
+    if (org) {
+        cbase[j] = D[org[j]];
+        coff[j] = tau[j];
+    } else {
+        cbase[j] = tau[j];
+        coff[j] = 0.0;
+    }
+}
+
+__global__ void k_disable_tasks(GemmTask* tasks, int n, const int* zero) {
+    const int i = threadIdx.x;
+    if (i < n) tasks[i].ncol_p = zero;
+}
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Compressed {
+    int p = 0, b = 0, rmax = 0;
+    std::vector<int> rank, pcol;
+    std::vector<double> y;
+    char* dev = nullptr;          // device block holding SrrscOut arrays
+    SrrscOut out{};
+};
+
+hipError_t compress(int K, int b, double tol, const double* D, const double* zhat,
+                    const double* cbase, const double* coff, const double* scale,
+                    hipStream_t s, Compressed& Cm) {
+    Cm.b = b;
+    Cm.p = (K + b - 1) / b;
+    Cm.rmax = std::min(MAX_R, std::max(1, b / 2));
+    const size_t p2 = (size_t)Cm.p * Cm.p;
+    size_t o = 0;
+    const size_t o_rank = o; o = al(o + p2 * sizeof(int));
+    const size_t o_prow = o; o = al(o + p2 * Cm.rmax * sizeof(int));
+    const size_t o_pcol = o; o = al(o + p2 * Cm.rmax * sizeof(int));
+    const size_t o_y = o; o = al(o + p2 * Cm.rmax * sizeof(double));
+    const size_t o_vk = o; o = al(o + p2 * (size_t)b * sizeof(double));
+    hipError_t err = hipMallocAsync((void**)&Cm.dev, o, s);
+    if (err != hipSuccess) return err;
+    Cm.out.rank = reinterpret_cast<int*>(Cm.dev + o_rank);
+    Cm.out.prow = reinterpret_cast<int*>(Cm.dev + o_prow);
+    Cm.out.pcol = reinterpret_cast<int*>(Cm.dev + o_pcol);
+    Cm.out.y = reinterpret_cast<double*>(Cm.dev + o_y);
+    Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o_vk);
+    hipLaunchKernelGGL(k_srrsc, dim3((unsigned)p2), dim3(NT), 0, s, K, b, Cm.p, D, zhat,
+                       cbase, coff, scale, tol, Cm.rmax, Cm.out);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    Cm.rank.resize(p2);
+    Cm.pcol.resize(p2 * Cm.rmax);
+    Cm.y.resize(p2 * Cm.rmax);
+    err = hipMemcpyAsync(Cm.rank.data(), Cm.out.rank, p2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(Cm.pcol.data(), Cm.out.pcol, p2 * Cm.rmax * sizeof(int),
+                             hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    return err;
+}
+
+// Device-side task list of one launch, with its tile prefix.
+struct Stage {
+    std::vector<GemmTask> tasks;
+    std::vector<int> start{0};
+    int kind = 0;
+    void add(const GemmTask& t) {
+        if (t.tiles_m * t.tiles_n == 0) return;
+        tasks.push_back(t);
+        start.push_back(start.back() + t.tiles_m * t.tiles_n);
+    }
+};
+
+}  // namespace
+
+hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
+                              const double* cbase, const double* coff, const double* scale,
+                              std::vector<LrHalf>& halves, int wrows, int variant,
+                              hipStream_t s, double* flops_out) {
+    Compressed Cm;
+    hipError_t err = compress(K, b, tol, D, zhat, cbase, coff, scale, s, Cm);
+    if (err != hipSuccess) {
+        if (Cm.dev) hipFreeAsync(Cm.dev, s);
+        return err;
+    }
+    const int p = Cm.p, rmax = Cm.rmax;
+    const int BM = dc_gemm_tile_m(variant), BN = dc_gemm_tile_n(variant);
+    auto bsz = [&](int I) { return std::min(b, K - I * b); };
+    // Skeleton size of block (I, J): its rank, or every column if kept dense.
+    auto rk = [&](int I, int J) {
+        const int r = Cm.rank[(size_t)I * p + J];
+        return r == -2 ? bsz(J) : r;
+    };
+    auto dense = [&](int I, int J) { return Cm.rank[(size_t)I * p + J] == -2; };
+    auto skel = [&](int I, int J, int a) {
+        return dense(I, J) ? a : Cm.pcol[((size_t)I * p + J) * rmax + a];
+    };
+
+    // W layout by output block J: [W_IJ for I != J low-rank], r_IJ columns each.
+    std::vector<long long> gstart(p + 1, 0), offIJ((size_t)p * p, 0);
+    for (int J = 0; J < p; ++J) {
+        long long run = 0;
+        for (int I = 0; I < p; ++I)
+            if (I != J && rk(I, J) > 0) { offIJ[(size_t)I * p + J] = run; run += rk(I, J); }
+        gstart[J + 1] = gstart[J] + run;
+    }
+    const long long NW = gstart[p];
+    // Interpolation row data, indexed by W column.
+    std::vector<double> ry(std::max<long long>(NW, 1));
+    std::vector<int> rgen(std::max<long long>(NW, 1));
+    std::vector<long long> rvo(std::max<long long>(NW, 1));
+    for (int J = 0; J < p; ++J)
+        for (int I = 0; I < p; ++I) {
+            const int r = (I != J) ? rk(I, J) : 0;
+            for (int a = 0; a < r; ++a) {
+                const long long col = gstart[J] + offIJ[(size_t)I * p + J] + a;
+                const size_t q = ((size_t)I * p + J) * rmax + a;
+                rgen[col] = J * b + skel(I, J, a);
+                rvo[col] = ((long long)I * p + J) * b;
+                (void)q;
+            }
+        }
+    // y lives on the device already; copy it into W-column order on the host.
+    Cm.y.resize((size_t)p * p * rmax);
+    err = hipMemcpyAsync(Cm.y.data(), Cm.out.y, Cm.y.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    for (int J = 0; J < p && err == hipSuccess; ++J)
+        for (int I = 0; I < p; ++I) {
+            const int r = (I != J) ? rk(I, J) : 0;
+            for (int a = 0; a < r; ++a)
+                ry[gstart[J] + offIJ[(size_t)I * p + J] + a] =
+                    dense(I, J) ? 0.0 : Cm.y[((size_t)I * p + J) * rmax + a];
+        }
+    // Stage-1b column lists per I (same for every half).
+    std::vector<std::vector<int>> ccol(p), wpos(p);
+    for (int I = 0; I < p; ++I)
+        for (int J = 0; J < p; ++J) {
+            if (I == J || rk(I, J) <= 0) continue;
+            for (int a = 0; a < rk(I, J); ++a) {
+                ccol[I].push_back(J * b + skel(I, J, a));
+                wpos[I].push_back((int)(gstart[J] + offIJ[(size_t)I * p + J] + a));
+            }
+        }
+    // Device staging of the small arrays: ry, rgen, rvo, ccol/wpos per I.
+    std::vector<size_t> cofs(p), wofs(p);
+    size_t o = 0;
+    const size_t o_ry = o; o = al(o + ry.size() * sizeof(double));
+    const size_t o_rg = o; o = al(o + rgen.size() * sizeof(int));
+    const size_t o_rv = o; o = al(o + rvo.size() * sizeof(long long));
+    for (int I = 0; I < p; ++I) {
+        cofs[I] = o; o = al(o + std::max<size_t>(ccol[I].size(), 1) * sizeof(int));
+        wofs[I] = o; o = al(o + std::max<size_t>(wpos[I].size(), 1) * sizeof(int));
+    }
+    const size_t small_bytes = o;
+    double* W = nullptr;
+    char* small = nullptr;
+    if (err == hipSuccess) err = hipMallocAsync((void**)&small, small_bytes, s);
+    if (err == hipSuccess && NW > 0)
+        err = hipMallocAsync((void**)&W, (size_t)wrows * NW * sizeof(double), s);
+    std::vector<char> host(small_bytes);
+    std::memcpy(host.data() + o_ry, ry.data(), ry.size() * sizeof(double));
+    std::memcpy(host.data() + o_rg, rgen.data(), rgen.size() * sizeof(int));
+    std::memcpy(host.data() + o_rv, rvo.data(), rvo.size() * sizeof(long long));
+    for (int I = 0; I < p; ++I) {
+        if (!ccol[I].empty()) {
+            std::memcpy(host.data() + cofs[I], ccol[I].data(), ccol[I].size() * sizeof(int));
+            std::memcpy(host.data() + wofs[I], wpos[I].data(), wpos[I].size() * sizeof(int));
+        }
+    }
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(small, host.data(), small_bytes, hipMemcpyHostToDevice, s);
+
+    // Task lists.
+    Stage s1a, s1b, s2;
+    s2.kind = 1;
+    double flops = 0.0;
+    auto tiles = [&](GemmTask& t) {
+        t.tiles_m = (t.rows + BM - 1) / BM;
+        t.tiles_n = (t.ncol + BN - 1) / BN;
+    };
+    for (const LrHalf& H : halves) {
+        if (H.rows <= 0) continue;
+        std::vector<int> lo(p), hi(p);
+        for (int I = 0; I < p; ++I) {
+            if (H.klist.empty()) {
+                lo[I] = I * b;
+                hi[I] = I * b + bsz(I);
+            } else {
+                lo[I] = (int)(std::lower_bound(H.klist.begin(), H.klist.end(), I * b) -
+                              H.klist.begin());
+                hi[I] = (int)(std::lower_bound(H.klist.begin(), H.klist.end(), I * b + b) -
+                              H.klist.begin());
+            }
+        }
+        GemmTask base;
+        std::memset(&base, 0, sizeof(base));
+        base.lda = H.lda;
+        base.rows = H.rows;
+        base.cbase = cbase;
+        base.coff = coff;
+        base.cs = scale;
+        for (int I = 0; I < p; ++I) {
+            GemmTask t = base;
+            t.A = H.A + (long long)lo[I] * H.lda;
+            t.klen = hi[I] - lo[I];
+            t.rD = H.gD + lo[I];
+            t.rz = H.gz + lo[I];
+            // 1a: diagonal block straight into C
+            GemmTask a = t;
+            a.col_off = I * b;
+            a.ncol = bsz(I);
+            a.C = H.C;
+            a.ldc = H.ldc;
+            a.cpos = H.cpos;
+            a.beta = 0;
+            tiles(a);
+            s1a.add(a);
+            flops += 2.0 * H.rows * a.klen * a.ncol;
+            // 1b: skeleton columns of every J != I into W
+            if (!ccol[I].empty()) {
+                GemmTask c = t;
+                c.ccol = reinterpret_cast<int*>(small + cofs[I]);
+                c.cpos = reinterpret_cast<int*>(small + wofs[I]);
+                c.ncol = (int)ccol[I].size();
+                c.C = W + H.w_row0;
+                c.ldc = wrows;
+                c.beta = 0;
+                tiles(c);
+                s1b.add(c);
+                flops += 2.0 * H.rows * c.klen * c.ncol;
+            }
+        }
+        // 2: interpolation rows of every block column J
+        for (int J = 0; J < p; ++J) {
+            const long long R = gstart[J + 1] - gstart[J];
+            if (R == 0) continue;
+            GemmTask t = base;
+            t.A = W + H.w_row0 + gstart[J] * (long long)wrows;
+            t.lda = wrows;
+            t.klen = (int)R;
+            t.ry = reinterpret_cast<double*>(small + o_ry) + gstart[J];
+            t.rgen = reinterpret_cast<int*>(small + o_rg) + gstart[J];
+            t.rvo = reinterpret_cast<long long*>(small + o_rv) + gstart[J];
+            t.vk = Cm.out.vk;
+            t.col_off = J * b;
+            t.ncol = bsz(J);
+            t.C = H.C;
+            t.ldc = H.ldc;
+            t.cpos = H.cpos;
+            t.beta = 1;
+            tiles(t);
+            s2.add(t);
+            flops += 2.0 * H.rows * t.klen * t.ncol;
+        }
+    }
+    // Upload the task lists and launch the stages in order.
+    constexpr int NS = 3;
+    Stage* stages[NS] = {&s1a, &s1b, &s2};
+    size_t to = 0;
+    std::vector<size_t> tof(NS), sof(NS);
+    for (int i = 0; i < NS; ++i) {
+        tof[i] = to; to = al(to + std::max<size_t>(stages[i]->tasks.size(), 1) * sizeof(GemmTask));
+        sof[i] = to; to = al(to + stages[i]->start.size() * sizeof(int));
+    }
+    char* tdev = nullptr;
+    std::vector<char> th(to);
+    for (int i = 0; i < NS; ++i) {
+        if (!stages[i]->tasks.empty())
+            std::memcpy(th.data() + tof[i], stages[i]->tasks.data(),
+                        stages[i]->tasks.size() * sizeof(GemmTask));
+        std::memcpy(th.data() + sof[i], stages[i]->start.data(),
+                    stages[i]->start.size() * sizeof(int));
+    }
+    if (err == hipSuccess) err = hipMallocAsync((void**)&tdev, to, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(tdev, th.data(), to, hipMemcpyHostToDevice, s);
+    for (int i = 0; i < NS && err == hipSuccess; ++i) {
+        const Stage& S = *stages[i];
+        if (S.tasks.empty()) continue;
+        const GemmTask* td = reinterpret_cast<GemmTask*>(tdev + tof[i]);
+        const int* sd = reinterpret_cast<int*>(tdev + sof[i]);
+        err = (S.kind == 0) ? dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(),
+                                                    variant, s)
+                            : dc_launch_interp_gemm(td, sd, (int)S.tasks.size(), S.start.back(),
+                                                    variant, s);
+    }
+    // The host staging vectors die with this scope: wait for the copies.
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (err == hipSuccess) err = e2;
+    if (tdev) hipFreeAsync(tdev, s);
+    if (W) hipFreeAsync(W, s);
+    if (small) hipFreeAsync(small, s);
+    hipFreeAsync(Cm.dev, s);
+    if (flops_out) *flops_out = flops;
+    return err;
+}
+
+hipError_t dc_node_arrays(int K, const double* Dbar, const int* org, const double* tau,
+                          double* cbase, double* coff, hipStream_t s) {
+    hipLaunchKernelGGL(k_nodes, dim3((K + 255) / 256), dim3(256), 0, s, K, Dbar, org, tau,
+                       cbase, coff);
+    return hipGetLastError();
+}
+
+hipError_t dc_disable_tasks(GemmTask* tasks, int n, const int* zero, hipStream_t s) {
+    hipLaunchKernelGGL(k_disable_tasks, dim3(1), dim3(64), 0, s, tasks, n, zero);
+    return hipGetLastError();
+}
+
+hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
+                             const int* org, const double* tau, const double* zhat,
+                             const double* scale, double* C, long long ldc, double lr_tol,
+                             int lr_block, hipStream_t stream) {
+    if (lr_block > MAX_B) lr_block = MAX_B;
+    double* nodes = nullptr;
+    hipError_t err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
+    if (err != hipSuccess) return err;
+    err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
+    std::vector<LrHalf> halves(1);
+    LrHalf& H = halves[0];
+    H.A = Qnd;
+    H.lda = ldq;
+    H.rows = m;
+    H.gD = Dbar;
+    H.gz = zhat;
+    H.C = C;
+    H.ldc = ldc;
+    H.cpos = nullptr;
+    H.w_row0 = 0;
+    if (err == hipSuccess)
+        err = dc_lowrank_product(K, lr_block, lr_tol, Dbar, zhat, nodes, nodes + K, scale,
+                                 halves, m, 0, stream, nullptr);
+    hipFreeAsync(nodes, stream);
+    return err;
+}
+
+extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
+                                      const double* tau, const double* zhat,
+                                      const double* scale, double lr_tol, int lr_block,
+                                      int* ranks_host, hipStream_t stream) {
+    if (K < 1) return -1;
+    if (!Dbar) return -2;
+    if (!tau) return -4;
+    if (!zhat) return -5;
+    if (!scale) return -6;
+    if (!(lr_tol > 0.0)) return -7;
+    if (lr_block <= 0) lr_block = 1024;
+    if (lr_block > MAX_B) return -8;
+    if (!ranks_host) return -9;
+    double* nodes = nullptr;
+    hipError_t err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
+    if (err != hipSuccess) return (int)err;
+    err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
+    Compressed Cm;
+    if (err == hipSuccess)
+        err = compress(K, lr_block, lr_tol, Dbar, zhat, nodes, nodes + K, scale, stream, Cm);
+    if (err == hipSuccess)
+        std::memcpy(ranks_host, Cm.rank.data(), Cm.rank.size() * sizeof(int));
+    if (Cm.dev) hipFreeAsync(Cm.dev, stream);
+    hipFreeAsync(nodes, stream);
+    hipError_t e2 = hipStreamSynchronize(stream);
+    return (int)(err != hipSuccess ? err : e2);
 }

@@ -1,6 +1,33 @@
-// Structured low-rank merge product (SRRSC compression + two generated products).
+// Structured low-rank merge product (SRRSC compression + generated products).
 #pragma once
+#include <vector>
+
 #include "common.hpp"
+
+// One row half of a merge product: C[rows, :] = A[rows, panel] * U[panel, :],
+// where panel column t holds the basis column of survivor klist[t] (klist
+// ascending; empty means the identity 0..K-1) and gD / gz are the row
+// generators in panel order.
+struct LrHalf {
+    const double* A = nullptr;
+    long long lda = 0;
+    int rows = 0;
+    std::vector<int> klist;
+    const double* gD = nullptr;
+    const double* gz = nullptr;
+    double* C = nullptr;
+    long long ldc = 0;
+    const int* cpos = nullptr;   // output column of generator g (null: g)
+    long long w_row0 = 0;        // row offset of this half inside W
+};
+
+// Low-rank product over the given halves (host-synchronising: reads the
+// ranks).  cbase/coff are the column nodes, scale the column scales.  wrows
+// is the row count of the skeleton panel W (sum of the halves' rows).
+hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
+                              const double* cbase, const double* coff, const double* scale,
+                              std::vector<LrHalf>& halves, int wrows, int variant,
+                              hipStream_t s, double* flops_out);
 
 hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
                              const int* org, const double* tau, const double* zhat,
@@ -10,3 +37,6 @@ hipError_t dc_plain_update(int m, int K, const double* Qnd, long long ldq, const
                            const int* org, const double* tau, const double* zhat,
                            const double* scale, double* C, long long ldc, int beta,
                            int variant, hipStream_t stream);
+hipError_t dc_node_arrays(int K, const double* Dbar, const int* org, const double* tau,
+                          double* cbase, double* coff, hipStream_t s);
+hipError_t dc_disable_tasks(GemmTask* tasks, int n, const int* zero, hipStream_t s);

@@ -233,6 +233,19 @@ def secular(D, z, rho, max_iter=64):
     return org, tau, zhat, scale
 
 
+def merge_lowrank_ranks(Dbar, org, tau, zhat, scale, lr_tol, lr_block):
+    """Block ranks (nb x nb numpy array, -1 diagonal, -2 kept dense)."""
+    import numpy as np
+    K = Dbar.numel()
+    nb = (K + lr_block - 1) // lr_block
+    out = (ctypes.c_int * (nb * nb))()
+    _check(load().dc_merge_lowrank_ranks(K, _ptr(Dbar), _ptr(org), _ptr(tau), _ptr(zhat),
+                                         _ptr(scale), float(lr_tol), int(lr_block),
+                                         ctypes.cast(out, ctypes.c_void_p), _stream()),
+           "dc_merge_lowrank_ranks")
+    return np.array(out[:], dtype=np.int64).reshape(nb, nb)
+
+
 def merge_update(Qnd_cm, m, K, Dbar, org, tau, zhat, scale, lr_tol=0.0, lr_block=0,
                  ldq=None, out=None, variant=None):
     """C = Qnd U with U generated from (Dbar, org, tau, zhat, scale).
