@@ -21,7 +21,9 @@ __global__ void k_write_blob(unsigned char* dst, Blob blob, int nbytes) {
 std::mutex g_status_mu;
 std::map<hipStream_t, int*> g_status;
 
-hipError_t status_word(hipStream_t s, int** out) {
+}  // namespace
+
+hipError_t dc_status_word(hipStream_t s, int** out) {
     std::lock_guard<std::mutex> lk(g_status_mu);
     auto it = g_status.find(s);
     if (it != g_status.end()) { *out = it->second; return hipSuccess; }
@@ -34,8 +36,6 @@ hipError_t status_word(hipStream_t s, int** out) {
     *out = p;
     return hipSuccess;
 }
-
-}  // namespace
 
 hipError_t dc_write_blob(void* dst, const void* src, int nbytes, hipStream_t s) {
     if (nbytes <= 0) return hipSuccess;
@@ -54,7 +54,7 @@ extern "C" int dc_stedc(int n, double* d, double* e, double* Q, int ldq, hipStre
     if (n > 0 && !Q) return -4;
     if (ldq < (n > 1 ? n : 1)) return -5;
     int* st = nullptr;
-    hipError_t err = status_word(stream, &st);
+    hipError_t err = dc_status_word(stream, &st);
     if (err != hipSuccess) return (int)err;
     const size_t lw = dc_stedc_workspace(n, nullptr);
     if (lw == 0) return (int)hipErrorInvalidValue;
@@ -69,7 +69,7 @@ extern "C" int dc_stedc(int n, double* d, double* e, double* Q, int ldq, hipStre
 
 extern "C" int dc_last_info(hipStream_t stream) {
     int* st = nullptr;
-    if (status_word(stream, &st) != hipSuccess) return (int)hipErrorUnknown;
+    if (dc_status_word(stream, &st) != hipSuccess) return (int)hipErrorUnknown;
     if (hipStreamSynchronize(stream) != hipSuccess) return (int)hipErrorUnknown;
     int v = 0;
     if (hipMemcpy(&v, st, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)

@@ -64,7 +64,7 @@ __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int 
     return lo;
 }
 
-template <int KIND, int BM, int BN, int BK, int WGM, int WGN>
+template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN>
 __global__ __launch_bounds__(WGM * WGN * 64)
 void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
                    int ntasks, int total_tiles) {
@@ -104,10 +104,18 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     const double* __restrict__ rz = T.rz;
     double cb = 0.0, co = 0.0, csj = 0.0;
     if (col_ok) {
-        cb = (KIND == 0 && T.corg) ? rD[T.corg[gcol]] : T.cbase[gcol];
-        co = T.coff ? T.coff[gcol] : 0.0;
+        if (KIND <= 1) {
+            cb = (KIND == 0 && T.corg) ? rD[T.corg[gcol]] : T.cbase[gcol];
+            co = T.coff ? T.coff[gcol] : 0.0;
+        }
         if (KIND == 0) csj = T.cs[gcol];
+        if (KIND == 3) {
+            cb = T.lam[gcol];                       // lam_c
+            co = T.lbar ? T.lbar[gcol] : 0.0;       // lbar_c
+            csj = T.Bm ? 0.0 : T.cs[gcol];          // g_c of a rank-one X
+        }
     }
+    bool equal_eig = false;
 
     // A entries this thread moves: row ar, k = ak0 + i * A_KSTEP.
     const int ar = tid % BM;
@@ -123,8 +131,8 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int j = 0; j < C_::FN; ++j) acc[i][j] = dc_double4{0.0, 0.0, 0.0, 0.0};
 
     double a_reg[C_::A_PER];
-    double d_reg[C_::B_PER];    // kind 0: row node; kind 1: y * vk
-    double z_reg[C_::B_PER];    // kind 0: row weight; kind 1: skeleton node base
+    double d_reg[C_::B_PER];    // 0: row node; 1: y * vk; 2: B entry; 3: X entry
+    double z_reg[C_::B_PER];    // 0: row weight; 1: skeleton node base; 3: lam_k
     double o_reg[KIND == 1 ? C_::B_PER : 1];   // kind 1: skeleton node offset
     int s_reg[KIND == 1 ? C_::B_PER : 1];      // kind 1: skeleton column (generator)
 
@@ -141,12 +149,19 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
             if (KIND == 0) {
                 d_reg[i] = ok ? rD[k] : 0.0;
                 z_reg[i] = ok ? rz[k] : 0.0;
-            } else {
+            } else if (KIND == 1) {
                 const int h = ok ? T.rgen[k] : 0;
                 d_reg[i] = (ok && col_ok) ? T.ry[k] * T.vk[T.rvo[k] + lcol] : 0.0;
                 z_reg[i] = ok ? T.cbase[h] : 0.0;
                 o_reg[i] = (ok && T.coff) ? T.coff[h] : 0.0;
                 s_reg[i] = ok ? h : -1;
+            } else if (KIND == 2) {
+                d_reg[i] = (ok && col_ok) ? T.Bm[(long long)gcol * T.ldb + k] : 0.0;
+            } else {
+                d_reg[i] = (ok && col_ok)
+                               ? (T.Bm ? T.Bm[(long long)gcol * T.ldb + k] : rz[k] * csj)
+                               : 0.0;
+                z_reg[i] = ok ? T.lam[k] : 0.0;
             }
         }
     };
@@ -165,9 +180,21 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
             if (KIND == 0) {
                 const double den = (d_reg[i] - cb) - co;
                 v = z_reg[i] * csj * dc_rcp(den);
-            } else {
+            } else if (KIND == 1) {
                 const double den = (z_reg[i] - cb) + (o_reg[i] - co);
                 v = (s_reg[i] == gcol) ? 1.0 : d_reg[i] * dc_rcp(den);
+            } else if (KIND == 2) {
+                v = d_reg[i];
+            } else {
+                const double den = cb - z_reg[i];          // lam_c - lam_k
+                if (kb + kk == gcol) {
+                    v = co;                                // lbar_c
+                } else if (den == 0.0) {
+                    v = 0.0;
+                    equal_eig |= (kb + kk < klen && col_ok);
+                } else {
+                    v = d_reg[i] * dc_rcp(den);
+                }
             }
             v = (kb + kk < klen && col_ok) ? v : 0.0;
             Bs[buf][kk * C_::LDB_S + bj] = v;
@@ -208,33 +235,72 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
 
     // Epilogue: for the FP64 16x16x4 MFMA, accumulator register v of a lane
     // holds row lane/16 + 4 v and column lane % 16 of the 16 x 16 block.
+    if (EPI == 0) {
 #pragma unroll
-    for (int j = 0; j < C_::FN; ++j) {
-        const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
-        if (c >= ncol) continue;
-        const int g = T.ccol ? T.ccol[c] : T.col_off + c;
-        const int oc = T.cpos ? T.cpos[T.ccol ? c : g] : g - T.out_off;
-        double* Ccol = T.C + (long long)oc * T.ldc;
+        for (int j = 0; j < C_::FN; ++j) {
+            const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
+            if (c >= ncol) continue;
+            const int g = T.ccol ? T.ccol[c] : T.col_off + c;
+            const int oc = T.cpos ? T.cpos[T.ccol ? c : g] : g - T.out_off;
+            double* Ccol = T.C + (long long)oc * T.ldc;
+#pragma unroll
+            for (int i = 0; i < C_::FM; ++i) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = row0 + wm * C_::WTM + i * 16 + (lane >> 4) + 4 * v;
+                    if (r < T.rows) {
+                        const double x = acc[i][j][v];
+                        Ccol[r] = T.beta ? Ccol[r] + x : x;
+                    }
+                }
+            }
+        }
+    } else {
+        // Band epilogue: row sums of P o Q, P o Q(+1 row), P o Q(-1 row).
+        const int part = tn * WGN + wn;
+        const long long ldq = T.ldqb;
 #pragma unroll
         for (int i = 0; i < C_::FM; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = row0 + wm * C_::WTM + i * 16 + (lane >> 4) + 4 * v;
+                double sd = 0.0, su = 0.0, sl = 0.0;
                 if (r < T.rows) {
-                    const double x = acc[i][j][v];
-                    Ccol[r] = T.beta ? Ccol[r] + x : x;
+#pragma unroll
+                    for (int j = 0; j < C_::FN; ++j) {
+                        const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
+                        if (c >= ncol) continue;
+                        const double x = acc[i][j][v];
+                        const double* q = T.Qb + (long long)c * ldq + r;
+                        sd += x * q[0];
+                        if (r + 1 < T.nband) su += x * q[1];
+                        if (r > 0) sl += x * q[-1];
+                    }
+                }
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    sd += __shfl_xor(sd, off, 64);
+                    su += __shfl_xor(su, off, 64);
+                    sl += __shfl_xor(sl, off, 64);
+                }
+                if ((lane & 15) == 0 && r < T.rows) {
+                    const long long o = (long long)part * T.nband + r;
+                    T.pd[o] = sd;
+                    T.pu[o] = su;
+                    T.pl[o] = sl;
                 }
             }
         }
     }
+    if (KIND == 3 && equal_eig && T.flag) atomicOr(T.flag, 1);
 }
 
-template <int KIND, int BM, int BN, int BK, int WGM, int WGN>
+template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN>
 hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
                   hipStream_t s) {
     int grid = (total + 7) & ~7;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cauchy_gemm<KIND, BM, BN, BK, WGM, WGN>), dim3(grid),
+    hipLaunchKernelGGL((k_cauchy_gemm<KIND, EPI, BM, BN, BK, WGM, WGN>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
     return hipGetLastError();
 }
@@ -243,10 +309,10 @@ template <int KIND>
 hipError_t launch_variant(const GemmTask* tasks, const int* tile_start, int ntasks,
                           int total, int variant, hipStream_t s) {
     switch (variant) {
-        case 1: return launch<KIND, 128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
-        case 2: return launch<KIND, 64, 64, 16, 1, 1>(tasks, tile_start, ntasks, total, s);
-        case 3: return launch<KIND, 128, 128, 32, 2, 2>(tasks, tile_start, ntasks, total, s);
-        default: return launch<KIND, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+        case 1: return launch<KIND, 0, 128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
+        case 2: return launch<KIND, 0, 64, 64, 16, 1, 1>(tasks, tile_start, ntasks, total, s);
+        case 3: return launch<KIND, 0, 128, 128, 32, 2, 2>(tasks, tile_start, ntasks, total, s);
+        default: return launch<KIND, 0, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
     }
 }
 
@@ -279,3 +345,15 @@ hipError_t dc_launch_interp_gemm(const GemmTask* tasks, const int* tile_start, i
                                  int total, int variant, hipStream_t s) {
     return launch_variant<1>(tasks, tile_start, ntasks, total, variant, s);
 }
+
+hipError_t dc_launch_loaded_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
+                                 int total, hipStream_t s) {
+    return launch<2, 0, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+}
+
+hipError_t dc_launch_adjoint_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
+                                  int total, hipStream_t s) {
+    return launch<3, 1, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+}
+
+int dc_band_waves_n() { return 2; }

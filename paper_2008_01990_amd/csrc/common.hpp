@@ -80,6 +80,27 @@ struct GemmTask {
     const int* rgen;
     const long long* rvo;
     const double* vk;
+    // kind 2: B loaded, B_kc = Bm[k + c ldb].
+    // kind 3 (adjoint, M = diag(lbar) + F o G with F_kc = 1/(lam_c - lam_k)):
+    //   B_kc = lbar[c] on the diagonal (k == c, lbar may be null = 0), else
+    //   X_kc / (lam_c - lam_k), X_kc = Bm[k + c ldb] if Bm is set, else
+    //   rz[k] * cs[c]; equal eigenvalues give 0 and set *flag.
+    const double* Bm;
+    long long ldb;
+    const double* lam;
+    const double* lbar;
+    int* flag;
+    // band epilogue: instead of storing C, row r of the tile product P adds
+    //   P[r, c] Q[r, c]    to pd[part][r],
+    //   P[r, c] Q[r+1, c]  to pu[part][r],
+    //   P[r, c] Q[r-1, c]  to pl[part][r],
+    // part = column tile * waves per row + wave column, parts of length nband.
+    const double* Qb;
+    long long ldqb;
+    int nband;
+    double* pd;
+    double* pu;
+    double* pl;
 };
 
 // Host-side launcher of the generated-Cauchy product over a task list.
@@ -93,5 +114,13 @@ hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks_dev, const int* tile_star
 hipError_t dc_launch_interp_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
                                  int ntasks, int total_tiles, int variant,
                                  hipStream_t stream);
+// Kind-2 (loaded B) product with the ordinary epilogue.
+hipError_t dc_launch_loaded_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
+                                 int ntasks, int total_tiles, hipStream_t stream);
+// Kind-3 (adjoint M) product with the band epilogue; the number of partial
+// sums per row is tiles_n * dc_band_waves_n().
+hipError_t dc_launch_adjoint_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
+                                  int ntasks, int total_tiles, hipStream_t stream);
+int dc_band_waves_n();
 int dc_gemm_tile_m(int variant);
 int dc_gemm_tile_n(int variant);

@@ -264,3 +264,72 @@ def merge_update(Qnd_cm, m, K, Dbar, org, tau, zhat, scale, lr_tol=0.0, lr_block
         _check(load().dc_merge_update(*args, float(lr_tol), int(lr_block), _stream()),
                "dc_merge_update")
     return C
+
+
+def backward(lam, Qbuf, lam_bar=None, Qbar_cm=None):
+    """(d_bar, e_bar) of (lam, Q) = eig(T); Qbuf / Qbar_cm are column-major
+    storages ((n, ld) row-major buffers)."""
+    n = lam.numel()
+    d_bar = torch.empty(n, dtype=torch.float64, device="cuda")
+    e_bar = torch.empty(max(n - 1, 1), dtype=torch.float64, device="cuda")
+    _check(load().dc_stedc_backward(n, _ptr(lam), _ptr(Qbuf), Qbuf.shape[1],
+                                    _ptr(lam_bar), _ptr(Qbar_cm),
+                                    Qbar_cm.shape[1] if Qbar_cm is not None else n,
+                                    _ptr(d_bar), _ptr(e_bar), _stream()),
+           "dc_stedc_backward")
+    return d_bar, e_bar[:max(n - 1, 0)]
+
+
+def backward_rank1(lam, Qbuf, u, g, lam_bar=None):
+    """Gradient for Q_bar = u g^T (rank one)."""
+    n = lam.numel()
+    d_bar = torch.empty(n, dtype=torch.float64, device="cuda")
+    e_bar = torch.empty(max(n - 1, 1), dtype=torch.float64, device="cuda")
+    _check(load().dc_stedc_backward_rank1(n, _ptr(lam), _ptr(Qbuf), Qbuf.shape[1],
+                                          _ptr(lam_bar), _ptr(_dev(u)), _ptr(_dev(g)),
+                                          _ptr(d_bar), _ptr(e_bar), _stream()),
+           "dc_stedc_backward_rank1")
+    return d_bar, e_bar[:max(n - 1, 0)]
+
+
+def backward_status():
+    """Status word of the last backward call on the current stream."""
+    return load().dc_last_info(_stream())
+
+
+class EighTridiagonal(torch.autograd.Function):
+    """(lam, Q) = eig(T(d, e)) with the library's adjoint as backward.
+
+    forward: dc_stedc_ex; backward: dc_stedc_backward on the saved final
+    (lam, Q) only -- no per-level state is kept.
+    """
+
+    @staticmethod
+    def forward(ctx, d, e, leaf=32, lr_tol=0.0, lr_block=1024, lr_min_k=4096):
+        n = d.numel()
+        s = Solver(n, leaf=leaf, lr_tol=lr_tol, lr_block=lr_block, lr_min_k=lr_min_k)
+        lam = d.detach().to("cuda", torch.float64).clone().contiguous()
+        ee = (e.detach().to("cuda", torch.float64).clone().contiguous() if n > 1
+              else torch.zeros(1, dtype=torch.float64, device="cuda"))
+        Qbuf = torch.empty(max(n, 1), max(n, 1), dtype=torch.float64, device="cuda")
+        s.solve_into(lam, ee, Qbuf)
+        st = s.status()
+        if st != 0:
+            raise DcError(f"device status {st}: {load().dc_strerror(st).decode()}")
+        ctx.save_for_backward(lam, Qbuf)
+        return lam.clone(), from_colmajor(Qbuf, n)
+
+    @staticmethod
+    def backward(ctx, lam_bar, Q_bar):
+        lam, Qbuf = ctx.saved_tensors
+        lb = lam_bar.contiguous() if lam_bar is not None else None
+        qb = Q_bar.t().contiguous() if Q_bar is not None else None
+        d_bar, e_bar = backward(lam, Qbuf, lb, qb)
+        return d_bar, e_bar, None, None, None, None
+
+
+def eigh_tridiagonal(d, e, **kw):
+    """Differentiable (lam ascending, Q) of the symmetric tridiagonal T(d, e)."""
+    return EighTridiagonal.apply(d, e, *[kw.get(k, v) for k, v in
+                                         (("leaf", 32), ("lr_tol", 0.0), ("lr_block", 1024),
+                                          ("lr_min_k", 4096))])
