@@ -35,12 +35,13 @@ struct Level {
     int tiles;          // worst-case product tiles
     int sec_blocks, row_blocks, copy_blocks, gather_blocks;
     int max_m;          // largest merge of the level
+    int variant, bm, bn;   // product tile shape of the level
     int off_tile, off_sec, off_row, off_copy, off_gather;   // offsets into the prefix array
 };
 
 struct Plan {
     std::vector<int> sizes;
-    int leaf, bm, bn;
+    int leaf, tile;
     std::vector<Node> leaves, merges;   // merges ordered by level, deepest first
     std::vector<Level> levels;
     std::vector<int> prefix;            // all per-level prefix sums
@@ -69,12 +70,20 @@ void split(std::vector<std::vector<Node>>& by_depth, std::vector<Node>& leaves, 
     by_depth[depth].push_back(Node{prob, off, k, m - k, depth, -1});
 }
 
-std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int bm, int bn) {
+// Product tile shape of a level: a forced variant, or by the level's largest
+// merge (small merges waste most of a 256 x 128 tile).
+int level_variant(int forced, int max_m) {
+    if (forced > 0) return forced;
+    if (max_m <= 256) return 2;
+    if (max_m <= 1024) return 1;
+    return 0;
+}
+
+std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int tile) {
     auto P = std::make_unique<Plan>();
     P->sizes = sizes;
     P->leaf = leaf;
-    P->bm = bm;
-    P->bn = bn;
+    P->tile = tile;
     std::vector<std::vector<Node>> by_depth;
     for (size_t p = 0; p < sizes.size(); ++p) {
         P->row0.push_back(P->rows);
@@ -95,6 +104,10 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int bm,
         L.max_m = 0;
         for (int i = 0; i < L.nm; ++i)
             L.max_m = std::max(L.max_m, P->merges[L.first + i].n1 + P->merges[L.first + i].n2);
+        L.variant = level_variant(tile, L.max_m);
+        L.bm = dc_gemm_tile_m(L.variant);
+        L.bn = dc_gemm_tile_n(L.variant);
+        const int bm = L.bm, bn = L.bn;
         auto& pre = P->prefix;
         L.off_tile = (int)pre.size();
         int acc = 0;
@@ -152,13 +165,12 @@ hipError_t upload(Plan& P) {
 std::mutex g_plan_mu;
 std::map<std::vector<int>, std::unique_ptr<Plan>> g_plans;
 
-// Plans are keyed by (device, leaf, tile shape, sizes).
+// Plans are keyed by (device, leaf, tile option, sizes).
 hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan** out) {
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return err;
-    const int bm = dc_gemm_tile_m(variant), bn = dc_gemm_tile_n(variant);
-    std::vector<int> key{dev, leaf, bm, bn};
+    std::vector<int> key{dev, leaf, variant};
     key.insert(key.end(), sizes.begin(), sizes.end());
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
@@ -166,7 +178,7 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
         *out = it->second.get();
         return hipSuccess;
     }
-    auto P = make_plan(sizes, leaf, bm, bn);
+    auto P = make_plan(sizes, leaf, variant);
     err = upload(*P);
     if (err != hipSuccess) return err;
     *out = P.get();
@@ -294,7 +306,7 @@ hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Sc
         double flops = 0.0;
         err = dc_lowrank_product(C.K, b, o.lr_tol, S.Dbar + base, S.zhat + base,
                                  S.cbase + base, S.tau + base, S.scale + base, halves,
-                                 N.n1 + N.n2, o.gemm_tile, s, &flops);
+                                 N.n1 + N.n2, 0, s, &flops);
         if (err != hipSuccess) return err;
         err = dc_disable_tasks(S.gtask + 2 * N.slot, 2, &S.cnt[N.slot].pad_[0], s);
         if (err != hipSuccess) return err;
@@ -314,8 +326,10 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
     if (err != hipSuccess) return err;
     const Node* d_leaves = P.d_nodes;
     const Node* d_merges = P.d_nodes + P.leaves.size();
-    err = dc_launch_build(d_merges, (int)P.merges.size(), P.bm, P.bn, S, s);
-    if (err != hipSuccess) return err;
+    for (const Level& Lv : P.levels) {
+        err = dc_launch_build(d_merges + Lv.first, Lv.nm, Lv.bm, Lv.bn, S, s);
+        if (err != hipSuccess) return err;
+    }
     err = dc_launch_leaf(d_leaves, (int)P.leaves.size(), S, s);
     if (err != hipSuccess) return err;
     g_ev_levels = (int)P.levels.size();
@@ -338,7 +352,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         if (o.lr_tol > 0.0 && Lv.max_m > o.lr_min_k)
             DC_TRY(lowrank_level(P, probs, S, Lv.first, Lv.nm, o, s));
         DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
-                                     2 * Lv.nm, Lv.tiles, o.gemm_tile, s));
+                                     2 * Lv.nm, Lv.tiles, Lv.variant, s));
         DC_TRY(prof_mark(li, 5, s));
         DC_TRY(dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks,
                                        S, s));
@@ -502,7 +516,8 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
         pr.info = info_dev + p;
         pr.pad_ = 0;
     }
-    if (!use_graph) {
+    // The low-rank switch reads sizes on the host and cannot be captured.
+    if (!use_graph || o.lr_tol > 0.0) {
         err = (hipError_t)dc_fill_int(info_dev, count, 0, stream);
         if (err != hipSuccess) return (int)err;
         return (int)run_plan(*P, probs, w, o, stream);
@@ -526,8 +541,11 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
         if (err != hipSuccess) return (int)err;
         err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
+            const bool prof = g_prof;
+            g_prof = false;                  // no event records inside the graph
             hipError_t e1 = dc_fill_int(info_dev, count, 0, cap);
             if (e1 == hipSuccess) e1 = run_plan(*P, G->probs, w, o, cap);
+            g_prof = prof;
             hipGraph_t graph = nullptr;
             err = hipStreamEndCapture(cap, &graph);
             if (e1 != hipSuccess) err = e1;

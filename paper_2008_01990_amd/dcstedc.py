@@ -333,3 +333,60 @@ def eigh_tridiagonal(d, e, **kw):
     return EighTridiagonal.apply(d, e, *[kw.get(k, v) for k, v in
                                          (("leaf", 32), ("lr_tol", 0.0), ("lr_block", 1024),
                                           ("lr_min_k", 4096))])
+
+
+class BatchedSolver:
+    """Workspace and pointer tables for one batch of tridiagonal problems.
+
+    solve() runs dc_stedc_batched (level schedule replayed as a HIP graph);
+    solve(graph=False) runs the same schedule eagerly.
+    """
+
+    def __init__(self, sizes, leaf=32, gemm_tile=0, lr_tol=0.0, lr_block=1024, lr_min_k=4096):
+        self.sizes = [int(v) for v in sizes]
+        self.count = len(self.sizes)
+        self.o = opts(leaf=leaf, gemm_tile=gemm_tile, lr_tol=lr_tol, lr_block=lr_block,
+                      lr_min_k=lr_min_k)
+        lib = load()
+        self.n_host = (ctypes.c_int * max(self.count, 1))(*self.sizes)
+        self.lwork = lib.dc_stedc_batched_workspace(self.count, self.n_host,
+                                                    ctypes.byref(self.o))
+        if self.lwork == 0 and self.count > 0:
+            raise DcError("dc_stedc_batched_workspace failed")
+        self.work = torch.empty(max(self.lwork, 256) // 8 + 32, dtype=torch.float64,
+                                device="cuda")
+        self.info = torch.zeros(max(self.count, 1), dtype=torch.int32, device="cuda")
+        self.d = [torch.zeros(max(n, 1), dtype=torch.float64, device="cuda") for n in self.sizes]
+        self.e = [torch.zeros(max(n - 1, 1), dtype=torch.float64, device="cuda")
+                  for n in self.sizes]
+        self.Q = [torch.empty(max(n, 1), max(n, 1), dtype=torch.float64, device="cuda")
+                  for n in self.sizes]
+        P = ctypes.c_void_p
+        self.dp = (P * max(self.count, 1))(*[t.data_ptr() for t in self.d])
+        self.ep = (P * max(self.count, 1))(*[t.data_ptr() for t in self.e])
+        self.qp = (P * max(self.count, 1))(*[t.data_ptr() for t in self.Q])
+        self.ldq = (ctypes.c_int * max(self.count, 1))(*[max(n, 1) for n in self.sizes])
+
+    def load_inputs(self, problems):
+        for i, (d, e) in enumerate(problems):
+            n = self.sizes[i]
+            if n:
+                self.d[i][:n].copy_(torch.as_tensor(d))
+            if n > 1:
+                self.e[i][:n - 1].copy_(torch.as_tensor(e))
+
+    def solve(self, graph=True):
+        lib = load()
+        fn = lib.dc_stedc_batched if graph else lib.dc_stedc_batched_eager
+        addr = self.work.data_ptr()
+        rc = fn(self.count, self.n_host, self.dp, self.ep, self.qp, self.ldq,
+                ctypes.c_void_p((addr + 255) & ~255), self.lwork, _ptr(self.info),
+                ctypes.byref(self.o), _stream())
+        _check(rc, "dc_stedc_batched")
+
+    def result(self, i):
+        n = self.sizes[i]
+        return self.d[i][:n], from_colmajor(self.Q[i], n)
+
+    def status(self):
+        return self.info[:self.count].cpu().tolist()
