@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary configurations (n=1024, n=16384, batched, adjoint)")
     return ap.parse_args()
 
 
@@ -99,6 +103,110 @@ def cpu_baseline(family, n_full, n_sample, leaf):
             "sample_seconds": dt}
 
 
+def measured_traffic(workload):
+    """HBM bytes per root-level product launch from the committed counter
+    summary, or None if it was taken on another workload or on a different
+    version of the kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_cauchy_gemm_clement_n32768_traffic.md")
+    src = os.path.join(ROOT, "paper_2008_01990_amd", "csrc", "cauchy_gemm.hip")
+    if workload != "clement_n32768_leaf64_plain" or not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC_JSON "):
+            rec = json.loads(line[len("TRAFFIC_JSON "):])
+    if rec is None:
+        return None
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return rec["traffic_bytes"] if h == rec["source_sha256_16"] else None
+
+
+def _time(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def extra_configs(L, torch):
+    """Secondary configurations, each timed on the GPU after a warm-up."""
+    import numpy as np
+    from paper_2008_01990_amd import workloads as W
+    res = {}
+    # n=1024 1-2-1 Toeplitz, leaf 32 (latency-bound correctness config)
+    d0, e0 = W.toeplitz(1024)
+    d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
+    d = torch.empty_like(d_in)
+    Qb = torch.empty(1024, 1024, dtype=torch.float64, device="cuda")
+    s = L.Solver(1024, leaf=32)
+
+    def c0():
+        d.copy_(d_in)
+        s.solve_into(d, e, Qb)
+    t = _time(c0, 20, torch)
+    res["toeplitz_n1024_leaf32"] = {"seconds": t, "accuracy": gpu_accuracy(d_in, e, d, Qb, "toeplitz")}
+    # n=16384 Toeplitz, leaf 64: plain vs low rank at 1e-10
+    n = 16384
+    d0, e0 = W.toeplitz(n)
+    d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
+    d = torch.empty_like(d_in)
+    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    r = {}
+    for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=1024, lr_min_k=4096))):
+        s = L.Solver(n, leaf=64, **kw)
+
+        def c1():
+            d.copy_(d_in)
+            s.solve_into(d, e, Qb)
+        t = _time(c1, 3, torch)
+        r[name] = {"seconds": t, "accuracy": gpu_accuracy(d_in, e, d, Qb, "toeplitz")}
+        del s
+    r["lowrank_speedup"] = r["plain"]["seconds"] / r["lowrank"]["seconds"]
+    res["toeplitz_n16384_leaf64"] = r
+    del Qb
+    torch.cuda.empty_cache()
+    # batched: 256 problems, sizes log-uniform in [64, 4096], d, e ~ U(-1, 1)
+    probs = W.batched_problems(256, 64, 4096, seed=3)
+    sizes = [len(p[0]) for p in probs]
+    B = L.BatchedSolver(sizes, leaf=32)
+    B.load_inputs(probs)
+    tg = _time(lambda: B.solve(graph=True), 5, torch)
+    te = _time(lambda: B.solve(graph=False), 5, torch)
+    res["batched_256_loguniform_64_4096"] = {
+        "seconds_graph": tg, "seconds_eager": te, "problems": len(sizes),
+        "sum_n": int(sum(sizes)), "status_ok": all(v == 0 for v in B.status())}
+    del B
+    torch.cuda.empty_cache()
+    # adjoint: n=4096, loss sum w lam + sum c (u^T q)^2
+    P = W.adjoint_problem(n=4096, seed=4, n_coords=32)
+    n = 4096
+    dd, ee = torch.tensor(P["d"], device="cuda"), torch.tensor(P["e"], device="cuda")
+    w, c, u = (torch.tensor(P[k], device="cuda") for k in ("w", "c", "u"))
+    s = L.Solver(n, leaf=32)
+    lam = dd.clone()
+    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
+
+    def fwd():
+        lam.copy_(dd)
+        s.solve_into(lam, ee, Qb)
+    tf = _time(fwd, 5, torch)
+    Q = Qb.t()
+    a = u @ Q
+    g = 2 * c * a
+    tb1 = _time(lambda: L.backward_rank1(lam, Qb, u, g, lam_bar=w), 5, torch)
+    Qbar_cm = torch.outer(u, g).t().contiguous()
+    tbg = _time(lambda: L.backward(lam, Qb, w, Qbar_cm), 5, torch)
+    res["adjoint_n4096"] = {"forward_seconds": tf, "backward_rank1_seconds": tb1,
+                            "backward_general_seconds": tbg,
+                            "backward_general_tflops": 4.0 * n ** 3 / tbg / 1e12,
+                            "backward_rank1_tflops": 2.0 * n ** 3 / tb1 / 1e12}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -111,6 +219,15 @@ def main():
     from paper_2008_01990_amd import dcstedc as L
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # A plain copy of known size: 2^27 doubles (1 GiB) read and written once.
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8}), flush=True)
+        return
     n = args.n
     d0, e0 = inputs(args.family, n)
     d_in = torch.tensor(d0, device="cuda")
@@ -180,7 +297,8 @@ def main():
                    "family": args.family, "leaf": args.leaf, "path": "plain"},
         "roofline": {"bound": "mfma", "achieved": achieved,
                      "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_MFMA_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+                     "traffic": measured_traffic(f"{args.family}_n{n}_leaf{args.leaf}_plain"),
                      "kernel": "k_cauchy_gemm (root-level merge product)",
                      "flops_per_launch": flops_lvl[-1],
                      "launch_ms": top["product_ms"]},
@@ -235,6 +353,8 @@ def main():
             out["lowrank"]["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
     del Qbuf
     torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["extra_configs"] = extra_configs(L, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.family, n, args.cpu_n, args.leaf)
     print(json.dumps(out), flush=True)

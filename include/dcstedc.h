@@ -52,7 +52,8 @@ typedef struct dc_opts {
     int lr_min_k;    /* use the low-rank merge only when the deflated size K
                         reaches this (Algorithm 3's "size of M is large");
                         default 4096 */
-    int max_iter;    /* secular iteration cap (default 64) */
+    int max_iter;    /* secular iteration cap (default 200: enough for pure
+                        bisection to reach 4-ulp relative accuracy) */
     int gemm_tile;   /* merge-product tile variant, 0 = automatic */
 } dc_opts;
 

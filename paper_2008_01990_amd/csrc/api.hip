@@ -97,7 +97,7 @@ extern "C" int dc_secular(int K, const double* Dbar, const double* zbar, double 
     if (!tau) return -6;
     if (!zhat) return -7;
     if (!scale) return -8;
-    if (max_iter <= 0) max_iter = 64;
+    if (max_iter <= 0) max_iter = 200;
     const int nblk = (K + DC_ROOTS_PER_BLOCK - 1) / DC_ROOTS_PER_BLOCK;
     const size_t off_bs = 256, off_cb = 512;
     char* tmp = nullptr;

@@ -393,7 +393,7 @@ extern "C" void dc_opts_default(dc_opts* o) {
     o->lr_tol = 0.0;
     o->lr_block = 1024;
     o->lr_min_k = 4096;
-    o->max_iter = 64;
+    o->max_iter = 200;
     o->gemm_tile = 0;
 }
 

@@ -109,7 +109,7 @@ def _dev(t, dtype=torch.float64):
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
-def opts(leaf=32, lr_tol=0.0, lr_block=1024, lr_min_k=4096, max_iter=64, gemm_tile=0):
+def opts(leaf=32, lr_tol=0.0, lr_block=1024, lr_min_k=4096, max_iter=200, gemm_tile=0):
     o = DcOpts()
     load().dc_opts_default(ctypes.byref(o))
     o.leaf, o.lr_tol, o.lr_block = leaf, lr_tol, lr_block
@@ -214,7 +214,7 @@ def profile_read():
     return [dict(zip(PHASES, buf[6 * i:6 * i + 6])) for i in range(nl)]
 
 
-def secular(D, z, rho, max_iter=64):
+def secular(D, z, rho, max_iter=200):
     """(org, tau, zhat, scale) of diag(D) + rho z z^T."""
     D = _dev(D)
     z = _dev(z)

@@ -98,3 +98,34 @@ def test_batched_equals_single_solves(lib):
         dots = (Q_b * Q_s).sum(0).abs()
         # eigenvectors agree up to sign where the spectrum is not clustered
         assert float((dots - 1).abs().median()) <= 1e-10
+
+
+def test_batched_full_configuration(lib):
+    # 256 problems, sizes log-uniform in [64, 4096], d, e ~ U(-1, 1), seed 3:
+    # every status clean; orthogonality and residual of every problem checked
+    # on the GPU (plain torch ops); the three smallest against the oracle.
+    probs = W.batched_problems(256, 64, 4096, seed=3)
+    sizes = [len(p[0]) for p in probs]
+    announce(f"batched full configuration sum_n={sum(sizes)}")
+    B = lib.BatchedSolver(sizes, leaf=32)
+    B.load_inputs(probs)
+    B.solve(graph=True)
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in B.status())
+    for i, (d, e) in enumerate(probs):
+        lam, Q = B.result(i)
+        n = sizes[i]
+        dd, ee = cuda(d), cuda(e)
+        TQ = dd[:, None] * Q
+        TQ[:-1] += ee[:, None] * Q[1:]
+        TQ[1:] += ee[:, None] * Q[:-1]
+        tn = float(lam.abs().max())
+        res = float(torch.linalg.norm(TQ - Q * lam[None, :])) / (n * tn)
+        G = Q.t() @ Q
+        G.diagonal().sub_(1.0)
+        assert res <= 1e-14 and float(G.abs().max()) <= 1e-12
+        assert bool((lam[1:] >= lam[:-1]).all())
+    for i in np.argsort(sizes)[:3]:
+        d, e = probs[i]
+        lam, Q = B.result(int(i))
+        _check(np.asarray(d), np.asarray(e), host(lam), host(Q), 32)
