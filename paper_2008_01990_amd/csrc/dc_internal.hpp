@@ -41,7 +41,8 @@ struct MergeCnt {
     int ndefl;          // deflated eigenpairs
     int ntop;           // survivors with non-zeros in the top rows
     int nbot;           // survivors with non-zeros in the bottom rows
-    int pad_[3];        // pad_[0] stays 0: a disabled product task points here
+    int nchain;         // rotation chains (a chain shares columns only inside itself)
+    int pad_[2];        // pad_[0] stays 0: a disabled product task points here
 };
 
 // Per-row scratch (indexed by prob.row0 + node.off + local index) and
@@ -59,6 +60,7 @@ struct Scratch {
     int *org;                   // root origin (K)
     int *dcol, *dtype;          // deflated -> local column, row-type bits
     int *rp, *ri, *rt;          // rotation column pair and row-type bits (p | i << 2)
+    int *rch;                   // first rotation of each rotation chain
     int *ktop, *kbot;           // generator lists of the top and bottom row halves
     int *pos_root, *pos_defl;   // output column of each root / deflated pair
     MergeCnt* cnt;              // per merge slot
@@ -94,4 +96,5 @@ hipError_t dc_launch_set_probs(const Prob* host_probs, int count, Prob* dev, hip
 #define DC_ROWS_PER_BLOCK 256
 #define DC_COLS_PER_BLOCK 4
 #define DC_GATHER_COLS 4
+#define DC_ROT_CHAINS 8     // rotation chains per block of the rotation kernel
 #define DC_ROOTS_PER_BLOCK 64

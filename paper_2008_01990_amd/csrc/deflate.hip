@@ -158,6 +158,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
             cnt->ndefl = m;
             cnt->ntop = 0;
             cnt->nbot = 0;
+            cnt->nchain = 0;
             cnt->pad_[0] = 0;
             S.rho2[N.slot] = 0.0;
         }
@@ -187,7 +188,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     __syncthreads();
 
     // Sequential deflation walk (lane 0), chunks staged through LDS.
-    int K = 0, nrot = 0, nd = 0;
+    int K = 0, nrot = 0, nd = 0, nch = 0;
     int p = -1, colp = 0, typp = 0;
     double Dp = 0.0, zp = 0.0, lastd = -INFINITY;
     auto emit_deflated = [&](double v, int col, int typ) {
@@ -232,10 +233,19 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
                     p = c0 + ii; Dp = Di; zp = zi; colp = coli; typp = typi;
                     continue;
                 }
-                const double r = hypot(zp, zi);
-                const double c = zi / r;
-                const double s = zp / r;
-                if (fabs((Di - Dp) * c * s) <= tol) {
+                // |(D_i - D_p) c s| <= tol with (c, s) = (z_i, z_p) / r, multiplied
+                // out by r^2 = z_p^2 + z_i^2 so that the common case (no
+                // rotation) needs no square root or reciprocal.  |z| <= 1 and
+                // surviving z are far above underflow.
+                const double r2 = zp * zp + zi * zi;
+                if (fabs(Di - Dp) * fabs(zi * zp) <= tol * r2) {
+                    const double r = sqrt(r2);
+                    const double ir = dc_rcp(r);
+                    const double c = zi * ir;
+                    const double s = zp * ir;
+                    // a new chain unless this rotation's first column is the
+                    // previous rotation's second one
+                    if (nrot == 0 || S.ri[base + nrot - 1] != colp) S.rch[base + nch++] = nrot;
                     S.rp[base + nrot] = colp;
                     S.ri[base + nrot] = coli;
                     S.rc[base + nrot] = c;
@@ -273,6 +283,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         cnt->K = K;
         cnt->nrot = nrot;
         cnt->ndefl = nd;
+        cnt->nchain = nch;
         cnt->pad_[0] = 0;
         S.rho2[N.slot] = rho2;
         s_K = K;
@@ -308,18 +319,39 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     }
 }
 
-// Apply the pair rotations of each merge to its basis, in order.  Thread r
-// owns row r of the merge block; entries outside a column's row type are
+// Apply the pair rotations of each merge to its basis.  In the deflation
+// walk a column is shared only by consecutive rotations (the rotated survivor
+// becomes the next candidate), so the rotations split into independent chains
+// whose first elements the walk records.  A thread owns one row of the merge
+// block and DC_ROT_CHAINS chains: the first rotation of every chain is loaded
+// up front, each chain is then carried through in registers, and only final
+// column values are stored.  Entries outside a column's row type are
 // structural zeros.
+__device__ __forceinline__ void rot_apply(int ty, int rbit, double c, double s, double& qp,
+                                          double& qi) {
+    const bool inp = (ty & rbit) != 0;
+    const bool ini = ((ty >> 2) & rbit) != 0;
+    if (inp || ini) {
+        const double a = qp, b = qi;
+        qp = c * a - s * b;
+        qi = s * a + c * b;
+    }
+}
+
 __global__ __launch_bounds__(DC_ROWS_PER_BLOCK)
 void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
               Scratch S) {
     const int mi = block_of(blk_start, nm, blockIdx.x);
     const Node N = merges[mi];
-    const int nrot = S.cnt[N.slot].nrot;
-    if (nrot == 0) return;
-    const int r = (blockIdx.x - blk_start[mi]) * DC_ROWS_PER_BLOCK + threadIdx.x;
+    const MergeCnt C = S.cnt[N.slot];
+    if (C.nrot == 0) return;
     const int m = N.n1 + N.n2;
+    const int nrb = (m + DC_ROWS_PER_BLOCK - 1) / DC_ROWS_PER_BLOCK;
+    const int local = blockIdx.x - blk_start[mi];
+    const int cg = local / nrb;
+    const int ch0 = cg * DC_ROT_CHAINS;
+    if (ch0 >= C.nchain) return;
+    const int r = (local - cg * nrb) * DC_ROWS_PER_BLOCK + threadIdx.x;
     if (r >= m) return;
     const Prob P = S.probs[N.prob];
     const long long base = (long long)P.row0 + N.off;
@@ -327,21 +359,42 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     double* Qi = node_buf(P, N.depth + 1, ld);
     double* row = Qi + (long long)N.off * ld + N.off + r;
     const int rbit = r < N.n1 ? 1 : 2;
-    for (int t = 0; t < nrot; ++t) {
-        const int cp = S.rp[base + t];
-        const int ci = S.ri[base + t];
-        const double c = S.rc[base + t];
-        const double s = S.rs[base + t];
-        const int ty = S.rt[base + t];
-        const bool inp = (ty & rbit) != 0;
-        const bool ini = ((ty >> 2) & rbit) != 0;
-        if (!(inp || ini)) continue;
-        double* ap = row + (long long)cp * ld;
-        double* ai = row + (long long)ci * ld;
-        const double qp = inp ? *ap : 0.0;
-        const double qi = ini ? *ai : 0.0;
-        *ap = c * qp - s * qi;
-        *ai = s * qp + c * qi;
+    int t0[DC_ROT_CHAINS], t1[DC_ROT_CHAINS];
+    double vp[DC_ROT_CHAINS], vi[DC_ROT_CHAINS];
+#pragma unroll
+    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+        const int ch = ch0 + q;
+        t0[q] = ch < C.nchain ? S.rch[base + ch] : 0;
+        t1[q] = ch < C.nchain ? (ch + 1 < C.nchain ? S.rch[base + ch + 1] : C.nrot) : 0;
+    }
+    // first rotation of every chain: loads issued together
+#pragma unroll
+    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+        vp[q] = 0.0;
+        vi[q] = 0.0;
+        if (t0[q] < t1[q]) {
+            const int ty = S.rt[base + t0[q]];
+            if (ty & rbit) vp[q] = row[(long long)S.rp[base + t0[q]] * ld];
+            if ((ty >> 2) & rbit) vi[q] = row[(long long)S.ri[base + t0[q]] * ld];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+        for (int t = t0[q]; t < t1[q]; ++t) {
+            const int ty = S.rt[base + t];
+            double a = vp[q];
+            double b = vi[q];
+            if (t > t0[q]) {            // the previous second column is this first one
+                a = vi[q];
+                b = ((ty >> 2) & rbit) ? row[(long long)S.ri[base + t] * ld] : 0.0;
+            }
+            rot_apply(ty, rbit, S.rc[base + t], S.rs[base + t], a, b);
+            if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)S.rp[base + t] * ld] = a;
+            vp[q] = a;
+            vi[q] = b;
+            if (t + 1 == t1[q] && (((ty & rbit) || ((ty >> 2) & rbit))))
+                row[(long long)S.ri[base + t] * ld] = b;
+        }
     }
 }
 

@@ -33,10 +33,10 @@ struct Level {
     int first;          // first merge (slot) of the level
     int nm;
     int tiles;          // worst-case product tiles
-    int sec_blocks, row_blocks, copy_blocks, gather_blocks;
+    int sec_blocks, row_blocks, copy_blocks, gather_blocks, rot_blocks;
     int max_m;          // largest merge of the level
     int variant, bm, bn;   // product tile shape of the level
-    int off_tile, off_sec, off_row, off_copy, off_gather;   // offsets into the prefix array
+    int off_tile, off_sec, off_row, off_copy, off_gather, off_rot;   // prefix offsets
 };
 
 struct Plan {
@@ -137,6 +137,20 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
         add(DC_ROWS_PER_BLOCK, L.off_row, L.row_blocks);
         add(DC_COLS_PER_BLOCK, L.off_copy, L.copy_blocks);
         add(DC_GATHER_COLS, L.off_gather, L.gather_blocks);
+        // rotations: (row blocks) x (chain groups); at most m/2 chains
+        L.off_rot = (int)pre.size();
+        {
+            int a = 0;
+            for (int i = 0; i < L.nm; ++i) {
+                const Node& N = P->merges[L.first + i];
+                const int m = N.n1 + N.n2;
+                pre.push_back(a);
+                a += ((m + DC_ROWS_PER_BLOCK - 1) / DC_ROWS_PER_BLOCK) *
+                     ((m / 2 + DC_ROT_CHAINS - 1) / DC_ROT_CHAINS);
+            }
+            pre.push_back(a);
+            L.rot_blocks = a;
+        }
         P->levels.push_back(L);
     }
     return P;
@@ -190,7 +204,7 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 struct Layout {
     size_t bytes = 0;
     size_t probs, gtask, stask, cnt, rho2, dbl, ints, bufs;
-    int nd = 16, ni = 13;
+    int nd = 16, ni = 14;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -221,7 +235,7 @@ Scratch carve(const Plan& P, const Layout& L, char* w) {
     for (int i = 0; i < L.nd; ++i) *dp[i] = db + i * R;
     int* ib = reinterpret_cast<int*>(w + L.ints);
     int** ip[] = {&S.perm, &S.surv, &S.stype, &S.org, &S.dcol, &S.dtype, &S.rp, &S.ri,
-                  &S.rt, &S.ktop, &S.kbot, &S.pos_root, &S.pos_defl};
+                  &S.rt, &S.ktop, &S.kbot, &S.pos_root, &S.pos_defl, &S.rch};
     for (int i = 0; i < L.ni; ++i) *ip[i] = ib + i * R;
     S.cnt = reinterpret_cast<MergeCnt*>(w + L.cnt);
     S.rho2 = reinterpret_cast<double*>(w + L.rho2);
@@ -340,7 +354,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         DC_TRY(prof_mark(li, 0, s));
         DC_TRY(dc_launch_deflate(mg, Lv.nm, S, s));
         DC_TRY(prof_mark(li, 1, s));
-        DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
+        DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_rot, Lv.nm, Lv.rot_blocks, S, s));
         DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks, S,
                                 s));
         DC_TRY(prof_mark(li, 2, s));

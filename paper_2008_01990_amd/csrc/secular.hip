@@ -15,18 +15,21 @@
 //     * prod_{j<i} (lam_j - D_i)/(D_j - D_i) * prod_{i<=j<K-1} (lam_j - D_i)/(D_{j+1} - D_i).
 // Column scales: s_j = (sum_i zhat_i^2 / (D_i - lam_j)^2)^(-1/2) (eq. Q_Cauchy).
 //
-// Mapping: a workgroup of four waves owns 64 roots (or 64 poles for the
-// Loewner product); lane r of every wave works on root r, and wave w sweeps
-// one quarter of the K poles, read with wave-uniform addresses; the four
-// partial sums meet in LDS.  All O(K^2) work is FP64 VALU with one
-// reciprocal per term; HBM traffic is O(K).
+// Mapping: a workgroup of NW waves owns NR = 64 roots (or 64 poles for the
+// Loewner product); lane r of every wave works on item r.  The other index
+// (poles, or roots for Loewner) is streamed through LDS in chunks that the
+// whole workgroup loads coalesced; each wave sweeps its slice of every chunk
+// with broadcast LDS reads, and the NW partial sums meet in LDS.  All O(K^2)
+// work is FP64 VALU with one reciprocal per term; HBM traffic is O(K) per
+// workgroup.
 #include "secular.hpp"
 
 namespace {
 
 constexpr double EPS = 2.220446049250313e-16;
-constexpr int NW = 4;           // waves per workgroup
+constexpr int NW = 8;           // waves per workgroup
 constexpr int NR = 64;          // roots per workgroup
+constexpr int CH = 1024;        // chunk of the streamed index staged in LDS
 
 __device__ __forceinline__ int task_of(const int* block_start, int ntasks, int b) {
     int lo = 0, hi = ntasks - 1;
@@ -41,39 +44,36 @@ struct Sums {
     double psi, dpsi, phi, dphi, aabs;
 };
 
-// Partial sums over this wave's pole range for a root with origin pole Do,
-// offset tau and interval index j (poles i <= j are "left").
-__device__ __forceinline__ Sums pole_sums(const double* __restrict__ D,
-                                          const double* __restrict__ z, int i0, int i1,
-                                          double Do, double tau, int j) {
-    Sums s{0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = i0; i < i1; ++i) {
-        const double Di = D[i];
-        const double zi = z[i];
-        const double t = (Di - Do) - tau;
+// Partial sums over the poles of one staged chunk assigned to this wave, for a
+// root with origin pole Do, offset tau and interval index j (poles i <= j
+// are "left").  sD/sz2 hold the chunk starting at pole c0.
+__device__ __forceinline__ void chunk_sums(const double* sD, const double* sz2, int c0,
+                                           int a, int b, double Do, double tau, int j,
+                                           Sums& s) {
+#pragma unroll 4
+    for (int q = a; q < b; ++q) {
+        const double t = (sD[q] - Do) - tau;
         const double r = dc_rcp(t);
-        const double term = zi * zi * r;
+        const double term = sz2[q] * r;
         const double dterm = term * r;
-        if (i <= j) {
-            s.psi += term;
-            s.dpsi += dterm;
-        } else {
-            s.phi += term;
-            s.dphi += dterm;
-        }
+        const bool left = c0 + q <= j;
+        s.psi += left ? term : 0.0;
+        s.dpsi += left ? dterm : 0.0;
+        s.phi += left ? 0.0 : term;
+        s.dphi += left ? 0.0 : dterm;
         s.aabs += fabs(term);
     }
-    return s;
 }
 
 __global__ __launch_bounds__(NW * 64)
 void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                      int ntasks, int max_iter) {
+    __shared__ double sD[CH], sz2[CH];
     __shared__ double red[5][NW][NR];
     __shared__ double s_tau[NR];
     __shared__ double s_do[NR];
-    __shared__ int s_org[NR];
     __shared__ int s_live;
+    __shared__ double s_zz;
 
     const int ti = task_of(block_start, ntasks, blockIdx.x);
     const SecTask& T = tasks[ti];
@@ -84,14 +84,30 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     const double* __restrict__ D = T.D;
     const double* __restrict__ z = T.z;
 
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int per = (K + NW - 1) / NW;
-    const int i0 = min(K, w * per);
-    const int i1 = min(K, i0 + per);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = j0 + lane;
     const bool valid = j < K;
     const bool last = j == K - 1;
+    const int per = CH / NW;        // poles of a chunk per wave
+
+    // ||z||^2 bounds the last root; only the workgroup owning it needs it
+    // (per-wave partials summed in a fixed order: deterministic).
+    if (j0 + NR >= K) {
+        double zz = 0.0;
+        for (int i = tid; i < K; i += NW * 64) zz += z[i] * z[i];
+        zz = dc_wave_sum(zz);
+        if (lane == 0) red[0][w][0] = zz;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double zz = 0.0;
+        if (j0 + NR >= K)
+            for (int q = 0; q < NW; ++q) zz += red[0][q][0];
+        s_zz = zz;
+    }
+    __syncthreads();
 
     // Wave 0 owns the per-root state.
     double lo = 0.0, hi = 0.0, tau = 0.0, dlo = 0.0, dhi = 0.0;
@@ -103,27 +119,36 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         Dj = D[j];
         Dj1 = last ? 0.0 : D[j + 1];
         if (last) {
-            // rho ||z||^2 bounds the last root; widen by a few ulps.
-            double zz = 0.0;
-            for (int i = 0; i < K; ++i) zz += z[i] * z[i];
-            hi = rho * zz * (1.0 + 8.0 * EPS);
+            hi = rho * s_zz * (1.0 + 8.0 * EPS);   // widened by a few ulps
             tau = 0.5 * hi;
         } else {
-            tau = 0.5 * (Dj1 - Dj);     // midpoint, origin j frame
+            tau = 0.5 * (Dj1 - Dj);                // midpoint, origin j frame
         }
         org = j;
     }
     if (w == 0) {
         s_tau[lane] = tau;
         s_do[lane] = valid ? D[j] : 0.0;
-        s_org[lane] = org;
     }
     __syncthreads();
 
     for (int it = 0;; ++it) {
         // Every wave: partial sums at the current iterate of root `lane`.
         Sums p{0.0, 0.0, 0.0, 0.0, 0.0};
-        if (valid) p = pole_sums(D, z, i0, i1, s_do[lane], s_tau[lane], j);
+        const double Do = s_do[lane];
+        const double tcur = s_tau[lane];
+        for (int c0 = 0; c0 < K; c0 += CH) {
+            const int cn = min(CH, K - c0);
+            __syncthreads();
+            for (int i = tid; i < cn; i += NW * 64) {
+                sD[i] = D[c0 + i];
+                const double zi = z[c0 + i];
+                sz2[i] = zi * zi;
+            }
+            __syncthreads();
+            const int a = min(cn, w * per), b = min(cn, a + per);
+            if (valid) chunk_sums(sD, sz2, c0, a, b, Do, tcur, j, p);
+        }
         red[0][w][lane] = p.psi;
         red[1][w][lane] = p.dpsi;
         red[2][w][lane] = p.phi;
@@ -155,7 +180,6 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                     dhi = Dj1 - (org == j ? Dj : Dj1);
                     if (g == 0.0) done = true;
                 } else {
-                    if (it == 0) { dlo = 0.0; dhi = 0.0; }
                     if (g > 0.0) hi = tau; else lo = tau;
                     const bool conv = fabs(g) <= 8.0 * EPS * (1.0 / rho + aabs) ||
                                       (hi - lo) <= 4.0 * EPS * fmax(fabs(lo), fabs(hi));
@@ -193,7 +217,6 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
             }
             s_tau[lane] = tau;
             if (valid) s_do[lane] = (org == j) ? Dj : Dj1;
-            s_org[lane] = org;
             const unsigned long long live = __ballot(!done);
             if (lane == 0) s_live = live != 0ull;
         }
@@ -209,11 +232,12 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     }
 }
 
-// zhat_i: lane r of each wave owns pole i = i0 + r; wave w multiplies the
-// factors of one quarter of the roots.
+// zhat_i: lane r of each wave owns pole i = p0 + r; the roots are streamed in
+// chunks and every wave multiplies the factors of its slice of each chunk.
 __global__ __launch_bounds__(NW * 64)
 void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                int ntasks) {
+    __shared__ double sB[CH], sT[CH], sD[CH + 1];
     __shared__ double part[NW][NR];
     const int ti = task_of(block_start, ntasks, blockIdx.x);
     const SecTask& T = tasks[ti];
@@ -221,62 +245,78 @@ void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_
     const int p0 = (blockIdx.x - block_start[ti]) * NR;
     if (p0 >= K) return;
     const double rho = T.rho_p ? *T.rho_p : T.rho;
-    const double* __restrict__ D = T.D;
-    const double* __restrict__ cb = T.cbase;
-    const double* __restrict__ tau = T.tau;
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i = p0 + lane;
     const bool valid = i < K;
-    const double Di = valid ? D[i] : 0.0;
-    const int per = (K + NW - 1) / NW;
-    const int j0 = min(K, w * per);
-    const int j1 = min(K, j0 + per);
+    const double Di = valid ? T.D[i] : 0.0;
+    const int per = CH / NW;
     double prod = 1.0;
-    if (valid) {
-        for (int j = j0; j < j1; ++j) {
-            const double lmd = (cb[j] - Di) + tau[j];      // lam_j - D_i
-            double den;
-            if (j == K - 1) den = rho;
-            else den = (j < i ? D[j] : D[j + 1]) - Di;
-            prod *= lmd * dc_rcp(den);
+    for (int c0 = 0; c0 < K; c0 += CH) {
+        const int cn = min(CH, K - c0);
+        __syncthreads();
+        for (int q = tid; q < cn; q += NW * 64) {
+            sB[q] = T.cbase[c0 + q];
+            sT[q] = T.tau[c0 + q];
+        }
+        for (int q = tid; q <= cn; q += NW * 64) sD[q] = (c0 + q < K) ? T.D[c0 + q] : 0.0;
+        __syncthreads();
+        const int a = min(cn, w * per), b = min(cn, a + per);
+        if (valid) {
+#pragma unroll 4
+            for (int q = a; q < b; ++q) {
+                const int jj = c0 + q;
+                const double lmd = (sB[q] - Di) + sT[q];        // lam_j - D_i
+                const double den = (jj == K - 1) ? rho : ((jj < i ? sD[q] : sD[q + 1]) - Di);
+                prod *= lmd * dc_rcp(den);
+            }
         }
     }
     part[w][lane] = prod;
     __syncthreads();
     if (w == 0 && valid) {
-        double p = part[0][lane];
+        double pr = part[0][lane];
 #pragma unroll
-        for (int q = 1; q < NW; ++q) p *= part[q][lane];
-        T.zhat[i] = copysign(sqrt(p), T.z[i]);
+        for (int q = 1; q < NW; ++q) pr *= part[q][lane];
+        T.zhat[i] = copysign(sqrt(pr), T.z[i]);
     }
 }
 
 __global__ __launch_bounds__(NW * 64)
 void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                 int ntasks) {
+    __shared__ double sD[CH], sZ[CH];
     __shared__ double part[NW][NR];
     const int ti = task_of(block_start, ntasks, blockIdx.x);
     const SecTask& T = tasks[ti];
     const int K = T.K_p ? *T.K_p : T.K;
     const int j0 = (blockIdx.x - block_start[ti]) * NR;
     if (j0 >= K) return;
-    const double* __restrict__ D = T.D;
-    const double* __restrict__ zh = T.zhat;
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = j0 + lane;
     const bool valid = j < K;
     const double base = valid ? T.cbase[j] : 0.0;
     const double tj = valid ? T.tau[j] : 0.0;
-    const int per = (K + NW - 1) / NW;
-    const int i0 = min(K, w * per);
-    const int i1 = min(K, i0 + per);
+    const int per = CH / NW;
     double s = 0.0;
-    if (valid) {
-        for (int i = i0; i < i1; ++i) {
-            const double q = zh[i] * dc_rcp((D[i] - base) - tj);
-            s += q * q;
+    for (int c0 = 0; c0 < K; c0 += CH) {
+        const int cn = min(CH, K - c0);
+        __syncthreads();
+        for (int q = tid; q < cn; q += NW * 64) {
+            sD[q] = T.D[c0 + q];
+            sZ[q] = T.zhat[c0 + q];
+        }
+        __syncthreads();
+        const int a = min(cn, w * per), b = min(cn, a + per);
+        if (valid) {
+#pragma unroll 4
+            for (int q = a; q < b; ++q) {
+                const double v = sZ[q] * dc_rcp((sD[q] - base) - tj);
+                s += v * v;
+            }
         }
     }
     part[w][lane] = s;
