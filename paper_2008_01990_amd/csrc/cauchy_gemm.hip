@@ -50,9 +50,9 @@ struct Cfg {
     static constexpr int KSTEPS = BK / 4;       // MFMA k-steps per chunk
     static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile split");
     static_assert(NT % BM == 0 && NT % BN == 0, "rows per pass");
-    static_assert(A_PER % KSTEPS == 0 && B_PER % KSTEPS == 0, "store slices");
-    static constexpr int A_SLICE = A_PER / KSTEPS;
-    static constexpr int B_SLICE = B_PER / KSTEPS;
+    // register entry i is written to LDS after MFMA k-step slice(i)
+    static constexpr int a_slice(int i) { return i * KSTEPS / A_PER; }
+    static constexpr int b_slice(int i) { return i * KSTEPS / B_PER; }
 };
 
 __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int t) {
@@ -136,45 +136,65 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     double o_reg[KIND == 1 ? C_::B_PER : 1];   // kind 1: skeleton node offset
     int s_reg[KIND == 1 ? C_::B_PER : 1];      // kind 1: skeleton column (generator)
 
+    // Interior chunks of interior tiles (the common case) load without
+    // bounds checks, with strength-reduced addresses.
+    const bool full_rows = row0 + BM <= T.rows;
+    const long long astep = (long long)C_::A_KSTEP * lda;
     auto load = [&](int kb) {
+        if (full_rows && kb + BK <= klen) {
+            const double* __restrict__ pa = Acol + (long long)(kb + ak0) * lda;
 #pragma unroll
-        for (int i = 0; i < C_::A_PER; ++i) {
-            const int k = kb + ak0 + i * C_::A_KSTEP;
-            a_reg[i] = (k < klen && row_ok) ? Acol[(long long)k * lda] : 0.0;
+            for (int i = 0; i < C_::A_PER; ++i) a_reg[i] = dc_ldg(pa + i * astep);
+            if (KIND == 0) {
+#pragma unroll
+                for (int i = 0; i < C_::B_PER; ++i) {
+                    const int k = kb + bk0 + i * C_::B_KSTEP;
+                    d_reg[i] = dc_ldg(rD + k);
+                    z_reg[i] = dc_ldg(rz + k);
+                }
+                return;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < C_::A_PER; ++i) {
+                const int k = kb + ak0 + i * C_::A_KSTEP;
+                a_reg[i] = (k < klen && row_ok) ? dc_ldg(Acol + (long long)k * lda) : 0.0;
+            }
         }
 #pragma unroll
         for (int i = 0; i < C_::B_PER; ++i) {
             const int k = kb + bk0 + i * C_::B_KSTEP;
             const bool ok = k < klen;
             if (KIND == 0) {
-                d_reg[i] = ok ? rD[k] : 0.0;
-                z_reg[i] = ok ? rz[k] : 0.0;
+                d_reg[i] = ok ? dc_ldg(rD + k) : 0.0;
+                z_reg[i] = ok ? dc_ldg(rz + k) : 0.0;
             } else if (KIND == 1) {
-                const int h = ok ? T.rgen[k] : 0;
-                d_reg[i] = (ok && col_ok) ? T.ry[k] * T.vk[T.rvo[k] + lcol] : 0.0;
-                z_reg[i] = ok ? T.cbase[h] : 0.0;
-                o_reg[i] = (ok && T.coff) ? T.coff[h] : 0.0;
+                const int h = ok ? dc_ldg(T.rgen + k) : 0;
+                d_reg[i] = (ok && col_ok) ? dc_ldg(T.ry + k) * dc_ldg(T.vk + T.rvo[k] + lcol) : 0.0;
+                z_reg[i] = ok ? dc_ldg(T.cbase + h) : 0.0;
+                o_reg[i] = (ok && T.coff) ? dc_ldg(T.coff + h) : 0.0;
                 s_reg[i] = ok ? h : -1;
             } else if (KIND == 2) {
-                d_reg[i] = (ok && col_ok) ? T.Bm[(long long)gcol * T.ldb + k] : 0.0;
+                d_reg[i] = (ok && col_ok) ? dc_ldg(T.Bm + (long long)gcol * T.ldb + k) : 0.0;
             } else {
                 d_reg[i] = (ok && col_ok)
-                               ? (T.Bm ? T.Bm[(long long)gcol * T.ldb + k] : rz[k] * csj)
+                               ? (T.Bm ? dc_ldg(T.Bm + (long long)gcol * T.ldb + k)
+                                       : dc_ldg(rz + k) * csj)
                                : 0.0;
-                z_reg[i] = ok ? T.lam[k] : 0.0;
+                z_reg[i] = ok ? dc_ldg(T.lam + k) : 0.0;
             }
         }
     };
     // Store slice s of the registers into LDS buffer `buf` (B generated).
     auto store_slice = [&](int buf, int kb, int s) {
 #pragma unroll
-        for (int q = 0; q < C_::A_SLICE; ++q) {
-            const int i = s * C_::A_SLICE + q;
+        for (int i = 0; i < C_::A_PER; ++i) {
+            if (C_::a_slice(i) != s) continue;
             As[buf][(ak0 + i * C_::A_KSTEP) * C_::LDA_S + ar] = a_reg[i];
         }
 #pragma unroll
-        for (int q = 0; q < C_::B_SLICE; ++q) {
-            const int i = s * C_::B_SLICE + q;
+        for (int i = 0; i < C_::B_PER; ++i) {
+            if (C_::b_slice(i) != s) continue;
             const int kk = bk0 + i * C_::B_KSTEP;
             double v;
             if (KIND == 0) {

@@ -22,6 +22,14 @@ __device__ __forceinline__ double dc_rcp(double x) {
     return r;
 }
 
+// Loads through the global address space: the compiler then emits
+// global_load (tracked by vmcnt only) instead of flat_load, whose lgkmcnt
+// share would make every LDS wait also wait for outstanding prefetches.
+typedef __attribute__((address_space(1))) const double dc_gdouble;
+typedef __attribute__((address_space(1))) const int dc_gint;
+__device__ __forceinline__ double dc_ldg(const double* p) { return *(dc_gdouble*)p; }
+__device__ __forceinline__ int dc_ldg(const int* p) { return *(dc_gint*)p; }
+
 __device__ __forceinline__ double dc_wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
