@@ -181,6 +181,45 @@ def extra_configs(L, torch):
         "sum_n": int(sum(sizes)), "status_ok": all(v == 0 for v in B.status())}
     del B
     torch.cuda.empty_cache()
+    # the paper's own sizes (Examples 2-3): n = 30000 Clement, Hermite-type,
+    # 1-2-1 Toeplitz and SHT (m = n), plain and low-rank; residual on all
+    # columns, orthogonality on 1024 sampled columns against all.
+    n = 30000
+    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    paper = {}
+    for fam, gen in (("clement", W.clement), ("hermite", W.hermite),
+                     ("toeplitz", W.toeplitz), ("sht", W.sht)):
+        d0, e0 = gen(n)
+        d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
+        d = torch.empty_like(d_in)
+        rec = {}
+        for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=1024,
+                                                          lr_min_k=4096))):
+            s = L.Solver(n, leaf=64, **kw)
+
+            def c5():
+                d.copy_(d_in)
+                s.solve_into(d, e, Qb)
+            t = _time(c5, 1, torch)
+            Q = Qb.t()
+            tn = float(d.abs().max())
+            TQ = d_in[:, None] * Q
+            TQ[:-1] += e[:, None] * Q[1:]
+            TQ[1:] += e[:, None] * Q[:-1]
+            resid = float(torch.linalg.norm(TQ - Q * d[None, :])) / (n * tn)
+            del TQ
+            idx = torch.randperm(n, device="cuda")[:1024]
+            G = Qb[idx] @ Qb.t()
+            G[torch.arange(1024, device="cuda"), idx] -= 1.0
+            rec[name] = {"seconds": t, "residual": resid,
+                         "orthogonality_sampled": float(G.abs().max()),
+                         "status": s.status()}
+            del G, s
+        rec["lowrank_speedup"] = rec["plain"]["seconds"] / rec["lowrank"]["seconds"]
+        paper[fam] = rec
+    res["paper_sizes_n30000"] = paper
+    del Qb
+    torch.cuda.empty_cache()
     # adjoint: n=4096, loss sum w lam + sum c (u^T q)^2
     P = W.adjoint_problem(n=4096, seed=4, n_coords=32)
     n = 4096

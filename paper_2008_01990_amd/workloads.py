@@ -10,6 +10,12 @@ method's arithmetic.
 * ``clement``   -- the Clement-type matrix of Example 2 as an n x n matrix:
                    d = 0, e_i = sqrt(i (n - i)), i = 1..n-1.
 * ``hermite``   -- the Hermite-type matrix of Example 2: d = 0, e_i = sqrt(i).
+* ``sht``       -- the spherical-harmonic-transform matrix of Example 3: row j
+                   has diagonal d_{m+2j} and off-diagonal c_{m+2j}, with
+                   xi_l = l - m,
+                   c_l = sqrt((xi_l+1)(xi_l+2)(l+m+1)(l+m+2) /
+                              ((2l+1)(2l+3)^2 (2l+5))),
+                   d_l = (2l(l+1) - 2m^2 - 1) / ((2l-1)(2l+3)); m = n by default.
 * ``random_tridiag`` / ``batched_sizes`` -- many small problems with
                    d, e ~ U(-1, 1) and sizes log-uniform in [lo, hi].
 * ``adjoint_problem`` -- perturbed 1-2-1 matrix plus loss weights w, c, u.
@@ -34,6 +40,16 @@ def clement(n):
 
 def hermite(n):
     return np.zeros(n), np.sqrt(np.arange(1, n, dtype=np.float64))
+
+
+def sht(n, m=None):
+    m = n if m is None else m
+    l = m + 2 * np.arange(n, dtype=np.float64)
+    xi = l - m
+    c = np.sqrt((xi + 1) * (xi + 2) * (l + m + 1) * (l + m + 2)
+                / ((2 * l + 1) * (2 * l + 3) ** 2 * (2 * l + 5)))
+    d = (2 * l * (l + 1) - 2.0 * m * m - 1) / ((2 * l - 1) * (2 * l + 3))
+    return d, c[:n - 1].copy()
 
 
 def random_tridiag(n, rng):

@@ -103,3 +103,21 @@ def test_nonfinite_input_sets_status(lib):
     s = lib.Solver(100, leaf=16)
     s(cuda(d), cuda(e))
     assert s.status() == -1000
+
+
+def test_hermite_type(lib):
+    from scipy.special import roots_hermitenorm
+    n = 700
+    announce(f"stedc hermite n={n}")
+    d, e = W.hermite(n)
+    lam, Q = _solve(lib, d, e, leaf=32)
+    assert metrics.eig_error(lam, np.sort(roots_hermitenorm(n)[0])) <= 1e-13
+    _check_against_oracle(d, e, lam, Q, 32)
+
+
+def test_sht_matrix(lib):
+    n = 1200
+    announce(f"stedc sht n={n}")
+    d, e = W.sht(n)
+    lam, Q = _solve(lib, d, e, leaf=64)
+    _check_against_oracle(d, e, lam, Q, 64)

@@ -150,3 +150,31 @@ def test_lowrank_variant_meets_bound():
         if r["path"] == "lowrank":
             rk = r["ranks"][r["ranks"] >= 0]
             assert rk.max() <= 40      # off-diagonal blocks are low rank
+
+
+def test_hermite_type_against_hermite_roots():
+    # d = 0, e_i = sqrt(i): the Jacobi matrix of the probabilists' Hermite
+    # polynomials; its eigenvalues are their roots (SciPy, library routine).
+    from scipy.special import roots_hermitenorm
+    n = 300
+    d, e = W.hermite(n)
+    lam, Q = dc.eigh_tridiagonal(d, e, leaf=32)
+    ref = np.sort(roots_hermitenorm(n)[0])
+    assert metrics.eig_error(lam, ref) <= 1e-13
+    assert metrics.orthogonality(Q) <= 1e-13
+    assert metrics.residual(d, e, lam, Q) <= 1e-15
+
+
+def test_sht_matrix_definition_and_solve():
+    # Example 3's SHT matrix: spot values from its formula and a solve that
+    # matches Sturm bisection.
+    n = 48
+    d, e = W.sht(n)
+    m = n
+    l0 = m
+    assert abs(d[0] - (2 * l0 * (l0 + 1) - 2 * m * m - 1) / ((2 * l0 - 1) * (2 * l0 + 3))) <= 1e-15
+    c0 = np.sqrt(1 * 2 * (2 * m + 1) * (2 * m + 2) / ((2 * l0 + 1) * (2 * l0 + 3) ** 2 * (2 * l0 + 5)))
+    assert abs(e[0] - c0) <= 1e-15
+    lam, Q = dc.eigh_tridiagonal(d, e, leaf=8)
+    assert metrics.eig_error(lam, sturm.eigvals(d, e)) <= 1e-14
+    assert metrics.orthogonality(Q) <= 1e-14
