@@ -132,6 +132,118 @@ def _time(fn, reps, torch):
     return (time.perf_counter() - t0) / reps
 
 
+def _events(fn, reps, torch):
+    """Best of reps event-timed runs after one warm-up (seconds)."""
+    fn()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    return best
+
+
+def example1(L, torch, sizes=(8192, 16384, 32768), tol=1e-10, b=1024):
+    """Example 1 on one GPU: C = A B with A random (N(0,1)) and B Example 0's
+    Cauchy-like matrix B_ij = u_i v_j / (d_i - w_j) given by its generators.
+      plain           generated-tile product, B never stored
+      lowrank_block   SRRSC product on contiguous b x b blocks (block layout)
+      lowrank_cyclic  the same on the block-cyclic storage order (block 64 over
+                      n/b process rows), whose blocks lose the low rank
+      dgemm           the library GEMM (torch.matmul) on the stored B
+    Errors are against the library GEMM; the low-rank bound is
+    tol * max_i sum_k |A_ik| (each U entry within tol)."""
+    from paper_2008_01990_amd import workloads as W
+    out = {}
+    f64 = torch.float64
+    for n in sizes:
+        u, v, d, w = W.example_cauchy(n, seed=7)
+        ud, vd, dd, wd = (torch.tensor(x, device="cuda") for x in (u, v, d, w))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(n)
+        At = torch.randn(n, n, generator=g, dtype=f64, device="cuda")   # column-major A
+        BmT = (vd[:, None] * ud[None, :]) / (dd[None, :] - wd[:, None])  # column-major B
+        Cref = torch.empty(n, n, dtype=f64, device="cuda")
+        C = torch.empty(n, n, dtype=f64, device="cuda")
+        reps = 2
+        t_gemm = _events(lambda: torch.matmul(BmT, At, out=Cref), reps, torch)
+        del BmT
+        flops = 2.0 * n ** 3
+        rowsum = float(At.abs().sum(dim=0).max())
+        scale = float(Cref.abs().max())
+        rec = {"dgemm": {"seconds": t_gemm, "tflops": flops / t_gemm / 1e12}}
+        t = _events(lambda: L.merge_update(At, n, n, dd, None, wd, ud, vd, out=C), reps, torch)
+        rec["plain"] = {"seconds": t, "tflops": flops / t / 1e12,
+                        "max_rel_err_vs_dgemm": float((C - Cref).abs().max()) / scale}
+        for name, perm in (("lowrank_block", None),
+                           ("lowrank_cyclic", W.block_cyclic_order(n, n // b, 64))):
+            if perm is None:
+                A_, gens = At, (dd, wd, ud, vd)
+            else:
+                pt = torch.tensor(perm, device="cuda")
+                A_ = At.index_select(0, pt)
+                gens = tuple(x.index_select(0, pt) for x in (dd, wd, ud, vd))
+            gd, gw, gu, gv = gens
+            t = _events(lambda: L.merge_update(A_, n, n, gd, None, gw, gu, gv, lr_tol=tol,
+                                               lr_block=b, out=C), reps, torch)
+            ranks = L.merge_lowrank_ranks(gd, None, gw, gu, gv, tol, b)
+            bs = [min(b, n - I * b) for I in range(ranks.shape[0])]
+            ex = 0.0
+            for I in range(ranks.shape[0]):
+                ex += bs[I] ** 2
+                for J in range(ranks.shape[0]):
+                    if I != J:
+                        r = bs[J] if ranks[I, J] == -2 else ranks[I, J]
+                        ex += r * (bs[I] + bs[J])
+            err = 0.0
+            for c0 in range(0, n, 2048):
+                rows = slice(c0, min(n, c0 + 2048))
+                ref = Cref[rows] if perm is None else Cref.index_select(0, pt[rows])
+                err = max(err, float((C[rows] - ref).abs().max()))
+            off = ranks[ranks >= 0]
+            rec[name] = {"seconds": t, "plain_equivalent_tflops": flops / t / 1e12,
+                         "executed_flops": 2.0 * n * ex,
+                         "ranks_mean": float(off.mean()) if off.size else None,
+                         "ranks_max": int(off.max()) if off.size else None,
+                         "blocks_dense": int((ranks == -2).sum()),
+                         "max_abs_err_vs_dgemm": err,
+                         "err_over_bound": err / (tol * rowsum)}
+            del A_
+        rec["speedup_plain_vs_dgemm"] = t_gemm / rec["plain"]["seconds"]
+        rec["speedup_lowrank_block_vs_dgemm"] = t_gemm / rec["lowrank_block"]["seconds"]
+        rec["speedup_lowrank_cyclic_vs_dgemm"] = t_gemm / rec["lowrank_cyclic"]["seconds"]
+        out[f"n{n}"] = rec
+        del At, Cref, C
+        torch.cuda.empty_cache()
+    return out
+
+
+def table_rank(L, torch, n=16384, nprocs=4, tol=1e-12):
+    """Table "rank": SRRSC ranks of B(2,1), B(3,1), B(4,1) of Example 1's B
+    (n = 16384, 4096 x 4096 local blocks on 4 x 4 processes) for block-cyclic
+    block sizes 64, 128, 256 and the block layout (4096)."""
+    from paper_2008_01990_amd import workloads as W
+    u, v, d, w = W.example_cauchy(n, seed=0)
+    b = n // nprocs
+    out = {"tol": tol, "n": n, "block": b, "printed": {"64": [1260, 892, 1252],
+                                                       "128": [711, 445, 699],
+                                                       "256": [401, 221, 390],
+                                                       "4096": [34, 11, 9]}}
+    for nb in (64, 128, 256, 4096):
+        perm = W.block_cyclic_order(n, nprocs, nb)
+        gens = [torch.tensor(x[perm], device="cuda") for x in (d, w, u, v)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ranks = L.merge_lowrank_ranks(gens[0], None, gens[1], gens[2], gens[3], tol, b,
+                                      rank_cap=b)
+        out[str(nb)] = {"ranks": [int(x) for x in ranks[1:, 0]],
+                        "seconds": time.perf_counter() - t0}
+    return out
+
+
 def extra_configs(L, torch):
     """Secondary configurations, each timed on the GPU after a warm-up."""
     import numpy as np
@@ -220,6 +332,8 @@ def extra_configs(L, torch):
     res["paper_sizes_n30000"] = paper
     del Qb
     torch.cuda.empty_cache()
+    res["example1"] = example1(L, torch)
+    res["table_rank"] = table_rank(L, torch)
     # adjoint: n=4096, loss sum w lam + sum c (u^T q)^2
     P = W.adjoint_problem(n=4096, seed=4, n_coords=32)
     n = 4096

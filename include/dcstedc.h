@@ -138,7 +138,8 @@ int dc_secular(int K, const double* Dbar, const double* zbar, double rho,
  *                blocks of U are replaced by SRRSC approximations with
  *                absolute entry error <= lr_tol (eq. sid; Algorithm 2 step
  *                3(b)-(c)); diagonal blocks stay exact.
- *   lr_block     block size for lr_tol > 0 (<= 0: default 1024)
+ *   lr_block     block size for lr_tol > 0 (<= 0: default 1024); at most
+ *                2048 with org, 4096 with org == NULL (else returns -13)
  * Allocates stream-ordered workspace when lr_tol > 0.
  */
 int dc_merge_update(int m, int K, const double* Qnd, int ldq,
@@ -147,14 +148,23 @@ int dc_merge_update(int m, int K, const double* Qnd, int ldq,
                     int ldc, double lr_tol, int lr_block, hipStream_t stream);
 
 /*
- * dc_merge_lowrank_ranks -- ranks the low-rank merge would use: for the
- * generators of dc_merge_update, writes nb*nb ints to ranks_host (HOST),
- * nb = ceil(K / lr_block), -1 on the diagonal.  Synchronises the stream.
+ * dc_merge_lowrank_ranks -- SRRSC ranks of the lr_block x lr_block blocks
+ * of U (section "SRRSC low-rank approximation", complete pivoting, stop when
+ * every Schur-complement entry is <= lr_tol; Table "rank" reports such ranks
+ * for Example 1's B).  For the generators of dc_merge_update, writes nb*nb
+ * ints row-major to ranks_host (HOST), nb = ceil(K / lr_block): the rank of
+ * off-diagonal block (I, J), -1 on the diagonal, -2 where the rank exceeds
+ * the cap.
+ *   rank_cap   0: the cap of the low-rank product itself (min(128,
+ *              lr_block/2)), i.e. the ranks dc_merge_update would use;
+ *              > 0: count ranks up to min(rank_cap, lr_block) without
+ *              forming the factors.
+ * lr_block limits as dc_merge_update (else -8).  Synchronises the stream.
  */
 int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
                            const double* tau, const double* zhat,
                            const double* scale, double lr_tol, int lr_block,
-                           int* ranks_host, hipStream_t stream);
+                           int rank_cap, int* ranks_host, hipStream_t stream);
 
 /*
  * dc_stedc_backward -- reverse-mode gradient of (lam, Q) = eig(T(d, e)).

@@ -19,7 +19,11 @@
 // writes them (A as loaded, U generated with one reciprocal per entry) into
 // the other buffer in slices placed between the MFMA groups, so the matrix
 // cores stay fed; one barrier per chunk.  Each wave owns a WTM x WTN
-// sub-tile of v_mfma_f64_16x16x4_f64 blocks.
+// sub-tile of v_mfma_f64_16x16x4_f64 blocks.  Chunks whose successor is
+// interior run in a loop of their own with unguarded loads, issued in the
+// order the LDS writes consume them; with the late-write schedule the writes
+// sit in the last k-steps, so the loads have most of a chunk to arrive
+// before the first wait on them.
 //
 // Work distribution: one flat grid over the tiles of every task (every merge
 // half of a tree level).  Workgroup b runs on XCD b % 8; the flat id is
@@ -32,7 +36,7 @@ namespace {
 
 constexpr int WAVE = 64;
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int BM, int BN, int BK, int WGM, int WGN, int SCHED>
 struct Cfg {
     static constexpr int NT = WGM * WGN * WAVE;
     static constexpr int WTM = BM / WGM;        // rows per wave
@@ -50,9 +54,17 @@ struct Cfg {
     static constexpr int KSTEPS = BK / 4;       // MFMA k-steps per chunk
     static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile split");
     static_assert(NT % BM == 0 && NT % BN == 0, "rows per pass");
-    // register entry i is written to LDS after MFMA k-step slice(i)
-    static constexpr int a_slice(int i) { return i * KSTEPS / A_PER; }
-    static constexpr int b_slice(int i) { return i * KSTEPS / B_PER; }
+    // Register entry i is written to LDS after MFMA k-step slice(i).
+    // SCHED 0 spreads the writes over the chunk; SCHED 1 writes U in the
+    // last two k-steps and A in the last one, so the global loads of the next
+    // chunk have most of a chunk of MFMAs to arrive.
+    static constexpr int a_slice(int i) {
+        return SCHED == 0 ? i * KSTEPS / A_PER : KSTEPS - 1;
+    }
+    static constexpr int b_slice(int i) {
+        return SCHED == 0 ? i * KSTEPS / B_PER
+                          : (KSTEPS >= 2 ? KSTEPS - 2 + (2 * i) / B_PER : 0);
+    }
 };
 
 __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int t) {
@@ -64,11 +76,11 @@ __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int 
     return lo;
 }
 
-template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN>
-__global__ __launch_bounds__(WGM * WGN * 64)
+template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC>
+__global__ __launch_bounds__(WGM * WGN * 64, OCC)
 void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
                    int ntasks, int total_tiles) {
-    using C_ = Cfg<BM, BN, BK, WGM, WGN>;
+    using C_ = Cfg<BM, BN, BK, WGM, WGN, SCHED>;
     __shared__ double As[2][BK * C_::LDA_S];
     __shared__ double Bs[2][BK * C_::LDB_S];
 
@@ -140,31 +152,11 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     // bounds checks, with strength-reduced addresses.
     const bool full_rows = row0 + BM <= T.rows;
     const long long astep = (long long)C_::A_KSTEP * lda;
-    auto load = [&](int kb) {
-        if (full_rows && kb + BK <= klen) {
-            const double* __restrict__ pa = Acol + (long long)(kb + ak0) * lda;
-#pragma unroll
-            for (int i = 0; i < C_::A_PER; ++i) a_reg[i] = dc_ldg(pa + i * astep);
-            if (KIND == 0) {
-#pragma unroll
-                for (int i = 0; i < C_::B_PER; ++i) {
-                    const int k = kb + bk0 + i * C_::B_KSTEP;
-                    d_reg[i] = dc_ldg(rD + k);
-                    z_reg[i] = dc_ldg(rz + k);
-                }
-                return;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < C_::A_PER; ++i) {
-                const int k = kb + ak0 + i * C_::A_KSTEP;
-                a_reg[i] = (k < klen && row_ok) ? dc_ldg(Acol + (long long)k * lda) : 0.0;
-            }
-        }
+    auto load_b = [&](int kb, bool interior) {
 #pragma unroll
         for (int i = 0; i < C_::B_PER; ++i) {
             const int k = kb + bk0 + i * C_::B_KSTEP;
-            const bool ok = k < klen;
+            const bool ok = interior || k < klen;
             if (KIND == 0) {
                 d_reg[i] = ok ? dc_ldg(rD + k) : 0.0;
                 z_reg[i] = ok ? dc_ldg(rz + k) : 0.0;
@@ -183,6 +175,30 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
                                : 0.0;
                 z_reg[i] = ok ? dc_ldg(T.lam + k) : 0.0;
             }
+        }
+    };
+    auto load_a = [&](int kb, bool interior) {
+        if (interior) {
+            const double* __restrict__ pa = Acol + (long long)(kb + ak0) * lda;
+#pragma unroll
+            for (int i = 0; i < C_::A_PER; ++i) a_reg[i] = dc_ldg(pa + i * astep);
+        } else {
+#pragma unroll
+            for (int i = 0; i < C_::A_PER; ++i) {
+                const int k = kb + ak0 + i * C_::A_KSTEP;
+                a_reg[i] = (k < klen && row_ok) ? dc_ldg(Acol + (long long)k * lda) : 0.0;
+            }
+        }
+    };
+    auto load = [&](int kb) {
+        const bool interior = full_rows && kb + BK <= klen;
+        if (SCHED == 0) {
+            load_a(kb, interior);
+            load_b(kb, interior);
+        } else {
+            // issued in the order the LDS writes consume them
+            load_b(kb, interior);
+            load_a(kb, interior);
         }
     };
     // Store slice s of the registers into LDS buffer `buf` (B generated).
@@ -227,11 +243,25 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     for (int s = 0; s < C_::KSTEPS; ++s) store_slice(0, 0, s);
     __syncthreads();
 
-    for (int c = 0; c < nchunks; ++c) {
+    // One chunk: MFMAs from LDS buffer c & 1 while the next chunk's loads
+    // land in registers and go to the other buffer between the k-steps.
+    // FAST: the next chunk is interior (static loads, no guards).
+    auto chunk = [&](int c, auto fast_tag) {
+        constexpr bool FAST = decltype(fast_tag)::value;
         const int cur = c & 1;
-        const bool more = c + 1 < nchunks;
+        const bool more = FAST || c + 1 < nchunks;
         const int kb_next = (c + 1) * BK;
-        if (more) load(kb_next);
+        if (FAST) {
+            if (SCHED == 0) {
+                load_a(kb_next, true);
+                load_b(kb_next, true);
+            } else {
+                load_b(kb_next, true);
+                load_a(kb_next, true);
+            }
+        } else if (more) {
+            load(kb_next);
+        }
 #pragma unroll
         for (int ks = 0; ks < C_::KSTEPS; ++ks) {
             double af[C_::FM], bf[C_::FN];
@@ -251,7 +281,14 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
             if (more) store_slice(cur ^ 1, kb_next, ks);
         }
         __syncthreads();
+    };
+    int c = 0;
+    if (SCHED != 0) {
+        // chunks whose successor is interior: c + 2 <= klen / BK
+        const int nfast = full_rows ? klen / BK - 1 : 0;
+        for (; c < nfast; ++c) chunk(c, dc_true_type{});
     }
+    for (; c < nchunks; ++c) chunk(c, dc_false_type{});
 
     // Epilogue: for the FP64 16x16x4 MFMA, accumulator register v of a lane
     // holds row lane/16 + 4 v and column lane % 16 of the 16 x 16 block.
@@ -315,43 +352,229 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     if (KIND == 3 && equal_eig && T.flag) atomicOr(T.flag, 1);
 }
 
-template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN>
-hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
-                  hipStream_t s) {
+// Register-pipelined form (no LDS, no barriers): each wave owns a
+// (16 FM) x (16 FN) block of C.  Its A operands come straight from global
+// memory (per MFMA, 16 consecutive rows at 4 values of k: one 128-byte
+// segment per k) and its U operands are generated in registers; a ring of
+// RING register slots keeps the loads PD k-steps ahead of the MFMAs.
+// Indices are clamped instead of branched on (rows past the tile end are
+// computed and not stored, k past klen gets U = 0), so the loop has no
+// branches and no waits but the in-order load counter.  Generating U costs
+// FP64 VALU time, which the MFMA pipe shares, so each generated entry should
+// feed many MFMAs: one entry per FM MFMAs.
+template <int FM, int FN, int WGM, int WGN, int RING, int OCC>
+__global__ __launch_bounds__(WGM * WGN * 64, OCC)
+void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
+                       int ntasks, int total_tiles) {
+    constexpr int WR = 16 * FM, WC = 16 * FN;
+    constexpr int BM = WGM * WR, BN = WGN * WC;
+    constexpr int PD = RING - 1;
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    if (t >= total_tiles) return;
+    const int ti = find_task(tile_start, ntasks, t);
+    const GemmTask& T = tasks[ti];
+    const int local = t - tile_start[ti];
+    const int tm = local / T.tiles_n;
+    const int tn = local - tm * T.tiles_n;
+    const int ncol = T.ncol_p ? *T.ncol_p : T.ncol;
+    const int row0 = tm * BM;
+    const int col0 = tn * BN;
+    if (col0 >= ncol || row0 >= T.rows) return;
+    // klen may be 0 (a block with no survivor of this half): the tile is
+    // then stored as zeros, and nothing is loaded from the generators.
+    const int klen = T.klen_p ? *T.klen_p : T.klen;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / WGN, wn = wave - (wave / WGN) * WGN;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int wrow = row0 + wm * WR;
+    const int wcol = col0 + wn * WC;
+    if (wrow >= T.rows) return;          // no barriers: waves retire independently
+
+    // Column generators of this lane's U columns (clamped; global-space
+    // loads: a flat load still pending at the loop header would make every
+    // wait in the loop a full drain).
+    double cb[FN], co[FN], cs[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int lc = min(wcol + j * 16 + lr, ncol - 1);
+        const int g = T.ccol ? dc_ldg(T.ccol + lc) : T.col_off + lc;
+        cb[j] = T.corg ? dc_ldg(T.rD + dc_ldg(T.corg + g)) : dc_ldg(T.cbase + g);
+        co[j] = T.coff ? dc_ldg(T.coff + g) : 0.0;
+        cs[j] = dc_ldg(T.cs + g);
+    }
+    const double* __restrict__ rD = T.rD;
+    const double* __restrict__ rz = T.rz;
+    const long long lda = T.lda;
+
+    dc_double4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = dc_double4{0.0, 0.0, 0.0, 0.0};
+
+    // SHIFT (the task has at least WR rows): the wave's rows are moved back
+    // inside the matrix if they run past it, so its A rows are one base
+    // pointer plus constant offsets; rows computed twice are stored once.
+    // Otherwise each row index is clamped on its own.
+    auto body = [&](auto shift_tag) {
+        constexpr bool SHIFT = decltype(shift_tag)::value;
+        const int crow = SHIFT ? min(wrow, T.rows - WR) : wrow;
+        const double* __restrict__ Ab = T.A + (SHIFT ? crow + lr : 0);
+        const int rlast = T.rows - 1;
+        double a[RING][FM], dd[RING], zz[RING];
+        auto issue = [&](int slot, int step) {
+            const int k = min(step * 4 + lk, klen - 1);
+            const double* __restrict__ pk = Ab + (long long)k * lda;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[slot][i] = dc_ldg(pk + (SHIFT ? i * 16 : min(wrow + i * 16 + lr, rlast)));
+            dd[slot] = dc_ldg(rD + k);
+            zz[slot] = dc_ldg(rz + k);
+        };
+        // U entries without the column scale s_n, which the epilogue applies
+        // once per output element instead of once per generated entry.
+        auto compute = [&](int slot, int step, auto masked_tag) {
+            constexpr bool MASKED = decltype(masked_tag)::value;
+            const bool kok = step * 4 + lk < klen;
+            double bf[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const double v = zz[slot] * dc_rcp3((dd[slot] - cb[j]) - co[j]);
+                bf[j] = (!MASKED || kok) ? v : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[slot][i], bf[j],
+                                                                     acc[i][j], 0, 0, 0);
+        };
+        const int nsteps = (klen + 3) / 4;
+        const int nfull = klen / 4;      // steps with every k < klen
+#pragma unroll
+        for (int s = 0; s < PD; ++s) issue(s, s);
+        int s = 0;
+        for (; s + RING <= nfull; s += RING) {
+#pragma unroll
+            for (int j = 0; j < RING; ++j) {
+                issue((j + PD) % RING, s + j + PD);
+                compute(j, s + j, dc_false_type{});
+                // keep each step's loads in its step: hoisting them would make
+                // the ring slots overlap and force a wait for every load in flight
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        for (; s < nsteps; s += RING) {
+#pragma unroll
+            for (int j = 0; j < RING; ++j) {
+                issue((j + PD) % RING, s + j + PD);
+                compute(j, s + j, dc_true_type{});
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        return crow;
+    };
+    const int crow = klen <= 0 ? wrow
+                     : (T.rows >= WR) ? body(dc_true_type{}) : body(dc_false_type{});
+
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int c = wcol + j * 16 + lr;
+        if (c >= ncol) continue;
+        const int g = T.ccol ? T.ccol[c] : T.col_off + c;
+        const int oc = T.cpos ? T.cpos[T.ccol ? c : g] : g - T.out_off;
+        double* Ccol = T.C + (long long)oc * T.ldc;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = crow + i * 16 + lk + 4 * v;
+                if (r >= wrow && r < T.rows) {
+                    const double x = acc[i][j][v] * cs[j];
+                    Ccol[r] = T.beta ? Ccol[r] + x : x;
+                }
+            }
+        }
+    }
+}
+
+template <int FM, int FN, int WGM, int WGN, int RING, int OCC = 2>
+hipError_t launch_reg(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
+                      hipStream_t s) {
     int grid = (total + 7) & ~7;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cauchy_gemm<KIND, EPI, BM, BN, BK, WGM, WGN>), dim3(grid),
+    hipLaunchKernelGGL((k_cauchy_gemm_reg<FM, FN, WGM, WGN, RING, OCC>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
     return hipGetLastError();
 }
 
+template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC = 1>
+hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
+                  hipStream_t s) {
+    int grid = (total + 7) & ~7;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cauchy_gemm<KIND, EPI, BM, BN, BK, WGM, WGN, SCHED, OCC>), dim3(grid),
+                       dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
+    return hipGetLastError();
+}
+
+// Two workgroups per CU for the 128 x 128 LDS kernel where its registers
+// allow it (generated and loaded B); the interpolation kind keeps one.
+template <int KIND>
+constexpr int occ128() { return KIND == 1 ? 1 : 2; }
+// The late-write schedule holds more registers; the interpolation and
+// adjoint kinds keep the spread schedule.
+template <int KIND>
+constexpr int sched256() { return (KIND == 1 || KIND == 3) ? 0 : 1; }
+
 template <int KIND>
 hipError_t launch_variant(const GemmTask* tasks, const int* tile_start, int ntasks,
                           int total, int variant, hipStream_t s) {
+    constexpr int O = occ128<KIND>();
+    constexpr int S = sched256<KIND>();
     switch (variant) {
-        case 1: return launch<KIND, 0, 128, 128, 16, 2, 2>(tasks, tile_start, ntasks, total, s);
-        case 2: return launch<KIND, 0, 64, 64, 16, 1, 1>(tasks, tile_start, ntasks, total, s);
-        case 3: return launch<KIND, 0, 128, 128, 32, 2, 2>(tasks, tile_start, ntasks, total, s);
-        default: return launch<KIND, 0, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+        case 1: return launch<KIND, 0, 128, 128, 16, 2, 2, 0, O>(tasks, tile_start, ntasks, total, s);
+        case 2: return launch<KIND, 0, 64, 64, 16, 1, 1, 0>(tasks, tile_start, ntasks, total, s);
+        case 3: return launch<KIND, 0, 128, 128, 32, 2, 2, 0>(tasks, tile_start, ntasks, total, s);
+        case 4: return launch<KIND, 0, 256, 128, 16, 4, 2, S>(tasks, tile_start, ntasks, total, s);
+        case 5:
+            if constexpr (KIND == 0)
+                return launch_reg<4, 4, 1, 1, 4>(tasks, tile_start, ntasks, total, s);
+            else
+                return launch<KIND, 0, 64, 64, 16, 1, 1, 0>(tasks, tile_start, ntasks, total, s);
+        default:
+            if constexpr (KIND == 0)
+                return launch_reg<8, 2, 1, 4, 3>(tasks, tile_start, ntasks, total, s);
+            else
+                return launch<KIND, 0, 128, 128, 16, 2, 2, 0, O>(tasks, tile_start, ntasks, total,
+                                                                 s);
     }
 }
 
 }  // namespace
 
-// Tile variants: 0 (default) 256 x 128, BK 16, 4 x 2 waves (two waves per
-// SIMD); 1: 128 x 128, BK 16, 2 x 2 waves; 2: 64 x 64, BK 16, one wave;
-// 3: 128 x 128, BK 32, 2 x 2 waves.
+// Tile variants (one tile shape per variant for every kernel kind, since the
+// host sizes the task tiles): 0 (default) 128 x 128, the register-pipelined
+// kernel for generated U (waves of 128 x 32), the LDS kernel otherwise;
+// 1: 128 x 128 LDS kernel, BK 16, two workgroups per CU; 2: 64 x 64 LDS
+// kernel, one wave; 3: 128 x 128 LDS kernel, BK 32; 4: 256 x 128 LDS kernel
+// with the late-write schedule; 5: 64 x 64, register-pipelined for generated
+// U (one 64 x 64 wave), LDS otherwise.
 int dc_gemm_tile_m(int variant) {
     switch (variant) {
-        case 1: case 3: return 128;
-        case 2: return 64;
-        default: return 256;
+        case 2: case 5: return 64;
+        case 4: return 256;
+        default: return 128;
     }
 }
 
 int dc_gemm_tile_n(int variant) {
     switch (variant) {
-        case 2: return 64;
+        case 2: case 5: return 64;
         default: return 128;
     }
 }
@@ -368,12 +591,12 @@ hipError_t dc_launch_interp_gemm(const GemmTask* tasks, const int* tile_start, i
 
 hipError_t dc_launch_loaded_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
                                  int total, hipStream_t s) {
-    return launch<2, 0, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+    return launch<2, 0, 256, 128, 16, 4, 2, sched256<2>()>(tasks, tile_start, ntasks, total, s);
 }
 
 hipError_t dc_launch_adjoint_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
                                   int total, hipStream_t s) {
-    return launch<3, 1, 256, 128, 16, 4, 2>(tasks, tile_start, ntasks, total, s);
+    return launch<3, 1, 256, 128, 16, 4, 2, sched256<3>()>(tasks, tile_start, ntasks, total, s);
 }
 
 int dc_band_waves_n() { return 2; }

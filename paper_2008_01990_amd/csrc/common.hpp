@@ -11,6 +11,10 @@
 
 typedef double dc_double4 __attribute__((ext_vector_type(4)));
 
+// Compile-time flags passed to generic lambdas.
+struct dc_true_type { static constexpr bool value = true; };
+struct dc_false_type { static constexpr bool value = false; };
+
 // Reciprocal to full double precision: hardware estimate plus two
 // Newton-Raphson corrections r <- r + r (1 - x r).
 __device__ __forceinline__ double dc_rcp(double x) {
@@ -20,6 +24,16 @@ __device__ __forceinline__ double dc_rcp(double x) {
     e = __builtin_fma(-x, r, 1.0);
     r = __builtin_fma(r, e, r);
     return r;
+}
+
+// Reciprocal with one cubic correction: with e = 1 - x r0 (exact in the fma),
+// 1/x = r0 (1 + e + e^2 + ...), and e^3 is far below double rounding for the
+// hardware estimate r0, so r0 + r0 (e + e^2) is as accurate as two
+// Newton-Raphson steps at three fma instead of four.
+__device__ __forceinline__ double dc_rcp3(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(__builtin_fma(e, e, e), r, r);
 }
 
 // Loads through the global address space: the compiler then emits

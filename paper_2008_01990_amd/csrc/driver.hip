@@ -71,11 +71,10 @@ void split(std::vector<std::vector<Node>>& by_depth, std::vector<Node>& leaves, 
 }
 
 // Product tile shape of a level: a forced variant, or by the level's largest
-// merge (small merges waste most of a 256 x 128 tile).
+// merge (levels of small merges take 64 x 64 tiles: more tiles per merge).
 int level_variant(int forced, int max_m) {
     if (forced > 0) return forced;
-    if (max_m <= 256) return 2;
-    if (max_m <= 1024) return 1;
+    if (max_m <= 256) return 5;
     return 0;
 }
 
@@ -285,7 +284,7 @@ hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Sc
                                     hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) return err;
-    const int b = std::min(o.lr_block, 2048);
+    const int b = std::min(o.lr_block, dc_lowrank_max_block(true));
     for (int i = 0; i < nm; ++i) {
         const Node& N = P.merges[first + i];
         const MergeCnt& C = cnt[i];
@@ -414,7 +413,7 @@ extern "C" void dc_opts_default(dc_opts* o) {
 static int check_opts(const dc_opts& o) {
     if (o.leaf < 1 || o.leaf > DC_MAX_LEAF) return 1;
     if (!(o.lr_tol >= 0.0)) return 1;
-    if (o.lr_block < 16 || o.lr_block > 2048) return 1;
+    if (o.lr_block < 16 || o.lr_block > dc_lowrank_max_block(true)) return 1;
     return 0;
 }
 

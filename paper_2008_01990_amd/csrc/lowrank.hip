@@ -37,7 +37,8 @@
 namespace {
 
 constexpr int NT = 1024;
-constexpr int MAX_B = 2048;
+constexpr int MAX_B_OFF = 2048;   // block size limit with column offsets (merge nodes)
+constexpr int MAX_B_GEN = 4096;   // block size limit with plain column nodes
 constexpr int MAX_R = 128;
 
 struct SrrscOut {
@@ -48,14 +49,21 @@ struct SrrscOut {
     double* vk;       // p*p*b: v^(r) of the block's columns (0 on skeletons)
 };
 
+// One workgroup per block (I, J).  MB: LDS capacity in generators; OFF: the
+// column nodes carry an offset (w_j = cbase_j + coff_j, the merge's (origin,
+// tau) form); STORE: write the skeleton and interpolation generators, else only
+// count the rank (up to rmax).
+template <int MB, bool OFF, bool STORE>
 __global__ __launch_bounds__(NT)
 void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __restrict__ u0,
              const double* __restrict__ cbase, const double* __restrict__ coff,
              const double* __restrict__ v0, double tol, int rmax, SrrscOut O) {
-    __shared__ double sd[MAX_B], su[MAX_B], swb[MAX_B], swo[MAX_B], sv[MAX_B];
+    constexpr int JJ = (MB + NT - 1) / NT;    // columns per thread
+    __shared__ double sd[MB], su[MB], swb[MB], sv[MB];
+    __shared__ double swo[OFF ? MB : 1];
     __shared__ double wv[NT / 64];
     __shared__ int wi[NT / 64];
-    __shared__ int spr[MAX_R], spc[MAX_R];
+    __shared__ int spr[STORE ? MAX_R : 1], spc[STORE ? MAX_R : 1];
     __shared__ double s_max;
     __shared__ int s_piv;
 
@@ -74,25 +82,40 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
     }
     for (int j = tid; j < bj; j += NT) {
         swb[j] = cbase[c0 + j];
-        swo[j] = coff ? coff[c0 + j] : 0.0;
+        if constexpr (OFF) swo[j] = coff[c0 + j];
         sv[j] = v0[c0 + j];
     }
     __syncthreads();
 
     const int lane = tid & 63, w = tid >> 6;
-    const int nflat = bi * bj;
     int k = 0;
     bool dense = false;
     for (;;) {
         // Complete pivoting: largest |A^(k)_ij| = |u_i v_j / (d_i - w_j)|,
-        // ties to the smallest row-major position.
-        double best = -1.0;
+        // ties to the smallest row-major position.  Each thread owns the
+        // columns tid, tid + NT, ... (held in registers) and walks all rows,
+        // so its own candidates arrive in increasing position order.
+        double cw[JJ], co[JJ], cv[JJ];
+#pragma unroll
+        for (int t = 0; t < JJ; ++t) {
+            const int j = tid + t * NT;
+            const bool ok = j < bj;
+            cw[t] = ok ? swb[j] : 0.0;
+            co[t] = (OFF && ok) ? swo[j] : 0.0;
+            cv[t] = ok ? sv[j] : 0.0;       // 0 => never a candidate
+        }
+        // best starts at 0: padded slots (v = 0) and zeroed pivot rows and
+        // columns never become candidates; the loop stops at tol > 0 anyway.
+        double best = 0.0;
         int bf = INT_MAX;
-        for (int f = tid; f < nflat; f += NT) {
-            const int i = f / bj;
-            const int j = f - i * bj;
-            const double val = fabs(su[i] * sv[j] * dc_rcp((sd[i] - swb[j]) - swo[j]));
-            if (val > best) { best = val; bf = f; }
+        for (int i = 0; i < bi; ++i) {
+            const double di = sd[i], ui = su[i];
+#pragma unroll
+            for (int t = 0; t < JJ; ++t) {
+                if (t * NT >= bj) break;        // uniform over the workgroup
+                const double val = fabs(ui * cv[t] * dc_rcp((di - cw[t]) - co[t]));
+                if (val > best) { best = val; bf = i * bj + tid + t * NT; }
+            }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -115,40 +138,48 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
         if (k == rmax) { dense = true; break; }
         const int pi = s_piv / bj;
         const int pj = s_piv - pi * bj;
-        if (tid == 0) { spr[k] = pi; spc[k] = pj; }
-        const double dk = sd[pi], wbk = swb[pj], wok = swo[pj];
+        if constexpr (STORE) {
+            if (tid == 0) { spr[k] = pi; spc[k] = pj; }
+        }
+        const double dk = sd[pi], wbk = swb[pj];
+        const double wok = OFF ? swo[pj] : 0.0;
         // Theorem 1 generator updates (the pivot row and column become 0).
         for (int i = tid; i < bi; i += NT)
             su[i] *= (sd[i] - dk) * dc_rcp((sd[i] - wbk) - wok);
-        for (int j = tid; j < bj; j += NT)
-            sv[j] *= ((swb[j] - wbk) + (swo[j] - wok)) * dc_rcp((swb[j] - dk) + swo[j]);
+        for (int j = tid; j < bj; j += NT) {
+            const double wo = OFF ? swo[j] : 0.0;
+            sv[j] *= ((swb[j] - wbk) + (wo - wok)) * dc_rcp((swb[j] - dk) + wo);
+        }
         ++k;
         __syncthreads();
     }
     if (tid == 0) O.rank[pair] = dense ? -2 : k;
-    if (dense) {
-        // every column becomes a skeleton column: v^(r) = 0 throughout
-        for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = 0.0;
-        return;
-    }
-    const long long pb = (long long)pair * rmax;
-    // Theorem 2, eq. yk: y_a = prod_{c != a} (d_c - w_a)/(w_c - w_a) * (d_a - w_a)/v0_a.
-    for (int a = tid; a < k; a += NT) {
-        const int ja = spc[a];
-        const double wba = swb[ja], woa = swo[ja];
-        double y = 1.0;
-        for (int c = 0; c < k; ++c) {
-            if (c == a) continue;
-            const double num = (sd[spr[c]] - wba) - woa;
-            const double den = (swb[spc[c]] - wba) + (swo[spc[c]] - woa);
-            y *= num * dc_rcp(den);
+    if constexpr (STORE) {
+        if (dense) {
+            // every column becomes a skeleton column: v^(r) = 0 throughout
+            for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = 0.0;
+            return;
         }
-        y *= ((sd[spr[a]] - wba) - woa) * dc_rcp(v0[c0 + ja]);
-        O.y[pb + a] = y;
-        O.prow[pb + a] = spr[a];
-        O.pcol[pb + a] = ja;
+        const long long pb = (long long)pair * rmax;
+        // Theorem 2, eq. yk: y_a = prod_{c != a} (d_c - w_a)/(w_c - w_a) * (d_a - w_a)/v0_a.
+        for (int a = tid; a < k; a += NT) {
+            const int ja = spc[a];
+            const double wba = swb[ja], woa = OFF ? swo[ja] : 0.0;
+            double y = 1.0;
+            for (int c = 0; c < k; ++c) {
+                if (c == a) continue;
+                const double woc = OFF ? swo[spc[c]] : 0.0;
+                const double num = (sd[spr[c]] - wba) - woa;
+                const double den = (swb[spc[c]] - wba) + (woc - woa);
+                y *= num * dc_rcp(den);
+            }
+            y *= ((sd[spr[a]] - wba) - woa) * dc_rcp(v0[c0 + ja]);
+            O.y[pb + a] = y;
+            O.prow[pb + a] = spr[a];
+            O.pcol[pb + a] = ja;
+        }
+        for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = sv[j];
     }
-    for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = sv[j];
 }
 
 __global__ void k_nodes(int K, const double* D, const int* org, const double* tau,
@@ -179,6 +210,40 @@ struct Compressed {
     SrrscOut out{};
 };
 
+// The SRRSC instance that fits: column offsets present (merge nodes, b up to
+// MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); store or count only.
+hipError_t launch_srrsc(int K, int b, int p, const double* D, const double* zhat,
+                        const double* cbase, const double* coff, const double* scale,
+                        double tol, int rmax, bool store, const SrrscOut& out, hipStream_t s) {
+    const dim3 g((unsigned)((size_t)p * p)), blk(NT);
+    if (coff && b > MAX_B_OFF) return hipErrorInvalidValue;
+    if (b > MAX_B_GEN) return hipErrorInvalidValue;
+    if (coff) {
+        if (store)
+            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, true, true>), g, blk, 0, s, K, b, p, D, zhat,
+                               cbase, coff, scale, tol, rmax, out);
+        else
+            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, true, false>), g, blk, 0, s, K, b, p, D, zhat,
+                               cbase, coff, scale, tol, rmax, out);
+    } else if (b <= MAX_B_OFF) {
+        if (store)
+            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, false, true>), g, blk, 0, s, K, b, p, D, zhat,
+                               cbase, coff, scale, tol, rmax, out);
+        else
+            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, false, false>), g, blk, 0, s, K, b, p, D,
+                               zhat, cbase, coff, scale, tol, rmax, out);
+    } else {
+        if (store)
+            hipLaunchKernelGGL((k_srrsc<MAX_B_GEN, false, true>), g, blk, 0, s, K, b, p, D, zhat,
+                               cbase, coff, scale, tol, rmax, out);
+        else
+            hipLaunchKernelGGL((k_srrsc<MAX_B_GEN, false, false>), g, blk, 0, s, K, b, p, D,
+                               zhat, cbase, coff, scale, tol, rmax, out);
+    }
+    return hipGetLastError();
+}
+
+// coff == nullptr: plain column nodes w_j = cbase_j.
 hipError_t compress(int K, int b, double tol, const double* D, const double* zhat,
                     const double* cbase, const double* coff, const double* scale,
                     hipStream_t s, Compressed& Cm) {
@@ -199,13 +264,10 @@ hipError_t compress(int K, int b, double tol, const double* D, const double* zha
     Cm.out.pcol = reinterpret_cast<int*>(Cm.dev + o_pcol);
     Cm.out.y = reinterpret_cast<double*>(Cm.dev + o_y);
     Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o_vk);
-    hipLaunchKernelGGL(k_srrsc, dim3((unsigned)p2), dim3(NT), 0, s, K, b, Cm.p, D, zhat,
-                       cbase, coff, scale, tol, Cm.rmax, Cm.out);
-    err = hipGetLastError();
+    err = launch_srrsc(K, b, Cm.p, D, zhat, cbase, coff, scale, tol, Cm.rmax, true, Cm.out, s);
     if (err != hipSuccess) return err;
     Cm.rank.resize(p2);
     Cm.pcol.resize(p2 * Cm.rmax);
-    Cm.y.resize(p2 * Cm.rmax);
     err = hipMemcpyAsync(Cm.rank.data(), Cm.out.rank, p2 * sizeof(int), hipMemcpyDeviceToHost, s);
     if (err == hipSuccess)
         err = hipMemcpyAsync(Cm.pcol.data(), Cm.out.pcol, p2 * Cm.rmax * sizeof(int),
@@ -462,15 +524,26 @@ hipError_t dc_disable_tasks(GemmTask* tasks, int n, const int* zero, hipStream_t
     return hipGetLastError();
 }
 
+int dc_lowrank_max_block(bool offsets) { return offsets ? MAX_B_OFF : MAX_B_GEN; }
+
 hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
                              const int* org, const double* tau, const double* zhat,
                              const double* scale, double* C, long long ldc, double lr_tol,
                              int lr_block, hipStream_t stream) {
-    if (lr_block > MAX_B) lr_block = MAX_B;
+    if (lr_block > dc_lowrank_max_block(org != nullptr)) return hipErrorInvalidValue;
+    // Merge generators become (base, offset) column nodes; plain column nodes
+    // (org == NULL) are used as they are.
+    const double* cb = tau;
+    const double* co = nullptr;
     double* nodes = nullptr;
-    hipError_t err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
-    if (err != hipSuccess) return err;
-    err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
+    hipError_t err = hipSuccess;
+    if (org) {
+        err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
+        if (err != hipSuccess) return err;
+        err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
+        cb = nodes;
+        co = nodes + K;
+    }
     std::vector<LrHalf> halves(1);
     LrHalf& H = halves[0];
     H.A = Qnd;
@@ -483,16 +556,16 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     H.cpos = nullptr;
     H.w_row0 = 0;
     if (err == hipSuccess)
-        err = dc_lowrank_product(K, lr_block, lr_tol, Dbar, zhat, nodes, nodes + K, scale,
-                                 halves, m, 0, stream, nullptr);
-    hipFreeAsync(nodes, stream);
+        err = dc_lowrank_product(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, halves, m, 0,
+                                 stream, nullptr);
+    if (nodes) hipFreeAsync(nodes, stream);
     return err;
 }
 
 extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
                                       const double* tau, const double* zhat,
                                       const double* scale, double lr_tol, int lr_block,
-                                      int* ranks_host, hipStream_t stream) {
+                                      int rank_cap, int* ranks_host, hipStream_t stream) {
     if (K < 1) return -1;
     if (!Dbar) return -2;
     if (!tau) return -4;
@@ -500,19 +573,44 @@ extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
     if (!scale) return -6;
     if (!(lr_tol > 0.0)) return -7;
     if (lr_block <= 0) lr_block = 1024;
-    if (lr_block > MAX_B) return -8;
-    if (!ranks_host) return -9;
+    if (lr_block > dc_lowrank_max_block(org != nullptr)) return -8;
+    if (rank_cap < 0) return -9;
+    if (!ranks_host) return -10;
+    const double* cb = tau;
+    const double* co = nullptr;
     double* nodes = nullptr;
-    hipError_t err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
-    if (err != hipSuccess) return (int)err;
-    err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
-    Compressed Cm;
-    if (err == hipSuccess)
-        err = compress(K, lr_block, lr_tol, Dbar, zhat, nodes, nodes + K, scale, stream, Cm);
-    if (err == hipSuccess)
-        std::memcpy(ranks_host, Cm.rank.data(), Cm.rank.size() * sizeof(int));
-    if (Cm.dev) hipFreeAsync(Cm.dev, stream);
-    hipFreeAsync(nodes, stream);
+    hipError_t err = hipSuccess;
+    if (org) {
+        err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
+        if (err != hipSuccess) return (int)err;
+        err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
+        cb = nodes;
+        co = nodes + K;
+    }
+    const int p = (K + lr_block - 1) / lr_block;
+    const size_t p2 = (size_t)p * p;
+    if (rank_cap == 0) {
+        // the ranks the low-rank product itself uses
+        Compressed Cm;
+        if (err == hipSuccess)
+            err = compress(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, stream, Cm);
+        if (err == hipSuccess)
+            std::memcpy(ranks_host, Cm.rank.data(), Cm.rank.size() * sizeof(int));
+        if (Cm.dev) hipFreeAsync(Cm.dev, stream);
+    } else {
+        // count only, up to rank_cap
+        int* rk = nullptr;
+        if (err == hipSuccess) err = hipMallocAsync((void**)&rk, p2 * sizeof(int), stream);
+        SrrscOut out{};
+        out.rank = rk;
+        if (err == hipSuccess)
+            err = launch_srrsc(K, lr_block, p, Dbar, zhat, cb, co, scale, lr_tol,
+                               std::min(rank_cap, lr_block), false, out, stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(ranks_host, rk, p2 * sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (rk) hipFreeAsync(rk, stream);
+    }
+    if (nodes) hipFreeAsync(nodes, stream);
     hipError_t e2 = hipStreamSynchronize(stream);
     return (int)(err != hipSuccess ? err : e2);
 }

@@ -22,12 +22,17 @@ struct LrHalf {
 };
 
 // Low-rank product over the given halves (host-synchronising: reads the
-// ranks).  cbase/coff are the column nodes, scale the column scales.  wrows
+// ranks).  cbase/coff are the column nodes w_j = cbase_j + coff_j (coff null:
+// plain nodes w_j = cbase_j), scale the column scales.  wrows
 // is the row count of the skeleton panel W (sum of the halves' rows).
 hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
                               const double* cbase, const double* coff, const double* scale,
                               std::vector<LrHalf>& halves, int wrows, int variant,
                               hipStream_t s, double* flops_out);
+
+// Largest block size b of the compression: with column offsets (merge nodes)
+// or with plain column nodes.
+int dc_lowrank_max_block(bool offsets);
 
 hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
                              const int* org, const double* tau, const double* zhat,

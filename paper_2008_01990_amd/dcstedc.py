@@ -48,7 +48,7 @@ SIGNATURES = [
     ("dc_secular", c_int, [c_int, P, P, c_double, P, P, P, P, P, c_int, P]),
     ("dc_merge_update", c_int, [c_int, c_int, P, c_int, P, P, P, P, P, P, c_int,
                                 c_double, c_int, P]),
-    ("dc_merge_lowrank_ranks", c_int, [c_int, P, P, P, P, P, c_double, c_int, P, P]),
+    ("dc_merge_lowrank_ranks", c_int, [c_int, P, P, P, P, P, c_double, c_int, c_int, P, P]),
     ("dc_stedc_backward", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P]),
     ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
     ("dc_last_info", c_int, [P]),
@@ -233,15 +233,20 @@ def secular(D, z, rho, max_iter=200):
     return org, tau, zhat, scale
 
 
-def merge_lowrank_ranks(Dbar, org, tau, zhat, scale, lr_tol, lr_block):
-    """Block ranks (nb x nb numpy array, -1 diagonal, -2 kept dense)."""
+def merge_lowrank_ranks(Dbar, org, tau, zhat, scale, lr_tol, lr_block, rank_cap=0):
+    """Block ranks (nb x nb numpy array, -1 diagonal, -2 above the cap).
+
+    rank_cap 0 gives the ranks the low-rank product uses (cap min(128, b/2));
+    rank_cap > 0 counts ranks up to that cap without forming the factors.
+    """
     import numpy as np
     K = Dbar.numel()
     nb = (K + lr_block - 1) // lr_block
     out = (ctypes.c_int * (nb * nb))()
     _check(load().dc_merge_lowrank_ranks(K, _ptr(Dbar), _ptr(org), _ptr(tau), _ptr(zhat),
                                          _ptr(scale), float(lr_tol), int(lr_block),
-                                         ctypes.cast(out, ctypes.c_void_p), _stream()),
+                                         int(rank_cap), ctypes.cast(out, ctypes.c_void_p),
+                                         _stream()),
            "dc_merge_lowrank_ranks")
     return np.array(out[:], dtype=np.int64).reshape(nb, nb)
 

@@ -16,6 +16,9 @@ method's arithmetic.
                    c_l = sqrt((xi_l+1)(xi_l+2)(l+m+1)(l+m+2) /
                               ((2l+1)(2l+3)^2 (2l+5))),
                    d_l = (2l(l+1) - 2m^2 - 1) / ((2l-1)(2l+3)); m = n by default.
+* ``block_cyclic_order`` -- the index order in which a 1-D block-cyclic
+                   distribution (block N_B over P process rows) stores a
+                   vector: process 0's blocks first, then process 1's, ...
 * ``random_tridiag`` / ``batched_sizes`` -- many small problems with
                    d, e ~ U(-1, 1) and sizes log-uniform in [lo, hi].
 * ``adjoint_problem`` -- perturbed 1-2-1 matrix plus loss weights w, c, u.
@@ -86,6 +89,15 @@ def example_cauchy(n, seed=0, a=1.0, b=9.0):
     u = rng.uniform(0.0, 1.0, n)
     v = rng.uniform(0.0, 1.0, n)
     return u, v, d, w
+
+
+def block_cyclic_order(n, nprocs, nb):
+    """Global indices in storage order of a block-cyclic layout: block k
+    (indices k*nb .. k*nb+nb-1) lives on process k mod nprocs, and each
+    process keeps its blocks in increasing order.  nb >= n/nprocs gives the
+    contiguous (block) layout, i.e. the identity."""
+    blocks = np.arange(n) // nb
+    return np.concatenate([np.flatnonzero(blocks % nprocs == p) for p in range(nprocs)])
 
 
 def random_secular(K, seed=0, spread=1.0, rho=None, cluster=False):

@@ -49,6 +49,17 @@ def test_host_side_argument_checks_need_no_gpu():
     assert lib.dc_merge_update(-1, 1, None, 1, None, None, None, None, None, None, 1,
                                0.0, 0, None) == -1
     assert lib.dc_secular(0, None, None, 1.0, None, None, None, None, None, 0, None) == -1
+    # block-size limits of the low-rank merge: 2048 with merge nodes (org
+    # given), 4096 with plain column nodes; checked before any device work
+    fake = ctypes.c_void_p(256)
+    assert lib.dc_merge_update(8192, 8192, fake, 8192, fake, fake, fake, fake, fake, fake,
+                               8192, 1e-10, 4096, None) == -13
+    assert lib.dc_merge_update(8192, 8192, fake, 8192, fake, None, fake, fake, fake, fake,
+                               8192, 1e-10, 8192, None) == -13
+    assert lib.dc_merge_lowrank_ranks(8192, fake, fake, fake, fake, fake, 1e-10, 4096, 0,
+                                      fake, None) == -8
+    assert lib.dc_merge_lowrank_ranks(8192, fake, None, fake, fake, fake, 1e-10, 1024, -1,
+                                      fake, None) == -9
     assert lib.dc_strerror(0) == b"success"
     o = dcstedc.DcOpts()
     lib.dc_opts_default(ctypes.byref(o))

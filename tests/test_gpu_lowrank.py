@@ -10,6 +10,7 @@ and the ranks agree up to such ties.
 """
 import numpy as np
 import pytest
+import scipy.linalg
 import torch
 
 from oracle import dc, metrics, secular, srrsc
@@ -77,11 +78,17 @@ def test_lowrank_general_cauchy_example1(lib):
     assert np.all(np.abs(C - A @ B) <= bound)
 
 
-@pytest.mark.parametrize("family,n", [("toeplitz", 2048), ("clement", 2048)])
-def test_lowrank_solver_meets_bounds(lib, family, n):
-    announce(f"lowrank stedc {family} n={n}")
-    d, e = W.toeplitz(n) if family == "toeplitz" else W.clement(n)
-    kw = dict(leaf=64, lr_tol=1e-10, lr_block=256, lr_min_k=512)
+@pytest.mark.parametrize("family,n,b", [("toeplitz", 2048, 256), ("clement", 2048, 256),
+                                        ("hermite", 2048, 128), ("sht", 2048, 128)])
+def test_lowrank_solver_meets_bounds(lib, family, n, b):
+    # The halves of the Hermite and SHT matrices have different spectral
+    # ranges, so with b = 128 some sorted blocks of the top merge hold no
+    # eigenvalue of the first half (2 for Hermite, 1 for SHT at n = 2048):
+    # that half's product over such a block is empty and must store zeros.
+    announce(f"lowrank stedc {family} n={n} b={b}")
+    d, e = {"toeplitz": W.toeplitz, "clement": W.clement, "hermite": W.hermite,
+            "sht": W.sht}[family](n)
+    kw = dict(leaf=64, lr_tol=1e-10, lr_block=b, lr_min_k=512)
     lam, Q = lib.stedc(cuda(d), cuda(e), **kw)
     stats = lib.last_stats()
     assert any(r["path"] == 1 for r in stats)
@@ -89,11 +96,55 @@ def test_lowrank_solver_meets_bounds(lib, family, n):
     if family == "toeplitz":
         k = np.arange(1, n + 1)
         ref = 2 - 2 * np.cos(k * np.pi / (n + 1))
-    else:
+    elif family == "clement":
         ref = np.arange(-(n - 1), n, 2, dtype=float)
+    else:
+        ref = np.sort(scipy.linalg.eigh_tridiagonal(d, e, eigvals_only=True))
     assert metrics.eig_error(lam, ref) <= 1e-13
     assert metrics.orthogonality(Q) <= 1e-9
     assert metrics.residual(d, e, lam, Q) <= 1e-9
-    lo, Qo = dc.eigh_tridiagonal(d, e, leaf=64, lr_tol=1e-10, lr_block=256, lr_min_k=512)
+    lo, Qo = dc.eigh_tridiagonal(d, e, **kw)
     # both sides perturb U by up to tol per entry: eigenvalues move at ~tol scale
     assert np.abs(lam - lo).max() <= 1e-11 * np.abs(lo).max()
+
+
+@pytest.mark.parametrize("nb", [16, 512])
+def test_rank_count_block_layouts_match_oracle(lib, nb):
+    # Example 0's B at n = 2048 on 4 process rows, blocks 512 x 512 (Table
+    # "rank" at a quarter of its size).  nb = 512 is the contiguous layout;
+    # nb = 16 the block-cyclic one, whose ranks exceed the product's cap.
+    n, P, b, tol = 2048, 4, 512, 1e-10
+    announce(f"rank count layout nb={nb}")
+    u, v, d, w = W.example_cauchy(n, seed=9)
+    perm = W.block_cyclic_order(n, P, nb)
+    u, v, d, w = u[perm], v[perm], d[perm], w[perm]
+    gens = (cuda(d), None, cuda(w), cuda(u), cuda(v), tol, b)
+    ranks_g = lib.merge_lowrank_ranks(*gens, rank_cap=b)
+    assert np.all(np.diag(ranks_g) == -1)
+    for I in (1, 2, 3):
+        r = np.arange(I * b, (I + 1) * b)
+        c = np.arange(0, b)
+        ro = srrsc.compress(srrsc.CauchyBlock(u[r], v[c], d[r], w[c], np.zeros(b)), tol)["rank"]
+        assert abs(int(ranks_g[I, 0]) - ro) <= 1
+    capped = lib.merge_lowrank_ranks(*gens)
+    if nb == 16:
+        assert ranks_g[1:, 0].min() > 128
+        assert np.all(capped[1:, 0] == -2)
+    else:
+        assert ranks_g[1:, 0].max() < 64
+        assert np.array_equal(capped, ranks_g)
+
+
+def test_lowrank_block4096_plain_nodes(lib):
+    # b = 4096 (allowed for plain column nodes) on Example 1's B, n = 8192.
+    n, m, b, tol = 8192, 64, 4096, 1e-10
+    announce("lowrank b=4096 plain nodes n=8192")
+    u, v, d, w = W.example_cauchy(n, seed=10)
+    A = W.random_matrix(m, n, seed=11)
+    B = secular.cauchy_matrix(d, None, w, u, v)
+    ranks = lib.merge_lowrank_ranks(cuda(d), None, cuda(w), cuda(u), cuda(v), tol, b)
+    assert ranks.shape == (2, 2) and ranks[0, 1] > 0 and ranks[1, 0] > 0
+    C = host(lib.merge_update(cuda(A.T), m, n, cuda(d), None, cuda(w), cuda(u), cuda(v),
+                              lr_tol=tol, lr_block=b)).T
+    bound = tol * np.abs(A).sum(axis=1)[:, None] * 1.01 + 8 * n * EPS * (np.abs(A) @ np.abs(B))
+    assert np.all(np.abs(C - A @ B) <= bound)
