@@ -108,7 +108,7 @@ def measured_traffic(workload):
     summary, or None if it was taken on another workload or on a different
     version of the kernel source."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cauchy_gemm_clement_n32768_traffic.md")
+    path = os.path.join(ROOT, "profiles", "k_cauchy_gemm_reg_clement_n32768_traffic.md")
     src = os.path.join(ROOT, "paper_2008_01990_amd", "csrc", "cauchy_gemm.hip")
     if workload != "clement_n32768_leaf64_plain" or not os.path.exists(path):
         return None
@@ -452,7 +452,7 @@ def main():
                      "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
                      "traffic": measured_traffic(f"{args.family}_n{n}_leaf{args.leaf}_plain"),
-                     "kernel": "k_cauchy_gemm (root-level merge product)",
+                     "kernel": "k_cauchy_gemm_reg (root-level merge product)",
                      "flops_per_launch": flops_lvl[-1],
                      "launch_ms": top["product_ms"]},
         "merge_product": {"total_ms": total_prod_ms, "total_flops": total_flops,

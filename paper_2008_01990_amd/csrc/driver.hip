@@ -45,9 +45,10 @@ struct Plan {
     std::vector<Node> leaves, merges;   // merges ordered by level, deepest first
     std::vector<Level> levels;
     std::vector<int> prefix;            // all per-level prefix sums
-    std::vector<long long> row0, buf_off;
+    std::vector<long long> row0, buf_off, pan_off;
     long long rows = 0;                 // sum of n
     long long buf_elems = 0;            // sum of n^2 (odd-depth buffers)
+    long long pan_elems = 0;            // sum of panel_ld(n) n (survivor panels)
     Node* d_nodes = nullptr;            // leaves then merges
     int* d_prefix = nullptr;
     int device = -1;
@@ -56,6 +57,11 @@ struct Plan {
         if (d_prefix) hipFree(d_prefix);
     }
 };
+
+// Leading dimension of a problem's survivor-panel buffer: a whole number of
+// 128-byte lines plus one, so the k-columns of a panel (read together by the
+// product's tiles) do not sit a power of two apart and share L2 sets.
+int panel_ld(int n) { return ((std::max(n, 1) + 15) & ~15) + 16; }
 
 void split(std::vector<std::vector<Node>>& by_depth, std::vector<Node>& leaves, int prob,
            int off, int m, int depth, int leaf) {
@@ -87,8 +93,10 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
     for (size_t p = 0; p < sizes.size(); ++p) {
         P->row0.push_back(P->rows);
         P->buf_off.push_back(P->buf_elems);
+        P->pan_off.push_back(P->pan_elems);
         P->rows += sizes[p];
         P->buf_elems += (long long)sizes[p] * sizes[p];
+        P->pan_elems += (long long)panel_ld(sizes[p]) * sizes[p];
         if (sizes[p] > 0) split(by_depth, P->leaves, (int)p, 0, sizes[p], 0, leaf);
     }
     for (int dep = (int)by_depth.size() - 1; dep >= 0; --dep) {
@@ -220,7 +228,7 @@ Layout layout(const Plan& P) {
     L.rho2 = o; o = align256(o + nm * sizeof(double));
     L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
     L.ints = o; o = align256(o + L.ni * R * sizeof(int));
-    L.bufs = o; o = align256(o + 2 * P.buf_elems * sizeof(double));
+    L.bufs = o; o = align256(o + (P.buf_elems + P.pan_elems) * sizeof(double));
     L.bytes = o;
     return L;
 }
@@ -455,7 +463,7 @@ extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void
     pr.B1 = reinterpret_cast<double*>(w + L.bufs);
     pr.ld1 = n;
     pr.B2 = reinterpret_cast<double*>(w + L.bufs) + (size_t)n * n;
-    pr.ld2 = n;
+    pr.ld2 = panel_ld(n);
     pr.n = n;
     pr.row0 = 0;
     pr.info = info_dev;
@@ -522,8 +530,8 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
         pr.ldq = ldq_host[p];
         pr.B1 = reinterpret_cast<double*>(w + L.bufs) + P->buf_off[p];
         pr.ld1 = std::max(1, sizes[p]);
-        pr.B2 = reinterpret_cast<double*>(w + L.bufs) + P->buf_elems + P->buf_off[p];
-        pr.ld2 = std::max(1, sizes[p]);
+        pr.B2 = reinterpret_cast<double*>(w + L.bufs) + P->buf_elems + P->pan_off[p];
+        pr.ld2 = panel_ld(sizes[p]);
         pr.n = sizes[p];
         pr.row0 = (int)P->row0[p];
         pr.info = info_dev + p;
