@@ -27,9 +27,10 @@
 //
 // Work distribution: one flat grid over the tiles of every task (every merge
 // half of a tree level).  Workgroup b runs on XCD b % 8; the flat id is
-// remapped so that each XCD owns a contiguous range of tiles, and within a
-// task the column tile varies fastest, so the workgroups resident on one XCD
-// share A row panels through that XCD's L2.
+// remapped so that each XCD runs groups of consecutive tiles (within a task
+// the column tile varies fastest, so a group shares A row panels through the
+// XCD's L2), with the groups dealt to the XCDs round-robin so that the two
+// halves of a merge, whose depths differ, load every XCD alike.
 #include "common.hpp"
 
 namespace {
@@ -76,6 +77,41 @@ __device__ __forceinline__ int find_task(const int* tile_start, int ntasks, int 
     return lo;
 }
 
+// Co-resident workgroups per XCD (32 CUs): the register kernel holds OCC
+// waves per SIMD; the LDS kernels are limited by LDS (above 80 KB: one
+// workgroup per CU) or by their waves.
+template <int WAVES, int OCC>
+constexpr int reg_group() { return 32 * (4 * OCC / WAVES > 0 ? 4 * OCC / WAVES : 1); }
+template <int BM, int BN, int WAVES, int OCC>
+constexpr int lds_group() {
+    return (2 * 16 * (BM + BN + 4) * 8 > 80 * 1024 || WAVES == 8) ? 32
+           : 32 * (4 * OCC / WAVES > 0 ? 4 * OCC / WAVES : 1);
+}
+
+// Flat tile id of workgroup b.  The hardware places workgroup b on XCD b % 8.
+// Groups of G consecutive tiles (one XCD's co-resident workgroups, which then
+// share A row panels through that XCD's L2) are dealt to the XCDs
+// round-robin, so the tiles of every task, and with them the task's depth
+// (which only the device knows), spread evenly over the eight XCDs.  The grid
+// is a multiple of 8 G.
+template <int G>
+__device__ __forceinline__ int xcd_tile(int b) {
+    const int i = b >> 3;
+    return (i / G) * (8 * G) + (b & 7) * G + (i % G);
+}
+
+// Tile of a task for its flat local index: the task's full groups are taken
+// in transposed order (8 rows of q groups), so the eight groups the XCDs run
+// at one time lie q groups apart in the task, not side by side: adjacent row
+// panels would put every XCD's loads on the same stretch of each A column.
+template <int G>
+__device__ __forceinline__ int spread_local(int local, int tiles) {
+    const int q = tiles / G / 8;
+    const int lg = local / G;
+    if (lg >= 8 * q) return local;
+    return ((lg & 7) * q + (lg >> 3)) * G + (local - lg * G);
+}
+
 template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC>
 __global__ __launch_bounds__(WGM * WGN * 64, OCC)
 void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
@@ -84,14 +120,12 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     __shared__ double As[2][BK * C_::LDA_S];
     __shared__ double Bs[2][BK * C_::LDB_S];
 
-    // XCD-aware flat id (grid size is a multiple of 8).
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    constexpr int G = lds_group<BM, BN, WGM * WGN, OCC>();
+    const int t = xcd_tile<G>(blockIdx.x);
     if (t >= total_tiles) return;
     const int ti = find_task(tile_start, ntasks, t);
     const GemmTask& T = tasks[ti];
-    const int local = t - tile_start[ti];
+    const int local = spread_local<G>(t - tile_start[ti], tile_start[ti + 1] - tile_start[ti]);
     const int tm = local / T.tiles_n;
     const int tn = local - tm * T.tiles_n;
     const int ncol = T.ncol_p ? *T.ncol_p : T.ncol;
@@ -369,13 +403,12 @@ void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict
     constexpr int WR = 16 * FM, WC = 16 * FN;
     constexpr int BM = WGM * WR, BN = WGN * WC;
     constexpr int PD = RING - 1;
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    constexpr int G = reg_group<WGM * WGN, OCC>();
+    const int t = xcd_tile<G>(blockIdx.x);
     if (t >= total_tiles) return;
     const int ti = find_task(tile_start, ntasks, t);
     const GemmTask& T = tasks[ti];
-    const int local = t - tile_start[ti];
+    const int local = spread_local<G>(t - tile_start[ti], tile_start[ti + 1] - tile_start[ti]);
     const int tm = local / T.tiles_n;
     const int tn = local - tm * T.tiles_n;
     const int ncol = T.ncol_p ? *T.ncol_p : T.ncol;
@@ -505,7 +538,8 @@ void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict
 template <int FM, int FN, int WGM, int WGN, int RING, int OCC = 2>
 hipError_t launch_reg(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
                       hipStream_t s) {
-    int grid = (total + 7) & ~7;
+    constexpr int G8 = 8 * reg_group<WGM * WGN, OCC>();
+    const int grid = (total + G8 - 1) / G8 * G8;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((k_cauchy_gemm_reg<FM, FN, WGM, WGN, RING, OCC>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
@@ -515,7 +549,8 @@ hipError_t launch_reg(const GemmTask* tasks, const int* tile_start, int ntasks, 
 template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC = 1>
 hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
                   hipStream_t s) {
-    int grid = (total + 7) & ~7;
+    constexpr int G8 = 8 * lds_group<BM, BN, WGM * WGN, OCC>();
+    const int grid = (total + G8 - 1) / G8 * G8;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((k_cauchy_gemm<KIND, EPI, BM, BN, BK, WGM, WGN, SCHED, OCC>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);

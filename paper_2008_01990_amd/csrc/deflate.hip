@@ -187,9 +187,12 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     const double tol = 8.0 * EPS * fmax(dmax, rho2);
     __syncthreads();
 
-    // Sequential deflation walk (lane 0), chunks staged through LDS.
+    // Sequential deflation walk (lane 0), chunks staged through LDS.  The
+    // walk only stores to global memory: a global load here would also wait
+    // for every store before it (one in-order counter), so state it needs
+    // again (the previous rotation's second column) stays in registers.
     int K = 0, nrot = 0, nd = 0, nch = 0;
-    int p = -1, colp = 0, typp = 0;
+    int p = -1, colp = 0, typp = 0, prev_ri = -1;
     double Dp = 0.0, zp = 0.0, lastd = -INFINITY;
     auto emit_deflated = [&](double v, int col, int typ) {
         // keep Dd ascending: insertion from the back (rarely moves)
@@ -218,12 +221,19 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         }
         __syncthreads();
         if (tid == 0) {
+            double nD = sD[0], nz = sz[0];
+            int np = sp[0];
             for (int ii = 0; ii < cn; ++ii) {
-                const double Di = sD[ii];
-                const double zi = sz[ii];
+                const double Di = nD;
+                const double zi = nz;
                 // every position is written by the merge path above; the clamp
                 // only guards the column range against a broken ordering
-                const int coli = min(max(sp[ii], 0), m - 1);
+                const int coli = min(max(np, 0), m - 1);
+                if (ii + 1 < cn) {          // next element's LDS reads in flight
+                    nD = sD[ii + 1];
+                    nz = sz[ii + 1];
+                    np = sp[ii + 1];
+                }
                 const int typi = coli < n1 ? 1 : 2;
                 if (rho2 * fabs(zi) <= tol) {
                     emit_deflated(Di, coli, typi);
@@ -245,7 +255,8 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
                     const double s = zp * ir;
                     // a new chain unless this rotation's first column is the
                     // previous rotation's second one
-                    if (nrot == 0 || S.ri[base + nrot - 1] != colp) S.rch[base + nch++] = nrot;
+                    if (nrot == 0 || prev_ri != colp) S.rch[base + nch++] = nrot;
+                    prev_ri = coli;
                     S.rp[base + nrot] = colp;
                     S.ri[base + nrot] = coli;
                     S.rc[base + nrot] = c;
