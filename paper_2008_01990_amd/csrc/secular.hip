@@ -41,27 +41,31 @@ __device__ __forceinline__ int task_of(const int* block_start, int ntasks, int b
 }
 
 struct Sums {
-    double psi, dpsi, phi, dphi, aabs;
+    double psi, dpsi, phi, dphi;
 };
 
 // Partial sums over the poles of one staged chunk assigned to this wave, for a
-// root with origin pole Do, offset tau and interval index j (poles i <= j
-// are "left").  sD/sz2 hold the chunk starting at pole c0.
+// root with origin pole Do, offset tau and interval index j.  sD/sz2 hold the
+// chunk starting at pole c0.  Poles i <= j lie left of the root (terms
+// negative, psi), the others right of it (terms positive, phi): the slice is
+// split at j instead of selecting per term, and sum |term| = phi - psi.
 __device__ __forceinline__ void chunk_sums(const double* sD, const double* sz2, int c0,
                                            int a, int b, double Do, double tau, int j,
                                            Sums& s) {
+    const int split = min(max(j - c0 + 1, a), b);
 #pragma unroll 4
-    for (int q = a; q < b; ++q) {
-        const double t = (sD[q] - Do) - tau;
-        const double r = dc_rcp(t);
+    for (int q = a; q < split; ++q) {
+        const double r = dc_rcp3((sD[q] - Do) - tau);
         const double term = sz2[q] * r;
-        const double dterm = term * r;
-        const bool left = c0 + q <= j;
-        s.psi += left ? term : 0.0;
-        s.dpsi += left ? dterm : 0.0;
-        s.phi += left ? 0.0 : term;
-        s.dphi += left ? 0.0 : dterm;
-        s.aabs += fabs(term);
+        s.psi += term;
+        s.dpsi += term * r;
+    }
+#pragma unroll 4
+    for (int q = split; q < b; ++q) {
+        const double r = dc_rcp3((sD[q] - Do) - tau);
+        const double term = sz2[q] * r;
+        s.phi += term;
+        s.dphi += term * r;
     }
 }
 
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(NW * 64)
 void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                      int ntasks, int max_iter) {
     __shared__ double sD[CH], sz2[CH];
-    __shared__ double red[5][NW][NR];
+    __shared__ double red[4][NW][NR];
     __shared__ double s_tau[NR];
     __shared__ double s_do[NR];
     __shared__ int s_live;
@@ -134,7 +138,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
 
     for (int it = 0;; ++it) {
         // Every wave: partial sums at the current iterate of root `lane`.
-        Sums p{0.0, 0.0, 0.0, 0.0, 0.0};
+        Sums p{0.0, 0.0, 0.0, 0.0};
         const double Do = s_do[lane];
         const double tcur = s_tau[lane];
         for (int c0 = 0; c0 < K; c0 += CH) {
@@ -153,18 +157,17 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         red[1][w][lane] = p.dpsi;
         red[2][w][lane] = p.phi;
         red[3][w][lane] = p.dphi;
-        red[4][w][lane] = p.aabs;
         __syncthreads();
         if (w == 0) {
-            double psi = 0, dpsi = 0, phi = 0, dphi = 0, aabs = 0;
+            double psi = 0, dpsi = 0, phi = 0, dphi = 0;
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
                 psi += red[0][q][lane];
                 dpsi += red[1][q][lane];
                 phi += red[2][q][lane];
                 dphi += red[3][q][lane];
-                aabs += red[4][q][lane];
             }
+            const double aabs = phi - psi;   // sum of |terms|
             const double g = 1.0 / rho + psi + phi;
             if (!done) {
                 ++iters;
