@@ -9,9 +9,13 @@
 // Deflation (tol = 8 eps max(max|D|, rho')): z-negligible entries become
 // eigenpairs as they are; neighbouring survivors p < i with
 // |(D_i - D_p) c s| <= tol for the Givens pair that zeroes z_p are rotated
-// and p deflated.  The walk over survivors is inherently sequential (each
-// test involves the last survivor), so one lane performs it while the
-// workgroup stages the sorted arrays through LDS in chunks.
+// and p deflated.  The walk over survivors is sequential in principle (each
+// test involves the last survivor, which a rotation modifies), but only along
+// runs of rotations: the workgroup walks segments of the survivor list in
+// parallel assuming an unrotated start, one lane corrects the segment starts
+// in order (re-walking only until the two walks agree on a pair that does not
+// rotate), and the segments are walked again from their true starts to count
+// and then to write their output.
 //
 // Every column of the merge block carries row-type bits: 1 if it may be
 // non-zero in the top rows [0, n1), 2 in the bottom rows [n1, m).  Columns of
@@ -26,7 +30,6 @@ namespace {
 
 constexpr double EPS = 2.220446049250313e-16;
 constexpr int NT = 1024;
-constexpr int CH = 2048;       // scan chunk staged through LDS
 
 __device__ __forceinline__ int block_of(const int* blk_start, int nm, int b) {
     int lo = 0, hi = nm - 1;
@@ -53,6 +56,79 @@ __device__ __forceinline__ int count_le(const double* a, int n, double x) {
         if (a[mid] <= x) lo = mid + 1; else hi = mid;
     }
     return lo;
+}
+
+// Exclusive prefix sum of one int per thread over the NT threads of the
+// workgroup; *total receives the sum.  ws: NT / 64 ints of LDS.
+__device__ int block_excl_scan(int v, int* ws, int* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int q = 0; q < NT / 64; ++q) {
+        if (q < w) before += ws[q];
+        tot += ws[q];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
+
+// Exclusive prefix maximum (-inf for thread 0) of one double per thread.
+__device__ double block_excl_max(double v, double* ws) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(x, off, 64);
+        if (lane >= off) x = fmax(x, y);
+    }
+    double ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = -INFINITY;
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    double before = -INFINITY;
+    for (int q = 0; q < w; ++q) before = fmax(before, ws[q]);
+    __syncthreads();
+    return fmax(before, ex);
+}
+
+// State of the walk: the current candidate survivor p (unrotated, or the
+// result of rotations).
+struct WState {
+    double D, z;
+    int col, typ;
+    int orig;       // 1: an unrotated survivor
+};
+
+// Pair test and rotation of the walk for candidate p = st and the next
+// survivor q.  Not inlined: every pass of the walk (speculative, correcting,
+// counting, writing) must run the same instructions, so that the counts and
+// the writes agree to the last bit.
+__device__ __noinline__ bool walk_decide(const WState& st, const WState& q, double tol,
+                                         WState& nxt, double& c, double& sn, double& dv) {
+    // |(D_i - D_p) c s| <= tol with (c, s) = (z_i, z_p) / r, multiplied out by
+    // r^2 = z_p^2 + z_i^2 so that the common case (no rotation) needs no
+    // square root or reciprocal.  |z| <= 1 and surviving z are far above
+    // underflow.
+    const double r2 = st.z * st.z + q.z * q.z;
+    if (fabs(q.D - st.D) * fabs(q.z * st.z) <= tol * r2) {
+        const double r = sqrt(r2);
+        const double ir = dc_rcp(r);
+        c = q.z * ir;
+        sn = st.z * ir;
+        dv = c * c * st.D + sn * sn * q.D;
+        nxt = WState{sn * sn * st.D + c * c * q.D, r, q.col, st.typ | q.typ, 0};
+        return true;
+    }
+    nxt = q;
+    return false;
 }
 
 // Writes up to 8 Prob records carried in the kernel arguments.
@@ -122,11 +198,11 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
 // One workgroup per merge: z, sort, deflation walk, generator lists.
 __global__ __launch_bounds__(NT)
 void k_deflate(const Node* __restrict__ merges, Scratch S) {
-    __shared__ double sD[CH];
-    __shared__ double sz[CH];
-    __shared__ int sp[CH];
+    // per segment of the survivor list: speculative end state, true start
+    __shared__ double oD[NT], oz[NT], iD[NT], iz[NT];
+    __shared__ int ocol[NT], otyp[NT], oorg[NT], icol[NT], ityp[NT], iorg[NT];
     __shared__ int wsum[NT / 64];
-    __shared__ int s_K;
+    __shared__ double wmax[NT / 64];
 
     const Node N = merges[blockIdx.x];
     const Prob P = S.probs[N.prob];
@@ -187,108 +263,203 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     const double tol = 8.0 * EPS * fmax(dmax, rho2);
     __syncthreads();
 
-    // Sequential deflation walk (lane 0), chunks staged through LDS.  The
-    // walk only stores to global memory: a global load here would also wait
-    // for every store before it (one in-order counter), so state it needs
-    // again (the previous rotation's second column) stays in registers.
-    int K = 0, nrot = 0, nd = 0, nch = 0;
-    int p = -1, colp = 0, typp = 0, prev_ri = -1;
-    double Dp = 0.0, zp = 0.0, lastd = -INFINITY;
-    auto emit_deflated = [&](double v, int col, int typ) {
-        // keep Dd ascending: insertion from the back (rarely moves)
-        int k = nd;
-        if (v < lastd) {
-            while (k > 0 && S.Dd[base + k - 1] > v) {
-                S.Dd[base + k] = S.Dd[base + k - 1];
-                S.dcol[base + k] = S.dcol[base + k - 1];
-                S.dtype[base + k] = S.dtype[base + k - 1];
-                --k;
-            }
-        } else {
-            lastd = v;
+    // ---- Deflation walk, segmented. ----
+    // z-test survivors in sorted order: SI[0..Ns).  Scratch borrowed for the
+    // walk (all written again later in this merge): SI in org, speculative
+    // decisions in pos_root, deflated entries keyed by the sorted position
+    // that triggers them in tau / pos_defl / ktop (ktop = 0: no entry).
+    int* SI = S.org + base;
+    int* dspec = S.pos_root + base;
+    double* tV = S.tau + base;
+    int* tC = S.pos_defl + base;
+    int* tT = S.ktop + base;
+    const int PL = (m + NT - 1) / NT;                 // sorted positions per thread
+    const int q0 = min(m, tid * PL), q1 = min(m, q0 + PL);
+    auto colof = [&](int i) { return min(max(S.perm[base + i], 0), m - 1); };
+    int nsl = 0;
+    for (int i = q0; i < q1; ++i) nsl += !(rho2 * fabs(S.zs[base + i]) <= tol);
+    int Ns = 0;
+    int w0 = block_excl_scan(nsl, wsum, &Ns);
+    for (int i = q0; i < q1; ++i) {
+        const int c = colof(i);
+        if (!(rho2 * fabs(S.zs[base + i]) <= tol)) {
+            SI[w0++] = i;
+            tT[i] = 0;
+        } else {                                      // deflated as it is
+            tV[i] = S.Ds[base + i];
+            tC[i] = c;
+            tT[i] = c < n1 ? 1 : 2;
         }
-        S.Dd[base + k] = v;
-        S.dcol[base + k] = col;
-        S.dtype[base + k] = typ;
-        ++nd;
-    };
-    for (int c0 = 0; c0 < m; c0 += CH) {
-        const int cn = min(CH, m - c0);
-        for (int i = tid; i < cn; i += NT) {
-            sD[i] = S.Ds[base + c0 + i];
-            sz[i] = S.zs[base + c0 + i];
-            sp[i] = S.perm[base + c0 + i];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double nD = sD[0], nz = sz[0];
-            int np = sp[0];
-            for (int ii = 0; ii < cn; ++ii) {
-                const double Di = nD;
-                const double zi = nz;
-                // every position is written by the merge path above; the clamp
-                // only guards the column range against a broken ordering
-                const int coli = min(max(np, 0), m - 1);
-                if (ii + 1 < cn) {          // next element's LDS reads in flight
-                    nD = sD[ii + 1];
-                    nz = sz[ii + 1];
-                    np = sp[ii + 1];
-                }
-                const int typi = coli < n1 ? 1 : 2;
-                if (rho2 * fabs(zi) <= tol) {
-                    emit_deflated(Di, coli, typi);
-                    continue;
-                }
-                if (p < 0) {
-                    p = c0 + ii; Dp = Di; zp = zi; colp = coli; typp = typi;
-                    continue;
-                }
-                // |(D_i - D_p) c s| <= tol with (c, s) = (z_i, z_p) / r, multiplied
-                // out by r^2 = z_p^2 + z_i^2 so that the common case (no
-                // rotation) needs no square root or reciprocal.  |z| <= 1 and
-                // surviving z are far above underflow.
-                const double r2 = zp * zp + zi * zi;
-                if (fabs(Di - Dp) * fabs(zi * zp) <= tol * r2) {
-                    const double r = sqrt(r2);
-                    const double ir = dc_rcp(r);
-                    const double c = zi * ir;
-                    const double s = zp * ir;
-                    // a new chain unless this rotation's first column is the
-                    // previous rotation's second one
-                    if (nrot == 0 || prev_ri != colp) S.rch[base + nch++] = nrot;
-                    prev_ri = coli;
-                    S.rp[base + nrot] = colp;
-                    S.ri[base + nrot] = coli;
-                    S.rc[base + nrot] = c;
-                    S.rs[base + nrot] = s;
-                    S.rt[base + nrot] = typp | (typi << 2);
-                    ++nrot;
-                    const int tu = typp | typi;
-                    emit_deflated(c * c * Dp + s * s * Di, colp, tu);
-                    Dp = s * s * Dp + c * c * Di;
-                    zp = r;
-                    colp = coli;
-                    typp = tu;
-                    p = c0 + ii;
-                } else {
-                    S.Dbar[base + K] = Dp;
-                    S.zbar[base + K] = zp;
-                    S.surv[base + K] = colp;
-                    S.stype[base + K] = typp;
-                    ++K;
-                    p = c0 + ii; Dp = Di; zp = zi; colp = coli; typp = typi;
-                }
-            }
-        }
-        __syncthreads();
     }
+    __syncthreads();
+
+    auto load_orig = [&](int k) {
+        const int i = SI[k];
+        const int c = colof(i);
+        return WState{S.Ds[base + i], S.zs[base + i], c, c < n1 ? 1 : 2, 1};
+    };
+    // Decision for the pair (st, survivor k + 1): nxt is the next candidate;
+    // on a rotation (c, s) and the deflated value are returned as well.
+    auto decide = [&](const WState& st, int k, WState& nxt, double& c, double& sn,
+                      double& dv, int& typi) {
+        const WState q = load_orig(k + 1);
+        typi = q.typ;
+        return walk_decide(st, q, tol, nxt, c, sn, dv);
+    };
+    const int npairs = Ns > 0 ? Ns - 1 : 0;
+    const int SL = npairs > 0 ? (npairs + NT - 1) / NT : 1;   // pairs per segment
+    const int nseg = (npairs + SL - 1) / SL;
+    const int ka = tid * SL, kb = min(npairs, ka + SL);
+    const bool myseg = tid < nseg;
+
+    // Speculative walk: every segment starts from its unrotated survivor.
+    if (myseg) {
+        WState st = load_orig(ka);
+        for (int k = ka; k < kb; ++k) {
+            WState nx;
+            double c, sn, dv;
+            int ti;
+            dspec[k] = decide(st, k, nx, c, sn, dv, ti) ? 1 : 0;
+            st = nx;
+        }
+        oD[tid] = st.D; oz[tid] = st.z; ocol[tid] = st.col; otyp[tid] = st.typ;
+        oorg[tid] = st.orig;
+    }
+    __syncthreads();
+    // True segment starts, in order.  A segment entered with a rotated
+    // candidate is re-walked until both walks decline a rotation at the same
+    // pair: from there on they coincide.
+    if (tid == 0 && nseg > 0) {
+        WState in = load_orig(0);
+        for (int sg = 0; sg < nseg; ++sg) {
+            iD[sg] = in.D; iz[sg] = in.z; icol[sg] = in.col; ityp[sg] = in.typ;
+            iorg[sg] = in.orig;
+            WState out{oD[sg], oz[sg], ocol[sg], otyp[sg], oorg[sg]};
+            if (!in.orig) {
+                WState st = in;
+                const int a = sg * SL, b = min(npairs, a + SL);
+                bool conv = false;
+                for (int k = a; k < b; ++k) {
+                    WState nx;
+                    double c, sn, dv;
+                    int ti;
+                    const bool rot = decide(st, k, nx, c, sn, dv, ti);
+                    st = nx;
+                    if (!rot && !dspec[k]) { conv = true; break; }
+                }
+                if (!conv) out = st;
+            }
+            in = out;
+        }
+    }
+    __syncthreads();
+
+    // Count, then write, from the true starts.  A rotation starts a new chain
+    // exactly when its first column is an unrotated survivor.
+    int cs = 0, cr = 0, cc = 0;
+    if (myseg) {
+        WState st{iD[tid], iz[tid], icol[tid], ityp[tid], iorg[tid]};
+        for (int k = ka; k < kb; ++k) {
+            WState nx;
+            double c, sn, dv;
+            int ti;
+            if (decide(st, k, nx, c, sn, dv, ti)) { ++cr; cc += st.orig; } else ++cs;
+            st = nx;
+        }
+        cs += tid == nseg - 1;                          // the last candidate
+    } else if (tid == 0 && Ns == 1) {
+        cs = 1;
+    }
+    int K = 0, nrot = 0, nch = 0;
+    int os = block_excl_scan(cs, wsum, &K);
+    int orr = block_excl_scan(cr, wsum, &nrot);
+    int oc = block_excl_scan(cc, wsum, &nch);
+    auto put_surv = [&](const WState& st, int k) {
+        S.Dbar[base + k] = st.D;
+        S.zbar[base + k] = st.z;
+        S.surv[base + k] = st.col;
+        S.stype[base + k] = st.typ;
+    };
+    if (myseg) {
+        WState st{iD[tid], iz[tid], icol[tid], ityp[tid], iorg[tid]};
+        for (int k = ka; k < kb; ++k) {
+            WState nx;
+            double c, sn, dv;
+            int ti;
+            if (decide(st, k, nx, c, sn, dv, ti)) {
+                if (st.orig) S.rch[base + oc++] = orr;
+                S.rp[base + orr] = st.col;
+                S.ri[base + orr] = nx.col;
+                S.rc[base + orr] = c;
+                S.rs[base + orr] = sn;
+                S.rt[base + orr] = st.typ | (ti << 2);
+                ++orr;
+                const int trig = SI[k + 1];
+                tV[trig] = dv;
+                tC[trig] = st.col;
+                tT[trig] = nx.typ;                     // typ_p | typ_i
+            } else {
+                put_surv(st, os++);
+            }
+            st = nx;
+        }
+        if (tid == nseg - 1) put_surv(st, os);
+    } else if (tid == 0 && Ns == 1) {
+        put_surv(load_orig(0), 0);
+    }
+    __syncthreads();
+
+    // Deflated entries in walk order (by triggering position), then ascending:
+    // an entry below the maximum of those before it is inserted backwards, in
+    // order (the prefix maximum is unchanged by insertions before it), which
+    // gives the walk's incremental insertion exactly.
+    int cd = 0;
+    for (int i = q0; i < q1; ++i) cd += tT[i] != 0;
+    int nd = 0;
+    int od = block_excl_scan(cd, wsum, &nd);
+    for (int i = q0; i < q1; ++i) {
+        if (tT[i] == 0) continue;
+        S.Dd[base + od] = tV[i];
+        S.dcol[base + od] = tC[i];
+        S.dtype[base + od] = tT[i];
+        ++od;
+    }
+    __syncthreads();
+    const int DL = (nd + NT - 1) / NT;
+    const int d0 = min(nd, tid * DL), d1 = min(nd, d0 + DL);
+    double lmax = -INFINITY;
+    for (int k = d0; k < d1; ++k) lmax = fmax(lmax, S.Dd[base + k]);
+    double run = block_excl_max(lmax, wmax);
+    int cf = 0;
+    for (int k = d0; k < d1; ++k) {
+        const double v = S.Dd[base + k];
+        cf += v < run;
+        run = fmax(run, v);
+    }
+    int nf = 0;
+    int of = block_excl_scan(cf, wsum, &nf);
+    run = block_excl_max(lmax, wmax);
+    for (int k = d0; k < d1; ++k) {
+        const double v = S.Dd[base + k];
+        if (v < run) dspec[of++] = k;
+        run = fmax(run, v);
+    }
+    __syncthreads();
     if (tid == 0) {
-        if (p >= 0) {
-            S.Dbar[base + K] = Dp;
-            S.zbar[base + K] = zp;
-            S.surv[base + K] = colp;
-            S.stype[base + K] = typp;
-            ++K;
+        for (int f = 0; f < nf; ++f) {
+            const int k = dspec[f];
+            const double v = S.Dd[base + k];
+            const int c = S.dcol[base + k], t = S.dtype[base + k];
+            int j = k;
+            while (j > 0 && S.Dd[base + j - 1] > v) {
+                S.Dd[base + j] = S.Dd[base + j - 1];
+                S.dcol[base + j] = S.dcol[base + j - 1];
+                S.dtype[base + j] = S.dtype[base + j - 1];
+                --j;
+            }
+            S.Dd[base + j] = v;
+            S.dcol[base + j] = c;
+            S.dtype[base + j] = t;
         }
         MergeCnt* cnt = S.cnt + N.slot;
         cnt->K = K;
@@ -297,10 +468,8 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         cnt->nchain = nch;
         cnt->pad_[0] = 0;
         S.rho2[N.slot] = rho2;
-        s_K = K;
     }
     __syncthreads();
-    K = s_K;
 
     // Order-preserving lists of survivors touching the top / bottom rows.
     const int lane = tid & 63, wv = tid >> 6;
