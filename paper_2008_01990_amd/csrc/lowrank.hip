@@ -102,19 +102,25 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
             const bool ok = j < bj;
             cw[t] = ok ? swb[j] : 0.0;
             co[t] = (OFF && ok) ? swo[j] : 0.0;
-            cv[t] = ok ? sv[j] : 0.0;       // 0 => never a candidate
+            cv[t] = ok ? fabs(sv[j]) : 0.0;  // 0 => never a candidate
         }
         // best starts at 0: padded slots (v = 0) and zeroed pivot rows and
         // columns never become candidates; the loop stops at tol > 0 anyway.
+        // |u v / den| > best is tested as |u v| > best |den| (no division);
+        // the quotient is formed only for a new leader.
         double best = 0.0;
         int bf = INT_MAX;
         for (int i = 0; i < bi; ++i) {
-            const double di = sd[i], ui = su[i];
+            const double di = sd[i], ui = fabs(su[i]);
 #pragma unroll
             for (int t = 0; t < JJ; ++t) {
                 if (t * NT >= bj) break;        // uniform over the workgroup
-                const double val = fabs(ui * cv[t] * dc_rcp((di - cw[t]) - co[t]));
-                if (val > best) { best = val; bf = i * bj + tid + t * NT; }
+                const double den = fabs((di - cw[t]) - co[t]);
+                const double num = ui * cv[t];
+                if (num > best * den) {
+                    best = num / den;
+                    bf = i * bj + tid + t * NT;
+                }
             }
         }
 #pragma unroll

@@ -16,6 +16,9 @@ method's arithmetic.
                    c_l = sqrt((xi_l+1)(xi_l+2)(l+m+1)(l+m+2) /
                               ((2l+1)(2l+3)^2 (2l+5))),
                    d_l = (2l(l+1) - 2m^2 - 1) / ((2l-1)(2l+3)); m = n by default.
+* ``glued_wilkinson`` -- copies of Wilkinson's W_21^+ (d_i = |10 - i|, e = 1)
+                   joined by off-diagonal entries delta: tightly clustered
+                   eigenvalues, the classic stress case of deflation.
 * ``block_cyclic_order`` -- the index order in which a 1-D block-cyclic
                    distribution (block N_B over P process rows) stores a
                    vector: process 0's blocks first, then process 1's, ...
@@ -89,6 +92,14 @@ def example_cauchy(n, seed=0, a=1.0, b=9.0):
     u = rng.uniform(0.0, 1.0, n)
     v = rng.uniform(0.0, 1.0, n)
     return u, v, d, w
+
+
+def glued_wilkinson(nblocks, delta=1e-10):
+    w = np.abs(np.arange(21, dtype=np.float64) - 10.0)
+    d = np.tile(w, nblocks)
+    e = np.ones(21 * nblocks - 1)
+    e[20::21] = delta
+    return d, e
 
 
 def block_cyclic_order(n, nprocs, nb):
