@@ -102,27 +102,30 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
             const bool ok = j < bj;
             cw[t] = ok ? swb[j] : 0.0;
             co[t] = (OFF && ok) ? swo[j] : 0.0;
-            cv[t] = ok ? fabs(sv[j]) : 0.0;  // 0 => never a candidate
+            cv[t] = ok ? sv[j] : 0.0;       // 0 => never a candidate
         }
         // best starts at 0: padded slots (v = 0) and zeroed pivot rows and
         // columns never become candidates; the loop stops at tol > 0 anyway.
-        // |u v / den| > best is tested as |u v| > best |den| (no division);
-        // the quotient is formed only for a new leader.
-        double best = 0.0;
-        int bf = INT_MAX;
-        for (int i = 0; i < bi; ++i) {
-            const double di = sd[i], ui = fabs(su[i]);
+        // Even and odd rows keep separate leaders (two independent
+        // compare-select chains), merged by value and then position.
+        double best = 0.0, best1 = 0.0;
+        int bf = INT_MAX, bf1 = INT_MAX;
+        auto scan_row = [&](int i, double& bv, int& bi_) {
+            const double di = sd[i], ui = su[i];
 #pragma unroll
             for (int t = 0; t < JJ; ++t) {
                 if (t * NT >= bj) break;        // uniform over the workgroup
-                const double den = fabs((di - cw[t]) - co[t]);
-                const double num = ui * cv[t];
-                if (num > best * den) {
-                    best = num / den;
-                    bf = i * bj + tid + t * NT;
-                }
+                const double val = fabs(ui * cv[t] * dc_rcp3((di - cw[t]) - co[t]));
+                if (val > bv) { bv = val; bi_ = i * bj + tid + t * NT; }
             }
+        };
+        int i = 0;
+        for (; i + 1 < bi; i += 2) {
+            scan_row(i, best, bf);
+            scan_row(i + 1, best1, bf1);
         }
+        if (i < bi) scan_row(i, best, bf);
+        if (best1 > best || (best1 == best && bf1 < bf)) { best = best1; bf = bf1; }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const double ov = __shfl_xor(best, off, 64);
