@@ -148,8 +148,10 @@ def _solve_chunk(D, z2, rho, j, org, lo, hi, method, max_iter):
             q = 0.5 * (B + np.copysign(np.sqrt(disc), B))
             r1 = q / c
             r2 = C / q
-            in1 = (r1 > d1) & (r1 < d2)
-            eta_int = np.where(in1, r1, r2)
+            # the model root inside the current bracket (the other root of the
+            # quadratic can also round into (d1, d2) when the root hugs a pole)
+            in2 = (r2 > lo - tau) & (r2 < hi - tau)
+            eta_int = np.where(in2, r2, r1)
             eta = np.where(last, eta_last, eta_int)
             new = tau + eta
         ok = np.isfinite(new) & (new > lo) & (new < hi)

@@ -210,7 +210,10 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                             const double q = 0.5 * (B + copysign(sqrt(disc), B));
                             const double r1 = q / c;
                             const double r2 = C / q;
-                            const double eta = (r1 > d1 && r1 < d2) ? r1 : r2;
+                            // the model root inside the current bracket (the
+                            // other root can also round into (d1, d2) when the
+                            // root hugs a pole, and bisection would follow)
+                            const double eta = (r2 > lo - tau && r2 < hi - tau) ? r2 : r1;
                             nt = tau + eta;
                         }
                         if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
