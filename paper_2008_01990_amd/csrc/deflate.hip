@@ -201,6 +201,10 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     // per segment of the survivor list: speculative end state, true start
     __shared__ double oD[NT], oz[NT], iD[NT], iz[NT];
     __shared__ int ocol[NT], otyp[NT], oorg[NT], icol[NT], ityp[NT], iorg[NT];
+    // per segment: its first next survivor and first speculative decision,
+    // so that the usual one-step correction reads only LDS
+    __shared__ double fD[NT], fz[NT];
+    __shared__ int fcol[NT], ftyp[NT], fdec[NT];
     __shared__ int wsum[NT / 64];
     __shared__ double wmax[NT / 64];
 
@@ -315,11 +319,14 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     // Speculative walk: every segment starts from its unrotated survivor.
     if (myseg) {
         WState st = load_orig(ka);
+        const WState f = load_orig(ka + 1);
+        fD[tid] = f.D; fz[tid] = f.z; fcol[tid] = f.col; ftyp[tid] = f.typ;
         for (int k = ka; k < kb; ++k) {
             WState nx;
             double c, sn, dv;
             int ti;
             dspec[k] = decide(st, k, nx, c, sn, dv, ti) ? 1 : 0;
+            if (k == ka) fdec[tid] = dspec[k];
             st = nx;
         }
         oD[tid] = st.D; oz[tid] = st.z; ocol[tid] = st.col; otyp[tid] = st.typ;
@@ -336,16 +343,18 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
             iorg[sg] = in.orig;
             WState out{oD[sg], oz[sg], ocol[sg], otyp[sg], oorg[sg]};
             if (!in.orig) {
-                WState st = in;
                 const int a = sg * SL, b = min(npairs, a + SL);
-                bool conv = false;
-                for (int k = a; k < b; ++k) {
-                    WState nx;
-                    double c, sn, dv;
+                WState nx;
+                double c, sn, dv;
+                const WState f{fD[sg], fz[sg], fcol[sg], ftyp[sg], 1};
+                const bool rot0 = walk_decide(in, f, tol, nx, c, sn, dv);
+                bool conv = !rot0 && !fdec[sg];
+                WState st = nx;
+                for (int k = a + 1; k < b && !conv; ++k) {
                     int ti;
                     const bool rot = decide(st, k, nx, c, sn, dv, ti);
                     st = nx;
-                    if (!rot && !dspec[k]) { conv = true; break; }
+                    if (!rot && !dspec[k]) conv = true;
                 }
                 if (!conv) out = st;
             }
