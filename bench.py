@@ -282,16 +282,44 @@ def extra_configs(L, torch):
     del Qb
     torch.cuda.empty_cache()
     # batched: 256 problems, sizes log-uniform in [64, 4096], d, e ~ U(-1, 1)
+    # (default tile rule, the bucket autotuner's table, then the choice
+    # measured on this batch; all replayed as graphs)
     probs = W.batched_problems(256, 64, 4096, seed=3)
     sizes = [len(p[0]) for p in probs]
     B = L.BatchedSolver(sizes, leaf=32)
     B.load_inputs(probs)
-    tg = _time(lambda: B.solve(graph=True), 5, torch)
-    te = _time(lambda: B.solve(graph=False), 5, torch)
-    res["batched_256_loguniform_64_4096"] = {
-        "seconds_graph": tg, "seconds_eager": te, "problems": len(sizes),
-        "sum_n": int(sum(sizes)), "status_ok": all(v == 0 for v in B.status())}
+
+    def step(graph):
+        B.restore()  # the solve overwrites d; each timed step starts from the inputs
+        B.solve(graph=graph)
+    tg_rule = _time(lambda: step(True), 5, torch)
+    t0 = time.perf_counter()
+    table = L.autotune(4096)
+    t_tune = time.perf_counter() - t0
     del B
+    B = L.BatchedSolver(sizes, leaf=32)
+    B.load_inputs(probs)
+    tg_bucket = _time(lambda: step(True), 5, torch)
+    L.autotune(0)
+    # measured on this batch: every level's product timed under every variant
+    del B
+    B = L.BatchedSolver(sizes, leaf=32)
+    B.load_inputs(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    levels = B.autotune()
+    t_meas = time.perf_counter() - t0
+    tg = _time(lambda: step(True), 5, torch)
+    te = _time(lambda: step(False), 5, torch)
+    res["batched_256_loguniform_64_4096"] = {
+        "seconds_graph": tg, "seconds_eager": te, "seconds_graph_default_tiles": tg_rule,
+        "seconds_graph_bucket_tuned": tg_bucket, "bucket_autotune_seconds": t_tune,
+        "bucket_variant_by_size": {f"<={1 << b}": v for b, v in enumerate(table) if 6 <= b <= 12},
+        "measured_autotune_seconds": t_meas, "measured_variant_by_level": levels,
+        "problems": len(sizes), "sum_n": int(sum(sizes)),
+        "status_ok": all(v == 0 for v in B.status())}
+    del B
+    L.autotune(0)
     torch.cuda.empty_cache()
     # the paper's own sizes (Examples 2-3): n = 30000 Clement, Hermite-type,
     # 1-2-1 Toeplitz and SHT (m = n), plain and low-rank; residual on all

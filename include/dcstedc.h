@@ -54,7 +54,14 @@ typedef struct dc_opts {
                         default 4096 */
     int max_iter;    /* secular iteration cap (default 200: enough for pure
                         bisection to reach 4-ulp relative accuracy) */
-    int gemm_tile;   /* merge-product tile variant, 0 = automatic */
+    int gemm_tile;   /* merge-product tile variant for every level:
+                        0 = automatic (the tuned choice when one exists,
+                        else 64 x 64 tiles for levels of merges up to 256
+                        rows and the 128 x 128 register kernel above);
+                        1 128 x 128 LDS kernel, two workgroups per CU;
+                        2 64 x 64 LDS; 3 128 x 128 LDS, k-step 32;
+                        4 256 x 128 LDS; 5 64 x 64 register kernel.
+                        Other values are invalid options. */
 } dc_opts;
 
 void dc_opts_default(dc_opts* opt);
@@ -165,6 +172,57 @@ int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
                            const double* tau, const double* zhat,
                            const double* scale, double lr_tol, int lr_block,
                            int rank_cap, int* ranks_host, hipStream_t stream);
+
+/*
+ * dc_autotune -- choose the merge-product tile variant per level size by
+ * timing (the batched driver's "autotuned tiles"; the paper leaves the local
+ * product's blocking to the implementation).  For each size bucket
+ * m = 64, 128, ..., min(max_n, 8192) it times every variant on a level of
+ * max_n / m synthetic m x m merges (HIP events on `stream`) and keeps the
+ * fastest; larger levels use the largest bucket's choice.  The table is per
+ * device; solves planned afterwards use it (earlier plans and captured
+ * graphs stay as they were).  Allocates and synchronises: not for use inside
+ * graph capture.  max_n = 0 clears the device's table and every table made
+ * by dc_autotune_batched on it (back to the default rule: 64 x 64 tiles up
+ * to 256 rows, 128 x 128 above).  A variant replaces the default rule's
+ * choice only when it is at least 3 % faster.  Returns 0, -1 for max_n < 0,
+ * or a HIP error code.
+ */
+int dc_autotune(int max_n, hipStream_t stream);
+
+/*
+ * dc_autotune_batched -- tile choice measured on the caller's own batch.
+ * Arguments as dc_stedc_batched (lr options included; gemm_tile must be 0).
+ * Solves the batch twice with every level forced to each tile variant,
+ * times each level's product phase with HIP events on `stream`, and keeps,
+ * per level, the fastest variant (the default rule's unless another is at
+ * least 3 % faster).  The per-level table applies to later plans with the
+ * same device, leaf and sizes (dc_stedc_ex for count == 1), and takes
+ * precedence over dc_autotune's buckets.  On return d and e hold the inputs
+ * again; Q, info_dev and work hold no defined result.  Allocates (a copy of
+ * the diagonals) and synchronises: not for graph capture.  Returns 0, the
+ * argument codes of dc_stedc_batched (-10 also for gemm_tile != 0), or a
+ * HIP error code.
+ */
+int dc_autotune_batched(int count, const int* n_host, double* const* d,
+                        double* const* e, double* const* Q, const int* ldq_host,
+                        void* work, size_t lwork, int* info_dev,
+                        const dc_opts* opt, hipStream_t stream);
+
+/*
+ * dc_autotune_levels -- copies the per-level variants that
+ * dc_autotune_batched chose for (current device, leaf, sizes) to
+ * variant_out[0..cap) (HOST; level 0 = the deepest merges) and returns the
+ * number of levels, 0 when that batch was not tuned, -1 for bad arguments.
+ */
+int dc_autotune_levels(int count, const int* n_host, int leaf, int* variant_out, int cap);
+
+/*
+ * dc_autotune_table -- copies the current device's tuned variant per size
+ * bucket (bucket b: largest merge in (2^(b-1), 2^b]; -1 = not tuned) to
+ * variant_out[0..cap) (HOST) and returns the number of buckets.
+ */
+int dc_autotune_table(int* variant_out, int cap);
 
 /*
  * dc_stedc_backward -- reverse-mode gradient of (lam, Q) = eig(T(d, e)).

@@ -144,5 +144,7 @@ hipError_t dc_launch_loaded_gemm(const GemmTask* tasks_dev, const int* tile_star
 hipError_t dc_launch_adjoint_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
                                   int ntasks, int total_tiles, hipStream_t stream);
 int dc_band_waves_n();
+// Number of merge-product tile variants (0 .. DC_TILE_VARIANTS - 1).
+constexpr int DC_TILE_VARIANTS = 6;
 int dc_gemm_tile_m(int variant);
 int dc_gemm_tile_n(int variant);

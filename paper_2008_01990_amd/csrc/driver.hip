@@ -18,6 +18,7 @@
 // for the worst case.
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -76,15 +77,35 @@ void split(std::vector<std::vector<Node>>& by_depth, std::vector<Node>& leaves, 
     by_depth[depth].push_back(Node{prob, off, k, m - k, depth, -1});
 }
 
-// Product tile shape of a level: a forced variant, or by the level's largest
-// merge (levels of small merges take 64 x 64 tiles: more tiles per merge).
-int level_variant(int forced, int max_m) {
+// Tile variants chosen by dc_autotune, per device, by the size bucket of a
+// level's largest merge: bucket b holds sizes in (2^(b-1), 2^b].
+// dc_autotune_batched keeps, per (device, leaf, sizes), one variant per level
+// of that plan; it takes precedence over the bucket table.
+constexpr int NBUCKET = 24;
+std::mutex g_tune_mu;
+std::map<int, std::vector<int>> g_tuned;
+std::map<std::vector<int>, std::vector<int>> g_level_tuned;
+int g_tune_epoch = 0;
+
+int size_bucket(int m) {
+    int b = 0;
+    while (b < NBUCKET - 1 && (1 << b) < m) ++b;
+    return b;
+}
+
+// Product tile shape of a level: a forced variant, the tuned choice for the
+// level's largest merge, or by default 64 x 64 tiles for levels of merges up
+// to 256 (more tiles per merge) and the 128 x 128 register kernel above.
+int level_variant(int forced, int max_m, const std::vector<int>* tuned) {
     if (forced > 0) return forced;
+    if (tuned && (*tuned)[size_bucket(max_m)] >= 0) return (*tuned)[size_bucket(max_m)];
     if (max_m <= 256) return 5;
     return 0;
 }
 
-std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int tile) {
+std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int tile,
+                                const std::vector<int>* tuned,
+                                const std::vector<int>* per_level) {
     auto P = std::make_unique<Plan>();
     P->sizes = sizes;
     P->leaf = leaf;
@@ -111,7 +132,10 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
         L.max_m = 0;
         for (int i = 0; i < L.nm; ++i)
             L.max_m = std::max(L.max_m, P->merges[L.first + i].n1 + P->merges[L.first + i].n2);
-        L.variant = level_variant(tile, L.max_m);
+        const size_t li = P->levels.size();
+        L.variant = tile <= 0 && per_level && li < per_level->size()
+                        ? (*per_level)[li]
+                        : level_variant(tile, L.max_m, tuned);
         L.bm = dc_gemm_tile_m(L.variant);
         L.bn = dc_gemm_tile_n(L.variant);
         const int bm = L.bm, bn = L.bn;
@@ -186,12 +210,25 @@ hipError_t upload(Plan& P) {
 std::mutex g_plan_mu;
 std::map<std::vector<int>, std::unique_ptr<Plan>> g_plans;
 
-// Plans are keyed by (device, leaf, tile option, sizes).
+// Plans are keyed by (device, leaf, tile option, tuning epoch, sizes).  A new
+// tuning leaves older plans (and graphs captured on them) valid.
 hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan** out) {
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return err;
-    std::vector<int> key{dev, leaf, variant};
+    int epoch = 0;
+    std::vector<int> tuned, per_level;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        epoch = g_tune_epoch;
+        auto t = g_tuned.find(dev);
+        if (t != g_tuned.end()) tuned = t->second;
+        std::vector<int> lkey{dev, leaf};
+        lkey.insert(lkey.end(), sizes.begin(), sizes.end());
+        auto pl = g_level_tuned.find(lkey);
+        if (pl != g_level_tuned.end()) per_level = pl->second;
+    }
+    std::vector<int> key{dev, leaf, variant, epoch};
     key.insert(key.end(), sizes.begin(), sizes.end());
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
@@ -199,7 +236,8 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
         *out = it->second.get();
         return hipSuccess;
     }
-    auto P = make_plan(sizes, leaf, variant);
+    auto P = make_plan(sizes, leaf, variant, tuned.empty() ? nullptr : &tuned,
+                       per_level.empty() ? nullptr : &per_level);
     err = upload(*P);
     if (err != hipSuccess) return err;
     *out = P.get();
@@ -422,6 +460,7 @@ static int check_opts(const dc_opts& o) {
     if (o.leaf < 1 || o.leaf > DC_MAX_LEAF) return 1;
     if (!(o.lr_tol >= 0.0)) return 1;
     if (o.lr_block < 16 || o.lr_block > dc_lowrank_max_block(true)) return 1;
+    if (o.gemm_tile < 0 || o.gemm_tile >= DC_TILE_VARIANTS) return 1;
     return 0;
 }
 
@@ -485,7 +524,47 @@ extern "C" size_t dc_stedc_batched_workspace(int count, const int* n_host, const
     return layout(*P).bytes;
 }
 
-// Batched solve; the graph cache lives in graph.cpp-equivalent code below.
+// Per-problem pointers of a batch over the workspace `w` laid out as L.
+static std::vector<Prob> batch_probs(const Plan& P, const Layout& L, char* w,
+                                     double* const* d, double* const* e, double* const* Q,
+                                     const int* ldq_host, int* info_dev) {
+    const int count = (int)P.sizes.size();
+    std::vector<Prob> probs(count);
+    for (int p = 0; p < count; ++p) {
+        Prob& pr = probs[p];
+        pr.d = d[p];
+        pr.e = e[p];
+        pr.Q = Q[p];
+        pr.ldq = ldq_host[p];
+        pr.B1 = reinterpret_cast<double*>(w + L.bufs) + P.buf_off[p];
+        pr.ld1 = std::max(1, P.sizes[p]);
+        pr.B2 = reinterpret_cast<double*>(w + L.bufs) + P.buf_elems + P.pan_off[p];
+        pr.ld2 = panel_ld(P.sizes[p]);
+        pr.n = P.sizes[p];
+        pr.row0 = (int)P.row0[p];
+        pr.info = info_dev + p;
+        pr.pad_ = 0;
+    }
+    return probs;
+}
+
+// Argument checks shared by the batched entry points (their error codes).
+static int check_batch(int count, const int* n_host, double* const* d, double* const* e,
+                       double* const* Q, const int* ldq_host, int* info_dev, const dc_opts& o) {
+    if (count < 0) return -1;
+    if (count > 0 && (!n_host || !d || !e || !Q || !ldq_host)) return -2;
+    if (check_opts(o)) return -10;
+    if (!info_dev) return -9;
+    for (int p = 0; p < count; ++p) {
+        if (n_host[p] < 0) return -2;
+        if (n_host[p] > 0 && (!d[p] || !Q[p])) return -3;
+        if (n_host[p] > 1 && !e[p]) return -4;
+        if (ldq_host[p] < std::max(1, n_host[p])) return -6;
+    }
+    return 0;
+}
+
+// Batched solve; the captured graphs are cached below, per plan and pointers.
 int dc_batched_impl(int count, const int* n_host, double* const* d, double* const* e,
                     double* const* Q, const int* ldq_host, void* work, size_t lwork,
                     int* info_dev, const dc_opts* opt, hipStream_t stream, bool use_graph);
@@ -502,18 +581,10 @@ std::map<std::vector<uintptr_t>, std::unique_ptr<GraphEntry>> g_graphs;
 int dc_batched_impl(int count, const int* n_host, double* const* d, double* const* e,
                     double* const* Q, const int* ldq_host, void* work, size_t lwork,
                     int* info_dev, const dc_opts* opt, hipStream_t stream, bool use_graph) {
-    if (count < 0) return -1;
-    if (count > 0 && (!n_host || !d || !e || !Q || !ldq_host)) return -2;
     const dc_opts o = dc_resolve_opts(opt);
-    if (check_opts(o)) return -10;
-    if (!info_dev) return -9;
+    const int bad = check_batch(count, n_host, d, e, Q, ldq_host, info_dev, o);
+    if (bad) return bad;
     std::vector<int> sizes(n_host, n_host + count);
-    for (int p = 0; p < count; ++p) {
-        if (sizes[p] < 0) return -2;
-        if (sizes[p] > 0 && (!d[p] || !Q[p])) return -3;
-        if (sizes[p] > 1 && !e[p]) return -4;
-        if (ldq_host[p] < std::max(1, sizes[p])) return -6;
-    }
     Plan* P = nullptr;
     hipError_t err = get_plan(sizes, o.leaf, o.gemm_tile, &P);
     if (err != hipSuccess) return (int)err;
@@ -521,22 +592,7 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
     if (!work || lwork < L.bytes) return -8;
     if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -7;
     char* w = static_cast<char*>(work);
-    std::vector<Prob> probs(count);
-    for (int p = 0; p < count; ++p) {
-        Prob& pr = probs[p];
-        pr.d = d[p];
-        pr.e = e[p];
-        pr.Q = Q[p];
-        pr.ldq = ldq_host[p];
-        pr.B1 = reinterpret_cast<double*>(w + L.bufs) + P->buf_off[p];
-        pr.ld1 = std::max(1, sizes[p]);
-        pr.B2 = reinterpret_cast<double*>(w + L.bufs) + P->buf_elems + P->pan_off[p];
-        pr.ld2 = panel_ld(sizes[p]);
-        pr.n = sizes[p];
-        pr.row0 = (int)P->row0[p];
-        pr.info = info_dev + p;
-        pr.pad_ = 0;
-    }
+    const std::vector<Prob> probs = batch_probs(*P, L, w, d, e, Q, ldq_host, info_dev);
     // The low-rank switch reads sizes on the host and cannot be captured.
     if (!use_graph || o.lr_tol > 0.0) {
         err = (hipError_t)dc_fill_int(info_dev, count, 0, stream);
@@ -651,4 +707,249 @@ extern "C" int dc_profile_read(double* ms, int cap) {
         }
     }
     return nl;
+}
+
+// ---- Tile autotuner ----
+namespace {
+
+// The fastest variant, unless it beats the default rule's choice by less
+// than 3 % (timing noise is not worth a different plan).
+int pick_variant(const float* ms, int dflt) {
+    int best = dflt;
+    for (int v = 0; v < DC_TILE_VARIANTS; ++v)
+        if (ms[v] < ms[best]) best = v;
+    return ms[best] < 0.97f * ms[dflt] ? best : dflt;
+}
+
+__global__ void k_tune_fill(double* a, long long n, double scale) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = scale * (double)((i * 2654435761ll) % 1000003ll) / 1000003.0 - 0.5 * scale;
+}
+
+__global__ void k_tune_gens(double* D, int* org, double* tau, double* zhat, double* scale,
+                            int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    D[i] = (double)i;
+    org[i] = i;
+    tau[i] = 0.5;
+    zhat[i] = 1.0 / sqrt((double)n);
+    scale[i] = 1.0;
+}
+
+}  // namespace
+
+extern "C" int dc_autotune(int max_n, hipStream_t stream) {
+    if (max_n < 0) return -1;
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return (int)err;
+    if (max_n == 0) {                    // back to the default rule
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned.erase(dev);
+        for (auto it = g_level_tuned.begin(); it != g_level_tuned.end();)
+            it = it->first[0] == dev ? g_level_tuned.erase(it) : std::next(it);
+        ++g_tune_epoch;
+        return 0;
+    }
+    const int cap = std::min(std::max(max_n, 64), 8192);
+    const long long elems = (long long)cap * cap;
+    double *A = nullptr, *C = nullptr, *g = nullptr;
+    err = hipMalloc((void**)&A, elems * sizeof(double));
+    if (err == hipSuccess) err = hipMalloc((void**)&C, elems * sizeof(double));
+    if (err == hipSuccess) err = hipMalloc((void**)&g, 5 * (size_t)cap * sizeof(double));
+    GemmTask* dtask = nullptr;
+    int* dstart = nullptr;
+    const int maxtasks = std::max(1, (cap / 64) * (cap / 64));
+    if (err == hipSuccess) err = hipMalloc((void**)&dtask, maxtasks * sizeof(GemmTask));
+    if (err == hipSuccess) err = hipMalloc((void**)&dstart, (maxtasks + 1) * sizeof(int));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    double* D = g;
+    double* tau = g + cap;
+    double* zhat = g + 2 * (size_t)cap;
+    double* scl = g + 3 * (size_t)cap;
+    int* org = reinterpret_cast<int*>(g + 4 * (size_t)cap);
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0,
+                           stream, A, elems, 2.0);
+        hipLaunchKernelGGL(k_tune_gens, dim3((cap + 255) / 256), dim3(256), 0, stream, D, org,
+                           tau, zhat, scl, cap);
+        err = hipGetLastError();
+    }
+    std::vector<int> table(NBUCKET, -1);
+    int last = -1;
+    // A level of merges of size m: (cap / m)^2 merges, each an m x m
+    // product, so that every bucket's level writes cap^2 outputs (a batch's
+    // lower levels hold many small merges, not a few).
+    for (int b = 6; err == hipSuccess && b < NBUCKET && (1 << (b - 1)) < cap; ++b) {
+        const int m = std::min(1 << b, cap);
+        const int nm = std::max(1, (cap / m) * (cap / m));
+        float ms_v[DC_TILE_VARIANTS];
+        for (int v = 0; v < DC_TILE_VARIANTS; ++v) {
+            const int bm = dc_gemm_tile_m(v), bn = dc_gemm_tile_n(v);
+            std::vector<GemmTask> tasks(nm);
+            std::vector<int> start(nm + 1, 0);
+            for (int t = 0; t < nm; ++t) {
+                GemmTask& T = tasks[t];
+                std::memset(&T, 0, sizeof(T));
+                T.A = A + (size_t)t * m * m;
+                T.lda = m;
+                T.klen = m;
+                T.rows = m;
+                T.rD = D;
+                T.rz = zhat;
+                T.corg = org;
+                T.coff = tau;
+                T.cs = scl;
+                T.ncol = m;
+                T.C = C + (size_t)t * m * m;
+                T.ldc = m;
+                T.tiles_m = (m + bm - 1) / bm;
+                T.tiles_n = (m + bn - 1) / bn;
+                start[t + 1] = start[t] + T.tiles_m * T.tiles_n;
+            }
+            err = hipMemcpyAsync(dtask, tasks.data(), nm * sizeof(GemmTask),
+                                 hipMemcpyHostToDevice, stream);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(dstart, start.data(), (nm + 1) * sizeof(int),
+                                     hipMemcpyHostToDevice, stream);
+            if (err == hipSuccess)
+                err = dc_launch_cauchy_gemm(dtask, dstart, nm, start[nm], v, stream);
+            const int reps = m >= 4096 ? 3 : 5;
+            if (err == hipSuccess) err = hipEventRecord(e0, stream);
+            for (int r = 0; r < reps && err == hipSuccess; ++r)
+                err = dc_launch_cauchy_gemm(dtask, dstart, nm, start[nm], v, stream);
+            if (err == hipSuccess) err = hipEventRecord(e1, stream);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) break;
+            ms_v[v] = ms;
+        }
+        if (err != hipSuccess) break;
+        table[b] = pick_variant(ms_v, level_variant(0, m, nullptr));
+        last = b;
+    }
+    for (int b = 0; b < 6 && last >= 0; ++b) table[b] = table[6];
+    for (int b = last + 1; b < NBUCKET && last >= 0; ++b) table[b] = table[last];
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (dtask) (void)hipFree(dtask);
+    if (dstart) (void)hipFree(dstart);
+    if (g) (void)hipFree(g);
+    if (C) (void)hipFree(C);
+    if (A) (void)hipFree(A);
+    if (err != hipSuccess) return (int)err;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[dev] = table;
+    ++g_tune_epoch;
+    return 0;
+}
+
+extern "C" int dc_autotune_batched(int count, const int* n_host, double* const* d,
+                                   double* const* e, double* const* Q, const int* ldq_host,
+                                   void* work, size_t lwork, int* info_dev, const dc_opts* opt,
+                                   hipStream_t stream) {
+    const dc_opts o = dc_resolve_opts(opt);
+    const int bad = check_batch(count, n_host, d, e, Q, ldq_host, info_dev, o);
+    if (bad) return bad;
+    if (o.gemm_tile != 0) return -10;   // nothing to tune with a forced tile
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return (int)err;
+    const std::vector<int> sizes(n_host, n_host + count);
+    Plan* P0 = nullptr;
+    err = get_plan(sizes, o.leaf, 0, &P0);
+    if (err != hipSuccess) return (int)err;
+    const Layout L = layout(*P0);
+    if (!work || lwork < L.bytes) return -8;
+    if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -7;
+    const int nl = (int)P0->levels.size();
+    if (nl == 0) return 0;
+    char* w = static_cast<char*>(work);
+    const std::vector<Prob> probs = batch_probs(*P0, L, w, d, e, Q, ldq_host, info_dev);
+    // Keep the diagonals: every timed solve starts from them, and the caller
+    // gets them back.
+    double* dsave = nullptr;
+    err = hipMalloc((void**)&dsave, std::max<long long>(P0->rows, 1) * sizeof(double));
+    for (int p = 0; p < count && err == hipSuccess; ++p)
+        if (sizes[p] > 0)
+            err = hipMemcpyAsync(dsave + P0->row0[p], d[p], sizes[p] * sizeof(double),
+                                 hipMemcpyDeviceToDevice, stream);
+    auto restore_d = [&]() {
+        hipError_t r = hipSuccess;
+        for (int p = 0; p < count && r == hipSuccess; ++p)
+            if (sizes[p] > 0)
+                r = hipMemcpyAsync(d[p], dsave + P0->row0[p], sizes[p] * sizeof(double),
+                                   hipMemcpyDeviceToDevice, stream);
+        return r;
+    };
+    // Product time of every level under every variant: the same tree with
+    // all levels forced to one variant, solved twice, best of the two.
+    std::vector<float> ms((size_t)nl * DC_TILE_VARIANTS, 1e30f);
+    const bool prof = g_prof;
+    g_prof = true;
+    for (int v = 0; v < DC_TILE_VARIANTS && err == hipSuccess; ++v) {
+        const std::vector<int> all_v(nl, v);
+        auto Pv = make_plan(sizes, o.leaf, 0, nullptr, &all_v);
+        err = upload(*Pv);
+        for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+            err = restore_d();
+            if (err == hipSuccess) err = dc_fill_int(info_dev, count, 0, stream);
+            if (err == hipSuccess) err = run_plan(*Pv, probs, w, o, stream);
+            for (int li = 0; li < nl && err == hipSuccess; ++li) {
+                const size_t a = (size_t)li * (NPHASE + 1) + 4;
+                float t = 0.0f;
+                err = hipEventSynchronize(g_ev[a + 1]);
+                if (err == hipSuccess) err = hipEventElapsedTime(&t, g_ev[a], g_ev[a + 1]);
+                float& best = ms[(size_t)li * DC_TILE_VARIANTS + v];
+                best = std::min(best, t);
+            }
+        }
+        // Pv's node tables are freed at the end of this iteration.
+        const hipError_t es = hipStreamSynchronize(stream);
+        if (err == hipSuccess) err = es;
+    }
+    g_prof = prof;
+    if (err == hipSuccess) err = restore_d();
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    if (dsave) (void)hipFree(dsave);
+    if (err != hipSuccess) return (int)err;
+    std::vector<int> per_level(nl);
+    for (int li = 0; li < nl; ++li)
+        per_level[li] = pick_variant(&ms[(size_t)li * DC_TILE_VARIANTS],
+                                     level_variant(0, P0->levels[li].max_m, nullptr));
+    std::vector<int> key{dev, o.leaf};
+    key.insert(key.end(), sizes.begin(), sizes.end());
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_level_tuned[key] = per_level;
+    ++g_tune_epoch;
+    return 0;
+}
+
+extern "C" int dc_autotune_levels(int count, const int* n_host, int leaf, int* variant_out,
+                                  int cap) {
+    if (count < 0 || (count > 0 && !n_host)) return -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    std::vector<int> key{dev, leaf};
+    key.insert(key.end(), n_host, n_host + count);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto t = g_level_tuned.find(key);
+    if (t == g_level_tuned.end()) return 0;
+    for (int li = 0; li < (int)t->second.size() && li < cap && variant_out; ++li)
+        variant_out[li] = t->second[li];
+    return (int)t->second.size();
+}
+
+extern "C" int dc_autotune_table(int* variant_out, int cap) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto t = g_tuned.find(dev);
+    for (int b = 0; b < NBUCKET && b < cap && variant_out; ++b)
+        variant_out[b] = t == g_tuned.end() ? -1 : t->second[b];
+    return NBUCKET;
 }

@@ -49,6 +49,11 @@ SIGNATURES = [
     ("dc_merge_update", c_int, [c_int, c_int, P, c_int, P, P, P, P, P, P, c_int,
                                 c_double, c_int, P]),
     ("dc_merge_lowrank_ranks", c_int, [c_int, P, P, P, P, P, c_double, c_int, c_int, P, P]),
+    ("dc_autotune", c_int, [c_int, P]),
+    ("dc_autotune_table", c_int, [P, c_int]),
+    ("dc_autotune_batched", c_int, [c_int, P, P, P, P, P, P, c_size_t, P,
+                                    ctypes.POINTER(DcOpts), P]),
+    ("dc_autotune_levels", c_int, [c_int, P, c_int, P, c_int]),
     ("dc_stedc_backward", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P]),
     ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
     ("dc_last_info", c_int, [P]),
@@ -153,6 +158,23 @@ class Solver:
                                 _stream())
         _check(rc, "dc_stedc_ex")
 
+    def autotune_on(self, d, e, Qbuf):
+        """Per-level tile choice measured on this problem (dc_autotune_batched
+        with one problem); d and e are left as given, Qbuf is scratch.
+        Returns the chosen variant per level, deepest first."""
+        lib = load()
+        n_host = (ctypes.c_int * 1)(self.n)
+        Pp = ctypes.c_void_p
+        dp, ep, qp = (Pp * 1)(d.data_ptr()), (Pp * 1)(e.data_ptr()), (Pp * 1)(Qbuf.data_ptr())
+        ldq = (ctypes.c_int * 1)(max(self.n, 1))
+        rc = lib.dc_autotune_batched(1, n_host, dp, ep, qp, ldq, self._wptr(), self.lwork,
+                                     _ptr(self.info), ctypes.byref(self.o), _stream())
+        _check(rc, "dc_autotune_batched")
+        nl = lib.dc_autotune_levels(1, n_host, self.o.leaf, None, 0)
+        out = (ctypes.c_int * max(nl, 1))()
+        lib.dc_autotune_levels(1, n_host, self.o.leaf, ctypes.cast(out, ctypes.c_void_p), nl)
+        return list(out)[:nl]
+
     def __call__(self, d, e):
         d = _dev(d).clone()
         e = _dev(e).clone() if self.n > 1 else torch.zeros(1, dtype=torch.float64,
@@ -231,6 +253,22 @@ def secular(D, z, rho, max_iter=200):
     if st != 0:
         raise DcError(f"dc_secular device status {st}")
     return org, tau, zhat, scale
+
+
+def autotune(max_n):
+    """Time the product tile variants per level size on this device; returns
+    the chosen variant per size bucket (bucket b: largest merge in
+    (2^(b-1), 2^b])."""
+    _check(load().dc_autotune(int(max_n), _stream()), "dc_autotune")
+    return autotune_table()
+
+
+def autotune_table():
+    lib = load()
+    nb = lib.dc_autotune_table(None, 0)
+    out = (ctypes.c_int * nb)()
+    lib.dc_autotune_table(ctypes.cast(out, ctypes.c_void_p), nb)
+    return list(out)
 
 
 def merge_lowrank_ranks(Dbar, org, tau, zhat, scale, lr_tol, lr_block, rank_cap=0):
@@ -373,12 +411,23 @@ class BatchedSolver:
         self.ldq = (ctypes.c_int * max(self.count, 1))(*[max(n, 1) for n in self.sizes])
 
     def load_inputs(self, problems):
+        """Copy the problems' (d, e) into the device buffers.
+
+        A device copy of the diagonals is kept so that restore() can put
+        them back after a solve (the solve overwrites d with eigenvalues;
+        e is only read).
+        """
         for i, (d, e) in enumerate(problems):
             n = self.sizes[i]
             if n:
                 self.d[i][:n].copy_(torch.as_tensor(d))
             if n > 1:
                 self.e[i][:n - 1].copy_(torch.as_tensor(e))
+        self.d_saved = [t.clone() for t in self.d]
+
+    def restore(self):
+        """Put back the diagonals given to the last load_inputs (device copy)."""
+        torch._foreach_copy_(self.d, self.d_saved)
 
     def solve(self, graph=True):
         lib = load()
@@ -388,6 +437,27 @@ class BatchedSolver:
                 ctypes.c_void_p((addr + 255) & ~255), self.lwork, _ptr(self.info),
                 ctypes.byref(self.o), _stream())
         _check(rc, "dc_stedc_batched")
+
+    def autotune(self):
+        """Measure the product tile variants on this batch's loaded inputs and
+        keep the fastest per level (dc_autotune_batched); returns the chosen
+        variant per level, deepest first.  d and e are left as loaded."""
+        lib = load()
+        addr = self.work.data_ptr()
+        rc = lib.dc_autotune_batched(self.count, self.n_host, self.dp, self.ep, self.qp,
+                                     self.ldq, ctypes.c_void_p((addr + 255) & ~255),
+                                     self.lwork, _ptr(self.info), ctypes.byref(self.o),
+                                     _stream())
+        _check(rc, "dc_autotune_batched")
+        return self.tuned_levels()
+
+    def tuned_levels(self):
+        lib = load()
+        nl = lib.dc_autotune_levels(self.count, self.n_host, self.o.leaf, None, 0)
+        out = (ctypes.c_int * max(nl, 1))()
+        lib.dc_autotune_levels(self.count, self.n_host, self.o.leaf,
+                               ctypes.cast(out, ctypes.c_void_p), nl)
+        return list(out)[:nl]
 
     def result(self, i):
         n = self.sizes[i]

@@ -60,7 +60,21 @@ def test_host_side_argument_checks_need_no_gpu():
                                       fake, None) == -8
     assert lib.dc_merge_lowrank_ranks(8192, fake, None, fake, fake, fake, 1e-10, 1024, -1,
                                       fake, None) == -9
+    assert lib.dc_autotune(-1, None) == -1
     assert lib.dc_strerror(0) == b"success"
     o = dcstedc.DcOpts()
     lib.dc_opts_default(ctypes.byref(o))
     assert o.leaf == 32 and o.lr_tol == 0.0
+    # tile variants are 0 (automatic) .. 5; others are invalid options
+    for bad in (-1, 6):
+        o.gemm_tile = bad
+        assert lib.dc_stedc_workspace(64, ctypes.byref(o)) == 0
+    # measured tuning: a negative count, and a forced tile (nothing to tune)
+    assert lib.dc_autotune_batched(-1, None, None, None, None, None, None, 0, fake,
+                                   None, None) == -1
+    n1 = (ctypes.c_int * 1)(64)
+    ptrs = (ctypes.c_void_p * 1)(256)
+    o.gemm_tile = 3
+    assert lib.dc_autotune_batched(1, n1, ptrs, ptrs, ptrs, n1, None, 0, fake,
+                                   ctypes.byref(o), None) == -10
+    assert lib.dc_autotune_levels(-1, None, 32, None, 0) == -1

@@ -129,3 +129,51 @@ def test_batched_full_configuration(lib):
         d, e = probs[i]
         lam, Q = B.result(int(i))
         _check(np.asarray(d), np.asarray(e), host(lam), host(Q), 32)
+
+
+def test_autotuned_tiles(lib):
+    # The tuner picks a valid variant for every size bucket; batched solves
+    # planned afterwards use it and still match the oracle, eagerly and as a
+    # replayed graph.
+    announce("autotune max_n=2048")
+    table = lib.autotune(2048)
+    assert all(0 <= v <= 5 for v in table)
+    assert lib.autotune_table() == table
+    sizes, probs = _problems(12, 64, 2048, seed=21)
+    B = lib.BatchedSolver(sizes, leaf=32)
+    for graph in (False, True):
+        B.load_inputs(probs)                  # the solve works in place
+        B.solve(graph=graph)
+        torch.cuda.synchronize()
+        assert all(v == 0 for v in B.status())
+        for p, (d, e) in enumerate(probs):
+            lam, Q = B.result(p)
+            _check(np.asarray(d), np.asarray(e), host(lam), host(Q), 32)
+    assert all(v == -1 for v in lib.autotune(0))      # back to the default rule
+
+
+def test_measured_tuning_on_the_batch(lib):
+    # dc_autotune_batched times every variant on the loaded batch, leaves d
+    # and e as loaded, and the per-level choice it keeps gives solves that
+    # still match the oracle; clearing the tuning empties the table.
+    sizes, probs = _problems(10, 64, 1536, seed=23)
+    B = lib.BatchedSolver(sizes, leaf=32)
+    B.load_inputs(probs)
+    d_before = [t.clone() for t in B.d]
+    e_before = [t.clone() for t in B.e]
+    announce(f"measured tuning, sizes {sizes}")
+    levels = B.autotune()
+    torch.cuda.synchronize()
+    assert len(levels) >= 5 and all(0 <= v <= 5 for v in levels)
+    assert all(torch.equal(a, b) for a, b in zip(B.d, d_before))
+    assert all(torch.equal(a, b) for a, b in zip(B.e, e_before))
+    for graph in (False, True):
+        B.restore()
+        B.solve(graph=graph)
+        torch.cuda.synchronize()
+        assert all(v == 0 for v in B.status())
+        for p, (d, e) in enumerate(probs):
+            lam, Q = B.result(p)
+            _check(np.asarray(d), np.asarray(e), host(lam), host(Q), 32)
+    lib.autotune(0)
+    assert B.tuned_levels() == []
