@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--family", default="clement", choices=["clement", "toeplitz"])
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--gemm-tile", type=int, default=0)
-    ap.add_argument("--lowrank-tol", type=float, default=0.0,
+    ap.add_argument("--lowrank-tol", type=float, default=1e-10,
                     help="also time the low-rank path at this tolerance (0: skip)")
     ap.add_argument("--lowrank-block", type=int, default=512)
     ap.add_argument("--lowrank-min-k", type=int, default=8192)

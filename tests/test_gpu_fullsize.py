@@ -66,6 +66,34 @@ def test_clement_n32768(lib, path):
         assert res <= 1e-9 and orth <= 1e-9
 
 
+def test_clement_n65536_largest_size(lib):
+    # Beyond 2^31 elements per n x n buffer (Q 34 GB, workspace 69 GB): every
+    # row x leading-dimension offset must be formed in 64 bits.  Checks that
+    # hold at any size: the closed-form spectrum, the residual over all
+    # columns, orthogonality of 512 sampled columns against all of Q.
+    n = 65536
+    announce(f"largest-size clement n={n} plain")
+    d0, e0 = W.clement(n)
+    d, e, lam, Q = _solve(lib, d0, e0, leaf=64)
+    ref = torch.arange(-(n - 1), n, 2, dtype=torch.float64, device="cuda")
+    assert float((lam - ref).abs().max()) <= 1e-13 * (n - 1)
+    tn = float(lam.abs().max())
+    res2 = 0.0
+    for c0 in range(0, n, 8192):                  # residual in column slabs
+        Qs = Q[:, c0:c0 + 8192]
+        TQ = d[:, None] * Qs
+        TQ[:-1] += e[:, None] * Qs[1:]
+        TQ[1:] += e[:, None] * Qs[:-1]
+        res2 += float(torch.linalg.norm(TQ - Qs * lam[None, c0:c0 + 8192])) ** 2
+        del TQ
+    assert math.sqrt(res2) / (n * tn) <= 1e-14
+    cols = torch.as_tensor(np.random.default_rng(1).choice(n, 512, replace=False),
+                           device="cuda")
+    G = Q[:, cols].t().contiguous() @ Q
+    G[torch.arange(512, device="cuda"), cols] -= 1.0
+    assert float(G.abs().max()) <= 1e-12
+
+
 def test_toeplitz_n16384_sampled_sine_vectors(lib):
     n = 16384
     announce(f"full-size toeplitz n={n}")
