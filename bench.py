@@ -521,9 +521,14 @@ def main():
         lms = (t1 - t0) * 1e3 / args.steps
         lstats = L.last_stats()
         lr_top_ms = sum(p[-1]["product"] for p in lprof) / len(lprof)
+        lnlev = len(lprof[0])
+        lr_levels = [{"level_from_root": lnlev - 1 - li,
+                      "phase_ms": {k: sum(p[li][k] for p in lprof) / len(lprof)
+                                   for k in L.PHASES}} for li in range(lnlev)]
         out["lowrank"] = {
             "tol": args.lowrank_tol, "block": args.lowrank_block,
             "min_k": args.lowrank_min_k, "seconds": lms / 1e3,
+            "levels": lr_levels,
             "speedup_vs_plain": ms / lms,
             "root_product_ms": lr_top_ms,
             "root_product_speedup_vs_plain": top["product_ms"] / lr_top_ms,

@@ -548,42 +548,58 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     double* Qi = node_buf(P, N.depth + 1, ld);
     double* row = Qi + (long long)N.off * ld + N.off + r;
     const int rbit = r < N.n1 ? 1 : 2;
-    int t0[DC_ROT_CHAINS], t1[DC_ROT_CHAINS];
-    double vp[DC_ROT_CHAINS], vi[DC_ROT_CHAINS];
+    const int* __restrict__ rt = S.rt + base;
+    const int* __restrict__ rp = S.rp + base;
+    const int* __restrict__ ri = S.ri + base;
+    const double* __restrict__ rc = S.rc + base;
+    const double* __restrict__ rs = S.rs + base;
+    // Every chain's bounds and first rotation are read before any store: the
+    // stores go to Q, which the compiler cannot tell apart from these lists,
+    // and a read after a store would cost one memory round trip per chain.
+    int t0[DC_ROT_CHAINS], t1[DC_ROT_CHAINS], ty0[DC_ROT_CHAINS], p0[DC_ROT_CHAINS],
+        i0[DC_ROT_CHAINS];
+    double c0[DC_ROT_CHAINS], s0[DC_ROT_CHAINS];
 #pragma unroll
     for (int q = 0; q < DC_ROT_CHAINS; ++q) {
         const int ch = ch0 + q;
         t0[q] = ch < C.nchain ? S.rch[base + ch] : 0;
         t1[q] = ch < C.nchain ? (ch + 1 < C.nchain ? S.rch[base + ch + 1] : C.nrot) : 0;
     }
-    // first rotation of every chain: loads issued together
 #pragma unroll
     for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        vp[q] = 0.0;
-        vi[q] = 0.0;
-        if (t0[q] < t1[q]) {
-            const int ty = S.rt[base + t0[q]];
-            if (ty & rbit) vp[q] = row[(long long)S.rp[base + t0[q]] * ld];
-            if ((ty >> 2) & rbit) vi[q] = row[(long long)S.ri[base + t0[q]] * ld];
-        }
+        const bool live = t0[q] < t1[q];
+        const int t = live ? t0[q] : 0;
+        ty0[q] = live ? rt[t] : 0;
+        p0[q] = rp[t];
+        i0[q] = ri[t];
+        c0[q] = rc[t];
+        s0[q] = rs[t];
+    }
+    // the first rotation's two columns of every chain: loads issued together
+    double vp[DC_ROT_CHAINS], vi[DC_ROT_CHAINS];
+#pragma unroll
+    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+        vp[q] = (ty0[q] & rbit) ? row[(long long)p0[q] * ld] : 0.0;
+        vi[q] = ((ty0[q] >> 2) & rbit) ? row[(long long)i0[q] * ld] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        for (int t = t0[q]; t < t1[q]; ++t) {
-            const int ty = S.rt[base + t];
-            double a = vp[q];
-            double b = vi[q];
-            if (t > t0[q]) {            // the previous second column is this first one
-                a = vi[q];
-                b = ((ty >> 2) & rbit) ? row[(long long)S.ri[base + t] * ld] : 0.0;
-            }
-            rot_apply(ty, rbit, S.rc[base + t], S.rs[base + t], a, b);
-            if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)S.rp[base + t] * ld] = a;
-            vp[q] = a;
-            vi[q] = b;
-            if (t + 1 == t1[q] && (((ty & rbit) || ((ty >> 2) & rbit))))
-                row[(long long)S.ri[base + t] * ld] = b;
+        if (t0[q] >= t1[q]) continue;
+        double a = vp[q], b = vi[q];
+        int ty = ty0[q], col_i = i0[q];
+        rot_apply(ty, rbit, c0[q], s0[q], a, b);
+        if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)p0[q] * ld] = a;
+        // the rest of a longer chain: the previous second column is this
+        // rotation's first one
+        for (int t = t0[q] + 1; t < t1[q]; ++t) {
+            ty = rt[t];
+            col_i = ri[t];
+            a = b;
+            b = ((ty >> 2) & rbit) ? row[(long long)col_i * ld] : 0.0;
+            rot_apply(ty, rbit, rc[t], rs[t], a, b);
+            if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)rp[t] * ld] = a;
         }
+        if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)col_i * ld] = b;
     }
 }
 
