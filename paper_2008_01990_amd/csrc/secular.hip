@@ -8,8 +8,15 @@
 // The iteration is the rational-interpolation scheme of Bunch-Nielsen-Sorensen
 // in R.-C. Li's "middle way" form: the pole sums left and right of the root
 // are each modelled by a constant plus one pole fitted to value and slope,
-// and the quadratic of the model gives the step; a bisection safeguard keeps
-// each iterate inside a sign-change bracket.
+// and the quadratic of the model gives the next iterate, solved directly for
+// the offset from the origin pole (so that a root within a few ulps of its
+// pole is not lost to cancellation).  The terms of the root's two bracketing
+// poles are formed exactly; when the middle-way iterate leaves the bracket
+// (a weak origin pole, whose fitted weight is mostly that of farther poles),
+// Li's fixed-weight model is tried, which keeps the origin pole's own weight;
+// a bisection safeguard keeps each iterate inside a sign-change bracket.  The
+// last root is bracketed by the last two poles and starts half a pole gap
+// right of the last pole when that is inside its bracket.
 //
 // Loewner (Gu-Eisenstat): zhat_i^2 = (lam_K - D_i)/rho
 //     * prod_{j<i} (lam_j - D_i)/(D_j - D_i) * prod_{i<=j<K-1} (lam_j - D_i)/(D_{j+1} - D_i).
@@ -44,29 +51,48 @@ struct Sums {
     double psi, dpsi, phi, dphi;
 };
 
-// Partial sums over the poles of one staged chunk assigned to this wave, for a
-// root with origin pole Do, offset tau and interval index j.  sD/sz2 hold the
-// chunk starting at pole c0.  Poles i <= j lie left of the root (terms
-// negative, psi), the others right of it (terms positive, phi): the slice is
-// split at j instead of selecting per term, and sum |term| = phi - psi.
+// Partial sums over the far poles of one staged chunk assigned to this wave,
+// for a root with origin pole Do and offset tau.  sD/sz2 hold the chunk
+// starting at pole c0.  The root's two bracketing poles e0 < e1 are left out
+// (their terms are formed exactly by the caller); poles i < e0 lie left of
+// the root (terms negative, psi), poles i > e1 right of it (terms positive,
+// phi), so the slice splits at e0 and e1 instead of selecting per term.
 __device__ __forceinline__ void chunk_sums(const double* sD, const double* sz2, int c0,
-                                           int a, int b, double Do, double tau, int j,
-                                           Sums& s) {
-    const int split = min(max(j - c0 + 1, a), b);
+                                           int a, int b, double Do, double tau, int e0,
+                                           int e1, Sums& s) {
+    const int l_end = min(max(e0 - c0, a), b);
+    const int r_beg = min(max(e1 + 1 - c0, a), b);
 #pragma unroll 4
-    for (int q = a; q < split; ++q) {
+    for (int q = a; q < l_end; ++q) {
         const double r = dc_rcp3((sD[q] - Do) - tau);
         const double term = sz2[q] * r;
         s.psi += term;
         s.dpsi += term * r;
     }
 #pragma unroll 4
-    for (int q = split; q < b; ++q) {
+    for (int q = r_beg; q < b; ++q) {
         const double r = dc_rcp3((sD[q] - Do) - tau);
         const double term = sz2[q] * r;
         s.phi += term;
         s.dphi += term * r;
     }
+}
+
+// Root x (offset from the origin pole) of the model
+//     c + s1 / (dl - x) + s2 / (dh - x) = 0,
+// poles dl < dh given as offsets from the origin (one of them is the origin
+// itself, so the constant term is a single product and the root next to the
+// origin comes out with full relative accuracy).  Of the quadratic's two
+// roots the one inside (lo, hi) is returned (or the other if neither is).
+__device__ __forceinline__ double model_root(double c, double s1, double s2, double dl,
+                                             double dh, double lo, double hi) {
+    const double B = c * (dl + dh) + s1 + s2;
+    const double C = c * dl * dh + s1 * dh + s2 * dl;
+    const double disc = fmax(B * B - 4.0 * c * C, 0.0);
+    const double q = 0.5 * (B + copysign(sqrt(disc), B));
+    const double r1 = q / c;
+    const double r2 = C / q;
+    return (r2 > lo && r2 < hi) ? r2 : r1;
 }
 
 __global__ __launch_bounds__(NW * 64)
@@ -95,6 +121,10 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     const bool valid = j < K;
     const bool last = j == K - 1;
     const int per = CH / NW;        // poles of a chunk per wave
+    // The root's bracketing poles e0 < e1, whose terms are formed exactly:
+    // (j, j+1) inside, (K-2, K-1) for the last root (K = 1: the one pole).
+    const int e1 = last ? K - 1 : j + 1;
+    const int e0 = last ? K - 2 : j;
 
     // ||z||^2 bounds the last root; only the workgroup owning it needs it
     // (per-wave partials summed in a fixed order: deterministic).
@@ -114,30 +144,37 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     __syncthreads();
 
     // Wave 0 owns the per-root state.
-    double lo = 0.0, hi = 0.0, tau = 0.0, dlo = 0.0, dhi = 0.0;
-    double Dj = 0.0, Dj1 = 0.0;
+    double lo = 0.0, hi = 0.0, tau = 0.0;
+    double De0 = 0.0, De1 = 0.0, w0 = 0.0, w1 = 0.0;   // bracketing poles, weights z^2
     int org = 0;
     bool done = !valid;
     int iters = 0;
     if (w == 0 && valid) {
-        Dj = D[j];
-        Dj1 = last ? 0.0 : D[j + 1];
+        De1 = D[e1];
+        De0 = e0 >= 0 ? D[e0] : 0.0;
+        const double z1 = z[e1], z0 = e0 >= 0 ? z[e0] : 0.0;
+        w1 = z1 * z1;
+        w0 = z0 * z0;
         if (last) {
             hi = rho * s_zz * (1.0 + 8.0 * EPS);   // widened by a few ulps
             tau = 0.5 * hi;
+            // start half a gap right of the last pole (where the root of a
+            // matrix with evenly spread spectrum sits) when that is closer
+            if (K > 1) tau = fmin(tau, 0.5 * (De1 - De0));
+            org = j;
         } else {
-            tau = 0.5 * (Dj1 - Dj);                // midpoint, origin j frame
+            tau = 0.5 * (De1 - De0);                // midpoint, origin j frame
+            org = j;
         }
-        org = j;
     }
     if (w == 0) {
         s_tau[lane] = tau;
-        s_do[lane] = valid ? D[j] : 0.0;
+        s_do[lane] = valid ? D[org] : 0.0;
     }
     __syncthreads();
 
     for (int it = 0;; ++it) {
-        // Every wave: partial sums at the current iterate of root `lane`.
+        // Every wave: partial sums over the far poles at the current iterate.
         Sums p{0.0, 0.0, 0.0, 0.0};
         const double Do = s_do[lane];
         const double tcur = s_tau[lane];
@@ -151,7 +188,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
             }
             __syncthreads();
             const int a = min(cn, w * per), b = min(cn, a + per);
-            if (valid) chunk_sums(sD, sz2, c0, a, b, Do, tcur, j, p);
+            if (valid) chunk_sums(sD, sz2, c0, a, b, Do, tcur, e0, e1, p);
         }
         red[0][w][lane] = p.psi;
         red[1][w][lane] = p.dpsi;
@@ -159,28 +196,34 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         red[3][w][lane] = p.dphi;
         __syncthreads();
         if (w == 0) {
-            double psi = 0, dpsi = 0, phi = 0, dphi = 0;
+            double fpsi = 0, fdpsi = 0, fphi = 0, fdphi = 0;
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
-                psi += red[0][q][lane];
-                dpsi += red[1][q][lane];
-                phi += red[2][q][lane];
-                dphi += red[3][q][lane];
+                fpsi += red[0][q][lane];
+                fdpsi += red[1][q][lane];
+                fphi += red[2][q][lane];
+                fdphi += red[3][q][lane];
             }
-            const double aabs = phi - psi;   // sum of |terms|
+            // the bracketing poles' terms, exactly, in the origin frame
+            const double dl = e0 >= 0 ? De0 - Do : 0.0;   // pole offsets from the origin
+            const double dh = De1 - Do;
+            const double d1 = dl - tau, d2 = dh - tau;    // and from the iterate
+            const double t0 = (valid && e0 >= 0) ? w0 / d1 : 0.0;
+            const double t1 = valid ? w1 / d2 : 0.0;
+            const double psi = fpsi + t0, dpsi = fdpsi + ((valid && e0 >= 0) ? t0 / d1 : 0.0);
+            const double phi = fphi + t1, dphi = fdphi + (valid ? t1 / d2 : 0.0);
+            const double aabs = (fphi - fpsi) + fabs(t0) + fabs(t1);   // sum of |terms|
             const double g = 1.0 / rho + psi + phi;
             if (!done) {
                 ++iters;
                 if (it == 0 && !last) {
                     // Origin choice from the sign at the midpoint.
-                    const double h = 0.5 * (Dj1 - Dj);
+                    const double h = 0.5 * (De1 - De0);
                     if (g > 0.0) {          // root left of the midpoint
                         org = j; lo = 0.0; hi = h;
                     } else {                // root right of it: re-frame at D_{j+1}
                         org = j + 1; lo = -h; hi = 0.0; tau = -h;
                     }
-                    dlo = Dj - (org == j ? Dj : Dj1);
-                    dhi = Dj1 - (org == j ? Dj : Dj1);
                     if (g == 0.0) done = true;
                 } else {
                     if (g > 0.0) hi = tau; else lo = tau;
@@ -193,28 +236,35 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                         done = true;
                         dc_set_info(T.info, j + 1);
                     } else {
-                        // Middle-way model step from tau.
-                        const double d1 = dlo - tau;
-                        const double d2 = dhi - tau;
-                        const double s1 = dpsi * d1 * d1;
+                        // Pole offsets in the (possibly new) origin frame.
+                        const double Dn = (org == j) ? (last ? De1 : De0) : De1;
+                        const double ol = e0 >= 0 ? De0 - Dn : 0.0, oh = De1 - Dn;
+                        const double q1 = ol - tau, q2 = oh - tau;
                         double nt;
-                        if (last) {
-                            const double c = 1.0 / rho + (psi - dpsi * d1);
-                            nt = tau + (d1 + s1 / c);
+                        if (e0 < 0) {
+                            // one pole: c + w1 / (0 - x) = 0 with c = 1/rho
+                            nt = rho * w1;
                         } else {
-                            const double s2 = dphi * d2 * d2;
-                            const double c = 1.0 / rho + (psi - dpsi * d1) + (phi - dphi * d2);
-                            const double B = c * (d1 + d2) + s1 + s2;
-                            const double C = c * d1 * d2 + s1 * d2 + s2 * d1;
-                            const double disc = fmax(B * B - 4.0 * c * C, 0.0);
-                            const double q = 0.5 * (B + copysign(sqrt(disc), B));
-                            const double r1 = q / c;
-                            const double r2 = C / q;
-                            // the model root inside the current bracket (the
-                            // other root can also round into (d1, d2) when the
-                            // root hugs a pole, and bisection would follow)
-                            const double eta = (r2 > lo - tau && r2 < hi - tau) ? r2 : r1;
-                            nt = tau + eta;
+                            // Middle-way model: both pole sums fitted to
+                            // value and slope by their bracketing pole.
+                            const double s1 = dpsi * q1 * q1;
+                            const double s2 = dphi * q2 * q2;
+                            const double c = 1.0 / rho + (psi - dpsi * q1) + (phi - dphi * q2);
+                            nt = model_root(c, s1, s2, ol, oh, lo, hi);
+                            if (!(nt > lo && nt < hi) && !last) {
+                                // Fixed-weight model: the origin pole's own
+                                // term exact, everything else fitted at the
+                                // other bracketing pole (a weak origin pole
+                                // fools the middle way's fit).
+                                const bool left = org == j;
+                                const double R = 1.0 / rho + fpsi + fphi + (left ? t1 : t0);
+                                const double Rp = fdpsi + fdphi + (left ? t1 / q2 : t0 / q1);
+                                const double qo = left ? q2 : q1;
+                                const double sf = Rp * qo * qo;
+                                const double cf = R - Rp * qo;
+                                nt = left ? model_root(cf, w0, sf, ol, oh, lo, hi)
+                                          : model_root(cf, sf, w1, ol, oh, lo, hi);
+                            }
                         }
                         if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
                         tau = nt;
@@ -222,7 +272,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                 }
             }
             s_tau[lane] = tau;
-            if (valid) s_do[lane] = (org == j) ? Dj : Dj1;
+            if (valid) s_do[lane] = (org == j) ? (last ? De1 : De0) : De1;
             const unsigned long long live = __ballot(!done);
             if (lane == 0) s_live = live != 0ull;
         }
@@ -230,9 +280,9 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         if (!s_live) break;
     }
     if (w == 0 && valid) {
+        const double base = (org == j) ? (last ? De1 : De0) : De1;
         T.org[j] = org;
         T.tau[j] = tau;
-        const double base = (org == j) ? Dj : Dj1;
         if (T.cbase) T.cbase[j] = base;
         if (T.lam) T.lam[j] = base + tau;
     }
