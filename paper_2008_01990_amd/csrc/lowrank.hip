@@ -53,15 +53,15 @@ struct SrrscOut {
 // column nodes carry an offset (w_j = cbase_j + coff_j, the merge's (origin,
 // tau) form); STORE: write the skeleton and interpolation generators, else only
 // count the rank (up to rmax).
-template <int MB, bool OFF, bool STORE>
+template <int MB, int RG, bool OFF, bool STORE>
 __global__ __launch_bounds__(NT)
 void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __restrict__ u0,
              const double* __restrict__ cbase, const double* __restrict__ coff,
              const double* __restrict__ v0, double tol, int rmax, SrrscOut O) {
-    constexpr int JJ = (MB + NT - 1) / NT;    // columns per thread
+    constexpr int JJ = (MB * RG + NT - 1) / NT;   // columns per thread
     __shared__ double sd[MB], su[MB], swb[MB], sv[MB];
     __shared__ double swo[OFF ? MB : 1];
-    __shared__ double wv[NT / 64];
+    __shared__ double wv[NT / 64], wd[NT / 64];
     __shared__ int wi[NT / 64];
     __shared__ int spr[STORE ? MAX_R : 1], spc[STORE ? MAX_R : 1];
     __shared__ double s_max;
@@ -91,56 +91,71 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
     int k = 0;
     bool dense = false;
     for (;;) {
-        // Complete pivoting: largest |A^(k)_ij| = |u_i v_j / (d_i - w_j)|,
-        // ties to the smallest row-major position.  Each thread owns the
-        // columns tid, tid + NT, ... (held in registers) and walks all rows,
-        // so its own candidates arrive in increasing position order.
+        // Complete pivoting: largest |A^(k)_ij| = |u_i v_j| / |d_i - w_j|,
+        // ties to the smallest row-major position.  The threads form RG row
+        // groups of NT / RG column slots (RG > 1 when the block has at most
+        // NT / RG columns); a thread holds its columns in registers and walks
+        // the rows of its group, so its own candidates arrive in increasing
+        // position order.  The running maximum is kept as a fraction
+        // (|u v|, |d - w|) and compared by cross-multiplication: no division
+        // per entry.
+        const int slots = NT / RG;
+        const int cs = tid % slots, rg = tid / slots;
         double cw[JJ], co[JJ], cv[JJ];
 #pragma unroll
         for (int t = 0; t < JJ; ++t) {
-            const int j = tid + t * NT;
+            const int j = cs + t * slots;
             const bool ok = j < bj;
             cw[t] = ok ? swb[j] : 0.0;
             co[t] = (OFF && ok) ? swo[j] : 0.0;
-            cv[t] = ok ? sv[j] : 0.0;       // 0 => never a candidate
+            cv[t] = ok ? fabs(sv[j]) : 0.0;     // 0 => never a candidate
         }
-        // best starts at 0: padded slots (v = 0) and zeroed pivot rows and
-        // columns never become candidates; the loop stops at tol > 0 anyway.
-        // Even and odd rows keep separate leaders (two independent
-        // compare-select chains), merged by value and then position.
-        double best = 0.0, best1 = 0.0;
+        // Leaders start at 0 / 1: padded slots (v = 0) and zeroed pivot rows
+        // and columns never become candidates; the loop stops at tol > 0
+        // anyway.  Even and odd rows of the group keep separate leaders (two
+        // independent compare-select chains), merged by value then position.
+        double bn = 0.0, bd = 1.0, bn1 = 0.0, bd1 = 1.0;
         int bf = INT_MAX, bf1 = INT_MAX;
-        auto scan_row = [&](int i, double& bv, int& bi_) {
-            const double di = sd[i], ui = su[i];
+        auto scan_row = [&](int i, double& n_, double& d_, int& f_) {
+            const double di = sd[i], ui = fabs(su[i]);
 #pragma unroll
             for (int t = 0; t < JJ; ++t) {
-                if (t * NT >= bj) break;        // uniform over the workgroup
-                const double val = fabs(ui * cv[t] * dc_rcp3((di - cw[t]) - co[t]));
-                if (val > bv) { bv = val; bi_ = i * bj + tid + t * NT; }
+                if (t * slots >= bj) break;     // uniform over the workgroup
+                const double a = ui * cv[t];
+                const double x = fabs((di - cw[t]) - co[t]);
+                const bool take = a * d_ > n_ * x;
+                n_ = take ? a : n_;
+                d_ = take ? x : d_;
+                f_ = take ? i * bj + cs + t * slots : f_;
             }
         };
-        int i = 0;
-        for (; i + 1 < bi; i += 2) {
-            scan_row(i, best, bf);
-            scan_row(i + 1, best1, bf1);
+        int i = rg;
+        for (; i + RG < bi; i += 2 * RG) {
+            scan_row(i, bn, bd, bf);
+            scan_row(i + RG, bn1, bd1, bf1);
         }
-        if (i < bi) scan_row(i, best, bf);
-        if (best1 > best || (best1 == best && bf1 < bf)) { best = best1; bf = bf1; }
+        if (i < bi) scan_row(i, bn, bd, bf);
+        auto better = [](double n1, double d1, int f1, double n0, double d0, int f0) {
+            const double l = n1 * d0, r = n0 * d1;
+            return l > r || (l == r && f1 < f0);
+        };
+        if (better(bn1, bd1, bf1, bn, bd, bf)) { bn = bn1; bd = bd1; bf = bf1; }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(best, off, 64);
+            const double on = __shfl_xor(bn, off, 64);
+            const double od = __shfl_xor(bd, off, 64);
             const int of = __shfl_xor(bf, off, 64);
-            if (ov > best || (ov == best && of < bf)) { best = ov; bf = of; }
+            if (better(on, od, of, bn, bd, bf)) { bn = on; bd = od; bf = of; }
         }
-        if (lane == 0) { wv[w] = best; wi[w] = bf; }
+        if (lane == 0) { wv[w] = bn; wd[w] = bd; wi[w] = bf; }
         __syncthreads();
         if (tid == 0) {
-            double bb = wv[0];
-            int bbf = wi[0];
+            double nn = wv[0], dd = wd[0];
+            int ff = wi[0];
             for (int q = 1; q < NT / 64; ++q)
-                if (wv[q] > bb || (wv[q] == bb && wi[q] < bbf)) { bb = wv[q]; bbf = wi[q]; }
-            s_max = bb;
-            s_piv = bbf;
+                if (better(wv[q], wd[q], wi[q], nn, dd, ff)) { nn = wv[q]; dd = wd[q]; ff = wi[q]; }
+            s_max = nn / dd;
+            s_piv = ff;
         }
         __syncthreads();
         if (!(s_max > tol)) break;
@@ -221,35 +236,57 @@ struct Compressed {
 
 // The SRRSC instance that fits: column offsets present (merge nodes, b up to
 // MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); store or count only.
+template <int MB, int RG, bool OFF>
+hipError_t launch_srrsc_mb(int K, int b, int p, const double* D, const double* zhat,
+                           const double* cbase, const double* coff, const double* scale,
+                           double tol, int rmax, bool store, const SrrscOut& out,
+                           hipStream_t s) {
+    const dim3 g((unsigned)((size_t)p * p)), blk(NT);
+    if (store)
+        hipLaunchKernelGGL((k_srrsc<MB, RG, OFF, true>), g, blk, 0, s, K, b, p, D, zhat, cbase,
+                           coff, scale, tol, rmax, out);
+    else
+        hipLaunchKernelGGL((k_srrsc<MB, RG, OFF, false>), g, blk, 0, s, K, b, p, D, zhat, cbase,
+                           coff, scale, tol, rmax, out);
+    return hipGetLastError();
+}
+
+// The SRRSC instance that fits: column offsets present (merge nodes, b up to
+// MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); the smallest LDS
+// capacity that holds b (two workgroups per CU up to b = 1024), with the rows
+// split among 4 or 2 thread groups when b <= 256 or 512; store or count only.
+template <bool OFF>
+hipError_t launch_srrsc_off(int K, int b, int p, const double* D, const double* zhat,
+                            const double* cbase, const double* coff, const double* scale,
+                            double tol, int rmax, bool store, const SrrscOut& out,
+                            hipStream_t s) {
+    if (b <= 256)
+        return launch_srrsc_mb<256, 4, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax,
+                                            store, out, s);
+    if (b <= 512)
+        return launch_srrsc_mb<512, 2, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax,
+                                            store, out, s);
+    if (b <= 1024)
+        return launch_srrsc_mb<1024, 1, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax,
+                                             store, out, s);
+    if (b <= MAX_B_OFF)
+        return launch_srrsc_mb<MAX_B_OFF, 1, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol,
+                                                  rmax, store, out, s);
+    if constexpr (!OFF)
+        return launch_srrsc_mb<MAX_B_GEN, 1, false>(K, b, p, D, zhat, cbase, coff, scale, tol,
+                                                    rmax, store, out, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_srrsc(int K, int b, int p, const double* D, const double* zhat,
                         const double* cbase, const double* coff, const double* scale,
                         double tol, int rmax, bool store, const SrrscOut& out, hipStream_t s) {
-    const dim3 g((unsigned)((size_t)p * p)), blk(NT);
     if (coff && b > MAX_B_OFF) return hipErrorInvalidValue;
     if (b > MAX_B_GEN) return hipErrorInvalidValue;
-    if (coff) {
-        if (store)
-            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, true, true>), g, blk, 0, s, K, b, p, D, zhat,
-                               cbase, coff, scale, tol, rmax, out);
-        else
-            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, true, false>), g, blk, 0, s, K, b, p, D, zhat,
-                               cbase, coff, scale, tol, rmax, out);
-    } else if (b <= MAX_B_OFF) {
-        if (store)
-            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, false, true>), g, blk, 0, s, K, b, p, D, zhat,
-                               cbase, coff, scale, tol, rmax, out);
-        else
-            hipLaunchKernelGGL((k_srrsc<MAX_B_OFF, false, false>), g, blk, 0, s, K, b, p, D,
-                               zhat, cbase, coff, scale, tol, rmax, out);
-    } else {
-        if (store)
-            hipLaunchKernelGGL((k_srrsc<MAX_B_GEN, false, true>), g, blk, 0, s, K, b, p, D, zhat,
-                               cbase, coff, scale, tol, rmax, out);
-        else
-            hipLaunchKernelGGL((k_srrsc<MAX_B_GEN, false, false>), g, blk, 0, s, K, b, p, D,
-                               zhat, cbase, coff, scale, tol, rmax, out);
-    }
-    return hipGetLastError();
+    return coff ? launch_srrsc_off<true>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax, store,
+                                         out, s)
+                : launch_srrsc_off<false>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax, store,
+                                          out, s);
 }
 
 // coff == nullptr: plain column nodes w_j = cbase_j.
