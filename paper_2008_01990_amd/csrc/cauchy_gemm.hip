@@ -150,8 +150,8 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     const double* __restrict__ rz = T.rz;
     double cb = 0.0, co = 0.0, csj = 0.0;
     if (col_ok) {
-        if (KIND <= 1) {
-            cb = (KIND == 0 && T.corg) ? rD[T.corg[gcol]] : T.cbase[gcol];
+        if (KIND == 0) {
+            cb = T.corg ? rD[T.corg[gcol]] : T.cbase[gcol];
             co = T.coff ? T.coff[gcol] : 0.0;
         }
         if (KIND == 0) csj = T.cs[gcol];
@@ -179,8 +179,6 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     double a_reg[C_::A_PER];
     double d_reg[C_::B_PER];    // 0: row node; 1: y * vk; 2: B entry; 3: X entry
     double z_reg[C_::B_PER];    // 0: row weight; 1: skeleton node base; 3: lam_k
-    double o_reg[KIND == 1 ? C_::B_PER : 1];   // kind 1: skeleton node offset
-    int s_reg[KIND == 1 ? C_::B_PER : 1];      // kind 1: skeleton column (generator)
 
     // Interior chunks of interior tiles (the common case) load without
     // bounds checks, with strength-reduced addresses.
@@ -194,12 +192,6 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
             if (KIND == 0) {
                 d_reg[i] = ok ? dc_ldg(rD + k) : 0.0;
                 z_reg[i] = ok ? dc_ldg(rz + k) : 0.0;
-            } else if (KIND == 1) {
-                const int h = ok ? dc_ldg(T.rgen + k) : 0;
-                d_reg[i] = (ok && col_ok) ? dc_ldg(T.ry + k) * dc_ldg(T.vk + T.rvo[k] + lcol) : 0.0;
-                z_reg[i] = ok ? dc_ldg(T.cbase + h) : 0.0;
-                o_reg[i] = (ok && T.coff) ? dc_ldg(T.coff + h) : 0.0;
-                s_reg[i] = ok ? h : -1;
             } else if (KIND == 2) {
                 d_reg[i] = (ok && col_ok) ? dc_ldg(T.Bm + (long long)gcol * T.ldb + k) : 0.0;
             } else {
@@ -250,9 +242,6 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
             if (KIND == 0) {
                 const double den = (d_reg[i] - cb) - co;
                 v = z_reg[i] * csj * dc_rcp(den);
-            } else if (KIND == 1) {
-                const double den = (z_reg[i] - cb) + (o_reg[i] - co);
-                v = (s_reg[i] == gcol) ? 1.0 : d_reg[i] * dc_rcp(den);
             } else if (KIND == 2) {
                 v = d_reg[i];
             } else {
@@ -396,7 +385,7 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
 // branches and no waits but the in-order load counter.  Generating U costs
 // FP64 VALU time, which the MFMA pipe shares, so each generated entry should
 // feed many MFMAs: one entry per FM MFMAs.
-template <int FM, int FN, int WGM, int WGN, int RING, int OCC>
+template <int FM, int FN, int WGM, int WGN, int RING, int OCC, bool P2>
 __global__ __launch_bounds__(WGM * WGN * 64, OCC)
 void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
                        int ntasks, int total_tiles) {
@@ -415,9 +404,11 @@ void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict
     const int row0 = tm * BM;
     const int col0 = tn * BN;
     if (col0 >= ncol || row0 >= T.rows) return;
-    // klen may be 0 (a block with no survivor of this half): the tile is
-    // then stored as zeros, and nothing is loaded from the generators.
+    // klen may be 0 (a block with no survivor of this half): without a
+    // second phase the tile is then stored as zeros, and nothing is loaded
+    // from the generators.
     const int klen = T.klen_p ? *T.klen_p : T.klen;
+    const int klen2 = P2 ? T.klen2 : 0;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -486,32 +477,90 @@ void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[slot][i], bf[j],
                                                                      acc[i][j], 0, 0, 0);
         };
-        const int nsteps = (klen + 3) / 4;
-        const int nfull = klen / 4;      // steps with every k < klen
+        if (!P2 || klen > 0) {
+            const int nsteps = (klen + 3) / 4;
+            const int nfull = klen / 4;      // steps with every k < klen
 #pragma unroll
-        for (int s = 0; s < PD; ++s) issue(s, s);
-        int s = 0;
-        for (; s + RING <= nfull; s += RING) {
+            for (int s = 0; s < PD; ++s) issue(s, s);
+            int s = 0;
+            for (; s + RING <= nfull; s += RING) {
 #pragma unroll
-            for (int j = 0; j < RING; ++j) {
-                issue((j + PD) % RING, s + j + PD);
-                compute(j, s + j, dc_false_type{});
-                // keep each step's loads in its step: hoisting them would make
-                // the ring slots overlap and force a wait for every load in flight
-                __builtin_amdgcn_sched_barrier(0);
+                for (int j = 0; j < RING; ++j) {
+                    issue((j + PD) % RING, s + j + PD);
+                    compute(j, s + j, dc_false_type{});
+                    // keep each step's loads in its step: hoisting them would
+                    // make the ring slots overlap and force a wait for every
+                    // load in flight
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            for (; s < nsteps; s += RING) {
+#pragma unroll
+                for (int j = 0; j < RING; ++j) {
+                    issue((j + PD) % RING, s + j + PD);
+                    compute(j, s + j, dc_true_type{});
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
-        for (; s < nsteps; s += RING) {
+        if constexpr (P2) {
+          if (klen2 > 0) {
+            // Second phase: A2 rows as A, B2 loaded (already divided by the
+            // column scale the epilogue applies).
+            const double* __restrict__ Ab2 = T.A2 + (SHIFT ? crow + lr : 0);
+            const double* __restrict__ B2 = T.B2;
+            const long long lda2 = T.lda2, ldb2 = T.ldb2;
+            double b2[RING][FN];
+            auto issue2 = [&](int slot, int step) {
+                const int k = min(step * 4 + lk, klen2 - 1);
+                const double* __restrict__ pk = Ab2 + (long long)k * lda2;
 #pragma unroll
-            for (int j = 0; j < RING; ++j) {
-                issue((j + PD) % RING, s + j + PD);
-                compute(j, s + j, dc_true_type{});
-                __builtin_amdgcn_sched_barrier(0);
+                for (int i = 0; i < FM; ++i)
+                    a[slot][i] = dc_ldg(pk + (SHIFT ? i * 16 : min(wrow + i * 16 + lr, rlast)));
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b2[slot][j] = dc_ldg(B2 + (long long)k * ldb2 +
+                                         min(wcol + j * 16 + lr, ncol - 1));
+            };
+            auto compute2 = [&](int slot, int step, auto masked_tag) {
+                constexpr bool MASKED = decltype(masked_tag)::value;
+                const bool kok = step * 4 + lk < klen2;
+                double bf[FN];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bf[j] = (!MASKED || kok) ? b2[slot][j] : 0.0;
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[slot][i], bf[j],
+                                                                         acc[i][j], 0, 0, 0);
+            };
+            const int nsteps = (klen2 + 3) / 4;
+            const int nfull = klen2 / 4;
+#pragma unroll
+            for (int s = 0; s < PD; ++s) issue2(s, s);
+            int s = 0;
+            for (; s + RING <= nfull; s += RING) {
+#pragma unroll
+                for (int j = 0; j < RING; ++j) {
+                    issue2((j + PD) % RING, s + j + PD);
+                    compute2(j, s + j, dc_false_type{});
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
+            for (; s < nsteps; s += RING) {
+#pragma unroll
+                for (int j = 0; j < RING; ++j) {
+                    issue2((j + PD) % RING, s + j + PD);
+                    compute2(j, s + j, dc_true_type{});
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+          }
         }
         return crow;
     };
-    const int crow = klen <= 0 ? wrow
+    const int crow = (klen <= 0 && (!P2 || klen2 <= 0)) ? wrow
                      : (T.rows >= WR) ? body(dc_true_type{}) : body(dc_false_type{});
 
 #pragma unroll
@@ -535,13 +584,13 @@ void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict
     }
 }
 
-template <int FM, int FN, int WGM, int WGN, int RING, int OCC = 2>
+template <int FM, int FN, int WGM, int WGN, int RING, int OCC = 2, bool P2 = false>
 hipError_t launch_reg(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
                       hipStream_t s) {
     constexpr int G8 = 8 * reg_group<WGM * WGN, OCC>();
     const int grid = (total + G8 - 1) / G8 * G8;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cauchy_gemm_reg<FM, FN, WGM, WGN, RING, OCC>), dim3(grid),
+    hipLaunchKernelGGL((k_cauchy_gemm_reg<FM, FN, WGM, WGN, RING, OCC, P2>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
     return hipGetLastError();
 }
@@ -557,14 +606,13 @@ hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int 
     return hipGetLastError();
 }
 
-// Two workgroups per CU for the 128 x 128 LDS kernel where its registers
-// allow it (generated and loaded B); the interpolation kind keeps one.
+// Two workgroups per CU for the 128 x 128 LDS kernel.
 template <int KIND>
-constexpr int occ128() { return KIND == 1 ? 1 : 2; }
-// The late-write schedule holds more registers; the interpolation and
-// adjoint kinds keep the spread schedule.
+constexpr int occ128() { return 2; }
+// The late-write schedule holds more registers; the adjoint kind keeps the
+// spread schedule.
 template <int KIND>
-constexpr int sched256() { return (KIND == 1 || KIND == 3) ? 0 : 1; }
+constexpr int sched256() { return KIND == 3 ? 0 : 1; }
 
 template <int KIND>
 hipError_t launch_variant(const GemmTask* tasks, const int* tile_start, int ntasks,
@@ -619,9 +667,11 @@ hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks, const int* tile_start, i
     return launch_variant<0>(tasks, tile_start, ntasks, total, variant, s);
 }
 
-hipError_t dc_launch_interp_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
-                                 int total, int variant, hipStream_t s) {
-    return launch_variant<1>(tasks, tile_start, ntasks, total, variant, s);
+hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks, const int* tile_start, int ntasks,
+                                  int total, int variant, hipStream_t s) {
+    if (variant == 5) return launch_reg<4, 4, 1, 1, 4, 2, true>(tasks, tile_start, ntasks, total, s);
+    if (variant == 0) return launch_reg<8, 2, 1, 4, 3, 2, true>(tasks, tile_start, ntasks, total, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t dc_launch_loaded_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,

@@ -65,15 +65,11 @@ __device__ __forceinline__ void dc_set_info(int* info, int code) {
 }
 
 // One product C[rows, cols] (=|+=) A[rows, 0:klen] * B[0:klen, cols] in which
-// B is generated on the fly, one of two kinds:
-//  kind 0 (Cauchy-like eigenvector block, eq. Q_Cauchy):
+// B is generated on the fly (kind 0, the Cauchy-like eigenvector block of
+// eq. Q_Cauchy):
 //    B_kc = rz[k] * cs[g] / ((rD[k] - cbase[g]) - coff[g]),
-//  kind 1 (interpolation rows [I Z] P^T of a compressed block, eq. sid /
-//  eq. geneZ): row k belongs to the skeleton column h = rgen[k] of its block,
-//    B_kc = 1                                        if g == h
-//    B_kc = ry[k] * vk[rvo[k] + c] / ((cbase[h] - cbase[g]) + (coff[h] - coff[g]))
 //  where g = ccol[c] if ccol is set, else col_off + c, is the generator index
-//  of output column c.  The output column of C is cpos[c] when both ccol and
+//  of output column c; kinds 2 and 3 below load or form B otherwise.  The output column of C is cpos[c] when both ccol and
 //  cpos are set, cpos[g] when only cpos is, and g - out_off otherwise.
 struct GemmTask {
     const double* A;      // row 0 of this task inside A (column-major, lda)
@@ -97,11 +93,6 @@ struct GemmTask {
     int out_off;          // subtracted from g when cpos is null
     int tiles_m, tiles_n; // worst-case tile grid of the task
     int beta;             // 0: overwrite, 1: accumulate
-    // kind 1 row data
-    const double* ry;
-    const int* rgen;
-    const long long* rvo;
-    const double* vk;
     // kind 2: B loaded, B_kc = Bm[k + c ldb].
     // kind 3 (adjoint, M = diag(lbar) + F o G with F_kc = 1/(lam_c - lam_k)):
     //   B_kc = lbar[c] on the diagonal (k == c, lbar may be null = 0), else
@@ -123,6 +114,16 @@ struct GemmTask {
     double* pd;
     double* pu;
     double* pl;
+    // kind 0, register kernel only: a second k-phase accumulated into the
+    // same tile after the generated one, with A2 (rows as A, lda2) and a
+    // loaded B2 (row-major: B2[k ldb2 + c], c the task's column), k < klen2.
+    // The epilogue's column scale multiplies it too (B2 is stored divided by
+    // it).  klen2 = 0: no second phase.
+    const double* A2;
+    long long lda2;
+    const double* B2;
+    long long ldb2;
+    int klen2;
 };
 
 // Host-side launcher of the generated-Cauchy product over a task list.
@@ -132,10 +133,11 @@ struct GemmTask {
 hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
                                  int ntasks, int total_tiles, int variant,
                                  hipStream_t stream);
-// Same for kind-1 (interpolation) tasks.
-hipError_t dc_launch_interp_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
-                                 int ntasks, int total_tiles, int variant,
-                                 hipStream_t stream);
+// Kind-0 tasks with a second, loaded k-phase (klen2 > 0): register kernel,
+// variant 0 or 5 only (hipErrorInvalidValue otherwise).
+hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks_dev, const int* tile_start_dev,
+                                  int ntasks, int total_tiles, int variant,
+                                  hipStream_t stream);
 // Kind-2 (loaded B) product with the ordinary epilogue.
 hipError_t dc_launch_loaded_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
                                  int ntasks, int total_tiles, hipStream_t stream);

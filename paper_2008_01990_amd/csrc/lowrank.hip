@@ -16,15 +16,17 @@
 // A block whose rank would exceed rmax is kept dense.
 //
 // Products (Algorithm 2 step 3(c), C += (A U_B) V_B, restated for one GPU):
-//   1a  C(:, J) = A(:, J) U_JJ                      diagonal blocks, exact
-//   1b  W(:, T_IJ) = A(:, I) U_I,T_IJ                skeleton columns, all J != I
-//   2   C(:, J) += [W(:, T_IJ)]_I [I Z_IJ]_I P^T      interpolation rows generated
-// A block kept dense is carried as a block whose skeleton is every column
-// (identity interpolation rows), so step 2 still owns each output block J
-// through exactly one task and no two tasks of a launch write the same
-// column.  W is laid out by output block J, so step 2 reads one contiguous
-// column range of W per J.  Every product is the generated-tile MFMA kernel; U, Z
-// and W's factors never exist as matrices except W itself (m x sum of ranks).
+//   1  W(:, T_IJ) = A(:, I) U_I,T_IJ                 skeleton columns, all J != I
+//   2  C(:, J) = A(:, J) U_JJ + [W(:, T_IJ)]_I [I Z_IJ]_I P^T
+// Step 2 is one launch of the register MFMA kernel with two k-phases per
+// tile: the diagonal block with U_JJ generated, then W's columns of block J
+// against the interpolation rows Y_J = [I Z_IJ]_I P^T, which are formed once
+// per merge from (y, v^(r), nodes) into a small dense array (sum of ranks x b)
+// and loaded.  C is written once.  A block kept dense is carried as a block
+// whose skeleton is every column (identity interpolation rows).  W is laid
+// out by output block J, so each J reads one contiguous column range of W
+// and of Y.  U and Z never exist as matrices; W and Y are m x (sum of ranks)
+// and (sum of ranks) x b.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -219,6 +221,35 @@ __global__ void k_nodes(int K, const double* D, const int* org, const double* ta
     }
 }
 
+// Interpolation rows [I Z_IJ] P^T of the low-rank blocks, one row per W
+// column k (Theorem 2, eq. geneZ): for output column c of block column
+// J = kJ[k], generator g = J b + c, the entry is 1 on the skeleton column
+// itself (g == rgen[k]) and y_k v^(r)_c / (w_h - w_g) otherwise.  Stored
+// row-major, Y[k b + c], divided by the column scale s_g that the product's
+// epilogue multiplies back; 0 past the block's last column.
+__global__ void k_build_y(long long nw, int b, int K, const double* __restrict__ ry,
+                          const int* __restrict__ rgen, const long long* __restrict__ rvo,
+                          const int* __restrict__ kJ, const double* __restrict__ vk,
+                          const double* __restrict__ cbase, const double* __restrict__ coff,
+                          const double* __restrict__ scale, double* __restrict__ Y) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nw * b) return;
+    const long long k = idx / b;
+    const int c = (int)(idx - k * b);
+    const int g = kJ[k] * b + c;
+    if (g >= K) {
+        Y[idx] = 0.0;
+        return;
+    }
+    const int h = rgen[k];
+    double v = 1.0;
+    if (h != g) {
+        const double den = (cbase[h] - cbase[g]) + (coff ? coff[h] - coff[g] : 0.0);
+        v = ry[k] * vk[rvo[k] + c] / den;
+    }
+    Y[idx] = v / scale[g];
+}
+
 __global__ void k_disable_tasks(GemmTask* tasks, int n, const int* zero) {
     const int i = threadIdx.x;
     if (i < n) tasks[i].ncol_p = zero;
@@ -326,7 +357,6 @@ hipError_t compress(int K, int b, double tol, const double* D, const double* zha
 struct Stage {
     std::vector<GemmTask> tasks;
     std::vector<int> start{0};
-    int kind = 0;
     void add(const GemmTask& t) {
         if (t.tiles_m * t.tiles_n == 0) return;
         tasks.push_back(t);
@@ -372,15 +402,15 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
     std::vector<double> ry(std::max<long long>(NW, 1));
     std::vector<int> rgen(std::max<long long>(NW, 1));
     std::vector<long long> rvo(std::max<long long>(NW, 1));
+    std::vector<int> kJ(std::max<long long>(NW, 1));
     for (int J = 0; J < p; ++J)
         for (int I = 0; I < p; ++I) {
             const int r = (I != J) ? rk(I, J) : 0;
             for (int a = 0; a < r; ++a) {
                 const long long col = gstart[J] + offIJ[(size_t)I * p + J] + a;
-                const size_t q = ((size_t)I * p + J) * rmax + a;
                 rgen[col] = J * b + skel(I, J, a);
                 rvo[col] = ((long long)I * p + J) * b;
-                (void)q;
+                kJ[col] = J;
             }
         }
     // y lives on the device already; copy it into W-column order on the host.
@@ -411,20 +441,25 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
     const size_t o_ry = o; o = al(o + ry.size() * sizeof(double));
     const size_t o_rg = o; o = al(o + rgen.size() * sizeof(int));
     const size_t o_rv = o; o = al(o + rvo.size() * sizeof(long long));
+    const size_t o_kj = o; o = al(o + kJ.size() * sizeof(int));
     for (int I = 0; I < p; ++I) {
         cofs[I] = o; o = al(o + std::max<size_t>(ccol[I].size(), 1) * sizeof(int));
         wofs[I] = o; o = al(o + std::max<size_t>(wpos[I].size(), 1) * sizeof(int));
     }
     const size_t small_bytes = o;
     double* W = nullptr;
+    double* Y = nullptr;
     char* small = nullptr;
     if (err == hipSuccess) err = hipMallocAsync((void**)&small, small_bytes, s);
     if (err == hipSuccess && NW > 0)
         err = hipMallocAsync((void**)&W, (size_t)wrows * NW * sizeof(double), s);
+    if (err == hipSuccess && NW > 0)
+        err = hipMallocAsync((void**)&Y, (size_t)NW * b * sizeof(double), s);
     std::vector<char> host(small_bytes);
     std::memcpy(host.data() + o_ry, ry.data(), ry.size() * sizeof(double));
     std::memcpy(host.data() + o_rg, rgen.data(), rgen.size() * sizeof(int));
     std::memcpy(host.data() + o_rv, rvo.data(), rvo.size() * sizeof(long long));
+    std::memcpy(host.data() + o_kj, kJ.data(), kJ.size() * sizeof(int));
     for (int I = 0; I < p; ++I) {
         if (!ccol[I].empty()) {
             std::memcpy(host.data() + cofs[I], ccol[I].data(), ccol[I].size() * sizeof(int));
@@ -433,14 +468,27 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
     }
     if (err == hipSuccess)
         err = hipMemcpyAsync(small, host.data(), small_bytes, hipMemcpyHostToDevice, s);
+    if (err == hipSuccess && NW > 0) {
+        const long long ny = NW * b;
+        hipLaunchKernelGGL(k_build_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, NW,
+                           b, K, reinterpret_cast<double*>(small + o_ry),
+                           reinterpret_cast<int*>(small + o_rg),
+                           reinterpret_cast<long long*>(small + o_rv),
+                           reinterpret_cast<int*>(small + o_kj), Cm.out.vk, cbase, coff, scale, Y);
+        err = hipGetLastError();
+    }
 
-    // Task lists.
-    Stage s1a, s1b, s2;
-    s2.kind = 1;
+    // Task lists: (1b) the skeleton columns into W, then one fused launch
+    // per output block J: the diagonal block A(:, J) U_JJ (generated) and
+    // W_J Y_J (loaded Y) accumulate in the same tile, so C is written once.
+    // The fused stage needs the register kernel (variants 0 and 5).
+    Stage s1b, sf;
+    const int fv = (variant == 2 || variant == 5) ? 5 : 0;
+    const int BMf = dc_gemm_tile_m(fv), BNf = dc_gemm_tile_n(fv);
     double flops = 0.0;
-    auto tiles = [&](GemmTask& t) {
-        t.tiles_m = (t.rows + BM - 1) / BM;
-        t.tiles_n = (t.ncol + BN - 1) / BN;
+    auto tiles = [&](GemmTask& t, int bm, int bn) {
+        t.tiles_m = (t.rows + bm - 1) / bm;
+        t.tiles_n = (t.ncol + bn - 1) / bn;
     };
     for (const LrHalf& H : halves) {
         if (H.rows <= 0) continue;
@@ -469,7 +517,7 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
             t.klen = hi[I] - lo[I];
             t.rD = H.gD + lo[I];
             t.rz = H.gz + lo[I];
-            // 1a: diagonal block straight into C
+            // diagonal block straight into C, plus the interpolation phase
             GemmTask a = t;
             a.col_off = I * b;
             a.ncol = bsz(I);
@@ -477,9 +525,17 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
             a.ldc = H.ldc;
             a.cpos = H.cpos;
             a.beta = 0;
-            tiles(a);
-            s1a.add(a);
-            flops += 2.0 * H.rows * a.klen * a.ncol;
+            const long long R = gstart[I + 1] - gstart[I];
+            if (R > 0) {
+                a.A2 = W + H.w_row0 + gstart[I] * (long long)wrows;
+                a.lda2 = wrows;
+                a.B2 = Y + gstart[I] * (long long)b;
+                a.ldb2 = b;
+                a.klen2 = (int)R;
+            }
+            tiles(a, BMf, BNf);
+            sf.add(a);
+            flops += 2.0 * H.rows * (a.klen + a.klen2) * a.ncol;
             // 1b: skeleton columns of every J != I into W
             if (!ccol[I].empty()) {
                 GemmTask c = t;
@@ -489,37 +545,15 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
                 c.C = W + H.w_row0;
                 c.ldc = wrows;
                 c.beta = 0;
-                tiles(c);
+                tiles(c, BM, BN);
                 s1b.add(c);
                 flops += 2.0 * H.rows * c.klen * c.ncol;
             }
         }
-        // 2: interpolation rows of every block column J
-        for (int J = 0; J < p; ++J) {
-            const long long R = gstart[J + 1] - gstart[J];
-            if (R == 0) continue;
-            GemmTask t = base;
-            t.A = W + H.w_row0 + gstart[J] * (long long)wrows;
-            t.lda = wrows;
-            t.klen = (int)R;
-            t.ry = reinterpret_cast<double*>(small + o_ry) + gstart[J];
-            t.rgen = reinterpret_cast<int*>(small + o_rg) + gstart[J];
-            t.rvo = reinterpret_cast<long long*>(small + o_rv) + gstart[J];
-            t.vk = Cm.out.vk;
-            t.col_off = J * b;
-            t.ncol = bsz(J);
-            t.C = H.C;
-            t.ldc = H.ldc;
-            t.cpos = H.cpos;
-            t.beta = 1;
-            tiles(t);
-            s2.add(t);
-            flops += 2.0 * H.rows * t.klen * t.ncol;
-        }
     }
     // Upload the task lists and launch the stages in order.
-    constexpr int NS = 3;
-    Stage* stages[NS] = {&s1a, &s1b, &s2};
+    constexpr int NS = 2;
+    Stage* stages[NS] = {&s1b, &sf};
     size_t to = 0;
     std::vector<size_t> tof(NS), sof(NS);
     for (int i = 0; i < NS; ++i) {
@@ -542,16 +576,17 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
         if (S.tasks.empty()) continue;
         const GemmTask* td = reinterpret_cast<GemmTask*>(tdev + tof[i]);
         const int* sd = reinterpret_cast<int*>(tdev + sof[i]);
-        err = (S.kind == 0) ? dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(),
-                                                    variant, s)
-                            : dc_launch_interp_gemm(td, sd, (int)S.tasks.size(), S.start.back(),
-                                                    variant, s);
+        err = (&S == &sf)
+                  ? dc_launch_cauchy_gemm2(td, sd, (int)S.tasks.size(), S.start.back(), fv, s)
+                  : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), variant,
+                                          s);
     }
     // The host staging vectors die with this scope: wait for the copies.
     hipError_t e2 = hipStreamSynchronize(s);
     if (err == hipSuccess) err = e2;
     if (tdev) hipFreeAsync(tdev, s);
     if (W) hipFreeAsync(W, s);
+    if (Y) hipFreeAsync(Y, s);
     if (small) hipFreeAsync(small, s);
     hipFreeAsync(Cm.dev, s);
     if (flops_out) *flops_out = flops;
