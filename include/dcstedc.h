@@ -48,7 +48,7 @@ typedef struct dc_opts {
                         1..64, default 32 */
     double lr_tol;   /* absolute tolerance of the structured low-rank merge
                         (0 = plain merge, the default) */
-    int lr_block;    /* block size b of the low-rank merge (default 512) */
+    int lr_block;    /* block size b of the low-rank merge (default 256) */
     int lr_min_k;    /* use the low-rank merge only when the deflated size K
                         reaches this (Algorithm 3's "size of M is large");
                         default 4096 */
@@ -145,7 +145,7 @@ int dc_secular(int K, const double* Dbar, const double* zbar, double rho,
  *                blocks of U are replaced by SRRSC approximations with
  *                absolute entry error <= lr_tol (eq. sid; Algorithm 2 step
  *                3(b)-(c)); diagonal blocks stay exact.
- *   lr_block     block size for lr_tol > 0 (<= 0: default 512); at most
+ *   lr_block     block size for lr_tol > 0 (<= 0: default 256); at most
  *                2048 with org, 4096 with org == NULL (else returns -13)
  * Allocates stream-ordered workspace when lr_tol > 0.
  */

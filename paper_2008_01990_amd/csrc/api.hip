@@ -183,7 +183,7 @@ extern "C" int dc_merge_update(int m, int K, const double* Qnd, int ldq, const d
     if (!C) return -10;
     if (ldc < m) return -11;
     if (!(lr_tol >= 0.0)) return -12;
-    if (lr_block <= 0) lr_block = 512;
+    if (lr_block <= 0) lr_block = 256;
     if (lr_tol > 0.0 && lr_block > dc_lowrank_max_block(org != nullptr)) return -13;
     if (lr_tol == 0.0 || K <= lr_block)
         return (int)dc_plain_update(m, K, Qnd, ldq, Dbar, org, tau, zhat, scale, C, ldc, 0, 0,

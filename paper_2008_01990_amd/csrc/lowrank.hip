@@ -653,7 +653,7 @@ extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
     if (!zhat) return -5;
     if (!scale) return -6;
     if (!(lr_tol > 0.0)) return -7;
-    if (lr_block <= 0) lr_block = 512;
+    if (lr_block <= 0) lr_block = 256;
     if (lr_block > dc_lowrank_max_block(org != nullptr)) return -8;
     if (rank_cap < 0) return -9;
     if (!ranks_host) return -10;
