@@ -89,8 +89,12 @@ size_t dc_stedc_workspace(int n, const dc_opts* opt);
  *   info_dev     device int; receives the status (see above)
  * With opt->lr_tol == 0 it allocates nothing and performs no host
  * synchronisation (graph-capturable).  With lr_tol > 0, each merge that takes
- * the low-rank product reads its sizes and ranks on the host and allocates
- * stream-ordered temporaries: not graph-capturable.
+ * the low-rank product reads its sizes and ranks on the host (the calling
+ * thread waits for the stream at those points): not graph-capturable.  Its
+ * device temporaries (SRRSC output, W = m x sum of ranks, the interpolation
+ * rows, layouts and task lists) are kept per host thread and device for
+ * reuse until the process ends, grown as needed; reuse from another stream
+ * is ordered after the last use by an event.
  * The first call for a given (n, options) builds and uploads the tree plan
  * synchronously; call dc_stedc_workspace first (it builds the plan) before
  * capturing.
@@ -147,7 +151,8 @@ int dc_secular(int K, const double* Dbar, const double* zbar, double rho,
  *                3(b)-(c)); diagonal blocks stay exact.
  *   lr_block     block size for lr_tol > 0 (<= 0: default 256); at most
  *                2048 with org, 4096 with org == NULL (else returns -13)
- * Allocates stream-ordered workspace when lr_tol > 0.
+ * With lr_tol > 0 it uses the per-thread low-rank buffers described at
+ * dc_stedc_ex and waits for the stream once (to read the ranks).
  */
 int dc_merge_update(int m, int K, const double* Qnd, int ldq,
                     const double* Dbar, const int* org, const double* tau,

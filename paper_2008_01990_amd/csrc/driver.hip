@@ -17,6 +17,7 @@
 // K of each merge) read by the kernels from device memory and grids sized
 // for the worst case.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <iterator>
 #include <map>
@@ -315,6 +316,131 @@ hipError_t prof_mark(int level, int phase, hipStream_t s) {
     return hipEventRecord(g_ev[idx], s);
 }
 
+}  // namespace
+
+// Byte copies between device memory and mapped pinned host memory, as
+// kernels on the caller's stream (the runtime's host copies wait for their
+// completion before returning, which costs a host wake-up per copy).
+__global__ void k_copy_bytes(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src,
+                             size_t n) {
+    const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+    if (i0 + 8 <= n && ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 7) == 0) {
+        *reinterpret_cast<uint64_t*>(dst + i0) = *reinterpret_cast<const uint64_t*>(src + i0);
+    } else {
+        for (size_t i = i0; i < n && i < i0 + 8; ++i) dst[i] = src[i];
+    }
+}
+
+// Stores seq into a pinned host word once every earlier kernel of the stream
+// has finished (stream order), for the host to spin on.
+__global__ void k_post_flag(volatile unsigned long long* flag, unsigned long long seq) {
+    if (threadIdx.x == 0) *flag = seq;
+}
+
+static hipError_t copy_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const size_t threads = (n + 7) / 8;
+    hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                       static_cast<unsigned char*>(dst), static_cast<const unsigned char*>(src),
+                       n);
+    return hipGetLastError();
+}
+
+// A pinned host buffer and its device-side address.
+static hipError_t pinned_alloc(size_t n, char** host, char** dev) {
+    hipError_t err = hipHostMalloc((void**)host, n, hipHostMallocMapped | hipHostMallocCoherent);
+    if (err != hipSuccess) return err;
+    err = hipHostGetDevicePointer((void**)dev, *host, 0);
+    if (err != hipSuccess) {
+        (void)hipHostFree(*host);
+        *host = nullptr;
+    }
+    return err;
+}
+
+hipError_t dc_readback(const std::vector<DcRead>& reads, hipStream_t s) {
+    thread_local char* pin = nullptr;
+    thread_local char* pin_dev = nullptr;
+    thread_local size_t cap = 0;
+    thread_local unsigned long long seq = 0;
+    size_t total = 256;                // the first 256 bytes hold the flag word
+    for (const DcRead& r : reads) total += (r.n + 255) & ~size_t(255);
+    if (total == 0) return hipSuccess;
+    hipError_t err = hipSuccess;
+    if (total > cap) {
+        // the previous batch is complete (every call waits before returning)
+        if (pin) (void)hipHostFree(pin);
+        pin = pin_dev = nullptr;
+        cap = 0;
+        const size_t want = std::max(total, size_t(1) << 20);
+        err = pinned_alloc(want, &pin, &pin_dev);
+        if (err != hipSuccess) return err;
+        *reinterpret_cast<volatile unsigned long long*>(pin) = 0;
+        cap = want;
+    }
+    size_t off = 256;
+    for (const DcRead& r : reads) {
+        err = copy_bytes(pin_dev + off, r.src, r.n, s);
+        if (err != hipSuccess) return err;
+        off += (r.n + 255) & ~size_t(255);
+    }
+    // Spin on the flag word: it is posted right after the copies finish.
+    // The stream is queried now and then, so a failed stream still returns.
+    volatile unsigned long long* flag = reinterpret_cast<volatile unsigned long long*>(pin);
+    const unsigned long long want = ++seq;
+    hipLaunchKernelGGL(k_post_flag, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<volatile unsigned long long*>(pin_dev), want);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (unsigned long spins = 1; *flag != want; ++spins) {
+        if (spins % 4096 == 0) {
+            err = hipStreamQuery(s);
+            if (err == hipSuccess) break;        // every kernel is done
+            if (err != hipErrorNotReady) return err;
+        }
+    }
+    off = 256;
+    for (const DcRead& r : reads) {
+        if (r.n > 0) std::memcpy(r.dst, pin + off, r.n);
+        off += (r.n + 255) & ~size_t(255);
+    }
+    return hipSuccess;
+}
+
+hipError_t dc_upload(void* dst, const void* src, size_t n, hipStream_t s) {
+    struct Chunk {
+        char* p;
+        char* dev;
+        size_t cap;
+        hipEvent_t ev;
+        bool used;
+    };
+    thread_local std::vector<Chunk> chunks;
+    if (n == 0) return hipSuccess;
+    Chunk* c = nullptr;
+    for (Chunk& k : chunks)
+        if (k.cap >= n && (!k.used || hipEventQuery(k.ev) == hipSuccess)) { c = &k; break; }
+    if (!c) {
+        Chunk k{nullptr, nullptr, std::max(n, size_t(1) << 20), nullptr, false};
+        hipError_t err = pinned_alloc(k.cap, &k.p, &k.dev);
+        if (err != hipSuccess) return err;
+        err = hipEventCreateWithFlags(&k.ev, hipEventDisableTiming);
+        if (err != hipSuccess) {
+            (void)hipHostFree(k.p);
+            return err;
+        }
+        chunks.push_back(k);
+        c = &chunks.back();
+    }
+    std::memcpy(c->p, src, n);
+    hipError_t err = copy_bytes(dst, c->dev, n, s);
+    if (err == hipSuccess) err = hipEventRecord(c->ev, s);
+    c->used = true;
+    return err;
+}
+
+namespace {
+
 // Per-merge product record of the last solve on this host thread:
 // path (0 plain, 1 low rank) and executed flops of low-rank merges.
 thread_local std::vector<int> t_path;
@@ -326,30 +452,42 @@ thread_local std::vector<double> t_lr_flops;
 hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Scratch& S,
                          int first, int nm, const dc_opts& o, hipStream_t s) {
     std::vector<MergeCnt> cnt(nm);
-    hipError_t err = hipMemcpyAsync(cnt.data(), S.cnt + first, nm * sizeof(MergeCnt),
-                                    hipMemcpyDeviceToHost, s);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    hipError_t err = dc_readback({{cnt.data(), S.cnt + first, nm * sizeof(MergeCnt)}}, s);
     if (err != hipSuccess) return err;
     const int b = std::min(o.lr_block, dc_lowrank_max_block(true));
+    // The row lists of every merge that switches, fetched in one round trip.
+    std::vector<std::vector<LrHalf>> lr_halves(nm);
+    std::vector<DcRead> reads;
     for (int i = 0; i < nm; ++i) {
         const Node& N = P.merges[first + i];
         const MergeCnt& C = cnt[i];
         if (C.K < o.lr_min_k || C.K <= b) continue;
         const Prob& pr = probs[N.prob];
         const long long base = (long long)pr.row0 + N.off;
+        lr_halves[i].resize(2);
+        for (int h = 0; h < 2; ++h) {
+            LrHalf& H = lr_halves[i][h];
+            const int cntk = h ? C.nbot : C.ntop;
+            H.klist.resize(cntk);
+            if (cntk > 0)
+                reads.push_back({H.klist.data(), (h ? S.kbot : S.ktop) + base,
+                                 cntk * sizeof(int)});
+        }
+    }
+    err = dc_readback(reads, s);
+    if (err != hipSuccess) return err;
+    for (int i = 0; i < nm; ++i) {
+        if (lr_halves[i].empty()) continue;
+        const Node& N = P.merges[first + i];
+        const MergeCnt& C = cnt[i];
+        const Prob& pr = probs[N.prob];
+        const long long base = (long long)pr.row0 + N.off;
         long long ldo;
         double* Qo = node_buf(pr, N.depth, ldo);
-        std::vector<LrHalf> halves(2);
+        std::vector<LrHalf>& halves = lr_halves[i];
         for (int h = 0; h < 2; ++h) {
             LrHalf& H = halves[h];
             const int r0 = h ? N.n1 : 0;
-            const int cntk = h ? C.nbot : C.ntop;
-            H.klist.resize(cntk);
-            if (cntk > 0) {
-                err = hipMemcpyAsync(H.klist.data(), (h ? S.kbot : S.ktop) + base,
-                                     cntk * sizeof(int), hipMemcpyDeviceToHost, s);
-                if (err != hipSuccess) return err;
-            }
             H.A = pr.B2 + (long long)N.off * pr.ld2 + N.off + r0;
             H.lda = pr.ld2;
             H.rows = h ? N.n2 : N.n1;
@@ -360,8 +498,6 @@ hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Sc
             H.cpos = S.pos_root + base;
             H.w_row0 = r0;
         }
-        err = hipStreamSynchronize(s);
-        if (err != hipSuccess) return err;
         double flops = 0.0;
         err = dc_lowrank_product(C.K, b, o.lr_tol, S.Dbar + base, S.zhat + base,
                                  S.cbase + base, S.tau + base, S.scale + base, halves,

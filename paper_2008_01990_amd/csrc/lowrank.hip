@@ -29,7 +29,9 @@
 // and (sum of ranks) x b.
 #include <algorithm>
 #include <climits>
+#include <cstdint>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "dc_internal.hpp"
@@ -250,6 +252,36 @@ __global__ void k_build_y(long long nw, int b, int K, const double* __restrict__
     Y[idx] = v / scale[g];
 }
 
+// Column layout of the low-rank product from the SRRSC output, one
+// workgroup per block pair (I, J), I != J, whose skeleton has r columns (its
+// rank, or every column of block J when kept dense): W column woff + a and
+// stage-1b list slot loff + a (a < r) get the skeleton column's generator
+// index, the pair's v^(r) row offset, the block column J and y_a (0 for a
+// dense block, whose interpolation rows are the identity).
+__global__ void k_layout(int p, int b, int K, int rmax, const int* __restrict__ rank,
+                         const int* __restrict__ pcol, const double* __restrict__ y,
+                         const long long* __restrict__ woff, const int* __restrict__ loff,
+                         int* __restrict__ rgen, long long* __restrict__ rvo,
+                         int* __restrict__ kJ, double* __restrict__ ry,
+                         int* __restrict__ ccol, int* __restrict__ wpos) {
+    const int pair = blockIdx.x;
+    const int I = pair / p, J = pair - (pair / p) * p;
+    if (I == J) return;
+    const int rk = rank[pair];
+    const bool dense = rk == -2;
+    const int r = dense ? min(b, K - J * b) : rk;
+    for (int a = threadIdx.x; a < r; a += blockDim.x) {
+        const long long col = woff[pair] + a;
+        const int h = J * b + (dense ? a : pcol[(long long)pair * rmax + a]);
+        rgen[col] = h;
+        rvo[col] = (long long)pair * b;
+        kJ[col] = J;
+        ry[col] = dense ? 0.0 : y[(long long)pair * rmax + a];
+        ccol[loff[pair] + a] = h;
+        wpos[loff[pair] + a] = (int)col;
+    }
+}
+
 __global__ void k_disable_tasks(GemmTask* tasks, int n, const int* zero) {
     const int i = threadIdx.x;
     if (i < n) tasks[i].ncol_p = zero;
@@ -259,9 +291,8 @@ size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Compressed {
     int p = 0, b = 0, rmax = 0;
-    std::vector<int> rank, pcol;
-    std::vector<double> y;
-    char* dev = nullptr;          // device block holding SrrscOut arrays
+    std::vector<int> rank;
+    char* dev = nullptr;          // device block holding SrrscOut arrays (not owned)
     SrrscOut out{};
 };
 
@@ -321,9 +352,19 @@ hipError_t launch_srrsc(int K, int b, int p, const double* D, const double* zhat
 }
 
 // coff == nullptr: plain column nodes w_j = cbase_j.
+// Bytes of the SRRSC output of a K-node problem in b x b blocks.
+size_t compress_bytes(int K, int b) {
+    const size_t p = (K + b - 1) / b, p2 = p * p;
+    const size_t rmax = std::min(MAX_R, std::max(1, b / 2));
+    return al(p2 * sizeof(int)) + 2 * al(p2 * rmax * sizeof(int)) +
+           al(p2 * rmax * sizeof(double)) + al(p2 * (size_t)b * sizeof(double));
+}
+
+// SRRSC of every off-diagonal block into `dev` (compress_bytes(K, b) bytes);
+// the ranks are read back to the host.
 hipError_t compress(int K, int b, double tol, const double* D, const double* zhat,
                     const double* cbase, const double* coff, const double* scale,
-                    hipStream_t s, Compressed& Cm) {
+                    hipStream_t s, Compressed& Cm, char* dev) {
     Cm.b = b;
     Cm.p = (K + b - 1) / b;
     Cm.rmax = std::min(MAX_R, std::max(1, b / 2));
@@ -333,24 +374,17 @@ hipError_t compress(int K, int b, double tol, const double* D, const double* zha
     const size_t o_prow = o; o = al(o + p2 * Cm.rmax * sizeof(int));
     const size_t o_pcol = o; o = al(o + p2 * Cm.rmax * sizeof(int));
     const size_t o_y = o; o = al(o + p2 * Cm.rmax * sizeof(double));
-    const size_t o_vk = o; o = al(o + p2 * (size_t)b * sizeof(double));
-    hipError_t err = hipMallocAsync((void**)&Cm.dev, o, s);
-    if (err != hipSuccess) return err;
+    hipError_t err = hipSuccess;
+    Cm.dev = dev;
     Cm.out.rank = reinterpret_cast<int*>(Cm.dev + o_rank);
     Cm.out.prow = reinterpret_cast<int*>(Cm.dev + o_prow);
     Cm.out.pcol = reinterpret_cast<int*>(Cm.dev + o_pcol);
     Cm.out.y = reinterpret_cast<double*>(Cm.dev + o_y);
-    Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o_vk);
+    Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o);
     err = launch_srrsc(K, b, Cm.p, D, zhat, cbase, coff, scale, tol, Cm.rmax, true, Cm.out, s);
     if (err != hipSuccess) return err;
     Cm.rank.resize(p2);
-    Cm.pcol.resize(p2 * Cm.rmax);
-    err = hipMemcpyAsync(Cm.rank.data(), Cm.out.rank, p2 * sizeof(int), hipMemcpyDeviceToHost, s);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(Cm.pcol.data(), Cm.out.pcol, p2 * Cm.rmax * sizeof(int),
-                             hipMemcpyDeviceToHost, s);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
-    return err;
+    return dc_readback({{Cm.rank.data(), Cm.out.rank, p2 * sizeof(int)}}, s);
 }
 
 // Device-side task list of one launch, with its tile prefix.
@@ -366,16 +400,71 @@ struct Stage {
 
 }  // namespace
 
+// Device buffers of the low-rank product, kept per host thread and device
+// for the process and grown on demand: stream-ordered allocation, and above
+// all freeing, cost several hundred microseconds of host time per merge.
+// Each use is ordered after the previous one: on the same stream by stream
+// order, on another stream through an event recorded after the last use.
+enum { SL_SRRSC, SL_LAYOUT, SL_W, SL_Y, SL_TASKS, NSLOT };
+struct Arena {
+    char* p[NSLOT] = {};
+    size_t cap[NSLOT] = {};
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
+};
+
+Arena& arena() {
+    thread_local std::map<int, Arena> per_device;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return per_device[dev];
+}
+
+hipError_t arena_begin(Arena& A, hipStream_t s) {
+    return (A.used && A.last != s) ? hipStreamWaitEvent(s, A.ev, 0) : hipSuccess;
+}
+
+hipError_t arena_get(Arena& A, int slot, size_t n, char** out) {
+    if (n > A.cap[slot]) {
+        if (A.p[slot]) {
+            // earlier work may still read the old buffer (rare: growth)
+            hipError_t err = hipDeviceSynchronize();
+            if (err == hipSuccess) err = hipFree(A.p[slot]);
+            if (err != hipSuccess) return err;
+            A.p[slot] = nullptr;
+            A.cap[slot] = 0;
+        }
+        const size_t want = n + n / 4;
+        hipError_t err = hipMalloc((void**)&A.p[slot], want);
+        if (err != hipSuccess) return err;
+        A.cap[slot] = want;
+    }
+    *out = A.p[slot];
+    return hipSuccess;
+}
+
+hipError_t arena_end(Arena& A, hipStream_t s) {
+    if (!A.ev) {
+        hipError_t err = hipEventCreateWithFlags(&A.ev, hipEventDisableTiming);
+        if (err != hipSuccess) return err;
+    }
+    A.last = s;
+    A.used = true;
+    return hipEventRecord(A.ev, s);
+}
+
 hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
                               const double* cbase, const double* coff, const double* scale,
                               std::vector<LrHalf>& halves, int wrows, int variant,
                               hipStream_t s, double* flops_out) {
+    Arena& A = arena();
+    hipError_t err = arena_begin(A, s);
+    char* cdev = nullptr;
+    if (err == hipSuccess) err = arena_get(A, SL_SRRSC, compress_bytes(K, b), &cdev);
     Compressed Cm;
-    hipError_t err = compress(K, b, tol, D, zhat, cbase, coff, scale, s, Cm);
-    if (err != hipSuccess) {
-        if (Cm.dev) hipFreeAsync(Cm.dev, s);
-        return err;
-    }
+    if (err == hipSuccess) err = compress(K, b, tol, D, zhat, cbase, coff, scale, s, Cm, cdev);
+    if (err != hipSuccess) return err;
     const int p = Cm.p, rmax = Cm.rmax;
     const int BM = dc_gemm_tile_m(variant), BN = dc_gemm_tile_n(variant);
     auto bsz = [&](int I) { return std::min(b, K - I * b); };
@@ -384,90 +473,66 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
         const int r = Cm.rank[(size_t)I * p + J];
         return r == -2 ? bsz(J) : r;
     };
-    auto dense = [&](int I, int J) { return Cm.rank[(size_t)I * p + J] == -2; };
-    auto skel = [&](int I, int J, int a) {
-        return dense(I, J) ? a : Cm.pcol[((size_t)I * p + J) * rmax + a];
-    };
 
-    // W layout by output block J: [W_IJ for I != J low-rank], r_IJ columns each.
-    std::vector<long long> gstart(p + 1, 0), offIJ((size_t)p * p, 0);
+    // Layouts from the ranks alone (the skeleton columns and y stay on the
+    // device): W by output block J, [W_IJ for I != J], r_IJ columns each;
+    // the stage-1b column list of block row I, [T_IJ for J != I].
+    std::vector<long long> gstart(p + 1, 0), woff((size_t)p * p, 0);
+    std::vector<int> loff((size_t)p * p, 0), lstart(p + 1, 0);
     for (int J = 0; J < p; ++J) {
         long long run = 0;
         for (int I = 0; I < p; ++I)
-            if (I != J && rk(I, J) > 0) { offIJ[(size_t)I * p + J] = run; run += rk(I, J); }
+            if (I != J && rk(I, J) > 0) { woff[(size_t)I * p + J] = gstart[J] + run; run += rk(I, J); }
         gstart[J + 1] = gstart[J] + run;
     }
-    const long long NW = gstart[p];
-    // Interpolation row data, indexed by W column.
-    std::vector<double> ry(std::max<long long>(NW, 1));
-    std::vector<int> rgen(std::max<long long>(NW, 1));
-    std::vector<long long> rvo(std::max<long long>(NW, 1));
-    std::vector<int> kJ(std::max<long long>(NW, 1));
-    for (int J = 0; J < p; ++J)
-        for (int I = 0; I < p; ++I) {
-            const int r = (I != J) ? rk(I, J) : 0;
-            for (int a = 0; a < r; ++a) {
-                const long long col = gstart[J] + offIJ[(size_t)I * p + J] + a;
-                rgen[col] = J * b + skel(I, J, a);
-                rvo[col] = ((long long)I * p + J) * b;
-                kJ[col] = J;
-            }
-        }
-    // y lives on the device already; copy it into W-column order on the host.
-    Cm.y.resize((size_t)p * p * rmax);
-    err = hipMemcpyAsync(Cm.y.data(), Cm.out.y, Cm.y.size() * sizeof(double),
-                         hipMemcpyDeviceToHost, s);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
-    for (int J = 0; J < p && err == hipSuccess; ++J)
-        for (int I = 0; I < p; ++I) {
-            const int r = (I != J) ? rk(I, J) : 0;
-            for (int a = 0; a < r; ++a)
-                ry[gstart[J] + offIJ[(size_t)I * p + J] + a] =
-                    dense(I, J) ? 0.0 : Cm.y[((size_t)I * p + J) * rmax + a];
-        }
-    // Stage-1b column lists per I (same for every half).
-    std::vector<std::vector<int>> ccol(p), wpos(p);
-    for (int I = 0; I < p; ++I)
-        for (int J = 0; J < p; ++J) {
-            if (I == J || rk(I, J) <= 0) continue;
-            for (int a = 0; a < rk(I, J); ++a) {
-                ccol[I].push_back(J * b + skel(I, J, a));
-                wpos[I].push_back((int)(gstart[J] + offIJ[(size_t)I * p + J] + a));
-            }
-        }
-    // Device staging of the small arrays: ry, rgen, rvo, ccol/wpos per I.
-    std::vector<size_t> cofs(p), wofs(p);
-    size_t o = 0;
-    const size_t o_ry = o; o = al(o + ry.size() * sizeof(double));
-    const size_t o_rg = o; o = al(o + rgen.size() * sizeof(int));
-    const size_t o_rv = o; o = al(o + rvo.size() * sizeof(long long));
-    const size_t o_kj = o; o = al(o + kJ.size() * sizeof(int));
     for (int I = 0; I < p; ++I) {
-        cofs[I] = o; o = al(o + std::max<size_t>(ccol[I].size(), 1) * sizeof(int));
-        wofs[I] = o; o = al(o + std::max<size_t>(wpos[I].size(), 1) * sizeof(int));
+        int run = 0;
+        for (int J = 0; J < p; ++J)
+            if (I != J && rk(I, J) > 0) { loff[(size_t)I * p + J] = lstart[I] + run; run += rk(I, J); }
+        lstart[I + 1] = lstart[I] + run;
     }
+    const long long NW = gstart[p];
+    // Device block: per-pair offsets (uploaded), then the per-W-column arrays
+    // that k_layout fills: skeleton generator, v^(r) row, block column, y;
+    // and the stage-1b lists (skeleton generator, W column).
+    const size_t p2 = (size_t)p * p;
+    const size_t nw1 = (size_t)std::max<long long>(NW, 1);
+    size_t o = 0;
+    const size_t o_wo = o; o = al(o + p2 * sizeof(long long));
+    const size_t o_lo = o; o = al(o + p2 * sizeof(int));
+    const size_t up_bytes = o;
+    const size_t o_ry = o; o = al(o + nw1 * sizeof(double));
+    const size_t o_rg = o; o = al(o + nw1 * sizeof(int));
+    const size_t o_rv = o; o = al(o + nw1 * sizeof(long long));
+    const size_t o_kj = o; o = al(o + nw1 * sizeof(int));
+    const size_t o_cc = o; o = al(o + nw1 * sizeof(int));
+    const size_t o_wp = o; o = al(o + nw1 * sizeof(int));
     const size_t small_bytes = o;
     double* W = nullptr;
     double* Y = nullptr;
     char* small = nullptr;
-    if (err == hipSuccess) err = hipMallocAsync((void**)&small, small_bytes, s);
+    if (err == hipSuccess) err = arena_get(A, SL_LAYOUT, small_bytes, &small);
     if (err == hipSuccess && NW > 0)
-        err = hipMallocAsync((void**)&W, (size_t)wrows * NW * sizeof(double), s);
+        err = arena_get(A, SL_W, (size_t)wrows * NW * sizeof(double), reinterpret_cast<char**>(&W));
     if (err == hipSuccess && NW > 0)
-        err = hipMallocAsync((void**)&Y, (size_t)NW * b * sizeof(double), s);
-    std::vector<char> host(small_bytes);
-    std::memcpy(host.data() + o_ry, ry.data(), ry.size() * sizeof(double));
-    std::memcpy(host.data() + o_rg, rgen.data(), rgen.size() * sizeof(int));
-    std::memcpy(host.data() + o_rv, rvo.data(), rvo.size() * sizeof(long long));
-    std::memcpy(host.data() + o_kj, kJ.data(), kJ.size() * sizeof(int));
-    for (int I = 0; I < p; ++I) {
-        if (!ccol[I].empty()) {
-            std::memcpy(host.data() + cofs[I], ccol[I].data(), ccol[I].size() * sizeof(int));
-            std::memcpy(host.data() + wofs[I], wpos[I].data(), wpos[I].size() * sizeof(int));
-        }
+        err = arena_get(A, SL_Y, (size_t)NW * b * sizeof(double), reinterpret_cast<char**>(&Y));
+    std::vector<char> host(up_bytes);
+    std::memcpy(host.data() + o_wo, woff.data(), p2 * sizeof(long long));
+    std::memcpy(host.data() + o_lo, loff.data(), p2 * sizeof(int));
+    if (err == hipSuccess) err = dc_upload(small, host.data(), up_bytes, s);
+    int* const d_ccol = reinterpret_cast<int*>(small + o_cc);
+    int* const d_wpos = reinterpret_cast<int*>(small + o_wp);
+    if (err == hipSuccess && NW > 0) {
+        hipLaunchKernelGGL(k_layout, dim3((unsigned)p2), dim3(128), 0, s, p, b, K, rmax,
+                           Cm.out.rank, Cm.out.pcol, Cm.out.y,
+                           reinterpret_cast<long long*>(small + o_wo),
+                           reinterpret_cast<int*>(small + o_lo),
+                           reinterpret_cast<int*>(small + o_rg),
+                           reinterpret_cast<long long*>(small + o_rv),
+                           reinterpret_cast<int*>(small + o_kj),
+                           reinterpret_cast<double*>(small + o_ry), d_ccol, d_wpos);
+        err = hipGetLastError();
     }
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(small, host.data(), small_bytes, hipMemcpyHostToDevice, s);
     if (err == hipSuccess && NW > 0) {
         const long long ny = NW * b;
         hipLaunchKernelGGL(k_build_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, NW,
@@ -537,11 +602,11 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
             sf.add(a);
             flops += 2.0 * H.rows * (a.klen + a.klen2) * a.ncol;
             // 1b: skeleton columns of every J != I into W
-            if (!ccol[I].empty()) {
+            if (lstart[I + 1] > lstart[I]) {
                 GemmTask c = t;
-                c.ccol = reinterpret_cast<int*>(small + cofs[I]);
-                c.cpos = reinterpret_cast<int*>(small + wofs[I]);
-                c.ncol = (int)ccol[I].size();
+                c.ccol = d_ccol + lstart[I];
+                c.cpos = d_wpos + lstart[I];
+                c.ncol = lstart[I + 1] - lstart[I];
                 c.C = W + H.w_row0;
                 c.ldc = wrows;
                 c.beta = 0;
@@ -569,8 +634,8 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
         std::memcpy(th.data() + sof[i], stages[i]->start.data(),
                     stages[i]->start.size() * sizeof(int));
     }
-    if (err == hipSuccess) err = hipMallocAsync((void**)&tdev, to, s);
-    if (err == hipSuccess) err = hipMemcpyAsync(tdev, th.data(), to, hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = arena_get(A, SL_TASKS, to, &tdev);
+    if (err == hipSuccess) err = dc_upload(tdev, th.data(), to, s);
     for (int i = 0; i < NS && err == hipSuccess; ++i) {
         const Stage& S = *stages[i];
         if (S.tasks.empty()) continue;
@@ -581,14 +646,8 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
                   : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), variant,
                                           s);
     }
-    // The host staging vectors die with this scope: wait for the copies.
-    hipError_t e2 = hipStreamSynchronize(s);
+    const hipError_t e2 = arena_end(A, s);
     if (err == hipSuccess) err = e2;
-    if (tdev) hipFreeAsync(tdev, s);
-    if (W) hipFreeAsync(W, s);
-    if (Y) hipFreeAsync(Y, s);
-    if (small) hipFreeAsync(small, s);
-    hipFreeAsync(Cm.dev, s);
     if (flops_out) *flops_out = flops;
     return err;
 }
@@ -673,11 +732,14 @@ extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
     if (rank_cap == 0) {
         // the ranks the low-rank product itself uses
         Compressed Cm;
+        char* cdev = nullptr;
         if (err == hipSuccess)
-            err = compress(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, stream, Cm);
+            err = hipMallocAsync((void**)&cdev, compress_bytes(K, lr_block), stream);
+        if (err == hipSuccess)
+            err = compress(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, stream, Cm, cdev);
         if (err == hipSuccess)
             std::memcpy(ranks_host, Cm.rank.data(), Cm.rank.size() * sizeof(int));
-        if (Cm.dev) hipFreeAsync(Cm.dev, stream);
+        if (cdev) hipFreeAsync(cdev, stream);
     } else {
         // count only, up to rank_cap
         int* rk = nullptr;
