@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--lowrank-tol", type=float, default=1e-10,
                     help="also time the low-rank path at this tolerance (0: skip)")
     ap.add_argument("--lowrank-block", type=int, default=256)
-    ap.add_argument("--lowrank-min-k", type=int, default=4096)
+    ap.add_argument("--lowrank-min-k", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096)
@@ -268,7 +268,7 @@ def extra_configs(L, torch):
     d = torch.empty_like(d_in)
     Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
     r = {}
-    for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=256, lr_min_k=4096))):
+    for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=256, lr_min_k=2048))):
         s = L.Solver(n, leaf=64, **kw)
 
         def c1():
@@ -334,7 +334,7 @@ def extra_configs(L, torch):
         d = torch.empty_like(d_in)
         rec = {}
         for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=256,
-                                                          lr_min_k=4096))):
+                                                          lr_min_k=2048))):
             s = L.Solver(n, leaf=64, **kw)
 
             def c5():

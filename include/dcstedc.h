@@ -51,7 +51,7 @@ typedef struct dc_opts {
     int lr_block;    /* block size b of the low-rank merge (default 256) */
     int lr_min_k;    /* use the low-rank merge only when the deflated size K
                         reaches this (Algorithm 3's "size of M is large");
-                        default 4096 */
+                        default 2048 */
     int max_iter;    /* secular iteration cap (default 200: enough for pure
                         bisection to reach 4-ulp relative accuracy) */
     int gemm_tile;   /* merge-product tile variant for every level:

@@ -587,7 +587,7 @@ extern "C" void dc_opts_default(dc_opts* o) {
     o->leaf = 32;
     o->lr_tol = 0.0;
     o->lr_block = 256;
-    o->lr_min_k = 4096;
+    o->lr_min_k = 2048;
     o->max_iter = 200;
     o->gemm_tile = 0;
 }

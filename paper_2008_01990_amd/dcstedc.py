@@ -114,7 +114,7 @@ def _dev(t, dtype=torch.float64):
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
-def opts(leaf=32, lr_tol=0.0, lr_block=256, lr_min_k=4096, max_iter=200, gemm_tile=0):
+def opts(leaf=32, lr_tol=0.0, lr_block=256, lr_min_k=2048, max_iter=200, gemm_tile=0):
     o = DcOpts()
     load().dc_opts_default(ctypes.byref(o))
     o.leaf, o.lr_tol, o.lr_block = leaf, lr_tol, lr_block
@@ -348,7 +348,7 @@ class EighTridiagonal(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, d, e, leaf=32, lr_tol=0.0, lr_block=256, lr_min_k=4096):
+    def forward(ctx, d, e, leaf=32, lr_tol=0.0, lr_block=256, lr_min_k=2048):
         n = d.numel()
         s = Solver(n, leaf=leaf, lr_tol=lr_tol, lr_block=lr_block, lr_min_k=lr_min_k)
         lam = d.detach().to("cuda", torch.float64).clone().contiguous()
@@ -375,7 +375,7 @@ def eigh_tridiagonal(d, e, **kw):
     """Differentiable (lam ascending, Q) of the symmetric tridiagonal T(d, e)."""
     return EighTridiagonal.apply(d, e, *[kw.get(k, v) for k, v in
                                          (("leaf", 32), ("lr_tol", 0.0), ("lr_block", 256),
-                                          ("lr_min_k", 4096))])
+                                          ("lr_min_k", 2048))])
 
 
 class BatchedSolver:
@@ -385,7 +385,7 @@ class BatchedSolver:
     solve(graph=False) runs the same schedule eagerly.
     """
 
-    def __init__(self, sizes, leaf=32, gemm_tile=0, lr_tol=0.0, lr_block=256, lr_min_k=4096):
+    def __init__(self, sizes, leaf=32, gemm_tile=0, lr_tol=0.0, lr_block=256, lr_min_k=2048):
         self.sizes = [int(v) for v in sizes]
         self.count = len(self.sizes)
         self.o = opts(leaf=leaf, gemm_tile=gemm_tile, lr_tol=lr_tol, lr_block=lr_block,

@@ -49,6 +49,31 @@ def test_lowrank_merge_update_within_tolerance(lib, m, K, b, tol, seed):
     assert (ranks_g[off] == ranks_o[off]).mean() >= 0.9
 
 
+def test_lowrank_buffers_reused_across_streams(lib):
+    # The low-rank product keeps its device buffers per thread and reuses them
+    # on whatever stream the next call comes from (ordered by an event): the
+    # same product, a larger one in between, and the same again on two other
+    # streams, all give the first result bit for bit.
+    m, K, b, tol = 400, 900, 128, 1e-10
+    announce("lowrank buffers across streams")
+    D, (org, tau, zhat, s) = _gens(K, 7)
+    args = (cuda(W.random_matrix(m, K, seed=8).T), m, K, cuda(D), cuda(org, torch.int32),
+            cuda(tau), cuda(zhat), cuda(s))
+    first = lib.merge_update(*args, lr_tol=tol, lr_block=b).clone()
+    D2, (org2, tau2, zhat2, s2) = _gens(2 * K, 9)
+    big = (cuda(W.random_matrix(m, 2 * K, seed=10).T), m, 2 * K, cuda(D2),
+           cuda(org2, torch.int32), cuda(tau2), cuda(zhat2), cuda(s2))
+    outs = []
+    for st in (torch.cuda.Stream(), torch.cuda.Stream()):
+        with torch.cuda.stream(st):
+            lib.merge_update(*big, lr_tol=tol, lr_block=b)
+            outs.append(lib.merge_update(*args, lr_tol=tol, lr_block=b))
+        torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert torch.equal(o, first)
+
+
 def test_lowrank_dense_fallback(lib):
     # b = 16 caps the rank at 8; at tol 1e-15 most blocks keep dense.
     K, m, b = 96, 50, 16
