@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--lowrank-only", action="store_true",
+                    help="profiling: time only the low-rank solve (not the benchmark line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-extra", action="store_true",
@@ -415,6 +417,20 @@ def main():
     e = torch.tensor(e0, device="cuda")
     d = torch.empty_like(d_in)
     Qbuf = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    if args.lowrank_only:
+        lr = L.Solver(n, leaf=args.leaf, gemm_tile=args.gemm_tile, lr_tol=args.lowrank_tol,
+                      lr_block=args.lowrank_block, lr_min_k=args.lowrank_min_k)
+
+        def lr_only():
+            d.copy_(d_in)
+            lr.solve_into(d, e, Qbuf)
+        for _ in range(args.warmup):
+            lr_only()
+        t = _time(lr_only, args.steps, torch) if args.steps > 0 else 0.0
+        print(json.dumps({"lowrank_seconds": t, "tol": args.lowrank_tol,
+                          "block": args.lowrank_block, "min_k": args.lowrank_min_k,
+                          "status": lr.status()}), flush=True)
+        return
     solver = L.Solver(n, leaf=args.leaf, gemm_tile=args.gemm_tile)
 
     def step():
