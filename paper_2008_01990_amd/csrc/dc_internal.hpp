@@ -80,7 +80,10 @@ __host__ __device__ inline double* node_buf(const Prob& P, int depth, long long&
 hipError_t dc_launch_leaf(const Node* leaves, int nleaves, Scratch S, hipStream_t s);
 hipError_t dc_launch_build(const Node* merges, int nmerges, int bm, int bn, Scratch S,
                            hipStream_t s);
-hipError_t dc_launch_deflate(const Node* merges, int nm, Scratch S, hipStream_t s);
+// k_merge_sort over row blocks (row_start: per-merge prefix of ceil(m /
+// DC_ROWS_PER_BLOCK) blocks, nrow_blk in total), then k_deflate per merge.
+hipError_t dc_launch_deflate(const Node* merges, const int* row_start, int nm, int nrow_blk,
+                             Scratch S, hipStream_t s);
 hipError_t dc_launch_rotate(const Node* merges, const int* blk_start, int nm, int nblk,
                             Scratch S, hipStream_t s);
 hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, int nblk,

@@ -108,11 +108,15 @@ struct WState {
 };
 
 // Pair test and rotation of the walk for candidate p = st and the next
-// survivor q.  Not inlined: every pass of the walk (speculative, correcting,
-// counting, writing) must run the same instructions, so that the counts and
-// the writes agree to the last bit.
-__device__ __noinline__ bool walk_decide(const WState& st, const WState& q, double tol,
-                                         WState& nxt, double& c, double& sn, double& dv) {
+// survivor q.  Every pass of the walk (speculative, correcting, counting,
+// writing) must take the same decisions to the last bit, so that the counts
+// and the writes agree: contraction into FMAs is off here, which leaves only
+// IEEE operations whose results do not depend on where the code is inlined.
+// (Out of line, the state structs went through scratch memory: several
+// memory round trips per step.)
+__device__ __forceinline__ bool walk_decide(const WState& st, const WState& q, double tol,
+                                            WState& nxt, double& c, double& sn, double& dv) {
+#pragma clang fp contract(off)
     // |(D_i - D_p) c s| <= tol with (c, s) = (z_i, z_p) / r, multiplied out by
     // r^2 = z_p^2 + z_i^2 so that the common case (no rotation) needs no
     // square root or reciprocal.  |z| <= 1 and surviving z are far above
@@ -196,6 +200,45 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
 }
 
 // One workgroup per merge: z, sort, deflation walk, generator lists.
+// Rank-one vector and sorted order of every merge of a level (eq. T3), one
+// thread per eigenpair of the two children:
+//   z = [last row of Q_1, sigma * first row of Q_2] / sqrt(2),
+// and the merge of the two ascending spectra (Lambda_1 first on ties):
+// Lambda_1[i] goes to i + #{Lambda_2 < it}, Lambda_2[j] to j + #{Lambda_1 <= it}.
+__global__ __launch_bounds__(DC_ROWS_PER_BLOCK)
+void k_merge_sort(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
+                  Scratch S) {
+    const int mi = block_of(blk_start, nm, blockIdx.x);
+    const Node N = merges[mi];
+    const Prob P = S.probs[N.prob];
+    if (*P.info == DC_STATUS_NONFINITE) return;      // k_deflate handles it
+    const int n1 = N.n1, n2 = N.n2, m = n1 + n2;
+    const int i = (blockIdx.x - blk_start[mi]) * DC_ROWS_PER_BLOCK + threadIdx.x;
+    if (i >= m) return;
+    const long long base = (long long)P.row0 + N.off;
+    long long ldi;
+    const double* Qi = node_buf(P, N.depth + 1, ldi);
+    const double* L1 = P.d + N.off;
+    const double* L2 = P.d + N.off + n1;
+    const double ek = P.e[N.off + n1 - 1];
+    const double sigma = ek < 0.0 ? -1.0 : 1.0;
+    const double rs2 = 0.70710678118654752440;
+    double Dv, zv;
+    int pos;
+    if (i < n1) {
+        Dv = L1[i];
+        zv = Qi[(long long)(N.off + i) * ldi + N.off + n1 - 1] * rs2;
+        pos = i + count_lt(L2, n2, Dv);
+    } else {
+        Dv = L2[i - n1];
+        zv = sigma * Qi[(long long)(N.off + i) * ldi + N.off + n1] * rs2;
+        pos = (i - n1) + count_le(L1, n1, Dv);
+    }
+    S.Ds[base + pos] = Dv;
+    S.zs[base + pos] = zv;
+    S.perm[base + pos] = i;
+}
+
 __global__ __launch_bounds__(NT)
 void k_deflate(const Node* __restrict__ merges, Scratch S) {
     // per segment of the survivor list: speculative end state, true start
@@ -212,14 +255,10 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     const Prob P = S.probs[N.prob];
     const int n1 = N.n1, n2 = N.n2, m = n1 + n2;
     const long long base = (long long)P.row0 + N.off;
-    long long ldi;
-    const double* Qi = node_buf(P, N.depth + 1, ldi);
     const double* L1 = P.d + N.off;          // Lambda_1 ascending
     const double* L2 = P.d + N.off + n1;     // Lambda_2 ascending
     const double ek = P.e[N.off + n1 - 1];
     const double rho2 = 2.0 * fabs(ek);
-    const double sigma = ek < 0.0 ? -1.0 : 1.0;
-    const double rs2 = 0.70710678118654752440;
     const int tid = threadIdx.x;
 
     // A problem with non-finite input (flagged by the leaf phase) cannot be
@@ -245,23 +284,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         return;
     }
 
-    // z, merge of the two sorted lists, scatter to sorted order.
-    for (int i = tid; i < m; i += NT) {
-        double Dv, zv;
-        int pos;
-        if (i < n1) {
-            Dv = L1[i];
-            zv = Qi[(long long)(N.off + i) * ldi + N.off + n1 - 1] * rs2;
-            pos = i + count_lt(L2, n2, Dv);
-        } else {
-            Dv = L2[i - n1];
-            zv = sigma * Qi[(long long)(N.off + i) * ldi + N.off + n1] * rs2;
-            pos = (i - n1) + count_le(L1, n1, Dv);
-        }
-        S.Ds[base + pos] = Dv;
-        S.zs[base + pos] = zv;
-        S.perm[base + pos] = i;
-    }
+    // (z and the merged order were written by k_merge_sort.)
     const double dmax = fmax(fmax(fabs(L1[0]), fabs(L1[n1 - 1])),
                              fmax(fabs(L2[0]), fabs(L2[n2 - 1])));
     const double tol = 8.0 * EPS * fmax(dmax, rho2);
@@ -296,11 +319,24 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         }
     }
     __syncthreads();
+    // The survivors' (D, z, column) laid out in walk order, so that a walk
+    // step reads index k + 1 directly (no chase through SI) and the next
+    // step's loads can be issued early.  Scratch: lamr, cbase and kbot, which
+    // later phases of this level write.
+    double* cD = S.lamr + base;
+    double* cz = S.cbase + base;
+    int* cc = S.kbot + base;
+    for (int k = tid; k < Ns; k += NT) {
+        const int i = SI[k];
+        cD[k] = S.Ds[base + i];
+        cz[k] = S.zs[base + i];
+        cc[k] = colof(i);
+    }
+    __syncthreads();
 
     auto load_orig = [&](int k) {
-        const int i = SI[k];
-        const int c = colof(i);
-        return WState{S.Ds[base + i], S.zs[base + i], c, c < n1 ? 1 : 2, 1};
+        const int c = cc[k];
+        return WState{cD[k], cz[k], c, c < n1 ? 1 : 2, 1};
     };
     // Decision for the pair (st, survivor k + 1): nxt is the next candidate;
     // on a rotation (c, s) and the deflated value are returned as well.
@@ -319,15 +355,16 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     // Speculative walk: every segment starts from its unrotated survivor.
     if (myseg) {
         WState st = load_orig(ka);
-        const WState f = load_orig(ka + 1);
-        fD[tid] = f.D; fz[tid] = f.z; fcol[tid] = f.col; ftyp[tid] = f.typ;
+        WState q = load_orig(ka + 1);
+        fD[tid] = q.D; fz[tid] = q.z; fcol[tid] = q.col; ftyp[tid] = q.typ;
         for (int k = ka; k < kb; ++k) {
+            const WState qn = load_orig(min(k + 2, npairs));   // next step's pair
             WState nx;
             double c, sn, dv;
-            int ti;
-            dspec[k] = decide(st, k, nx, c, sn, dv, ti) ? 1 : 0;
+            dspec[k] = walk_decide(st, q, tol, nx, c, sn, dv) ? 1 : 0;
             if (k == ka) fdec[tid] = dspec[k];
             st = nx;
+            q = qn;
         }
         oD[tid] = st.D; oz[tid] = st.z; ocol[tid] = st.col; otyp[tid] = st.typ;
         oorg[tid] = st.orig;
@@ -365,15 +402,17 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
 
     // Count, then write, from the true starts.  A rotation starts a new chain
     // exactly when its first column is an unrotated survivor.
-    int cs = 0, cr = 0, cc = 0;
+    int cs = 0, cr = 0, nchn = 0;
     if (myseg) {
         WState st{iD[tid], iz[tid], icol[tid], ityp[tid], iorg[tid]};
+        WState q = load_orig(ka + 1);
         for (int k = ka; k < kb; ++k) {
+            const WState qn = load_orig(min(k + 2, npairs));
             WState nx;
             double c, sn, dv;
-            int ti;
-            if (decide(st, k, nx, c, sn, dv, ti)) { ++cr; cc += st.orig; } else ++cs;
+            if (walk_decide(st, q, tol, nx, c, sn, dv)) { ++cr; nchn += st.orig; } else ++cs;
             st = nx;
+            q = qn;
         }
         cs += tid == nseg - 1;                          // the last candidate
     } else if (tid == 0 && Ns == 1) {
@@ -382,7 +421,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     int K = 0, nrot = 0, nch = 0;
     int os = block_excl_scan(cs, wsum, &K);
     int orr = block_excl_scan(cr, wsum, &nrot);
-    int oc = block_excl_scan(cc, wsum, &nch);
+    int oc = block_excl_scan(nchn, wsum, &nch);
     auto put_surv = [&](const WState& st, int k) {
         S.Dbar[base + k] = st.D;
         S.zbar[base + k] = st.z;
@@ -391,11 +430,15 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     };
     if (myseg) {
         WState st{iD[tid], iz[tid], icol[tid], ityp[tid], iorg[tid]};
+        WState q = load_orig(ka + 1);
         for (int k = ka; k < kb; ++k) {
+            const WState qn = load_orig(min(k + 2, npairs));
             WState nx;
             double c, sn, dv;
-            int ti;
-            if (decide(st, k, nx, c, sn, dv, ti)) {
+            const int ti = q.typ;
+            const bool rot = walk_decide(st, q, tol, nx, c, sn, dv);
+            q = qn;
+            if (rot) {
                 if (st.orig) S.rch[base + oc++] = orr;
                 S.rp[base + orr] = st.col;
                 S.ri[base + orr] = nx.col;
@@ -728,8 +771,11 @@ hipError_t dc_launch_build(const Node* merges, int nm, int bm, int bn, Scratch S
     return hipGetLastError();
 }
 
-hipError_t dc_launch_deflate(const Node* merges, int nm, Scratch S, hipStream_t s) {
+hipError_t dc_launch_deflate(const Node* merges, const int* row_start, int nm, int nrow_blk,
+                             Scratch S, hipStream_t s) {
     if (nm <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_sort, dim3(nrow_blk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
+                       row_start, nm, S);
     hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(NT), 0, s, merges, S);
     return hipGetLastError();
 }
