@@ -466,7 +466,6 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
     if (err == hipSuccess) err = compress(K, b, tol, D, zhat, cbase, coff, scale, s, Cm, cdev);
     if (err != hipSuccess) return err;
     const int p = Cm.p, rmax = Cm.rmax;
-    const int BM = dc_gemm_tile_m(variant), BN = dc_gemm_tile_n(variant);
     auto bsz = [&](int I) { return std::min(b, K - I * b); };
     // Skeleton size of block (I, J): its rank, or every column if kept dense.
     auto rk = [&](int I, int J) {
@@ -550,6 +549,11 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
     Stage s1b, sf;
     const int fv = (variant == 2 || variant == 5) ? 5 : 0;
     const int BMf = dc_gemm_tile_m(fv), BNf = dc_gemm_tile_n(fv);
+    // The skeleton stage's column count per block row (a sum of ranks) is
+    // rarely a multiple of 128: with the default tile rule it takes 64 x 64
+    // register tiles, which waste less on the last column tile.
+    const int sv = variant == 0 ? 5 : variant;
+    const int BMs = dc_gemm_tile_m(sv), BNs = dc_gemm_tile_n(sv);
     double flops = 0.0;
     auto tiles = [&](GemmTask& t, int bm, int bn) {
         t.tiles_m = (t.rows + bm - 1) / bm;
@@ -610,7 +614,7 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
                 c.C = W + H.w_row0;
                 c.ldc = wrows;
                 c.beta = 0;
-                tiles(c, BM, BN);
+                tiles(c, BMs, BNs);
                 s1b.add(c);
                 flops += 2.0 * H.rows * c.klen * c.ncol;
             }
@@ -643,8 +647,7 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
         const int* sd = reinterpret_cast<int*>(tdev + sof[i]);
         err = (&S == &sf)
                   ? dc_launch_cauchy_gemm2(td, sd, (int)S.tasks.size(), S.start.back(), fv, s)
-                  : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), variant,
-                                          s);
+                  : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), sv, s);
     }
     const hipError_t e2 = arena_end(A, s);
     if (err == hipSuccess) err = e2;
