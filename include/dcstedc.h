@@ -30,6 +30,15 @@
  *  - A positive return value is a HIP runtime error code.
  *  - The short forms allocate stream-ordered workspace; only the _ex forms
  *    with caller workspace allocate nothing and may be captured in a graph.
+ *  - Host threads: solves may be issued from several threads (on separate
+ *    streams, with separate workspaces).  The tree plans, captured graphs
+ *    and tuning tables are shared under locks; the low-rank buffers, the
+ *    pinned staging for host reads and uploads, and the records read by
+ *    dc_last_stats belong to the calling thread.  The instrumentation
+ *    (dc_profile_enable / dc_profile_read) and dc_autotune_batched, which
+ *    uses it, are process-wide: call them while no other thread solves.
+ *  - Where the host must read device results before its next launch (the
+ *    low-rank switch), the calling thread waits by polling, not sleeping.
  */
 #ifndef DCSTEDC_H
 #define DCSTEDC_H
