@@ -422,11 +422,22 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     int os = block_excl_scan(cs, wsum, &K);
     int orr = block_excl_scan(cr, wsum, &nrot);
     int oc = block_excl_scan(nchn, wsum, &nch);
-    auto put_surv = [&](const WState& st, int k) {
+    // rend[t]: the survivor that the column produced by rotation t becomes
+    // when t ends its chain, else -1 (perm is free once the walk state is
+    // laid out).  The rotation kernel writes such a column straight into
+    // the survivor panel, and the gather skips it.
+    int* rend = S.perm + base;
+    for (int t = tid; t < nrot; t += NT) rend[t] = -1;
+    __syncthreads();
+    // A survivor's type bit 4 marks a chain end.  The rotation that produced
+    // a rotated candidate is the last one before it: index orr - 1 (also
+    // across a segment boundary, where the previous segment ended with it).
+    auto put_surv = [&](const WState& st, int k, int last_rot) {
         S.Dbar[base + k] = st.D;
         S.zbar[base + k] = st.z;
         S.surv[base + k] = st.col;
-        S.stype[base + k] = st.typ;
+        S.stype[base + k] = st.typ | (st.orig ? 0 : 4);
+        if (!st.orig) rend[last_rot] = k;
     };
     if (myseg) {
         WState st{iD[tid], iz[tid], icol[tid], ityp[tid], iorg[tid]};
@@ -451,13 +462,13 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
                 tC[trig] = st.col;
                 tT[trig] = nx.typ;                     // typ_p | typ_i
             } else {
-                put_surv(st, os++);
+                put_surv(st, os++, orr - 1);
             }
             st = nx;
         }
-        if (tid == nseg - 1) put_surv(st, os);
+        if (tid == nseg - 1) put_surv(st, os, orr - 1);
     } else if (tid == 0 && Ns == 1) {
-        put_surv(load_orig(0), 0);
+        put_surv(load_orig(0), 0, -1);
     }
     __syncthreads();
 
@@ -523,11 +534,14 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     }
     __syncthreads();
 
-    // Order-preserving lists of survivors touching the top / bottom rows.
+    // Order-preserving lists of survivors touching the top / bottom rows
+    // (the survivor panel's columns), and each survivor's place in them
+    // (pos_root / pos_defl are free until the eigenvalue order is formed).
     const int lane = tid & 63, wv = tid >> 6;
     for (int half = 0; half < 2; ++half) {
         const int bit = half ? 2 : 1;
         int* out = (half ? S.kbot : S.ktop) + base;
+        int* inv = (half ? S.pos_defl : S.pos_root) + base;
         int running = 0;
         for (int c0 = 0; c0 < K; c0 += NT) {
             const int j = c0 + tid;
@@ -540,7 +554,10 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
             for (int q = 0; q < wv; ++q) woff += wsum[q];
             int tot = 0;
             for (int q = 0; q < NT / 64; ++q) tot += wsum[q];
-            if (f) out[running + woff + before] = j;
+            if (f) {
+                out[running + woff + before] = j;
+                inv[j] = running + woff + before;
+            }
             running += tot;
             __syncthreads();
         }
@@ -593,6 +610,10 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     const int rbit = r < N.n1 ? 1 : 2;
     const int* __restrict__ rt = S.rt + base;
     const int* __restrict__ rp = S.rp + base;
+    const int* __restrict__ rend = S.perm + base;
+    const int* __restrict__ ptop = S.pos_root + base;
+    const int* __restrict__ pbot = S.pos_defl + base;
+    double* panel = P.B2 + (long long)N.off * P.ld2 + N.off + r;
     const int* __restrict__ ri = S.ri + base;
     const double* __restrict__ rc = S.rc + base;
     const double* __restrict__ rs = S.rs + base;
@@ -642,7 +663,11 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
             rot_apply(ty, rbit, rc[t], rs[t], a, b);
             if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)rp[t] * ld] = a;
         }
-        if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)col_i * ld] = b;
+        // The chain's last column is a survivor: it goes straight to its
+        // column of the survivor panel (the gather skips it).
+        const int ks = rend[t1[q] - 1];
+        if (ks >= 0 && (S.stype[base + ks] & rbit))
+            panel[(long long)(rbit == 1 ? ptop[ks] : pbot[ks]) * P.ld2] = b;
     }
 }
 
@@ -705,17 +730,22 @@ void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start
     const double* blk = Qi + (long long)N.off * ldi + N.off;
     double* G = P.B2 + (long long)N.off * P.ld2 + N.off;
     for (int t = t0; t < t0 + DC_GATHER_COLS; ++t) {
+        // (survivors that end a rotation chain were written by the rotation)
         if (t < C.ntop) {
-            const int src = S.surv[base + S.ktop[base + t]];
-            const double* a = blk + (long long)src * ldi;
-            double* o = G + (long long)t * P.ld2;
-            for (int r = threadIdx.x; r < N.n1; r += 256) o[r] = a[r];
+            const int ks = S.ktop[base + t];
+            if (!(S.stype[base + ks] & 4)) {
+                const double* a = blk + (long long)S.surv[base + ks] * ldi;
+                double* o = G + (long long)t * P.ld2;
+                for (int r = threadIdx.x; r < N.n1; r += 256) o[r] = a[r];
+            }
         }
         if (t < C.nbot) {
-            const int src = S.surv[base + S.kbot[base + t]];
-            const double* a = blk + (long long)src * ldi + N.n1;
-            double* o = G + (long long)t * P.ld2 + N.n1;
-            for (int r = threadIdx.x; r < N.n2; r += 256) o[r] = a[r];
+            const int ks = S.kbot[base + t];
+            if (!(S.stype[base + ks] & 4)) {
+                const double* a = blk + (long long)S.surv[base + ks] * ldi + N.n1;
+                double* o = G + (long long)t * P.ld2 + N.n1;
+                for (int r = threadIdx.x; r < N.n2; r += 256) o[r] = a[r];
+            }
         }
     }
 }
