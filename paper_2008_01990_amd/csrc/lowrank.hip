@@ -68,8 +68,6 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
     __shared__ double wv[NT / 64], wd[NT / 64];
     __shared__ int wi[NT / 64];
     __shared__ int spr[STORE ? MAX_R : 1], spc[STORE ? MAX_R : 1];
-    __shared__ double s_max;
-    __shared__ int s_piv;
 
     const int pair = blockIdx.x;
     const int I = pair / p, J = pair - (pair / p) * p;
@@ -153,19 +151,29 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
         }
         if (lane == 0) { wv[w] = bn; wd[w] = bd; wi[w] = bf; }
         __syncthreads();
-        if (tid == 0) {
-            double nn = wv[0], dd = wd[0];
-            int ff = wi[0];
-            for (int q = 1; q < NT / 64; ++q)
-                if (better(wv[q], wd[q], wi[q], nn, dd, ff)) { nn = wv[q]; dd = wd[q]; ff = wi[q]; }
-            s_max = nn / dd;
-            s_piv = ff;
+        // Every wave reduces the NT / 64 wave results itself (same values,
+        // same order: the same pivot everywhere), so no second barrier.
+        {
+            constexpr int NWV = NT / 64;
+            double nn = lane < NWV ? wv[lane] : 0.0;
+            double dd = lane < NWV ? wd[lane] : 1.0;
+            int ff = lane < NWV ? wi[lane] : INT_MAX;
+#pragma unroll
+            for (int off = NWV / 2; off > 0; off >>= 1) {
+                const double on = __shfl_xor(nn, off, 64);
+                const double od = __shfl_xor(dd, off, 64);
+                const int of = __shfl_xor(ff, off, 64);
+                if (better(on, od, of, nn, dd, ff)) { nn = on; dd = od; ff = of; }
+            }
+            bn = __shfl(nn, 0, 64);
+            bd = __shfl(dd, 0, 64);
+            bf = __shfl(ff, 0, 64);
         }
-        __syncthreads();
-        if (!(s_max > tol)) break;
+        const double pmax = bn / bd;
+        if (!(pmax > tol)) break;
         if (k == rmax) { dense = true; break; }
-        const int pi = s_piv / bj;
-        const int pj = s_piv - pi * bj;
+        const int pi = bf / bj;
+        const int pj = bf - pi * bj;
         if constexpr (STORE) {
             if (tid == 0) { spr[k] = pi; spc[k] = pj; }
         }
