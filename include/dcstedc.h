@@ -274,8 +274,9 @@ int dc_last_info(hipStream_t stream);
 const char* dc_strerror(int code);
 
 /*
- * dc_stats -- per-merge record of the last dc_stedc / dc_stedc_ex call on
- * the calling host thread (copied back synchronously when requested):
+ * dc_stats -- per-merge record of the last dc_stedc / dc_stedc_ex /
+ * dc_stedc_batched call on the calling host thread (copied back synchronously
+ * when requested; for a batch, the merges of every problem by tree level):
  * order m, deflated size K, number of pair rotations, path (0 plain,
  * 1 low-rank), and the product's algorithmic flop count.
  */

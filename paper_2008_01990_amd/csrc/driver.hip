@@ -729,12 +729,16 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
     if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -7;
     char* w = static_cast<char*>(work);
     const std::vector<Prob> probs = batch_probs(*P, L, w, d, e, Q, ldq_host, info_dev);
+    t_last_plan = P;                     // for dc_last_stats
+    t_last_work = w;
     // The low-rank switch reads sizes on the host and cannot be captured.
     if (!use_graph || o.lr_tol > 0.0) {
         err = (hipError_t)dc_fill_int(info_dev, count, 0, stream);
         if (err != hipSuccess) return (int)err;
         return (int)run_plan(*P, probs, w, o, stream);
     }
+    t_path.assign(P->merges.size(), 0);   // a replayed schedule is all plain
+    t_lr_flops.assign(P->merges.size(), 0.0);
     // Graph path: capture the whole level schedule once per signature.
     std::vector<uintptr_t> key{(uintptr_t)P, (uintptr_t)work, (uintptr_t)info_dev,
                                (uintptr_t)o.max_iter};

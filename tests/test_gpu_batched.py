@@ -56,6 +56,36 @@ def test_batched_matches_oracle(lib, graph):
         _check(np.asarray(d), np.asarray(e), host(lam), host(Q), 16)
 
 
+def test_batched_lowrank_matches_oracle_within_tolerance(lib):
+    # Several problems whose merges of one level take the low-rank product
+    # together (one read of the level's sizes and row lists, the low-rank
+    # buffers reused across merges of different problems); the graph request
+    # falls back to the eager schedule on this path.  Bars of the low-rank
+    # path at tol 1e-10: 1e-9 on residual and orthogonality.
+    # (random tridiagonals deflate to K ~ 100 and never switch: 1-2-1
+    # Toeplitz and Clement matrices keep most of each merge)
+    sizes = [3000, 2400, 4000, 700, 1500]
+    gens = [W.toeplitz, W.clement, W.toeplitz, W.toeplitz, W.clement]
+    probs = [tuple(np.asarray(x) for x in g(n)) for g, n in zip(gens, sizes)]
+    announce(f"batched lowrank sizes={sizes}")
+    B = lib.BatchedSolver(sizes, leaf=32, lr_tol=1e-10, lr_block=128, lr_min_k=512)
+    for graph in (False, True):
+        B.load_inputs(probs)
+        B.solve(graph=graph)
+        torch.cuda.synchronize()
+        assert all(v == 0 for v in B.status())
+        for p, (d, e) in enumerate(probs):
+            lam, Q = B.result(p)
+            lam, Q = host(lam), host(Q)
+            lo = np.sort(dc.eigh_tridiagonal(np.asarray(d), np.asarray(e), leaf=32)[0])
+            tn = max(np.abs(lo).max(), 1e-300)
+            assert np.abs(lam - lo).max() <= 1e-9 * tn
+            assert metrics.orthogonality(Q) <= 1e-9
+            assert metrics.residual(np.asarray(d), np.asarray(e), lam, Q) <= 1e-9
+    stats = lib.last_stats()
+    assert sum(r["path"] == 1 for r in stats) >= 4    # several low-rank merges
+
+
 def test_graph_replays_equal_eager(lib):
     sizes, probs = _problems(20, 16, 600, seed=12)
     announce(f"batched graph replay sizes={sizes}")

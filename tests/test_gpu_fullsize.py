@@ -48,7 +48,7 @@ def _solve(lib, d0, e0, **kw):
     return d, e, lam, Qb.t()
 
 
-@pytest.mark.parametrize("path", ["plain", "lowrank"])
+@pytest.mark.parametrize("path", ["plain", "lowrank", "lowrank_default"])
 def test_clement_n32768(lib, path):
     n = 32768
     announce(f"full-size clement n={n} path={path}")
@@ -56,6 +56,8 @@ def test_clement_n32768(lib, path):
     kw = dict(leaf=64)
     if path == "lowrank":
         kw.update(lr_tol=1e-10, lr_block=1024, lr_min_k=4096)
+    elif path == "lowrank_default":                 # the library's b and switch
+        kw.update(lr_tol=1e-10)
     d, e, lam, Q = _solve(lib, d0, e0, **kw)
     ref = torch.arange(-(n - 1), n, 2, dtype=torch.float64, device="cuda")
     assert float((lam - ref).abs().max()) <= 1e-13 * (n - 1)
