@@ -510,6 +510,19 @@ def main():
         "merges_top": [dict(m=r["m"], K=r["K"], nrot=r["nrot"]) for r in stats
                        if r["level"] <= 1],
     }
+    # HBM-bound phases of the root merge: the deflated-column copy moves
+    # 16 m (m - K) bytes; the rotations of pairs from opposite halves read one
+    # column and write two per row, 24 m nrot bytes (the survivors they produce
+    # go straight to the panel, so the gather has nothing left at this root).
+    root = [r for r in stats if r["level"] == 0][0]
+    cp_b = 16.0 * root["m"] * (root["m"] - root["K"])
+    rot_b = 24.0 * root["m"] * root["nrot"]
+    out["root_hbm_phases"] = {
+        "copy": {"ms": top["phase_ms"]["copy"], "bytes": cp_b,
+                 "gbs": cp_b / (top["phase_ms"]["copy"] * 1e-3) / 1e9 if top["phase_ms"]["copy"] > 0 else 0.0},
+        "rotate_gather": {"ms": top["phase_ms"]["rotate"], "bytes": rot_b,
+                          "gbs": rot_b / (top["phase_ms"]["rotate"] * 1e-3) / 1e9 if top["phase_ms"]["rotate"] > 0 else 0.0},
+        "peak_gbs": PEAK_HBM_GBS}
     if not args.no_accuracy:
         out["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
     if args.lowrank_tol > 0.0:
@@ -548,8 +561,13 @@ def main():
             "speedup_vs_plain": ms / lms,
             "root_product_ms": lr_top_ms,
             "root_product_speedup_vs_plain": top["product_ms"] / lr_top_ms,
-            "merges": [dict(m=r["m"], K=r["K"], path=r["path"], flops=r["flops"])
+            "merges": [dict(m=r["m"], K=r["K"], path=r["path"], flops=r["flops"],
+                            blocks=r["lr_blocks"], dense=r["lr_dense"], rank_max=r["lr_rank_max"],
+                            rank_mean=r["lr_rank_sum"] / max(r["lr_blocks"] - r["lr_dense"], 1))
                        for r in lstats if r["path"] == 1],
+            # the root merge's plain algorithmic flops over the low-rank
+            # product phase's time (compression included)
+            "root_plain_equivalent_tflops": flops_lvl[-1] / (lr_top_ms * 1e-3) / 1e12,
         }
         if not args.no_accuracy:
             out["lowrank"]["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)

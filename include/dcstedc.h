@@ -283,6 +283,9 @@ const char* dc_strerror(int code);
 typedef struct dc_merge_stat {
     int level, m, K, nrot, path;
     double flops;
+    /* low-rank merges: off-diagonal blocks, sum and maximum of the ranks of
+       the compressed ones, blocks kept dense (0 on the plain path) */
+    int lr_blocks, lr_rank_sum, lr_rank_max, lr_dense;
 } dc_merge_stat;
 
 /* Copies up to cap records into out (HOST); returns the number available. */

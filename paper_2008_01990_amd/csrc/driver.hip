@@ -445,6 +445,7 @@ namespace {
 // path (0 plain, 1 low rank) and executed flops of low-rank merges.
 thread_local std::vector<int> t_path;
 thread_local std::vector<double> t_lr_flops;
+thread_local std::vector<LrRankSummary> t_lr_ranks;
 
 // Algorithm 3's switch: every merge of the level whose deflated size reaches
 // lr_min_k (and exceeds one block) gets the structured low-rank product; its
@@ -499,14 +500,16 @@ hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Sc
             H.w_row0 = r0;
         }
         double flops = 0.0;
+        LrRankSummary rs;
         err = dc_lowrank_product(C.K, b, o.lr_tol, S.Dbar + base, S.zhat + base,
                                  S.cbase + base, S.tau + base, S.scale + base, halves,
-                                 N.n1 + N.n2, 0, s, &flops);
+                                 N.n1 + N.n2, 0, s, &flops, &rs);
         if (err != hipSuccess) return err;
         err = dc_disable_tasks(S.gtask + 2 * N.slot, 2, &S.cnt[N.slot].pad_[0], s);
         if (err != hipSuccess) return err;
         t_path[N.slot] = 1;
         t_lr_flops[N.slot] = flops;
+        t_lr_ranks[N.slot] = rs;
     }
     return hipSuccess;
 }
@@ -515,6 +518,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
                     const dc_opts& o, hipStream_t s) {
     t_path.assign(P.merges.size(), 0);
     t_lr_flops.assign(P.merges.size(), 0.0);
+    t_lr_ranks.assign(P.merges.size(), LrRankSummary{});
     const Layout L = layout(P);
     Scratch S = carve(P, L, work);
     hipError_t err = dc_launch_set_probs(probs.data(), (int)probs.size(), S.probs, s);
@@ -739,6 +743,7 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
     }
     t_path.assign(P->merges.size(), 0);   // a replayed schedule is all plain
     t_lr_flops.assign(P->merges.size(), 0.0);
+    t_lr_ranks.assign(P->merges.size(), LrRankSummary{});
     // Graph path: capture the whole level schedule once per signature.
     std::vector<uintptr_t> key{(uintptr_t)P, (uintptr_t)work, (uintptr_t)info_dev,
                                (uintptr_t)o.max_iter};
@@ -816,6 +821,11 @@ extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
                 r.nrot = cnt[g].nrot;
                 const bool lr = g < (int)t_path.size() && t_path[g] == 1;
                 r.path = lr ? 1 : 0;
+                const LrRankSummary rk = lr ? t_lr_ranks[g] : LrRankSummary{};
+                r.lr_blocks = rk.blocks;
+                r.lr_rank_sum = rk.rank_sum;
+                r.lr_rank_max = rk.rank_max;
+                r.lr_dense = rk.dense;
                 r.flops = lr ? t_lr_flops[g]
                              : 2.0 * ((double)N.n1 * cnt[g].ntop + (double)N.n2 * cnt[g].nbot) *
                                    cnt[g].K;

@@ -465,7 +465,7 @@ hipError_t arena_end(Arena& A, hipStream_t s) {
 hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
                               const double* cbase, const double* coff, const double* scale,
                               std::vector<LrHalf>& halves, int wrows, int variant,
-                              hipStream_t s, double* flops_out) {
+                              hipStream_t s, double* flops_out, LrRankSummary* ranks_out) {
     Arena& A = arena();
     hipError_t err = arena_begin(A, s);
     char* cdev = nullptr;
@@ -474,6 +474,19 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
     if (err == hipSuccess) err = compress(K, b, tol, D, zhat, cbase, coff, scale, s, Cm, cdev);
     if (err != hipSuccess) return err;
     const int p = Cm.p, rmax = Cm.rmax;
+    if (ranks_out) {
+        LrRankSummary R;
+        for (int I = 0; I < p; ++I)
+            for (int J = 0; J < p; ++J) {
+                if (I == J) continue;
+                const int r = Cm.rank[(size_t)I * p + J];
+                ++R.blocks;
+                if (r == -2) { ++R.dense; continue; }
+                R.rank_sum += r;
+                R.rank_max = std::max(R.rank_max, r);
+            }
+        *ranks_out = R;
+    }
     auto bsz = [&](int I) { return std::min(b, K - I * b); };
     // Skeleton size of block (I, J): its rank, or every column if kept dense.
     auto rk = [&](int I, int J) {

@@ -25,10 +25,17 @@ struct LrHalf {
 // ranks).  cbase/coff are the column nodes w_j = cbase_j + coff_j (coff null:
 // plain nodes w_j = cbase_j), scale the column scales.  wrows
 // is the row count of the skeleton panel W (sum of the halves' rows).
+// Ranks of the off-diagonal blocks of one low-rank product: block count,
+// sum and maximum of the ranks of the compressed blocks, blocks kept dense.
+struct LrRankSummary {
+    int blocks = 0, rank_sum = 0, rank_max = 0, dense = 0;
+};
+
 hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
                               const double* cbase, const double* coff, const double* scale,
                               std::vector<LrHalf>& halves, int wrows, int variant,
-                              hipStream_t s, double* flops_out);
+                              hipStream_t s, double* flops_out,
+                              LrRankSummary* ranks_out = nullptr);
 
 // Largest block size b of the compression: with column offsets (merge nodes)
 // or with plain column nodes.

@@ -32,7 +32,8 @@ class DcOpts(ctypes.Structure):
 
 class MergeStat(ctypes.Structure):
     _fields_ = [("level", c_int), ("m", c_int), ("K", c_int), ("nrot", c_int),
-                ("path", c_int), ("flops", c_double)]
+                ("path", c_int), ("flops", c_double), ("lr_blocks", c_int),
+                ("lr_rank_sum", c_int), ("lr_rank_max", c_int), ("lr_dense", c_int)]
 
 
 # (name, restype, argtypes) of every exported entry point.
@@ -216,8 +217,9 @@ def last_stats():
     cnt = lib.dc_last_stats(None, 0)
     arr = (MergeStat * max(cnt, 1))()
     lib.dc_last_stats(arr, cnt)
-    return [dict(level=r.level, m=r.m, K=r.K, nrot=r.nrot, path=r.path, flops=r.flops)
-            for r in arr[:cnt]]
+    return [dict(level=r.level, m=r.m, K=r.K, nrot=r.nrot, path=r.path, flops=r.flops,
+                 lr_blocks=r.lr_blocks, lr_rank_sum=r.lr_rank_sum, lr_rank_max=r.lr_rank_max,
+                 lr_dense=r.lr_dense) for r in arr[:cnt]]
 
 
 PHASES = ("deflate", "rotate", "secular", "assemble", "product", "copy")
