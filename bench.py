@@ -571,6 +571,25 @@ def main():
         }
         if not args.no_accuracy:
             out["lowrank"]["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
+        if not args.no_extra:
+            # block size and switch left to the library, tuned on this
+            # problem by whole solves (then the tuning is cleared again)
+            lt = L.Solver(n, leaf=args.leaf, lr_tol=args.lowrank_tol)
+            d.copy_(d_in)
+            t0 = time.perf_counter()
+            lt.autotune_on(d, e, Qbuf)
+            torch.cuda.synchronize()
+            t_tune = time.perf_counter() - t0
+            pair = lt.tuned_lowrank()
+
+            def lt_step():
+                d.copy_(d_in)
+                lt.solve_into(d, e, Qbuf)
+
+            t_lt = _time(lt_step, args.steps, torch)
+            out["lowrank"]["tuned"] = {"block": pair[0], "min_k": pair[1], "seconds": t_lt,
+                                       "tuning_seconds": t_tune}
+            L.autotune(0)
     del Qbuf
     torch.cuda.empty_cache()
     if not args.no_extra:

@@ -57,10 +57,12 @@ typedef struct dc_opts {
                         1..64, default 32 */
     double lr_tol;   /* absolute tolerance of the structured low-rank merge
                         (0 = plain merge, the default) */
-    int lr_block;    /* block size b of the low-rank merge (default 256) */
+    int lr_block;    /* block size b of the low-rank merge; 0 (the
+                        default) = automatic: the value dc_autotune_batched
+                        chose for this problem, else 256 */
     int lr_min_k;    /* use the low-rank merge only when the deflated size K
                         reaches this (Algorithm 3's "size of M is large");
-                        default 2048 */
+                        0 (the default) = automatic: tuned, else 2048 */
     int max_iter;    /* secular iteration cap (default 200: enough for pure
                         bisection to reach 4-ulp relative accuracy) */
     int gemm_tile;   /* merge-product tile variant for every level:
@@ -212,7 +214,11 @@ int dc_autotune(int max_n, hipStream_t stream);
  * per level, the fastest variant (the default rule's unless another is at
  * least 3 % faster).  The per-level table applies to later plans with the
  * same device, leaf and sizes (dc_stedc_ex for count == 1), and takes
- * precedence over dc_autotune's buckets.  On return d and e hold the inputs
+ * precedence over dc_autotune's buckets.  With opt->lr_tol > 0 it then
+ * times whole solves over b in {128, 256, 512} and the switch in
+ * {1024, 2048, 4096} (only for the fields the caller left at 0) and keeps
+ * the fastest pair (256 / 2048 unless another is at least 3 % faster) for
+ * later solves of the same device, leaf and sizes whose fields are 0.  On return d and e hold the inputs
  * again; Q, info_dev and work hold no defined result.  Allocates (a copy of
  * the diagonals) and synchronises: not for graph capture.  Returns 0, the
  * argument codes of dc_stedc_batched (-10 also for gemm_tile != 0), or a
@@ -230,6 +236,15 @@ int dc_autotune_batched(int count, const int* n_host, double* const* d,
  * number of levels, 0 when that batch was not tuned, -1 for bad arguments.
  */
 int dc_autotune_levels(int count, const int* n_host, int leaf, int* variant_out, int cap);
+
+/*
+ * dc_autotune_lowrank -- the low-rank block size and switch that
+ * dc_autotune_batched chose for (current device, leaf, sizes): writes them to
+ * *block_out, *min_k_out (HOST) and returns 1; 0 when none was chosen, -1 for
+ * bad arguments.
+ */
+int dc_autotune_lowrank(int count, const int* n_host, int leaf, int* block_out,
+                        int* min_k_out);
 
 /*
  * dc_autotune_table -- copies the current device's tuned variant per size

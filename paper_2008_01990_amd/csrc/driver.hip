@@ -86,6 +86,9 @@ constexpr int NBUCKET = 24;
 std::mutex g_tune_mu;
 std::map<int, std::vector<int>> g_tuned;
 std::map<std::vector<int>, std::vector<int>> g_level_tuned;
+// dc_autotune_batched with lr_tol > 0: low-rank block size and switch per
+// (device, leaf, sizes).
+std::map<std::vector<int>, std::pair<int, int>> g_lr_tuned;
 int g_tune_epoch = 0;
 
 int size_bucket(int m) {
@@ -566,6 +569,11 @@ thread_local char* t_last_work = nullptr;
 
 }  // namespace
 
+// Fields left at 0 (automatic) take the defaults here; resolve_for may
+// replace the low-rank ones by tuned values.
+constexpr int DC_DEFAULT_LR_BLOCK = 256;
+constexpr int DC_DEFAULT_LR_MIN_K = 2048;
+
 dc_opts dc_resolve_opts(const dc_opts* opt) {
     dc_opts o;
     dc_opts_default(&o);
@@ -577,6 +585,26 @@ dc_opts dc_resolve_opts(const dc_opts* opt) {
         if (opt->max_iter > 0) o.max_iter = opt->max_iter;
         o.gemm_tile = opt->gemm_tile;
     }
+    if (o.lr_block <= 0) o.lr_block = DC_DEFAULT_LR_BLOCK;
+    if (o.lr_min_k <= 0) o.lr_min_k = DC_DEFAULT_LR_MIN_K;
+    return o;
+}
+
+// Options for a solve of these sizes: the low-rank block size and switch
+// the caller left at 0 take the values dc_autotune_batched chose for this
+// (device, leaf, sizes), if any, else the defaults.
+static dc_opts resolve_for(const dc_opts* opt, const std::vector<int>& sizes) {
+    dc_opts o = dc_resolve_opts(opt);
+    if (!opt || !(o.lr_tol > 0.0) || (opt->lr_block > 0 && opt->lr_min_k > 0)) return o;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return o;
+    std::vector<int> key{dev, o.leaf};
+    key.insert(key.end(), sizes.begin(), sizes.end());
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_lr_tuned.find(key);
+    if (it == g_lr_tuned.end()) return o;
+    if (opt->lr_block <= 0) o.lr_block = it->second.first;
+    if (opt->lr_min_k <= 0) o.lr_min_k = it->second.second;
     return o;
 }
 
@@ -590,8 +618,8 @@ extern "C" void dc_opts_default(dc_opts* o) {
     if (!o) return;
     o->leaf = 32;
     o->lr_tol = 0.0;
-    o->lr_block = 256;
-    o->lr_min_k = 2048;
+    o->lr_block = 0;                    // automatic: tuned, else 256
+    o->lr_min_k = 0;                    // automatic: tuned, else 2048
     o->max_iter = 200;
     o->gemm_tile = 0;
 }
@@ -621,7 +649,7 @@ extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void
     if (n > 1 && !e) return -3;
     if (n > 0 && !Q) return -4;
     if (ldq < std::max(1, n)) return -5;
-    const dc_opts o = dc_resolve_opts(opt);
+    const dc_opts o = resolve_for(opt, {n});
     if (check_opts(o)) return -9;
     if (!info_dev) return -8;
     Plan* P = nullptr;
@@ -721,10 +749,11 @@ std::map<std::vector<uintptr_t>, std::unique_ptr<GraphEntry>> g_graphs;
 int dc_batched_impl(int count, const int* n_host, double* const* d, double* const* e,
                     double* const* Q, const int* ldq_host, void* work, size_t lwork,
                     int* info_dev, const dc_opts* opt, hipStream_t stream, bool use_graph) {
-    const dc_opts o = dc_resolve_opts(opt);
+    dc_opts o = dc_resolve_opts(opt);
     const int bad = check_batch(count, n_host, d, e, Q, ldq_host, info_dev, o);
     if (bad) return bad;
     std::vector<int> sizes(n_host, n_host + count);
+    o = resolve_for(opt, sizes);
     Plan* P = nullptr;
     hipError_t err = get_plan(sizes, o.leaf, o.gemm_tile, &P);
     if (err != hipSuccess) return (int)err;
@@ -899,6 +928,8 @@ extern "C" int dc_autotune(int max_n, hipStream_t stream) {
         g_tuned.erase(dev);
         for (auto it = g_level_tuned.begin(); it != g_level_tuned.end();)
             it = it->first[0] == dev ? g_level_tuned.erase(it) : std::next(it);
+        for (auto it = g_lr_tuned.begin(); it != g_lr_tuned.end();)
+            it = it->first[0] == dev ? g_lr_tuned.erase(it) : std::next(it);
         ++g_tune_epoch;
         return 0;
     }
@@ -1063,20 +1094,80 @@ extern "C" int dc_autotune_batched(int count, const int* n_host, double* const* 
         if (err == hipSuccess) err = es;
     }
     g_prof = prof;
-    if (err == hipSuccess) err = restore_d();
-    if (err == hipSuccess) err = hipStreamSynchronize(stream);
-    if (dsave) (void)hipFree(dsave);
-    if (err != hipSuccess) return (int)err;
     std::vector<int> per_level(nl);
     for (int li = 0; li < nl; ++li)
         per_level[li] = pick_variant(&ms[(size_t)li * DC_TILE_VARIANTS],
                                      level_variant(0, P0->levels[li].max_m, nullptr));
     std::vector<int> key{dev, o.leaf};
     key.insert(key.end(), sizes.begin(), sizes.end());
+    if (err == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_level_tuned[key] = per_level;
+        ++g_tune_epoch;
+    }
+    // Low-rank block size and switch (Algorithm 3's "large"): whole solves
+    // over a small grid, for the fields the caller left to the library (0);
+    // the default pair is kept unless another is at least 3 % faster.
+    if (err == hipSuccess && o.lr_tol > 0.0 && (opt->lr_block <= 0 || opt->lr_min_k <= 0)) {
+        Plan* PT = nullptr;
+        err = get_plan(sizes, o.leaf, 0, &PT);           // with the tuned tiles
+        std::vector<int> bs, ks;
+        if (opt->lr_block > 0) bs = {o.lr_block};
+        else for (int b : {128, 256, 512}) if (b <= dc_lowrank_max_block(true)) bs.push_back(b);
+        if (opt->lr_min_k > 0) ks = {o.lr_min_k};
+        else ks = {1024, 2048, 4096};
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (err == hipSuccess) err = hipEventCreate(&e0);
+        if (err == hipSuccess) err = hipEventCreate(&e1);
+        float best = 1e30f, dflt = 1e30f;
+        int bb = o.lr_block, bk = o.lr_min_k;
+        for (int b : bs)
+            for (int k : ks) {
+                dc_opts oc = o;
+                oc.lr_block = b;
+                oc.lr_min_k = k;
+                float t = 1e30f;
+                for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+                    err = restore_d();
+                    if (err == hipSuccess) err = dc_fill_int(info_dev, count, 0, stream);
+                    if (err == hipSuccess) err = hipEventRecord(e0, stream);
+                    if (err == hipSuccess) err = run_plan(*PT, probs, w, oc, stream);
+                    if (err == hipSuccess) err = hipEventRecord(e1, stream);
+                    if (err == hipSuccess) err = hipEventSynchronize(e1);
+                    float ms1 = 0.0f;
+                    if (err == hipSuccess) err = hipEventElapsedTime(&ms1, e0, e1);
+                    t = std::min(t, ms1);
+                }
+                if (b == o.lr_block && k == o.lr_min_k) dflt = t;
+                if (t < best) { best = t; bb = b; bk = k; }
+            }
+        if (!(best < 0.97f * dflt)) { bb = o.lr_block; bk = o.lr_min_k; }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (err == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_lr_tuned[key] = {bb, bk};
+        }
+    }
+    if (err == hipSuccess) err = restore_d();
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    if (dsave) (void)hipFree(dsave);
+    return (int)err;
+}
+
+extern "C" int dc_autotune_lowrank(int count, const int* n_host, int leaf, int* block_out,
+                                   int* min_k_out) {
+    if (count < 0 || (count > 0 && !n_host) || !block_out || !min_k_out) return -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    std::vector<int> key{dev, leaf};
+    key.insert(key.end(), n_host, n_host + count);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_level_tuned[key] = per_level;
-    ++g_tune_epoch;
-    return 0;
+    auto it = g_lr_tuned.find(key);
+    if (it == g_lr_tuned.end()) return 0;
+    *block_out = it->second.first;
+    *min_k_out = it->second.second;
+    return 1;
 }
 
 extern "C" int dc_autotune_levels(int count, const int* n_host, int leaf, int* variant_out,

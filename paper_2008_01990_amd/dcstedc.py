@@ -55,6 +55,7 @@ SIGNATURES = [
     ("dc_autotune_batched", c_int, [c_int, P, P, P, P, P, P, c_size_t, P,
                                     ctypes.POINTER(DcOpts), P]),
     ("dc_autotune_levels", c_int, [c_int, P, c_int, P, c_int]),
+    ("dc_autotune_lowrank", c_int, [c_int, P, c_int, P, P]),
     ("dc_stedc_backward", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P]),
     ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
     ("dc_last_info", c_int, [P]),
@@ -115,7 +116,7 @@ def _dev(t, dtype=torch.float64):
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
-def opts(leaf=32, lr_tol=0.0, lr_block=256, lr_min_k=2048, max_iter=200, gemm_tile=0):
+def opts(leaf=32, lr_tol=0.0, lr_block=0, lr_min_k=0, max_iter=200, gemm_tile=0):
     o = DcOpts()
     load().dc_opts_default(ctypes.byref(o))
     o.leaf, o.lr_tol, o.lr_block = leaf, lr_tol, lr_block
@@ -175,6 +176,14 @@ class Solver:
         out = (ctypes.c_int * max(nl, 1))()
         lib.dc_autotune_levels(1, n_host, self.o.leaf, ctypes.cast(out, ctypes.c_void_p), nl)
         return list(out)[:nl]
+
+    def tuned_lowrank(self):
+        """(block, min_k) that autotune_on chose for this size with lr_tol > 0,
+        or None."""
+        n_host = (ctypes.c_int * 1)(self.n)
+        b, k = ctypes.c_int(0), ctypes.c_int(0)
+        r = load().dc_autotune_lowrank(1, n_host, self.o.leaf, ctypes.byref(b), ctypes.byref(k))
+        return (b.value, k.value) if r == 1 else None
 
     def __call__(self, d, e):
         d = _dev(d).clone()
@@ -350,7 +359,7 @@ class EighTridiagonal(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, d, e, leaf=32, lr_tol=0.0, lr_block=256, lr_min_k=2048):
+    def forward(ctx, d, e, leaf=32, lr_tol=0.0, lr_block=0, lr_min_k=0):
         n = d.numel()
         s = Solver(n, leaf=leaf, lr_tol=lr_tol, lr_block=lr_block, lr_min_k=lr_min_k)
         lam = d.detach().to("cuda", torch.float64).clone().contiguous()
@@ -376,8 +385,8 @@ class EighTridiagonal(torch.autograd.Function):
 def eigh_tridiagonal(d, e, **kw):
     """Differentiable (lam ascending, Q) of the symmetric tridiagonal T(d, e)."""
     return EighTridiagonal.apply(d, e, *[kw.get(k, v) for k, v in
-                                         (("leaf", 32), ("lr_tol", 0.0), ("lr_block", 256),
-                                          ("lr_min_k", 2048))])
+                                         (("leaf", 32), ("lr_tol", 0.0), ("lr_block", 0),
+                                          ("lr_min_k", 0))])
 
 
 class BatchedSolver:
@@ -387,7 +396,7 @@ class BatchedSolver:
     solve(graph=False) runs the same schedule eagerly.
     """
 
-    def __init__(self, sizes, leaf=32, gemm_tile=0, lr_tol=0.0, lr_block=256, lr_min_k=2048):
+    def __init__(self, sizes, leaf=32, gemm_tile=0, lr_tol=0.0, lr_block=0, lr_min_k=0):
         self.sizes = [int(v) for v in sizes]
         self.count = len(self.sizes)
         self.o = opts(leaf=leaf, gemm_tile=gemm_tile, lr_tol=lr_tol, lr_block=lr_block,
@@ -452,6 +461,14 @@ class BatchedSolver:
                                      _stream())
         _check(rc, "dc_autotune_batched")
         return self.tuned_levels()
+
+    def tuned_lowrank(self):
+        """(block, min_k) chosen for this batch by autotune() with lr_tol > 0,
+        or None."""
+        b, k = ctypes.c_int(0), ctypes.c_int(0)
+        r = load().dc_autotune_lowrank(self.count, self.n_host, self.o.leaf, ctypes.byref(b),
+                                       ctypes.byref(k))
+        return (b.value, k.value) if r == 1 else None
 
     def tuned_levels(self):
         lib = load()

@@ -78,3 +78,9 @@ def test_host_side_argument_checks_need_no_gpu():
     assert lib.dc_autotune_batched(1, n1, ptrs, ptrs, ptrs, n1, None, 0, fake,
                                    ctypes.byref(o), None) == -10
     assert lib.dc_autotune_levels(-1, None, 32, None, 0) == -1
+    # the tuned low-rank pair: bad counts and missing outputs are rejected
+    bo, ko = ctypes.c_int(0), ctypes.c_int(0)
+    assert lib.dc_autotune_lowrank(-1, None, 32, ctypes.byref(bo), ctypes.byref(ko)) == -1
+    assert lib.dc_autotune_lowrank(1, None, 32, ctypes.byref(bo), ctypes.byref(ko)) == -1
+    assert lib.dc_autotune_lowrank(1, n1, 32, None, ctypes.byref(ko)) == -1
+    assert lib.dc_autotune_lowrank(1, n1, 32, ctypes.byref(bo), None) == -1

@@ -207,3 +207,35 @@ def test_measured_tuning_on_the_batch(lib):
             _check(np.asarray(d), np.asarray(e), host(lam), host(Q), 32)
     lib.autotune(0)
     assert B.tuned_levels() == []
+
+
+def test_lowrank_block_and_switch_tuning(lib):
+    # With lr_tol > 0 and the block size and switch left automatic (0),
+    # dc_autotune_batched also times whole solves over a grid of pairs and
+    # keeps one of them; later solves take it and still meet the low-rank
+    # bars, and clearing the tuning forgets it.
+    sizes = [4096, 3000]
+    probs = [tuple(np.asarray(x) for x in W.toeplitz(n)) for n in sizes]
+    B = lib.BatchedSolver(sizes, leaf=32, lr_tol=1e-10)
+    assert B.o.lr_block == 0 and B.o.lr_min_k == 0
+    B.load_inputs(probs)
+    announce(f"low-rank tuning, sizes {sizes}")
+    B.autotune()
+    torch.cuda.synchronize()
+    pair = B.tuned_lowrank()
+    assert pair is not None
+    assert pair[0] in (128, 256, 512) and pair[1] in (1024, 2048, 4096)
+    B.restore()
+    B.solve()
+    torch.cuda.synchronize()
+    assert all(v == 0 for v in B.status())
+    for p, (d, e) in enumerate(probs):
+        lam, Q = B.result(p)
+        lam, Q = host(lam), host(Q)
+        lo = np.sort(dc.eigh_tridiagonal(d, e, leaf=32)[0])
+        tn = max(np.abs(lo).max(), 1e-300)
+        assert np.abs(lam - lo).max() <= 1e-9 * tn
+        assert metrics.orthogonality(Q) <= 1e-9
+        assert metrics.residual(d, e, lam, Q) <= 1e-9
+    lib.autotune(0)
+    assert B.tuned_lowrank() is None
