@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--lowrank-min-k", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=5120)
+    ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--lowrank-only", action="store_true",
                     help="profiling: time only the low-rank solve (not the benchmark line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -445,15 +445,20 @@ def main():
 
     L.profile_enable(True)
     prof = []
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for a, b in marks:
+        a.record()
         step()
+        b.record()
         prof.append(L.profile_read())          # waits on this step's events
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     L.profile_enable(False)
     ms = (t1 - t0) * 1e3 / args.steps
+    step_s = sorted(a.elapsed_time(b) / 1e3 for a, b in marks)
     stats = L.last_stats()
 
     # Per-level merge-product rates (algorithmic flops of the launch over its
@@ -476,6 +481,9 @@ def main():
     sec_ms = sum(l["phase_ms"]["secular"] for l in levels)
     Ks = [r["K"] for r in stats]
     sec_bytes = sum(48.0 * k for k in Ks)
+    # at least one reciprocal per (row, column) pair in each of the three
+    # kernels (one secular evaluation, the Loewner products, the scales)
+    sec_rcp = sum(3.0 * k * k for k in Ks)
 
     out = {
         "metric": METRIC,
@@ -503,9 +511,15 @@ def main():
                           "tflops": total_flops / (total_prod_ms * 1e-3) / 1e12,
                           "frac_peak": total_flops / (total_prod_ms * 1e-3) / 1e12
                           / PEAK_FP64_MFMA_TFLOPS},
+        "step_seconds": {"best": step_s[0], "median": step_s[len(step_s) // 2],
+                         "mean": ms / 1e3},
         "secular_phase": {"total_ms": sec_ms,
                           "hbm_gbs_algorithmic": sec_bytes / (sec_ms * 1e-3) / 1e9
-                          if sec_ms > 0 else 0.0},
+                          if sec_ms > 0 else 0.0,
+                          "reciprocals_min": sec_rcp,
+                          "reciprocals_per_s_min": sec_rcp / (sec_ms * 1e-3)
+                          if sec_ms > 0 else 0.0,
+                          "fp64_valu_fma_per_s_peak": PEAK_FP64_MFMA_TFLOPS * 1e12 / 2},
         "levels": levels,
         "merges_top": [dict(m=r["m"], K=r["K"], nrot=r["nrot"]) for r in stats
                        if r["level"] <= 1],

@@ -2,10 +2,15 @@
 // at most 64 rows, one wave per leaf.
 //
 // Implicit symmetric tridiagonal QR with a Wilkinson shift (Golub & Van Loan,
-// section 8.3): the bulge chase is a chain of scalar Givens steps that every
-// lane evaluates identically from LDS, while lane r applies each rotation to
-// row r of the eigenvector block kept in LDS.  Deflation uses the absolute
-// threshold eps * ||T||_inf of the leaf.
+// section 8.3).  The tridiagonal lives in registers, entry i in lane i; the
+// bulge chase is a chain of Givens steps that every lane evaluates
+// identically, reading entries ahead of the chase with readlane and carrying
+// the entries the chase has touched in registers, while lane r applies each
+// rotation to row r of the eigenvector block (one LDS read and one write per
+// step: the column the chase leaves behind).  The leaf is scaled by a power of
+// two (exact) so that x^2 + y^2 of a rotation neither overflows nor
+// underflows on the usual path; deflation uses the absolute threshold
+// eps * ||T||_inf of the leaf.
 //
 // The leaf's diagonal carries the tear corrections of eq. T2: every boundary
 // between two adjacent leaves is the split point of exactly one merge, whose
@@ -17,11 +22,51 @@ namespace {
 constexpr double EPS = 2.220446049250313e-16;
 constexpr int MAX_SWEEPS = 40;
 
+// Value of v in lane k (k wave-uniform).
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double set_lane(double v, int k, double x) {
+    return (int)threadIdx.x == k ? x : v;
+}
+
+// Givens rotation c = x / r, s = y / r, r = sqrt(x^2 + y^2), so that
+// c x + s y = r and c y - s x = 0.  The reciprocal square root is the
+// hardware estimate refined by two Newton steps q <- q (3 - t q^2) / 2 when t
+// lies well inside the exponent range; hypot and divisions otherwise.
+__device__ __forceinline__ void givens(double x, double y, double& c, double& s, double& r) {
+    if (y == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        r = x;
+        return;
+    }
+    const double t = __builtin_fma(x, x, y * y);
+    if (t > 0x1p-960 && t < 0x1p960) {
+        const double h = 0.5 * t;
+        double q = __builtin_amdgcn_rsq(t);
+        double e = __builtin_fma(-h * q, q, 0.5);
+        q = __builtin_fma(q, e, q);
+        e = __builtin_fma(-h * q, q, 0.5);
+        q = __builtin_fma(q, e, q);
+        c = x * q;
+        s = y * q;
+        r = t * q;
+    } else {
+        r = hypot(x, y);
+        c = x / r;
+        s = y / r;
+    }
+}
+
 __global__ __launch_bounds__(64)
 void k_leaf(const Node* __restrict__ leaves, Scratch S) {
     __shared__ double Z[DC_MAX_LEAF * DC_MAX_LEAF];   // column-major, 64 rows
     __shared__ double sd[DC_MAX_LEAF];
-    __shared__ double se[DC_MAX_LEAF];
     __shared__ int rank[DC_MAX_LEAF];
 
     const Node L = leaves[blockIdx.x];
@@ -32,37 +77,42 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
 
     // Load, apply the tear corrections, check for non-finite input.
     bool bad = false;
+    double dv = 0.0, ev = 0.0;
     if (lane < nl) {
-        double dv = P.d[off + lane];
+        dv = P.d[off + lane];
         bad |= !isfinite(dv);
         if (lane == 0 && off > 0) {
-            const double ev = P.e[off - 1];
-            bad |= !isfinite(ev);
-            dv -= fabs(ev);
+            const double x = P.e[off - 1];
+            bad |= !isfinite(x);
+            dv -= fabs(x);
         }
         if (lane == nl - 1 && off + nl < P.n) {
-            const double ev = P.e[off + nl - 1];
-            bad |= !isfinite(ev);
-            dv -= fabs(ev);
+            const double x = P.e[off + nl - 1];
+            bad |= !isfinite(x);
+            dv -= fabs(x);
         }
-        sd[lane] = dv;
         if (lane < nl - 1) {
-            const double ev = P.e[off + lane];
+            ev = P.e[off + lane];
             bad |= !isfinite(ev);
-            se[lane] = ev;
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) dc_set_info(P.info, DC_STATUS_NONFINITE);
     for (int c = 0; c < nl; ++c) Z[c * DC_MAX_LEAF + lane] = (c == lane) ? 1.0 : 0.0;
-    __syncthreads();
 
-    // Absolute deflation threshold eps * ||T||_inf.
-    double anorm = 0.0;
-    for (int i = 0; i < nl; ++i) {
-        double r = fabs(sd[i]);
-        if (i > 0) r += fabs(se[i - 1]);
-        if (i < nl - 1) r += fabs(se[i]);
-        anorm = fmax(anorm, r);
+    // ||T||_inf of the leaf, then an exact power-of-two scale to [1, 2).
+    const double eprev = __shfl_up(ev, 1, 64);
+    double rowsum = lane < nl ? fabs(dv) + fabs(ev) + (lane > 0 ? fabs(eprev) : 0.0) : 0.0;
+    double anorm = lane_value(dc_wave_max(rowsum), 0);
+    double unscale = 1.0;
+    if (anorm > 0.0 && anorm < INFINITY) {
+        const int ex = (int)((__double_as_longlong(anorm) >> 52) & 0x7ff) - 1023;
+        if (ex > -1000 && ex < 1000) {
+            const double sc = __longlong_as_double((long long)(1023 - ex) << 52);
+            unscale = __longlong_as_double((long long)(1023 + ex) << 52);
+            dv *= sc;
+            ev *= sc;
+            anorm *= sc;
+        }
     }
     const double thresh = EPS * anorm;
 
@@ -70,55 +120,70 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
     int sweeps = 0;
     bool failed = false;
     while (hi > 0) {
-        if (fabs(se[hi - 1]) <= thresh) {
-            se[hi - 1] = 0.0;
+        const double ehi = lane_value(ev, hi - 1);
+        if (fabs(ehi) <= thresh) {
+            ev = set_lane(ev, hi - 1, 0.0);
             --hi;
             sweeps = 0;
             continue;
         }
-        int lo = hi - 1;
-        while (lo > 0 && fabs(se[lo - 1]) > thresh) --lo;
-        if (lo > 0) se[lo - 1] = 0.0;
+        // lo: one past the last negligible off-diagonal below hi - 1
+        const unsigned long long small = __ballot(lane < hi - 1 && fabs(ev) <= thresh);
+        const int lo = small ? 64 - __builtin_clzll(small) : 0;
+        if (lo > 0) ev = set_lane(ev, lo - 1, 0.0);
         if (++sweeps > MAX_SWEEPS) { failed = true; break; }
-        const double delta = 0.5 * (sd[hi - 1] - sd[hi]);
-        const double b = se[hi - 1];
+        const double dhi = lane_value(dv, hi);
+        const double delta = 0.5 * (lane_value(dv, hi - 1) - dhi);
         const double sgn = delta >= 0.0 ? 1.0 : -1.0;
-        const double mu = sd[hi] - b * b / (delta + sgn * hypot(delta, b));
-        double x = sd[lo] - mu;
-        double y = se[lo];
-        double bulge = 0.0;
+        const double mu = dhi - ehi * ehi / (delta + sgn * hypot(delta, ehi));
+
+        // Entries ahead of the chase are read from the sweep's starting
+        // values (d0, e0); the chase writes its finished entries into dv, ev.
+        const double d0 = dv, e0 = ev;
+        double a = lane_value(d0, lo);           // current d[k]
+        double f = lane_value(e0, lo);           // current e[k]
+        double x = a - mu, y = f;
+        double zc = Z[lo * DC_MAX_LEAF + lane];  // current column k, this row
+        double g = lane_value(d0, lo + 1);
+        double en = lo + 1 < hi ? lane_value(e0, lo + 1) : 0.0;
+        double zn = Z[(lo + 1) * DC_MAX_LEAF + lane];
         for (int k = lo; k < hi; ++k) {
-            if (k > lo) { x = se[k - 1]; y = bulge; }
-            double c = 1.0, s = 0.0, r = x;
-            if (y != 0.0) {
-                r = hypot(x, y);
-                c = x / r;
-                s = y / r;
+            double g2 = 0.0, en2 = 0.0, zn2 = 0.0;
+            if (k + 2 <= hi) {
+                g2 = lane_value(d0, k + 2);
+                zn2 = Z[(k + 2) * DC_MAX_LEAF + lane];
             }
-            if (k > lo) se[k - 1] = r;
-            const double a = sd[k], f = se[k], g = sd[k + 1];
-            sd[k] = c * c * a + 2.0 * c * s * f + s * s * g;
-            sd[k + 1] = s * s * a - 2.0 * c * s * f + c * c * g;
-            se[k] = c * s * (g - a) + (c * c - s * s) * f;
-            if (k + 1 < hi) {
-                bulge = s * se[k + 1];
-                se[k + 1] = c * se[k + 1];
-            }
-            if (lane < nl) {
-                const double zk = Z[k * DC_MAX_LEAF + lane];
-                const double zk1 = Z[(k + 1) * DC_MAX_LEAF + lane];
-                Z[k * DC_MAX_LEAF + lane] = c * zk + s * zk1;
-                Z[(k + 1) * DC_MAX_LEAF + lane] = -s * zk + c * zk1;
-            }
+            if (k + 2 < hi) en2 = lane_value(e0, k + 2);
+            double c, s, r;
+            givens(x, y, c, s, r);
+            if (k > lo) ev = set_lane(ev, k - 1, r);
+            const double cc = c * c, ss = s * s, cs = c * s;
+            dv = set_lane(dv, k, cc * a + 2.0 * cs * f + ss * g);
+            const double gn = ss * a - 2.0 * cs * f + cc * g;
+            const double fn = cs * (g - a) + (cc - ss) * f;
+            Z[k * DC_MAX_LEAF + lane] = c * zc + s * zn;
+            zc = -s * zc + c * zn;
+            y = s * en;                           // the bulge (0 at the last step)
+            f = c * en;
+            x = fn;
+            a = gn;
+            g = g2;
+            en = en2;
+            zn = zn2;
         }
+        dv = set_lane(dv, hi, a);
+        ev = set_lane(ev, hi - 1, x);
+        Z[hi * DC_MAX_LEAF + lane] = zc;
     }
     if (failed && lane == 0) dc_set_info(P.info, 1 + P.row0 + off);
+    dv *= unscale;
+    if (lane < nl) sd[lane] = dv;
     __syncthreads();
 
     // Ascending order: rank of each eigenvalue, ties by index; NaN ranks as
     // +inf so the ranks always form a permutation.
     if (lane < nl) {
-        const double v = isnan(sd[lane]) ? INFINITY : sd[lane];
+        const double v = isnan(dv) ? INFINITY : dv;
         int r = 0;
         for (int k = 0; k < nl; ++k) {
             const double u = isnan(sd[k]) ? INFINITY : sd[k];
@@ -130,7 +195,7 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
     long long ld;
     double* Qo = node_buf(P, L.depth, ld);
     if (lane < nl) {
-        P.d[off + rank[lane]] = sd[lane];
+        P.d[off + rank[lane]] = dv;
         for (int c = 0; c < nl; ++c)
             Qo[(long long)(off + rank[c]) * ld + off + lane] = Z[c * DC_MAX_LEAF + lane];
     }
