@@ -86,6 +86,9 @@ void dc_opts_default(dc_opts* opt);
  *   e    in: off-diagonal (n-1); left unchanged
  *   Q    out: ldq x n, column j the unit eigenvector of d[j]
  *   ldq  >= max(1, n)
+ * T is scaled internally by the power of two that brings max(|d|, |e|) into
+ * [1, 2), and the eigenvalues are scaled back: exact, so the result does not
+ * depend on the magnitude of T (any finite T).
  * Returns 0, -i for a bad argument i, or a HIP error.
  */
 int dc_stedc(int n, double* d, double* e, double* Q, int ldq, hipStream_t stream);

@@ -65,6 +65,7 @@ struct Scratch {
     int *pos_root, *pos_defl;   // output column of each root / deflated pair
     MergeCnt* cnt;              // per merge slot
     double* rho2;               // per merge slot: 2 |e_k|
+    double* psc;                // per problem: power-of-two scale of d and e
     Prob* probs;
     GemmTask* gtask;            // two per merge slot
     SecTask* stask;             // one per merge slot
@@ -77,6 +78,11 @@ __host__ __device__ inline double* node_buf(const Prob& P, int depth, long long&
 }
 
 // Kernel launchers (deflate.hip / leaf.hip).
+// Scaling by powers of two: undo = false picks, per problem, the power of two
+// that brings max(|d|, |e|) into [1, 2), stores it in S.psc and scales d in
+// place (e stays as given; its readers apply S.psc); undo = true divides the
+// eigenvalues in d by it again.
+hipError_t dc_launch_scale(int nprob, bool undo, Scratch S, hipStream_t s);
 hipError_t dc_launch_leaf(const Node* leaves, int nleaves, Scratch S, hipStream_t s);
 hipError_t dc_launch_build(const Node* merges, int nmerges, int bm, int bn, Scratch S,
                            hipStream_t s);

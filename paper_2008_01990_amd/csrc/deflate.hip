@@ -220,7 +220,7 @@ void k_merge_sort(const Node* __restrict__ merges, const int* __restrict__ blk_s
     const double* Qi = node_buf(P, N.depth + 1, ldi);
     const double* L1 = P.d + N.off;
     const double* L2 = P.d + N.off + n1;
-    const double ek = P.e[N.off + n1 - 1];
+    const double ek = P.e[N.off + n1 - 1];            // its sign only: scale-free
     const double sigma = ek < 0.0 ? -1.0 : 1.0;
     const double rs2 = 0.70710678118654752440;
     double Dv, zv;
@@ -257,7 +257,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     const long long base = (long long)P.row0 + N.off;
     const double* L1 = P.d + N.off;          // Lambda_1 ascending
     const double* L2 = P.d + N.off + n1;     // Lambda_2 ascending
-    const double ek = P.e[N.off + n1 - 1];
+    const double ek = P.e[N.off + n1 - 1] * S.psc[N.prob];   // d is scaled, e on read
     const double rho2 = 2.0 * fabs(ek);
     const int tid = threadIdx.x;
 

@@ -252,7 +252,7 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 // Workspace layout.
 struct Layout {
     size_t bytes = 0;
-    size_t probs, gtask, stask, cnt, rho2, dbl, ints, bufs;
+    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, bufs;
     int nd = 16, ni = 14;
 };
 
@@ -268,6 +268,7 @@ Layout layout(const Plan& P) {
     L.stask = o; o = align256(o + nm * sizeof(SecTask));
     L.cnt = o; o = align256(o + nm * sizeof(MergeCnt));
     L.rho2 = o; o = align256(o + nm * sizeof(double));
+    L.psc = o; o = align256(o + std::max<size_t>(P.sizes.size(), 1) * sizeof(double));
     L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
     L.ints = o; o = align256(o + L.ni * R * sizeof(int));
     L.bufs = o; o = align256(o + (P.buf_elems + P.pan_elems) * sizeof(double));
@@ -288,6 +289,7 @@ Scratch carve(const Plan& P, const Layout& L, char* w) {
     for (int i = 0; i < L.ni; ++i) *ip[i] = ib + i * R;
     S.cnt = reinterpret_cast<MergeCnt*>(w + L.cnt);
     S.rho2 = reinterpret_cast<double*>(w + L.rho2);
+    S.psc = reinterpret_cast<double*>(w + L.psc);
     S.probs = reinterpret_cast<Prob*>(w + L.probs);
     S.gtask = reinterpret_cast<GemmTask*>(w + L.gtask);
     S.stask = reinterpret_cast<SecTask*>(w + L.stask);
@@ -526,6 +528,11 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
     Scratch S = carve(P, L, work);
     hipError_t err = dc_launch_set_probs(probs.data(), (int)probs.size(), S.probs, s);
     if (err != hipSuccess) return err;
+    // Exact power-of-two scaling of every problem to max(|d|, |e|) in [1, 2)
+    // (results are unchanged where nothing under- or overflows; it keeps the
+    // squared pole distances of the secular and scale steps in range).
+    err = dc_launch_scale((int)probs.size(), false, S, s);
+    if (err != hipSuccess) return err;
     const Node* d_leaves = P.d_nodes;
     const Node* d_merges = P.d_nodes + P.leaves.size();
     for (const Level& Lv : P.levels) {
@@ -561,7 +568,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         DC_TRY(prof_mark(li, 6, s));
 #undef DC_TRY
     }
-    return hipSuccess;
+    return dc_launch_scale((int)probs.size(), true, S, s);
 }
 
 thread_local const Plan* t_last_plan = nullptr;

@@ -71,6 +71,7 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
 
     const Node L = leaves[blockIdx.x];
     const Prob P = S.probs[L.prob];
+    const double esc = S.psc[L.prob];        // d is scaled in place, e on read
     const int nl = L.n1;
     const int lane = threadIdx.x;
     const int off = L.off;
@@ -82,17 +83,17 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         dv = P.d[off + lane];
         bad |= !isfinite(dv);
         if (lane == 0 && off > 0) {
-            const double x = P.e[off - 1];
+            const double x = P.e[off - 1] * esc;
             bad |= !isfinite(x);
             dv -= fabs(x);
         }
         if (lane == nl - 1 && off + nl < P.n) {
-            const double x = P.e[off + nl - 1];
+            const double x = P.e[off + nl - 1] * esc;
             bad |= !isfinite(x);
             dv -= fabs(x);
         }
         if (lane < nl - 1) {
-            ev = P.e[off + lane];
+            ev = P.e[off + lane] * esc;
             bad |= !isfinite(ev);
         }
     }
@@ -201,7 +202,52 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
     }
 }
 
+// Per problem: the power of two 2^-x with max(|d|, |e|) 2^-x in [1, 2)
+// (x clamped to [-1020, 1020]; 1 for an all-zero or non-finite maximum), d
+// scaled by it in place; or, undoing, the eigenvalues in d divided by it.
+__global__ __launch_bounds__(256)
+void k_scale(Scratch S, bool undo) {
+    __shared__ double wmax[4];
+    __shared__ double s_sc;
+    const Prob P = S.probs[blockIdx.x];
+    const int n = P.n;
+    const int tid = threadIdx.x;
+    if (undo) {
+        const double inv = 1.0 / S.psc[blockIdx.x];
+        for (int i = tid; i < n; i += 256) P.d[i] *= inv;
+        return;
+    }
+    double m = 0.0;
+    for (int i = tid; i < n; i += 256) {
+        m = fmax(m, fabs(P.d[i]));
+        if (i < n - 1) m = fmax(m, fabs(P.e[i]));
+    }
+    m = dc_wave_max(m);
+    if ((tid & 63) == 0) wmax[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        double sc = 1.0;
+        if (m > 0.0 && m < INFINITY) {
+            int ex = (int)((__double_as_longlong(m) >> 52) & 0x7ff) - 1023;
+            ex = min(max(ex, -1020), 1020);
+            sc = __longlong_as_double((long long)(1023 - ex) << 52);
+        }
+        s_sc = sc;
+        S.psc[blockIdx.x] = sc;
+    }
+    __syncthreads();
+    const double sc = s_sc;
+    for (int i = tid; i < n; i += 256) P.d[i] *= sc;
+}
+
 }  // namespace
+
+hipError_t dc_launch_scale(int nprob, bool undo, Scratch S, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(nprob), dim3(256), 0, s, S, undo);
+    return hipGetLastError();
+}
 
 hipError_t dc_launch_leaf(const Node* leaves, int nleaves, Scratch S, hipStream_t s) {
     if (nleaves <= 0) return hipSuccess;

@@ -239,3 +239,27 @@ def test_lowrank_block_and_switch_tuning(lib):
         assert metrics.residual(d, e, lam, Q) <= 1e-9
     lib.autotune(0)
     assert B.tuned_lowrank() is None
+
+
+def test_batched_problems_scaled_separately(lib):
+    # Each problem of a batch takes its own power-of-two scale: problems at
+    # 2^-900, 1 and 2^900 in one batch solve exactly as their unscaled copies,
+    # eigenvalues times the scale, eigenvectors equal.
+    sizes, probs = _problems(6, 40, 700, seed=41)
+    ks = [-900, 0, 900, -500, 500, 0]
+    announce(f"batched per-problem scales {ks} sizes={sizes}")
+    B = lib.BatchedSolver(sizes, leaf=16)
+    B.load_inputs(probs)
+    B.solve()
+    torch.cuda.synchronize()
+    base = [(host(B.result(i)[0]).copy(), host(B.result(i)[1]).copy())
+            for i in range(len(sizes))]
+    B.load_inputs([(np.asarray(d) * 2.0 ** k, np.asarray(e) * 2.0 ** k)
+                   for (d, e), k in zip(probs, ks)])
+    B.solve(graph=True)
+    torch.cuda.synchronize()
+    assert all(v == 0 for v in B.status())
+    for i, k in enumerate(ks):
+        lam, Q = B.result(i)
+        assert np.array_equal(host(lam), base[i][0] * 2.0 ** k)
+        assert np.array_equal(host(Q), base[i][1])

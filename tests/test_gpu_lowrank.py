@@ -173,3 +173,20 @@ def test_lowrank_block4096_plain_nodes(lib):
                               lr_tol=tol, lr_block=b)).T
     bound = tol * np.abs(A).sum(axis=1)[:, None] * 1.01 + 8 * n * EPS * (np.abs(A) @ np.abs(B))
     assert np.all(np.abs(C - A @ B) <= bound)
+
+
+@pytest.mark.parametrize("k", [-800, 800])
+def test_lowrank_solve_at_extreme_scales(lib, k):
+    # The compression works on entries of U, which do not change when T is
+    # scaled, so the low-rank solve of T 2^k is the one of T, eigenvalues
+    # times 2^k, bit for bit.
+    d, e = W.toeplitz(2048)
+    announce(f"lowrank stedc toeplitz n=2048 scaled 2^{k}")
+    kw = dict(leaf=64, lr_tol=1e-10, lr_block=256, lr_min_k=512)
+    lam, Q = lib.stedc(cuda(d), cuda(e), **kw)
+    lam, Q = host(lam), host(Q)
+    f = 2.0 ** k
+    lam_s, Q_s = lib.stedc(cuda(d * f), cuda(e * f), **kw)
+    assert any(r["path"] == 1 for r in lib.last_stats())
+    assert np.array_equal(host(lam_s), lam * f)
+    assert np.array_equal(host(Q_s), Q)

@@ -145,3 +145,34 @@ def test_glued_wilkinson_rotation_chains(lib, nblocks, delta):
     # two root finders).  What is unique, the eigenpairs, is checked above.
     assert abs(rg - ro) <= 0.04 * ro, (rg, ro)
     assert abs(top_g["K"] - top_o["K"]) <= 0.04 * top_o["K"] + 2, (top_g["K"], top_o["K"])
+
+
+@pytest.mark.parametrize("k", [-900, -300, 300, 900])
+def test_power_of_two_scaling_is_exact(lib, k):
+    # Every problem is brought to max(|d|, |e|) in [1, 2) by a power of two
+    # before the solve, so T 2^k gives exactly the eigenvalues of T times 2^k
+    # and the same eigenvectors, also where the squared pole distances of the
+    # secular and scale steps of T 2^k would leave the exponent range.
+    rng = np.random.default_rng(31)
+    d, e = W.random_tridiag(600, rng)
+    announce(f"stedc power-of-two scale 2^{k}")
+    lam, Q = _solve(lib, d, e, leaf=32)
+    f = 2.0 ** k
+    lam_s, Q_s = _solve(lib, d * f, e * f, leaf=32)
+    assert np.array_equal(lam_s, lam * f)
+    assert np.array_equal(Q_s, Q)
+
+
+@pytest.mark.parametrize("f", [1e-250, 3e-200, 7e200, 1e250])
+def test_tiny_and_huge_norms_meet_the_bars(lib, f):
+    # Scales that are not powers of two, near the ends of the exponent range:
+    # the bars hold relative to the scale (the oracle solves the unscaled
+    # matrix; residual and orthogonality are measured on it).
+    d, e = W.clement(500)
+    announce(f"stedc clement n=500 scaled by {f:g}")
+    lam, Q = _solve(lib, d * f, e * f, leaf=32)
+    assert np.all(np.isfinite(lam)) and np.all(np.isfinite(Q))
+    lo = np.arange(-499, 500, 2, dtype=float)
+    assert metrics.eig_error(lam / f, lo) <= 1e-13
+    assert metrics.orthogonality(Q) <= 1e-12
+    assert metrics.residual(d, e, lam / f, Q) <= 1e-14
