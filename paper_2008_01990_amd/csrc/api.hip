@@ -121,7 +121,8 @@ extern "C" int dc_secular(int K, const double* Dbar, const double* zbar, double 
     if (err == hipSuccess && info_dev) err = dc_fill_int(info_dev, 1, 0, stream);
     if (err == hipSuccess)
         err = dc_launch_secular(reinterpret_cast<SecTask*>(tmp),
-                                reinterpret_cast<int*>(tmp + off_bs), 1, nblk, max_iter, stream);
+                                reinterpret_cast<int*>(tmp + off_bs), 1, nblk, K, max_iter,
+                                stream);
     hipError_t e2 = hipFreeAsync(tmp, stream);
     return (int)(err != hipSuccess ? err : e2);
 }

@@ -554,7 +554,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
                                 s));
         DC_TRY(prof_mark(li, 2, s));
         DC_TRY(dc_launch_secular(S.stask + Lv.first, P.d_prefix + Lv.off_sec, Lv.nm,
-                                 Lv.sec_blocks, o.max_iter, s));
+                                 Lv.sec_blocks, Lv.max_m, o.max_iter, s));
         DC_TRY(prof_mark(li, 3, s));
         DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
         DC_TRY(prof_mark(li, 4, s));

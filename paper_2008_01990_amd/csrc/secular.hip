@@ -34,9 +34,17 @@
 namespace {
 
 constexpr double EPS = 2.220446049250313e-16;
-constexpr int NW = 8;           // waves per workgroup
 constexpr int NR = 64;          // roots per workgroup
-constexpr int CH = 1024;        // chunk of the streamed index staged in LDS
+// Two shapes: NW = 8 waves streaming chunks of CH = 1024 poles, and NW = 1
+// wave with CH = 256.  The eight-wave shape splits the poles of K <= 256 over
+// at most two waves and leaves the others idle, and its LDS holds a compute
+// unit to five workgroups; the one-wave shape fits many more.  It is taken
+// when K <= 128 (where one wave of the eight did all the work anyway), and
+// for K <= 256 when the level has more blocks than one round of the
+// eight-wave shape holds (about four per compute unit).
+constexpr int SMALL_K = 256;
+constexpr int SMALL_K_ALWAYS = 128;
+constexpr int ROUND_BLOCKS = 1024;
 
 __device__ __forceinline__ int task_of(const int* block_start, int ntasks, int b) {
     int lo = 0, hi = ntasks - 1;
@@ -95,6 +103,7 @@ __device__ __forceinline__ double model_root(double c, double s1, double s2, dou
     return (r2 > lo && r2 < hi) ? r2 : r1;
 }
 
+template <int NW, int CH>
 __global__ __launch_bounds__(NW * 64)
 void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                      int ntasks, int max_iter) {
@@ -290,6 +299,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
 
 // zhat_i: lane r of each wave owns pole i = p0 + r; the roots are streamed in
 // chunks and every wave multiplies the factors of its slice of each chunk.
+template <int NW, int CH>
 __global__ __launch_bounds__(NW * 64)
 void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                int ntasks) {
@@ -339,6 +349,7 @@ void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_
     }
 }
 
+template <int NW, int CH>
 __global__ __launch_bounds__(NW * 64)
 void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block_start,
                 int ntasks) {
@@ -385,20 +396,28 @@ void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block
     }
 }
 
-}  // namespace
-
-hipError_t dc_launch_secular(const SecTask* tasks, const int* block_start, int ntasks,
-                             int total_blocks, int max_iter, hipStream_t s) {
-    if (total_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_secular_roots, dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
-                       block_start, ntasks, max_iter);
+template <int NW, int CH>
+hipError_t launch_secular(const SecTask* tasks, const int* block_start, int ntasks,
+                          int total_blocks, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL((k_secular_roots<NW, CH>), dim3(total_blocks), dim3(NW * 64), 0, s,
+                       tasks, block_start, ntasks, max_iter);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_loewner, dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
+    hipLaunchKernelGGL((k_loewner<NW, CH>), dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
                        block_start, ntasks);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_colscale, dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
+    hipLaunchKernelGGL((k_colscale<NW, CH>), dim3(total_blocks), dim3(NW * 64), 0, s, tasks,
                        block_start, ntasks);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t dc_launch_secular(const SecTask* tasks, const int* block_start, int ntasks,
+                             int total_blocks, int max_k, int max_iter, hipStream_t s) {
+    if (total_blocks <= 0) return hipSuccess;
+    if (max_k <= SMALL_K_ALWAYS || (max_k <= SMALL_K && total_blocks > ROUND_BLOCKS))
+        return launch_secular<1, SMALL_K>(tasks, block_start, ntasks, total_blocks, max_iter, s);
+    return launch_secular<8, 1024>(tasks, block_start, ntasks, total_blocks, max_iter, s);
 }

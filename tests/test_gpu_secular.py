@@ -18,7 +18,8 @@ EPS = np.finfo(float).eps
 
 
 @pytest.mark.parametrize("K,seed,cluster", [(1, 0, False), (2, 1, False), (63, 2, False),
-                                            (700, 3, False), (300, 4, True)])
+                                            (700, 3, False), (300, 4, True), (200, 5, True),
+                                            (256, 6, False)])
 def test_secular_matches_oracle(lib, K, seed, cluster):
     announce(f"secular K={K} seed={seed} cluster={cluster}")
     D, z, rho = W.random_secular(K, seed=seed, cluster=cluster)
