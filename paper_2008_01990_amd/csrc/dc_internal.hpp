@@ -83,13 +83,15 @@ __host__ __device__ inline double* node_buf(const Prob& P, int depth, long long&
 // place (e stays as given; its readers apply S.psc); undo = true divides the
 // eigenvalues in d by it again.
 hipError_t dc_launch_scale(int nprob, bool undo, Scratch S, hipStream_t s);
-hipError_t dc_launch_leaf(const Node* leaves, int nleaves, Scratch S, hipStream_t s);
+// Every leaf has at most max_leaf (<= DC_MAX_LEAF) rows.
+hipError_t dc_launch_leaf(const Node* leaves, int nleaves, int max_leaf, Scratch S,
+                          hipStream_t s);
 hipError_t dc_launch_build(const Node* merges, int nmerges, int bm, int bn, Scratch S,
                            hipStream_t s);
 // k_merge_sort over row blocks (row_start: per-merge prefix of ceil(m /
 // DC_ROWS_PER_BLOCK) blocks, nrow_blk in total), then k_deflate per merge.
 hipError_t dc_launch_deflate(const Node* merges, const int* row_start, int nm, int nrow_blk,
-                             Scratch S, hipStream_t s);
+                             int max_m, Scratch S, hipStream_t s);
 hipError_t dc_launch_rotate(const Node* merges, const int* blk_start, int nm, int nblk,
                             Scratch S, hipStream_t s);
 hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, int nblk,

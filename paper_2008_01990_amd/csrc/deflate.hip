@@ -29,7 +29,6 @@
 namespace {
 
 constexpr double EPS = 2.220446049250313e-16;
-constexpr int NT = 1024;
 
 __device__ __forceinline__ int block_of(const int* blk_start, int nm, int b) {
     int lo = 0, hi = nm - 1;
@@ -60,6 +59,7 @@ __device__ __forceinline__ int count_le(const double* a, int n, double x) {
 
 // Exclusive prefix sum of one int per thread over the NT threads of the
 // workgroup; *total receives the sum.  ws: NT / 64 ints of LDS.
+template <int NT>
 __device__ int block_excl_scan(int v, int* ws, int* total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int x = v;
@@ -239,6 +239,10 @@ void k_merge_sort(const Node* __restrict__ merges, const int* __restrict__ blk_s
     S.perm[base + pos] = i;
 }
 
+// NT threads per merge (64, 256 or 1024, by the level's largest merge): the
+// walk's LDS grows with NT, and a workgroup sized for large merges holds a
+// compute unit to one of the many small merges of a lower level.
+template <int NT>
 __global__ __launch_bounds__(NT)
 void k_deflate(const Node* __restrict__ merges, Scratch S) {
     // per segment of the survivor list: speculative end state, true start
@@ -306,7 +310,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     int nsl = 0;
     for (int i = q0; i < q1; ++i) nsl += !(rho2 * fabs(S.zs[base + i]) <= tol);
     int Ns = 0;
-    int w0 = block_excl_scan(nsl, wsum, &Ns);
+    int w0 = block_excl_scan<NT>(nsl, wsum, &Ns);
     for (int i = q0; i < q1; ++i) {
         const int c = colof(i);
         if (!(rho2 * fabs(S.zs[base + i]) <= tol)) {
@@ -419,9 +423,9 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         cs = 1;
     }
     int K = 0, nrot = 0, nch = 0;
-    int os = block_excl_scan(cs, wsum, &K);
-    int orr = block_excl_scan(cr, wsum, &nrot);
-    int oc = block_excl_scan(nchn, wsum, &nch);
+    int os = block_excl_scan<NT>(cs, wsum, &K);
+    int orr = block_excl_scan<NT>(cr, wsum, &nrot);
+    int oc = block_excl_scan<NT>(nchn, wsum, &nch);
     // rend[t]: the survivor that the column produced by rotation t becomes
     // when t ends its chain, else -1 (perm is free once the walk state is
     // laid out).  The rotation kernel writes such a column straight into
@@ -479,7 +483,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     int cd = 0;
     for (int i = q0; i < q1; ++i) cd += tT[i] != 0;
     int nd = 0;
-    int od = block_excl_scan(cd, wsum, &nd);
+    int od = block_excl_scan<NT>(cd, wsum, &nd);
     for (int i = q0; i < q1; ++i) {
         if (tT[i] == 0) continue;
         S.Dd[base + od] = tV[i];
@@ -500,7 +504,7 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         run = fmax(run, v);
     }
     int nf = 0;
-    int of = block_excl_scan(cf, wsum, &nf);
+    int of = block_excl_scan<NT>(cf, wsum, &nf);
     run = block_excl_max(lmax, wmax);
     for (int k = d0; k < d1; ++k) {
         const double v = S.Dd[base + k];
@@ -802,11 +806,16 @@ hipError_t dc_launch_build(const Node* merges, int nm, int bm, int bn, Scratch S
 }
 
 hipError_t dc_launch_deflate(const Node* merges, const int* row_start, int nm, int nrow_blk,
-                             Scratch S, hipStream_t s) {
+                             int max_m, Scratch S, hipStream_t s) {
     if (nm <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_merge_sort, dim3(nrow_blk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
                        row_start, nm, S);
-    hipLaunchKernelGGL(k_deflate, dim3(nm), dim3(NT), 0, s, merges, S);
+    if (max_m <= 128)
+        hipLaunchKernelGGL(k_deflate<64>, dim3(nm), dim3(64), 0, s, merges, S);
+    else if (max_m <= 512)
+        hipLaunchKernelGGL(k_deflate<256>, dim3(nm), dim3(256), 0, s, merges, S);
+    else
+        hipLaunchKernelGGL(k_deflate<1024>, dim3(nm), dim3(1024), 0, s, merges, S);
     return hipGetLastError();
 }
 

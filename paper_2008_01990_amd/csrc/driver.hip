@@ -539,7 +539,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         err = dc_launch_build(d_merges + Lv.first, Lv.nm, Lv.bm, Lv.bn, S, s);
         if (err != hipSuccess) return err;
     }
-    err = dc_launch_leaf(d_leaves, (int)P.leaves.size(), S, s);
+    err = dc_launch_leaf(d_leaves, (int)P.leaves.size(), P.leaf, S, s);
     if (err != hipSuccess) return err;
     g_ev_levels = (int)P.levels.size();
     for (int li = 0; li < (int)P.levels.size(); ++li) {
@@ -547,7 +547,8 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         const Node* mg = d_merges + Lv.first;
 #define DC_TRY(x) do { err = (x); if (err != hipSuccess) return err; } while (0)
         DC_TRY(prof_mark(li, 0, s));
-        DC_TRY(dc_launch_deflate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
+        DC_TRY(dc_launch_deflate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, Lv.max_m,
+                                 S, s));
         DC_TRY(prof_mark(li, 1, s));
         DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_rot, Lv.nm, Lv.rot_blocks, S, s));
         DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks, S,

@@ -63,17 +63,22 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
     }
 }
 
+// LD: leaf size bound and row stride of the eigenvector block in LDS (16,
+// 32 or 64): a block sized for the plan's leaves lets more of them share a
+// compute unit, which hides the chase's latency.
+template <int LD>
 __global__ __launch_bounds__(64)
 void k_leaf(const Node* __restrict__ leaves, Scratch S) {
-    __shared__ double Z[DC_MAX_LEAF * DC_MAX_LEAF];   // column-major, 64 rows
-    __shared__ double sd[DC_MAX_LEAF];
-    __shared__ int rank[DC_MAX_LEAF];
+    __shared__ double Z[LD * LD];   // column-major, LD rows
+    __shared__ double sd[LD];
+    __shared__ int rank[LD];
 
     const Node L = leaves[blockIdx.x];
     const Prob P = S.probs[L.prob];
     const double esc = S.psc[L.prob];        // d is scaled in place, e on read
     const int nl = L.n1;
     const int lane = threadIdx.x;
+    const bool zrow = LD == 64 || lane < LD;   // lane holds a row of the block
     const int off = L.off;
 
     // Load, apply the tear corrections, check for non-finite input.
@@ -98,7 +103,8 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) dc_set_info(P.info, DC_STATUS_NONFINITE);
-    for (int c = 0; c < nl; ++c) Z[c * DC_MAX_LEAF + lane] = (c == lane) ? 1.0 : 0.0;
+    if (zrow)
+        for (int c = 0; c < nl; ++c) Z[c * LD + lane] = (c == lane) ? 1.0 : 0.0;
 
     // ||T||_inf of the leaf, then an exact power-of-two scale to [1, 2).
     const double eprev = __shfl_up(ev, 1, 64);
@@ -144,15 +150,15 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         double a = lane_value(d0, lo);           // current d[k]
         double f = lane_value(e0, lo);           // current e[k]
         double x = a - mu, y = f;
-        double zc = Z[lo * DC_MAX_LEAF + lane];  // current column k, this row
+        double zc = zrow ? Z[lo * LD + lane] : 0.0;   // current column k, this row
         double g = lane_value(d0, lo + 1);
         double en = lo + 1 < hi ? lane_value(e0, lo + 1) : 0.0;
-        double zn = Z[(lo + 1) * DC_MAX_LEAF + lane];
+        double zn = zrow ? Z[(lo + 1) * LD + lane] : 0.0;
         for (int k = lo; k < hi; ++k) {
             double g2 = 0.0, en2 = 0.0, zn2 = 0.0;
             if (k + 2 <= hi) {
                 g2 = lane_value(d0, k + 2);
-                zn2 = Z[(k + 2) * DC_MAX_LEAF + lane];
+                zn2 = zrow ? Z[(k + 2) * LD + lane] : 0.0;
             }
             if (k + 2 < hi) en2 = lane_value(e0, k + 2);
             double c, s, r;
@@ -162,7 +168,7 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
             dv = set_lane(dv, k, cc * a + 2.0 * cs * f + ss * g);
             const double gn = ss * a - 2.0 * cs * f + cc * g;
             const double fn = cs * (g - a) + (cc - ss) * f;
-            Z[k * DC_MAX_LEAF + lane] = c * zc + s * zn;
+            if (zrow) Z[k * LD + lane] = c * zc + s * zn;
             zc = -s * zc + c * zn;
             y = s * en;                           // the bulge (0 at the last step)
             f = c * en;
@@ -174,7 +180,7 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         }
         dv = set_lane(dv, hi, a);
         ev = set_lane(ev, hi - 1, x);
-        Z[hi * DC_MAX_LEAF + lane] = zc;
+        if (zrow) Z[hi * LD + lane] = zc;
     }
     if (failed && lane == 0) dc_set_info(P.info, 1 + P.row0 + off);
     dv *= unscale;
@@ -198,7 +204,7 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
     if (lane < nl) {
         P.d[off + rank[lane]] = dv;
         for (int c = 0; c < nl; ++c)
-            Qo[(long long)(off + rank[c]) * ld + off + lane] = Z[c * DC_MAX_LEAF + lane];
+            Qo[(long long)(off + rank[c]) * ld + off + lane] = Z[c * LD + lane];
     }
 }
 
@@ -249,8 +255,14 @@ hipError_t dc_launch_scale(int nprob, bool undo, Scratch S, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t dc_launch_leaf(const Node* leaves, int nleaves, Scratch S, hipStream_t s) {
+hipError_t dc_launch_leaf(const Node* leaves, int nleaves, int max_leaf, Scratch S,
+                          hipStream_t s) {
     if (nleaves <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_leaf, dim3(nleaves), dim3(64), 0, s, leaves, S);
+    if (max_leaf <= 16)
+        hipLaunchKernelGGL(k_leaf<16>, dim3(nleaves), dim3(64), 0, s, leaves, S);
+    else if (max_leaf <= 32)
+        hipLaunchKernelGGL(k_leaf<32>, dim3(nleaves), dim3(64), 0, s, leaves, S);
+    else
+        hipLaunchKernelGGL(k_leaf<64>, dim3(nleaves), dim3(64), 0, s, leaves, S);
     return hipGetLastError();
 }
