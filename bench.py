@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--lowrank-min-k", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=8192)
+    ap.add_argument("--cpu-n", type=int, default=7168)
     ap.add_argument("--lowrank-only", action="store_true",
                     help="profiling: time only the low-rank solve (not the benchmark line)")
     ap.add_argument("--copy-calibration", action="store_true",
