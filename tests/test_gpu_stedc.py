@@ -176,3 +176,44 @@ def test_tiny_and_huge_norms_meet_the_bars(lib, f):
     assert metrics.eig_error(lam / f, lo) <= 1e-13
     assert metrics.orthogonality(Q) <= 1e-12
     assert metrics.residual(d, e, lam / f, Q) <= 1e-14
+
+
+def _structured(case):
+    rng = np.random.default_rng(77)
+    if case == "graded":                 # eigenvalues from 1 down to about 1e-8
+        n = 500
+        d = 10.0 ** (-8.0 * np.arange(n) / n)
+        e = 0.5 * 10.0 ** (-8.0 * (np.arange(n - 1) + 0.5) / n)
+        return d, e, 32
+    if case == "zero_couplings":         # rho = 0 at the root and inner tears, and in leaves
+        n = 700
+        d, e = W.random_tridiag(n, rng)
+        e = np.array(e)
+        e[[349, 174, 524, 10, 600, 43, 44]] = 0.0
+        return d, e, 32
+    if case == "constant_tiny":          # every pair deflates at every merge
+        n = 640
+        return np.full(n, 3.0), 1e-20 * rng.choice([-1.0, 1.0], n - 1), 16
+    if case == "wilkinson":              # W_201^+: pairs of nearly equal eigenvalues
+        m = 100
+        return np.abs(m - np.arange(2 * m + 1)).astype(float), np.ones(2 * m), 32
+    if case == "clusters":               # three clusters, couplings 1e-9
+        n = 600
+        return np.tile([1.0, 2.0, 3.0], n // 3), 1e-9 * rng.standard_normal(n - 1), 32
+    if case == "prime_leaf7":
+        d, e = W.random_tridiag(997, rng)
+        return d, e, 7
+    if case == "prime_leaf13":
+        d, e = W.random_tridiag(1009, rng)
+        return d, e, 13
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["graded", "zero_couplings", "constant_tiny", "wilkinson",
+                                  "clusters", "prime_leaf7", "prime_leaf13"])
+def test_structured_inputs(lib, case):
+    d, e, leaf = _structured(case)
+    announce(f"stedc structured {case} n={len(d)} leaf={leaf}")
+    lam, Q = _solve(lib, d, e, leaf=leaf)
+    assert np.all(lam[1:] >= lam[:-1])
+    _check_against_oracle(np.asarray(d), np.asarray(e), lam, Q, leaf)
