@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--lowrank-min-k", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=7168)
+    ap.add_argument("--cpu-n", type=int, default=0)
     ap.add_argument("--lowrank-only", action="store_true",
                     help="profiling: time only the low-rank solve (not the benchmark line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -89,20 +89,37 @@ def gpu_accuracy(d, e, lam, Qbuf, family):
 
 def cpu_baseline(family, n_full, n_sample, leaf):
     """The oracle on the host cores: a full solve at n_sample, scaled by the
-    cubic flop ratio of divide and conquer to the benchmark's order."""
+    cubic flop ratio of divide and conquer to the benchmark's order.  With
+    n_sample = 0 the sample size is chosen for about 10-30 s of oracle work:
+    a solve at n = 4096 is timed first and the size scaled from it (a
+    multiple of 512 in [4096, 12288]); host speeds differ from box to box."""
     from threadpoolctl import threadpool_info
     from oracle import dc
+    pre = None
+    if n_sample <= 0:
+        d, e = inputs(family, 4096)
+        t0 = time.perf_counter()
+        dc.eigh_tridiagonal(d, e, leaf=leaf)
+        pre = time.perf_counter() - t0
+        # cubic growth aims at 15 s; the oracle's time has also grown about
+        # as n^4.5 once its matrices left cache, so the size is capped to
+        # stay within 40 s under that growth too
+        r = 15.0 / max(pre, 1e-3)
+        cap = 40.0 / max(pre, 1e-3)
+        n_sample = int(4096 * min(r ** (1.0 / 3.0), cap ** (1.0 / 4.5))) // 512 * 512
+        n_sample = min(max(n_sample, 4096), 12288)
     d, e = inputs(family, n_sample)
     t0 = time.perf_counter()
     dc.eigh_tridiagonal(d, e, leaf=leaf)
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     scale = (n_full / n_sample) ** 3
+    sizing = (f" (size chosen from a {pre:.2f} s solve at n=4096)" if pre is not None else "")
     return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": f"full oracle solve of the {family} matrix at n={n_sample} "
                       f"(leaf {leaf}) took {dt:.2f} s; scaled by (n/{n_sample})^3 = "
-                      f"{scale:.0f} to n={n_full}",
-            "sample_seconds": dt}
+                      f"{scale:.0f} to n={n_full}{sizing}",
+            "sample_seconds": dt, "sample_n": n_sample}
 
 
 def measured_traffic(workload):

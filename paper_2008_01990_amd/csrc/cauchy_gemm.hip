@@ -112,7 +112,7 @@ __device__ __forceinline__ int spread_local(int local, int tiles) {
     return ((lg & 7) * q + (lg >> 3)) * G + (local - lg * G);
 }
 
-template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC>
+template <int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC>
 __global__ __launch_bounds__(WGM * WGN * 64, OCC)
 void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
                    int ntasks, int total_tiles) {
@@ -150,18 +150,10 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
     const double* __restrict__ rz = T.rz;
     double cb = 0.0, co = 0.0, csj = 0.0;
     if (col_ok) {
-        if (KIND == 0) {
-            cb = T.corg ? rD[T.corg[gcol]] : T.cbase[gcol];
-            co = T.coff ? T.coff[gcol] : 0.0;
-        }
-        if (KIND == 0) csj = T.cs[gcol];
-        if (KIND == 3) {
-            cb = T.lam[gcol];                       // lam_c
-            co = T.lbar ? T.lbar[gcol] : 0.0;       // lbar_c
-            csj = T.Bm ? 0.0 : T.cs[gcol];          // g_c of a rank-one X
-        }
+        cb = T.corg ? rD[T.corg[gcol]] : T.cbase[gcol];
+        co = T.coff ? T.coff[gcol] : 0.0;
+        csj = T.cs[gcol];
     }
-    bool equal_eig = false;
 
     // A entries this thread moves: row ar, k = ak0 + i * A_KSTEP.
     const int ar = tid % BM;
@@ -177,8 +169,8 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int j = 0; j < C_::FN; ++j) acc[i][j] = dc_double4{0.0, 0.0, 0.0, 0.0};
 
     double a_reg[C_::A_PER];
-    double d_reg[C_::B_PER];    // 0: row node; 1: y * vk; 2: B entry; 3: X entry
-    double z_reg[C_::B_PER];    // 0: row weight; 1: skeleton node base; 3: lam_k
+    double d_reg[C_::B_PER];    // row nodes
+    double z_reg[C_::B_PER];    // row weights
 
     // Interior chunks of interior tiles (the common case) load without
     // bounds checks, with strength-reduced addresses.
@@ -189,18 +181,8 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int i = 0; i < C_::B_PER; ++i) {
             const int k = kb + bk0 + i * C_::B_KSTEP;
             const bool ok = interior || k < klen;
-            if (KIND == 0) {
-                d_reg[i] = ok ? dc_ldg(rD + k) : 0.0;
-                z_reg[i] = ok ? dc_ldg(rz + k) : 0.0;
-            } else if (KIND == 2) {
-                d_reg[i] = (ok && col_ok) ? dc_ldg(T.Bm + (long long)gcol * T.ldb + k) : 0.0;
-            } else {
-                d_reg[i] = (ok && col_ok)
-                               ? (T.Bm ? dc_ldg(T.Bm + (long long)gcol * T.ldb + k)
-                                       : dc_ldg(rz + k) * csj)
-                               : 0.0;
-                z_reg[i] = ok ? dc_ldg(T.lam + k) : 0.0;
-            }
+            d_reg[i] = ok ? dc_ldg(rD + k) : 0.0;
+            z_reg[i] = ok ? dc_ldg(rz + k) : 0.0;
         }
     };
     auto load_a = [&](int kb, bool interior) {
@@ -238,23 +220,8 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
         for (int i = 0; i < C_::B_PER; ++i) {
             if (C_::b_slice(i) != s) continue;
             const int kk = bk0 + i * C_::B_KSTEP;
-            double v;
-            if (KIND == 0) {
-                const double den = (d_reg[i] - cb) - co;
-                v = z_reg[i] * csj * dc_rcp(den);
-            } else if (KIND == 2) {
-                v = d_reg[i];
-            } else {
-                const double den = cb - z_reg[i];          // lam_c - lam_k
-                if (kb + kk == gcol) {
-                    v = co;                                // lbar_c
-                } else if (den == 0.0) {
-                    v = 0.0;
-                    equal_eig |= (kb + kk < klen && col_ok);
-                } else {
-                    v = d_reg[i] * dc_rcp(den);
-                }
-            }
+            const double den = (d_reg[i] - cb) - co;
+            double v = z_reg[i] * csj * dc_rcp(den);
             v = (kb + kk < klen && col_ok) ? v : 0.0;
             Bs[buf][kk * C_::LDB_S + bj] = v;
         }
@@ -315,64 +282,25 @@ void k_cauchy_gemm(const GemmTask* __restrict__ tasks, const int* __restrict__ t
 
     // Epilogue: for the FP64 16x16x4 MFMA, accumulator register v of a lane
     // holds row lane/16 + 4 v and column lane % 16 of the 16 x 16 block.
-    if (EPI == 0) {
 #pragma unroll
-        for (int j = 0; j < C_::FN; ++j) {
-            const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
-            if (c >= ncol) continue;
-            const int g = T.ccol ? T.ccol[c] : T.col_off + c;
-            const int oc = T.cpos ? T.cpos[T.ccol ? c : g] : g - T.out_off;
-            double* Ccol = T.C + (long long)oc * T.ldc;
-#pragma unroll
-            for (int i = 0; i < C_::FM; ++i) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = row0 + wm * C_::WTM + i * 16 + (lane >> 4) + 4 * v;
-                    if (r < T.rows) {
-                        const double x = acc[i][j][v];
-                        Ccol[r] = T.beta ? Ccol[r] + x : x;
-                    }
-                }
-            }
-        }
-    } else {
-        // Band epilogue: row sums of P o Q, P o Q(+1 row), P o Q(-1 row).
-        const int part = tn * WGN + wn;
-        const long long ldq = T.ldqb;
+    for (int j = 0; j < C_::FN; ++j) {
+        const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
+        if (c >= ncol) continue;
+        const int g = T.ccol ? T.ccol[c] : T.col_off + c;
+        const int oc = T.cpos ? T.cpos[T.ccol ? c : g] : g - T.out_off;
+        double* Ccol = T.C + (long long)oc * T.ldc;
 #pragma unroll
         for (int i = 0; i < C_::FM; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = row0 + wm * C_::WTM + i * 16 + (lane >> 4) + 4 * v;
-                double sd = 0.0, su = 0.0, sl = 0.0;
                 if (r < T.rows) {
-#pragma unroll
-                    for (int j = 0; j < C_::FN; ++j) {
-                        const int c = col0 + wn * C_::WTN + j * 16 + (lane & 15);
-                        if (c >= ncol) continue;
-                        const double x = acc[i][j][v];
-                        const double* q = T.Qb + (long long)c * ldq + r;
-                        sd += x * q[0];
-                        if (r + 1 < T.nband) su += x * q[1];
-                        if (r > 0) sl += x * q[-1];
-                    }
-                }
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) {
-                    sd += __shfl_xor(sd, off, 64);
-                    su += __shfl_xor(su, off, 64);
-                    sl += __shfl_xor(sl, off, 64);
-                }
-                if ((lane & 15) == 0 && r < T.rows) {
-                    const long long o = (long long)part * T.nband + r;
-                    T.pd[o] = sd;
-                    T.pu[o] = su;
-                    T.pl[o] = sl;
+                    const double x = acc[i][j][v];
+                    Ccol[r] = T.beta ? Ccol[r] + x : x;
                 }
             }
         }
     }
-    if (KIND == 3 && equal_eig && T.flag) atomicOr(T.flag, 1);
 }
 
 // Register-pipelined form (no LDS, no barriers): each wave owns a
@@ -595,58 +523,38 @@ hipError_t launch_reg(const GemmTask* tasks, const int* tile_start, int ntasks, 
     return hipGetLastError();
 }
 
-template <int KIND, int EPI, int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC = 1>
+template <int BM, int BN, int BK, int WGM, int WGN, int SCHED, int OCC = 1>
 hipError_t launch(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
                   hipStream_t s) {
     constexpr int G8 = 8 * lds_group<BM, BN, WGM * WGN, OCC>();
     const int grid = (total + G8 - 1) / G8 * G8;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_cauchy_gemm<KIND, EPI, BM, BN, BK, WGM, WGN, SCHED, OCC>), dim3(grid),
+    hipLaunchKernelGGL((k_cauchy_gemm<BM, BN, BK, WGM, WGN, SCHED, OCC>), dim3(grid),
                        dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
     return hipGetLastError();
 }
 
-// Two workgroups per CU for the 128 x 128 LDS kernel.
-template <int KIND>
-constexpr int occ128() { return 2; }
-// The late-write schedule holds more registers; the adjoint kind keeps the
-// spread schedule.
-template <int KIND>
-constexpr int sched256() { return KIND == 3 ? 0 : 1; }
-
-template <int KIND>
 hipError_t launch_variant(const GemmTask* tasks, const int* tile_start, int ntasks,
                           int total, int variant, hipStream_t s) {
-    constexpr int O = occ128<KIND>();
-    constexpr int S = sched256<KIND>();
+    // the 128 x 128 LDS kernel runs two workgroups per CU; the 256 x 128 one
+    // uses the late-write schedule
     switch (variant) {
-        case 1: return launch<KIND, 0, 128, 128, 16, 2, 2, 0, O>(tasks, tile_start, ntasks, total, s);
-        case 2: return launch<KIND, 0, 64, 64, 16, 1, 1, 0>(tasks, tile_start, ntasks, total, s);
-        case 3: return launch<KIND, 0, 128, 128, 32, 2, 2, 0>(tasks, tile_start, ntasks, total, s);
-        case 4: return launch<KIND, 0, 256, 128, 16, 4, 2, S>(tasks, tile_start, ntasks, total, s);
-        case 5:
-            if constexpr (KIND == 0)
-                return launch_reg<4, 4, 1, 1, 4>(tasks, tile_start, ntasks, total, s);
-            else
-                return launch<KIND, 0, 64, 64, 16, 1, 1, 0>(tasks, tile_start, ntasks, total, s);
-        default:
-            if constexpr (KIND == 0)
-                return launch_reg<8, 2, 1, 4, 3>(tasks, tile_start, ntasks, total, s);
-            else
-                return launch<KIND, 0, 128, 128, 16, 2, 2, 0, O>(tasks, tile_start, ntasks, total,
-                                                                 s);
+        case 1: return launch<128, 128, 16, 2, 2, 0, 2>(tasks, tile_start, ntasks, total, s);
+        case 2: return launch<64, 64, 16, 1, 1, 0>(tasks, tile_start, ntasks, total, s);
+        case 3: return launch<128, 128, 32, 2, 2, 0>(tasks, tile_start, ntasks, total, s);
+        case 4: return launch<256, 128, 16, 4, 2, 1>(tasks, tile_start, ntasks, total, s);
+        case 5: return launch_reg<4, 4, 1, 1, 4>(tasks, tile_start, ntasks, total, s);
+        default: return launch_reg<8, 2, 1, 4, 3>(tasks, tile_start, ntasks, total, s);
     }
 }
 
 }  // namespace
 
-// Tile variants (one tile shape per variant for every kernel kind, since the
-// host sizes the task tiles): 0 (default) 128 x 128, the register-pipelined
-// kernel for generated U (waves of 128 x 32), the LDS kernel otherwise;
-// 1: 128 x 128 LDS kernel, BK 16, two workgroups per CU; 2: 64 x 64 LDS
-// kernel, one wave; 3: 128 x 128 LDS kernel, BK 32; 4: 256 x 128 LDS kernel
-// with the late-write schedule; 5: 64 x 64, register-pipelined for generated
-// U (one 64 x 64 wave), LDS otherwise.
+// Tile variants (the host sizes the task tiles by variant): 0 (default)
+// 128 x 128, the register-pipelined kernel (waves of 128 x 32); 1: 128 x 128
+// LDS kernel, BK 16, two workgroups per CU; 2: 64 x 64 LDS kernel, one wave;
+// 3: 128 x 128 LDS kernel, BK 32; 4: 256 x 128 LDS kernel with the
+// late-write schedule; 5: 64 x 64, register-pipelined (one 64 x 64 wave).
 int dc_gemm_tile_m(int variant) {
     switch (variant) {
         case 2: case 5: return 64;
@@ -664,7 +572,7 @@ int dc_gemm_tile_n(int variant) {
 
 hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
                                  int total, int variant, hipStream_t s) {
-    return launch_variant<0>(tasks, tile_start, ntasks, total, variant, s);
+    return launch_variant(tasks, tile_start, ntasks, total, variant, s);
 }
 
 hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks, const int* tile_start, int ntasks,
@@ -673,15 +581,3 @@ hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks, const int* tile_start, 
     if (variant == 0) return launch_reg<8, 2, 1, 4, 3, 2, true>(tasks, tile_start, ntasks, total, s);
     return hipErrorInvalidValue;
 }
-
-hipError_t dc_launch_loaded_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
-                                 int total, hipStream_t s) {
-    return launch<2, 0, 256, 128, 16, 4, 2, sched256<2>()>(tasks, tile_start, ntasks, total, s);
-}
-
-hipError_t dc_launch_adjoint_gemm(const GemmTask* tasks, const int* tile_start, int ntasks,
-                                  int total, hipStream_t s) {
-    return launch<3, 1, 256, 128, 16, 4, 2, sched256<3>()>(tasks, tile_start, ntasks, total, s);
-}
-
-int dc_band_waves_n() { return 2; }

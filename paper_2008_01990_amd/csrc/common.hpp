@@ -65,11 +65,11 @@ __device__ __forceinline__ void dc_set_info(int* info, int code) {
 }
 
 // One product C[rows, cols] (=|+=) A[rows, 0:klen] * B[0:klen, cols] in which
-// B is generated on the fly (kind 0, the Cauchy-like eigenvector block of
+// B is generated on the fly (the Cauchy-like eigenvector block of
 // eq. Q_Cauchy):
 //    B_kc = rz[k] * cs[g] / ((rD[k] - cbase[g]) - coff[g]),
 //  where g = ccol[c] if ccol is set, else col_off + c, is the generator index
-//  of output column c; kinds 2 and 3 below load or form B otherwise.  The output column of C is cpos[c] when both ccol and
+//  of output column c.  The output column of C is cpos[c] when both ccol and
 //  cpos are set, cpos[g] when only cpos is, and g - out_off otherwise.
 struct GemmTask {
     const double* A;      // row 0 of this task inside A (column-major, lda)
@@ -77,12 +77,12 @@ struct GemmTask {
     const int* klen_p;    // device number of k-entries, or null (= klen)
     int klen;
     int rows;             // rows of the task
-    const double* rD;     // kind 0: row nodes
-    const double* rz;     // kind 0: row weights
+    const double* rD;     // row nodes
+    const double* rz;     // row weights
     const double* cbase;  // column node bases (by generator index)
-    const int* corg;      // kind 0: if set, node base of g is rD[corg[g]] (cbase unused)
+    const int* corg;      // if set, node base of g is rD[corg[g]] (cbase unused)
     const double* coff;   // column node offsets, or null (= 0)
-    const double* cs;     // kind 0: column scales
+    const double* cs;     // column scales
     const int* ncol_p;    // device number of columns, or null (= ncol)
     int ncol;
     int col_off;          // generator index of column 0 when ccol is null
@@ -93,28 +93,7 @@ struct GemmTask {
     int out_off;          // subtracted from g when cpos is null
     int tiles_m, tiles_n; // worst-case tile grid of the task
     int beta;             // 0: overwrite, 1: accumulate
-    // kind 2: B loaded, B_kc = Bm[k + c ldb].
-    // kind 3 (adjoint, M = diag(lbar) + F o G with F_kc = 1/(lam_c - lam_k)):
-    //   B_kc = lbar[c] on the diagonal (k == c, lbar may be null = 0), else
-    //   X_kc / (lam_c - lam_k), X_kc = Bm[k + c ldb] if Bm is set, else
-    //   rz[k] * cs[c]; equal eigenvalues give 0 and set *flag.
-    const double* Bm;
-    long long ldb;
-    const double* lam;
-    const double* lbar;
-    int* flag;
-    // band epilogue: instead of storing C, row r of the tile product P adds
-    //   P[r, c] Q[r, c]    to pd[part][r],
-    //   P[r, c] Q[r+1, c]  to pu[part][r],
-    //   P[r, c] Q[r-1, c]  to pl[part][r],
-    // part = column tile * waves per row + wave column, parts of length nband.
-    const double* Qb;
-    long long ldqb;
-    int nband;
-    double* pd;
-    double* pu;
-    double* pl;
-    // kind 0, register kernel only: a second k-phase accumulated into the
+    // Register kernel only: a second k-phase accumulated into the
     // same tile after the generated one, with A2 (rows as A, lda2) and a
     // loaded B2 (row-major: B2[k ldb2 + c], c the task's column), k < klen2.
     // The epilogue's column scale multiplies it too (B2 is stored divided by
@@ -133,19 +112,12 @@ struct GemmTask {
 hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
                                  int ntasks, int total_tiles, int variant,
                                  hipStream_t stream);
-// Kind-0 tasks with a second, loaded k-phase (klen2 > 0): register kernel,
-// variant 0 or 5 only (hipErrorInvalidValue otherwise).
+// Tasks with a second, loaded k-phase (klen2 > 0; klen may be 0, which leaves
+// only the loaded phase): register kernel, variant 0 or 5 only
+// (hipErrorInvalidValue otherwise).
 hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks_dev, const int* tile_start_dev,
                                   int ntasks, int total_tiles, int variant,
                                   hipStream_t stream);
-// Kind-2 (loaded B) product with the ordinary epilogue.
-hipError_t dc_launch_loaded_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
-                                 int ntasks, int total_tiles, hipStream_t stream);
-// Kind-3 (adjoint M) product with the band epilogue; the number of partial
-// sums per row is tiles_n * dc_band_waves_n().
-hipError_t dc_launch_adjoint_gemm(const GemmTask* tasks_dev, const int* tile_start_dev,
-                                  int ntasks, int total_tiles, hipStream_t stream);
-int dc_band_waves_n();
 // Number of merge-product tile variants (0 .. DC_TILE_VARIANTS - 1).
 constexpr int DC_TILE_VARIANTS = 6;
 int dc_gemm_tile_m(int variant);
