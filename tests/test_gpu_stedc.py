@@ -217,3 +217,88 @@ def test_structured_inputs(lib, case):
     lam, Q = _solve(lib, d, e, leaf=leaf)
     assert np.all(lam[1:] >= lam[:-1])
     _check_against_oracle(np.asarray(d), np.asarray(e), lam, Q, leaf)
+
+
+def test_ex_form_captured_in_a_graph(lib):
+    # dc_stedc_ex on the plain path allocates nothing and never waits on the
+    # host, so it can be captured: the captured solve, replayed three times
+    # with other work and synchronisation in between (new inputs before each
+    # replay), equals the eager solve of the same inputs bit for bit.
+    import torch
+    n = 1500
+    rng = np.random.default_rng(91)
+    s = lib.Solver(n, leaf=32)                   # builds the plan before capture
+    d_in = cuda(np.zeros(n))
+    e_in = cuda(np.zeros(n - 1))
+    dd = torch.empty_like(d_in)
+    Qg = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):                # warm-up outside the capture
+        dd.copy_(d_in)
+        s.solve_into(dd, e_in, Qg)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dd.copy_(d_in)
+        s.solve_into(dd, e_in, Qg)
+    for rep in range(3):
+        announce(f"stedc_ex graph replay {rep}")
+        d, e = W.random_tridiag(n, rng)
+        d_in.copy_(cuda(d))
+        e_in.copy_(cuda(e))
+        scratch = torch.randn(800, 800, dtype=torch.float64, device="cuda")
+        float((scratch @ scratch).sum())
+        g.replay()
+        torch.cuda.synchronize()
+        lam_g, Q_g = host(dd).copy(), host(Qg).copy()
+        assert s.status() == 0
+        lam, Q = _solve(lib, d, e, leaf=32)
+        assert np.array_equal(lam_g, lam)
+        assert np.array_equal(Q_g.T, Q)              # the buffer holds Q column-major
+    _check_against_oracle(np.asarray(d), np.asarray(e), lam, Q, 32)
+
+
+def test_concurrent_solves_from_two_threads(lib):
+    # Two host threads, each with its own stream and workspace, one on the
+    # plain path and one on the low-rank path (per-thread low-rank buffers
+    # and host staging), solve repeatedly at the same time; every result
+    # equals the same solve run alone, bit for bit.
+    import threading
+    import torch
+    jobs = [(W.random_tridiag(1200, np.random.default_rng(5)), dict(leaf=32)),
+            (W.toeplitz(2048), dict(leaf=64, lr_tol=1e-10, lr_block=256, lr_min_k=512))]
+    ref = []
+    for (d, e), kw in jobs:
+        lam, Q = _solve(lib, d, e, **kw)
+        ref.append((lam, Q))
+    out = [[], []]
+    errs = []
+
+    def work(i):
+        try:
+            (d, e), kw = jobs[i]
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                s = lib.Solver(len(d), **kw)
+                for _ in range(4):
+                    lam, Q = s(cuda(d), cuda(e))
+                    st.synchronize()
+                    out[i].append((host(lam).copy(), host(Q).copy(), s.status()))
+        except Exception as ex:                  # reported below
+            errs.append(repr(ex))
+
+    announce("stedc two threads, plain and low rank")
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not errs, errs
+    for i in range(2):
+        assert len(out[i]) == 4
+        for lam, Q, st in out[i]:
+            assert st == 0
+            assert np.array_equal(lam, ref[i][0])
+            assert np.array_equal(Q, ref[i][1])
