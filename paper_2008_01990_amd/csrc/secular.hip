@@ -27,7 +27,8 @@
 // (poles, or roots for Loewner) is streamed through LDS in chunks that the
 // whole workgroup loads coalesced; each wave sweeps its slice of every chunk
 // with broadcast LDS reads, and the NW partial sums meet in LDS.  All O(K^2)
-// work is FP64 VALU with one reciprocal per term; HBM traffic is O(K) per
+// work is FP64 VALU with one reciprocal per term of a root's sums and one per
+// two terms of the Loewner products and the scales; HBM traffic is O(K) per
 // workgroup.
 #include "secular.hpp"
 
@@ -330,12 +331,26 @@ void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_
         __syncthreads();
         const int a = min(cn, w * per), b = min(cn, a + per);
         if (valid) {
-#pragma unroll 4
-            for (int q = a; q < b; ++q) {
+            // Factors in pairs: one reciprocal per two denominators (a few
+            // ulps per factor; the roots' own sums keep one reciprocal per
+            // term, since their stopping test sits at a few ulps).
+            auto factor = [&](int q, double& num, double& den) {
                 const int jj = c0 + q;
-                const double lmd = (sB[q] - Di) + sT[q];        // lam_j - D_i
-                const double den = (jj == K - 1) ? rho : ((jj < i ? sD[q] : sD[q + 1]) - Di);
-                prod *= lmd * dc_rcp(den);
+                num = (sB[q] - Di) + sT[q];                         // lam_j - D_i
+                den = (jj == K - 1) ? rho : ((jj < i ? sD[q] : sD[q + 1]) - Di);
+            };
+            int q = a;
+#pragma unroll 2
+            for (; q + 1 < b; q += 2) {
+                double n1, d1, n2, d2;
+                factor(q, n1, d1);
+                factor(q + 1, n2, d2);
+                prod *= (n1 * n2) * dc_rcp3(d1 * d2);
+            }
+            if (q < b) {
+                double n1, d1;
+                factor(q, n1, d1);
+                prod *= n1 * dc_rcp3(d1);
             }
         }
     }
@@ -379,9 +394,16 @@ void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block
         __syncthreads();
         const int a = min(cn, w * per), b = min(cn, a + per);
         if (valid) {
-#pragma unroll 4
-            for (int q = a; q < b; ++q) {
-                const double v = sZ[q] * dc_rcp((sD[q] - base) - tj);
+            int q = a;
+#pragma unroll 2
+            for (; q + 1 < b; q += 2) {
+                const double x = (sD[q] - base) - tj, y = (sD[q + 1] - base) - tj;
+                const double rp = dc_rcp3(x * y);
+                const double v = sZ[q] * (y * rp), w = sZ[q + 1] * (x * rp);
+                s += v * v + w * w;
+            }
+            if (q < b) {
+                const double v = sZ[q] * dc_rcp3((sD[q] - base) - tj);
                 s += v * v;
             }
         }
