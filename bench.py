@@ -29,8 +29,8 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--family", default="clement", choices=["clement", "toeplitz"])
     ap.add_argument("--leaf", type=int, default=64)
