@@ -268,6 +268,11 @@ int dc_autotune_table(int* variant_out, int cap);
  *   d_bar      out (n);  e_bar  out (n-1)
  * Equal eigenvalues make F undefined: such pairs get F_ij = 0 and the status
  * word is set to -2000 (read with dc_last_info).
+ * With Q_bar, G^T = Q_bar^T Q is formed first (both operands transposed
+ * into temporaries); P = Q M then runs on register tiles with M generated
+ * and only the band reduced.  Temporaries (three n x n arrays with Q_bar,
+ * O(n^2 / 32) partial sums) are allocated stream-ordered and freed on the
+ * stream: not for graph capture.
  */
 int dc_stedc_backward(int n, const double* lam, const double* Q, int ldq,
                       const double* lam_bar, const double* Q_bar, int ldqb,
@@ -277,7 +282,8 @@ int dc_stedc_backward(int n, const double* lam, const double* Q, int ldq,
  * dc_stedc_backward_rank1 -- the same gradient when Q_bar = u g^T has rank
  * one (for instance a loss sum_i c_i (u^T q_i)^2, where g_i = 2 c_i u^T q_i).
  * Then F o (Q^T Q_bar) is itself Cauchy-like, (Q^T u)_i g_j / (lam_j -
- * lam_i), and the product Q M runs through the generated-tile merge kernel.
+ * lam_i), and M is generated from (Q^T u, g, lam) inside the register-tile
+ * product P = Q M.  Temporaries are allocated stream-ordered, as above.
  *   u (n), g (n) device vectors; lam_bar may be NULL.
  */
 int dc_stedc_backward_rank1(int n, const double* lam, const double* Q, int ldq,
