@@ -482,6 +482,10 @@ hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Sc
     }
     err = dc_readback(reads, s);
     if (err != hipSuccess) return err;
+    // Every switching merge of the level together: their compressions run
+    // back to back and their ranks come back in one round trip.
+    std::vector<LrMerge> ms;
+    std::vector<int> which;
     for (int i = 0; i < nm; ++i) {
         if (lr_halves[i].empty()) continue;
         const Node& N = P.merges[first + i];
@@ -504,17 +508,27 @@ hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Sc
             H.cpos = S.pos_root + base;
             H.w_row0 = r0;
         }
-        double flops = 0.0;
-        LrRankSummary rs;
-        err = dc_lowrank_product(C.K, b, o.lr_tol, S.Dbar + base, S.zhat + base,
-                                 S.cbase + base, S.tau + base, S.scale + base, halves,
-                                 N.n1 + N.n2, 0, s, &flops, &rs);
-        if (err != hipSuccess) return err;
+        LrMerge M;
+        M.K = C.K;
+        M.D = S.Dbar + base;
+        M.zhat = S.zhat + base;
+        M.cbase = S.cbase + base;
+        M.coff = S.tau + base;
+        M.scale = S.scale + base;
+        M.halves = std::move(halves);
+        M.wrows = N.n1 + N.n2;
+        ms.push_back(std::move(M));
+        which.push_back(i);
+    }
+    err = dc_lowrank_products(b, o.lr_tol, ms, 0, s);
+    if (err != hipSuccess) return err;
+    for (size_t q = 0; q < ms.size(); ++q) {
+        const Node& N = P.merges[first + which[q]];
         err = dc_disable_tasks(S.gtask + 2 * N.slot, 2, &S.cnt[N.slot].pad_[0], s);
         if (err != hipSuccess) return err;
         t_path[N.slot] = 1;
-        t_lr_flops[N.slot] = flops;
-        t_lr_ranks[N.slot] = rs;
+        t_lr_flops[N.slot] = ms[q].flops;
+        t_lr_ranks[N.slot] = ms[q].ranks;
     }
     return hipSuccess;
 }

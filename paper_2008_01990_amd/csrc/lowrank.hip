@@ -369,10 +369,10 @@ size_t compress_bytes(int K, int b) {
 }
 
 // SRRSC of every off-diagonal block into `dev` (compress_bytes(K, b) bytes);
-// the ranks are read back to the host.
-hipError_t compress(int K, int b, double tol, const double* D, const double* zhat,
-                    const double* cbase, const double* coff, const double* scale,
-                    hipStream_t s, Compressed& Cm, char* dev) {
+// the caller reads the ranks back (Cm.rank is sized for them).
+hipError_t compress_launch(int K, int b, double tol, const double* D, const double* zhat,
+                           const double* cbase, const double* coff, const double* scale,
+                           hipStream_t s, Compressed& Cm, char* dev) {
     Cm.b = b;
     Cm.p = (K + b - 1) / b;
     Cm.rmax = std::min(MAX_R, std::max(1, b / 2));
@@ -390,9 +390,8 @@ hipError_t compress(int K, int b, double tol, const double* D, const double* zha
     Cm.out.y = reinterpret_cast<double*>(Cm.dev + o_y);
     Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o);
     err = launch_srrsc(K, b, Cm.p, D, zhat, cbase, coff, scale, tol, Cm.rmax, true, Cm.out, s);
-    if (err != hipSuccess) return err;
     Cm.rank.resize(p2);
-    return dc_readback({{Cm.rank.data(), Cm.out.rank, p2 * sizeof(int)}}, s);
+    return err;
 }
 
 // Device-side task list of one launch, with its tile prefix.
@@ -462,31 +461,33 @@ hipError_t arena_end(Arena& A, hipStream_t s) {
     return hipEventRecord(A.ev, s);
 }
 
-hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
-                              const double* cbase, const double* coff, const double* scale,
-                              std::vector<LrHalf>& halves, int wrows, int variant,
-                              hipStream_t s, double* flops_out, LrRankSummary* ranks_out) {
-    Arena& A = arena();
-    hipError_t err = arena_begin(A, s);
-    char* cdev = nullptr;
-    if (err == hipSuccess) err = arena_get(A, SL_SRRSC, compress_bytes(K, b), &cdev);
-    Compressed Cm;
-    if (err == hipSuccess) err = compress(K, b, tol, D, zhat, cbase, coff, scale, s, Cm, cdev);
-    if (err != hipSuccess) return err;
+namespace {
+
+LrRankSummary rank_summary(const Compressed& Cm) {
+    LrRankSummary R;
+    const int p = Cm.p;
+    for (int I = 0; I < p; ++I)
+        for (int J = 0; J < p; ++J) {
+            if (I == J) continue;
+            const int r = Cm.rank[(size_t)I * p + J];
+            ++R.blocks;
+            if (r == -2) { ++R.dense; continue; }
+            R.rank_sum += r;
+            R.rank_max = std::max(R.rank_max, r);
+        }
+    return R;
+}
+
+// Products of one compressed merge: layouts from the ranks, the skeleton
+// columns W, the interpolation rows Y, then the skeleton and fused launches.
+// Its layout, W, Y and task buffers are the arena's, reused by the next
+// merge after these launches in stream order.
+hipError_t finish_product(Arena& A, const Compressed& Cm, int K, int b, const double* cbase,
+                          const double* coff, const double* scale,
+                          std::vector<LrHalf>& halves, int wrows, int variant, hipStream_t s,
+                          double* flops_out) {
+    hipError_t err = hipSuccess;
     const int p = Cm.p, rmax = Cm.rmax;
-    if (ranks_out) {
-        LrRankSummary R;
-        for (int I = 0; I < p; ++I)
-            for (int J = 0; J < p; ++J) {
-                if (I == J) continue;
-                const int r = Cm.rank[(size_t)I * p + J];
-                ++R.blocks;
-                if (r == -2) { ++R.dense; continue; }
-                R.rank_sum += r;
-                R.rank_max = std::max(R.rank_max, r);
-            }
-        *ranks_out = R;
-    }
     auto bsz = [&](int I) { return std::min(b, K - I * b); };
     // Skeleton size of block (I, J): its rank, or every column if kept dense.
     auto rk = [&](int I, int J) {
@@ -670,9 +671,59 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
                   ? dc_launch_cauchy_gemm2(td, sd, (int)S.tasks.size(), S.start.back(), fv, s)
                   : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), sv, s);
     }
-    const hipError_t e2 = arena_end(A, s);
-    if (err == hipSuccess) err = e2;
     if (flops_out) *flops_out = flops;
+    return err;
+}
+
+}  // namespace
+
+hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int variant,
+                               hipStream_t s) {
+    if (ms.empty()) return hipSuccess;
+    Arena& A = arena();
+    hipError_t err = arena_begin(A, s);
+    // Every merge's compression output in its own part of one slot, so that
+    // all of them are launched before their ranks come back together.
+    std::vector<size_t> off(ms.size() + 1, 0);
+    for (size_t i = 0; i < ms.size(); ++i) off[i + 1] = off[i] + al(compress_bytes(ms[i].K, b));
+    char* cdev = nullptr;
+    if (err == hipSuccess) err = arena_get(A, SL_SRRSC, off.back(), &cdev);
+    std::vector<Compressed> Cm(ms.size());
+    std::vector<DcRead> reads;
+    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
+        const LrMerge& M = ms[i];
+        err = compress_launch(M.K, b, tol, M.D, M.zhat, M.cbase, M.coff, M.scale, s, Cm[i],
+                              cdev + off[i]);
+        reads.push_back({Cm[i].rank.data(), Cm[i].out.rank, Cm[i].rank.size() * sizeof(int)});
+    }
+    if (err == hipSuccess) err = dc_readback(reads, s);
+    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
+        LrMerge& M = ms[i];
+        M.ranks = rank_summary(Cm[i]);
+        err = finish_product(A, Cm[i], M.K, b, M.cbase, M.coff, M.scale, M.halves, M.wrows,
+                             variant, s, &M.flops);
+    }
+    const hipError_t e2 = arena_end(A, s);
+    return err != hipSuccess ? err : e2;
+}
+
+hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
+                              const double* cbase, const double* coff, const double* scale,
+                              std::vector<LrHalf>& halves, int wrows, int variant,
+                              hipStream_t s, double* flops_out, LrRankSummary* ranks_out) {
+    std::vector<LrMerge> ms(1);
+    LrMerge& M = ms[0];
+    M.K = K;
+    M.D = D;
+    M.zhat = zhat;
+    M.cbase = cbase;
+    M.coff = coff;
+    M.scale = scale;
+    M.halves = halves;
+    M.wrows = wrows;
+    const hipError_t err = dc_lowrank_products(b, tol, ms, variant, s);
+    if (flops_out) *flops_out = M.flops;
+    if (ranks_out) *ranks_out = M.ranks;
     return err;
 }
 
@@ -760,9 +811,10 @@ extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
         if (err == hipSuccess)
             err = hipMallocAsync((void**)&cdev, compress_bytes(K, lr_block), stream);
         if (err == hipSuccess)
-            err = compress(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, stream, Cm, cdev);
+            err = compress_launch(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, stream, Cm,
+                                  cdev);
         if (err == hipSuccess)
-            std::memcpy(ranks_host, Cm.rank.data(), Cm.rank.size() * sizeof(int));
+            err = dc_readback({{ranks_host, Cm.out.rank, p2 * sizeof(int)}}, stream);
         if (cdev) hipFreeAsync(cdev, stream);
     } else {
         // count only, up to rank_cap

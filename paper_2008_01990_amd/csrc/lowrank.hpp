@@ -37,6 +37,27 @@ hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const d
                               hipStream_t s, double* flops_out,
                               LrRankSummary* ranks_out = nullptr);
 
+// One merge of dc_lowrank_products: its generators and halves as for
+// dc_lowrank_product; flops and ranks are filled in.
+struct LrMerge {
+    int K = 0;
+    const double* D = nullptr;
+    const double* zhat = nullptr;
+    const double* cbase = nullptr;
+    const double* coff = nullptr;
+    const double* scale = nullptr;
+    std::vector<LrHalf> halves;
+    int wrows = 0;
+    double flops = 0.0;
+    LrRankSummary ranks;
+};
+
+// Low-rank products of several merges (one tree level) on one stream: every
+// compression is launched first and all ranks are read in one round trip,
+// then each merge's products follow in turn (host-synchronising once).
+hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int variant,
+                               hipStream_t s);
+
 // Largest block size b of the compression: with column offsets (merge nodes)
 // or with plain column nodes.
 int dc_lowrank_max_block(bool offsets);
