@@ -130,7 +130,6 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     const int j = j0 + lane;
     const bool valid = j < K;
     const bool last = j == K - 1;
-    const int per = CH / NW;        // poles of a chunk per wave
     // The root's bracketing poles e0 < e1, whose terms are formed exactly:
     // (j, j+1) inside, (K-2, K-1) for the last root (K = 1: the one pole).
     const int e1 = last ? K - 1 : j + 1;
@@ -197,6 +196,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                 sz2[i] = zi * zi;
             }
             __syncthreads();
+            const int per = (cn + NW - 1) / NW;   // the chunk split over all waves
             const int a = min(cn, w * per), b = min(cn, a + per);
             if (valid) chunk_sums(sD, sz2, c0, a, b, Do, tcur, e0, e1, p);
         }
@@ -318,7 +318,6 @@ void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_
     const int i = p0 + lane;
     const bool valid = i < K;
     const double Di = valid ? T.D[i] : 0.0;
-    const int per = CH / NW;
     double prod = 1.0;
     for (int c0 = 0; c0 < K; c0 += CH) {
         const int cn = min(CH, K - c0);
@@ -329,6 +328,7 @@ void k_loewner(const SecTask* __restrict__ tasks, const int* __restrict__ block_
         }
         for (int q = tid; q <= cn; q += NW * 64) sD[q] = (c0 + q < K) ? T.D[c0 + q] : 0.0;
         __syncthreads();
+        const int per = (cn + NW - 1) / NW;   // the chunk split over all waves
         const int a = min(cn, w * per), b = min(cn, a + per);
         if (valid) {
             // Factors in pairs: one reciprocal per two denominators (a few
@@ -382,7 +382,6 @@ void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block
     const bool valid = j < K;
     const double base = valid ? T.cbase[j] : 0.0;
     const double tj = valid ? T.tau[j] : 0.0;
-    const int per = CH / NW;
     double s = 0.0;
     for (int c0 = 0; c0 < K; c0 += CH) {
         const int cn = min(CH, K - c0);
@@ -392,6 +391,7 @@ void k_colscale(const SecTask* __restrict__ tasks, const int* __restrict__ block
             sZ[q] = T.zhat[c0 + q];
         }
         __syncthreads();
+        const int per = (cn + NW - 1) / NW;   // the chunk split over all waves
         const int a = min(cn, w * per), b = min(cn, a + per);
         if (valid) {
             int q = a;
