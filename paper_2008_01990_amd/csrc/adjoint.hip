@@ -120,9 +120,11 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
 
     double lc[FN], lb[FN], gc[FN];
     int cix[FN];
+    bool cval[FN];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         cix[j] = wcol + j * 16 + lr;
+        cval[j] = cix[j] < n;
         const int c = min(cix[j], n - 1);
         lc[j] = dc_ldg(lam + c);
         lb[j] = lbar ? dc_ldg(lbar + c) : 0.0;
@@ -161,18 +163,34 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
             constexpr bool MASKED = decltype(masked_tag)::value;
             const int kk = step * 4 + lk;
             const bool kok = kk < n;
+            // k == c only where the step's four k meet the wave's columns
+            // (a uniform test); elsewhere every k is a row of the matrix
+            // (unmasked) and off the diagonal.
+            const bool dstep = MASKED || (unsigned)(step * 4 + 3 - wcol) < (unsigned)(WC + 3);
             double bf[FN];
+            if (dstep) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const double den = lc[j] - dk[slot];
-                const double x = LOADED ? xk[slot][j] : xk[slot][0] * gc[j];
-                const bool diag = kk == cix[j];
-                const bool eq = den == 0.0;
-                double v = x * dc_rcp3(den);
-                v = eq ? 0.0 : v;
-                v = diag ? lb[j] : v;
-                equal_eig |= eq && !diag && kok && cix[j] < n;
-                bf[j] = (!MASKED || kok) ? v : 0.0;
+                for (int j = 0; j < FN; ++j) {
+                    const double den = lc[j] - dk[slot];
+                    const double x = LOADED ? xk[slot][j] : xk[slot][0] * gc[j];
+                    const bool diag = kk == cix[j];
+                    const bool eq = den == 0.0;
+                    double v = x * dc_rcp3(den);
+                    v = eq ? 0.0 : v;
+                    v = diag ? lb[j] : v;
+                    equal_eig |= eq && !diag && kok && cval[j];
+                    bf[j] = (!MASKED || kok) ? v : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const double den = lc[j] - dk[slot];
+                    const double x = LOADED ? xk[slot][j] : xk[slot][0] * gc[j];
+                    const bool eq = den == 0.0;
+                    const double v = x * dc_rcp3(den);
+                    bf[j] = eq ? 0.0 : v;
+                    equal_eig |= eq && cval[j];
+                }
             }
 #pragma unroll
             for (int i = 0; i < FM; ++i)
