@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=0)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched configuration (profiling)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint configuration (profiling)")
     ap.add_argument("--lowrank-only", action="store_true",
                     help="profiling: time only the low-rank solve (not the benchmark line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -265,46 +269,12 @@ def table_rank(L, torch, n=16384, nprocs=4, tol=1e-12):
     return out
 
 
-def extra_configs(L, torch):
-    """Secondary configurations, each timed on the GPU after a warm-up."""
-    import numpy as np
+def batched_config(L, torch):
+    """Batched configuration: 256 problems, sizes log-uniform in [64, 4096],
+    d, e ~ U(-1, 1), seed 3; default tile rule, bucket-tuned and
+    batch-measured tiles, all replayed as graphs."""
     from paper_2008_01990_amd import workloads as W
     res = {}
-    # n=1024 1-2-1 Toeplitz, leaf 32 (latency-bound correctness config)
-    d0, e0 = W.toeplitz(1024)
-    d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
-    d = torch.empty_like(d_in)
-    Qb = torch.empty(1024, 1024, dtype=torch.float64, device="cuda")
-    s = L.Solver(1024, leaf=32)
-
-    def c0():
-        d.copy_(d_in)
-        s.solve_into(d, e, Qb)
-    t = _time(c0, 20, torch)
-    res["toeplitz_n1024_leaf32"] = {"seconds": t, "accuracy": gpu_accuracy(d_in, e, d, Qb, "toeplitz")}
-    # n=16384 Toeplitz, leaf 64: plain vs low rank at 1e-10
-    n = 16384
-    d0, e0 = W.toeplitz(n)
-    d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
-    d = torch.empty_like(d_in)
-    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
-    r = {}
-    for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=256, lr_min_k=2048))):
-        s = L.Solver(n, leaf=64, **kw)
-
-        def c1():
-            d.copy_(d_in)
-            s.solve_into(d, e, Qb)
-        t = _time(c1, 3, torch)
-        r[name] = {"seconds": t, "accuracy": gpu_accuracy(d_in, e, d, Qb, "toeplitz")}
-        del s
-    r["lowrank_speedup"] = r["plain"]["seconds"] / r["lowrank"]["seconds"]
-    res["toeplitz_n16384_leaf64"] = r
-    del Qb
-    torch.cuda.empty_cache()
-    # batched: 256 problems, sizes log-uniform in [64, 4096], d, e ~ U(-1, 1)
-    # (default tile rule, the bucket autotuner's table, then the choice
-    # measured on this batch; all replayed as graphs)
     probs = W.batched_problems(256, 64, 4096, seed=3)
     sizes = [len(p[0]) for p in probs]
     B = L.BatchedSolver(sizes, leaf=32)
@@ -342,6 +312,77 @@ def extra_configs(L, torch):
     del B
     L.autotune(0)
     torch.cuda.empty_cache()
+    return res
+
+
+def adjoint_config(L, torch):
+    """Adjoint configuration: n = 4096, loss sum w lam + sum c (u^T q)^2;
+    forward, rank-one and general backward."""
+    from paper_2008_01990_amd import workloads as W
+    res = {}
+    P = W.adjoint_problem(n=4096, seed=4, n_coords=32)
+    n = 4096
+    dd, ee = torch.tensor(P["d"], device="cuda"), torch.tensor(P["e"], device="cuda")
+    w, c, u = (torch.tensor(P[k], device="cuda") for k in ("w", "c", "u"))
+    s = L.Solver(n, leaf=32)
+    lam = dd.clone()
+    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
+
+    def fwd():
+        lam.copy_(dd)
+        s.solve_into(lam, ee, Qb)
+    tf = _time(fwd, 5, torch)
+    Q = Qb.t()
+    a = u @ Q
+    g = 2 * c * a
+    tb1 = _time(lambda: L.backward_rank1(lam, Qb, u, g, lam_bar=w), 5, torch)
+    Qbar_cm = torch.outer(u, g).t().contiguous()
+    tbg = _time(lambda: L.backward(lam, Qb, w, Qbar_cm), 5, torch)
+    res["adjoint_n4096"] = {"forward_seconds": tf, "backward_rank1_seconds": tb1,
+                            "backward_general_seconds": tbg,
+                            "backward_general_tflops": 4.0 * n ** 3 / tbg / 1e12,
+                            "backward_rank1_tflops": 2.0 * n ** 3 / tb1 / 1e12}
+    return res
+
+
+def extra_configs(L, torch):
+    """Secondary configurations, each timed on the GPU after a warm-up."""
+    import numpy as np
+    from paper_2008_01990_amd import workloads as W
+    res = {}
+    # n=1024 1-2-1 Toeplitz, leaf 32 (latency-bound correctness config)
+    d0, e0 = W.toeplitz(1024)
+    d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
+    d = torch.empty_like(d_in)
+    Qb = torch.empty(1024, 1024, dtype=torch.float64, device="cuda")
+    s = L.Solver(1024, leaf=32)
+
+    def c0():
+        d.copy_(d_in)
+        s.solve_into(d, e, Qb)
+    t = _time(c0, 20, torch)
+    res["toeplitz_n1024_leaf32"] = {"seconds": t, "accuracy": gpu_accuracy(d_in, e, d, Qb, "toeplitz")}
+    # n=16384 Toeplitz, leaf 64: plain vs low rank at 1e-10
+    n = 16384
+    d0, e0 = W.toeplitz(n)
+    d_in, e = torch.tensor(d0, device="cuda"), torch.tensor(e0, device="cuda")
+    d = torch.empty_like(d_in)
+    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    r = {}
+    for name, kw in (("plain", {}), ("lowrank", dict(lr_tol=1e-10, lr_block=256, lr_min_k=2048))):
+        s = L.Solver(n, leaf=64, **kw)
+
+        def c1():
+            d.copy_(d_in)
+            s.solve_into(d, e, Qb)
+        t = _time(c1, 3, torch)
+        r[name] = {"seconds": t, "accuracy": gpu_accuracy(d_in, e, d, Qb, "toeplitz")}
+        del s
+    r["lowrank_speedup"] = r["plain"]["seconds"] / r["lowrank"]["seconds"]
+    res["toeplitz_n16384_leaf64"] = r
+    del Qb
+    torch.cuda.empty_cache()
+    res.update(batched_config(L, torch))
     # the paper's own sizes (Examples 2-3): n = 30000 Clement, Hermite-type,
     # 1-2-1 Toeplitz and SHT (m = n), plain and low-rank; residual on all
     # columns, orthogonality on 1024 sampled columns against all.
@@ -383,29 +424,7 @@ def extra_configs(L, torch):
     torch.cuda.empty_cache()
     res["example1"] = example1(L, torch)
     res["table_rank"] = table_rank(L, torch)
-    # adjoint: n=4096, loss sum w lam + sum c (u^T q)^2
-    P = W.adjoint_problem(n=4096, seed=4, n_coords=32)
-    n = 4096
-    dd, ee = torch.tensor(P["d"], device="cuda"), torch.tensor(P["e"], device="cuda")
-    w, c, u = (torch.tensor(P[k], device="cuda") for k in ("w", "c", "u"))
-    s = L.Solver(n, leaf=32)
-    lam = dd.clone()
-    Qb = torch.empty(n, n, dtype=torch.float64, device="cuda")
-
-    def fwd():
-        lam.copy_(dd)
-        s.solve_into(lam, ee, Qb)
-    tf = _time(fwd, 5, torch)
-    Q = Qb.t()
-    a = u @ Q
-    g = 2 * c * a
-    tb1 = _time(lambda: L.backward_rank1(lam, Qb, u, g, lam_bar=w), 5, torch)
-    Qbar_cm = torch.outer(u, g).t().contiguous()
-    tbg = _time(lambda: L.backward(lam, Qb, w, Qbar_cm), 5, torch)
-    res["adjoint_n4096"] = {"forward_seconds": tf, "backward_rank1_seconds": tb1,
-                            "backward_general_seconds": tbg,
-                            "backward_general_tflops": 4.0 * n ** 3 / tbg / 1e12,
-                            "backward_rank1_tflops": 2.0 * n ** 3 / tb1 / 1e12}
+    res.update(adjoint_config(L, torch))
     return res
 
 
@@ -429,6 +448,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8}), flush=True)
+        return
+    if args.batched_only or args.adjoint_only:
+        out = batched_config(L, torch) if args.batched_only else adjoint_config(L, torch)
+        print(json.dumps(out), flush=True)
         return
     n = args.n
     d0, e0 = inputs(args.family, n)
