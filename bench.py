@@ -95,32 +95,36 @@ def cpu_baseline(family, n_full, n_sample, leaf):
     """The oracle on the host cores: a full solve at n_sample, scaled by the
     cubic flop ratio of divide and conquer to the benchmark's order.  With
     n_sample = 0 the sample size is chosen for about 10-30 s of oracle work:
-    a solve at n = 4096 is timed first and the size scaled from it (a
-    multiple of 512 in [4096, 12288]); host speeds differ from box to box."""
+    a solve at n = 4000 is timed first and the size scaled from it (a
+    multiple of 250 in [4000, 12000]); host speeds differ from box to box."""
     from threadpoolctl import threadpool_info
     from oracle import dc
     pre = None
     if n_sample <= 0:
-        d, e = inputs(family, 1024)             # untimed: the first solve pays start-up
+        # Orders with a large power-of-two factor make the host BLAS thrash its
+        # caches (n = 4096 ran slower than n = 5120), so the pre-sample is
+        # n = 4000 and the sample a multiple of 250 that is no power of two.
+        d, e = inputs(family, 1000)             # untimed: the first solve pays start-up
         dc.eigh_tridiagonal(d, e, leaf=leaf)
-        d, e = inputs(family, 4096)
+        d, e = inputs(family, 4000)
         t0 = time.perf_counter()
         dc.eigh_tridiagonal(d, e, leaf=leaf)
         pre = time.perf_counter() - t0
-        # cubic growth aims at 15 s; the oracle's time has also grown about
-        # as n^4.5 once its matrices left cache, so the size is capped to
-        # stay within 40 s under that growth too
+        # cubic growth aims at 15 s; the size is also capped to stay within
+        # 40 s should the time grow as n^4.5
         r = 15.0 / max(pre, 1e-3)
         cap = 40.0 / max(pre, 1e-3)
-        n_sample = int(4096 * min(r ** (1.0 / 3.0), cap ** (1.0 / 4.5))) // 512 * 512
-        n_sample = min(max(n_sample, 4096), 12288)
+        n_sample = int(4000 * min(r ** (1.0 / 3.0), cap ** (1.0 / 4.5))) // 250 * 250
+        n_sample = min(max(n_sample, 4000), 12000)
+        if n_sample & (n_sample - 1) == 0:
+            n_sample -= 250
     d, e = inputs(family, n_sample)
     t0 = time.perf_counter()
     dc.eigh_tridiagonal(d, e, leaf=leaf)
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     scale = (n_full / n_sample) ** 3
-    sizing = (f" (size chosen from a {pre:.2f} s solve at n=4096)" if pre is not None else "")
+    sizing = (f" (size chosen from a {pre:.2f} s solve at n=4000)" if pre is not None else "")
     return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": f"full oracle solve of the {family} matrix at n={n_sample} "
                       f"(leaf {leaf}) took {dt:.2f} s; scaled by (n/{n_sample})^3 = "
