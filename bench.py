@@ -94,37 +94,41 @@ def gpu_accuracy(d, e, lam, Qbuf, family):
 def cpu_baseline(family, n_full, n_sample, leaf):
     """The oracle on the host cores: a full solve at n_sample, scaled by the
     cubic flop ratio of divide and conquer to the benchmark's order.  With
-    n_sample = 0 the sample size is chosen for about 10-30 s of oracle work:
-    a solve at n = 4000 is timed first and the size scaled from it (a
-    multiple of 250 in [4000, 12000]); host speeds differ from box to box."""
+    n_sample = 0 the sample grows until it takes at least 10 s: solves at
+    n = 4000 and up (at most 1.5x per step, multiples of 250, capped at
+    16000), the last one reported.  Host speed and how the oracle's time
+    grows with n differ from box to box; orders with a large power-of-two
+    factor make the host BLAS thrash its caches, so none is used."""
     from threadpoolctl import threadpool_info
     from oracle import dc
-    pre = None
+    visited = []
     if n_sample <= 0:
-        # Orders with a large power-of-two factor make the host BLAS thrash its
-        # caches (n = 4096 ran slower than n = 5120), so the pre-sample is
-        # n = 4000 and the sample a multiple of 250 that is no power of two.
         d, e = inputs(family, 1000)             # untimed: the first solve pays start-up
         dc.eigh_tridiagonal(d, e, leaf=leaf)
-        d, e = inputs(family, 4000)
+        n = 4000
+        while True:
+            d, e = inputs(family, n)
+            t0 = time.perf_counter()
+            dc.eigh_tridiagonal(d, e, leaf=leaf)
+            dt = time.perf_counter() - t0
+            visited.append((n, dt))
+            if dt >= 10.0 or n >= 16000:
+                break
+            grow = min(1.5, max(1.15, (15.0 / dt) ** 0.5))
+            nxt = min(16000, int(n * grow) // 250 * 250)
+            if nxt & (nxt - 1) == 0:
+                nxt -= 250
+            n = nxt
+        n_sample = n
+    else:
+        d, e = inputs(family, n_sample)
         t0 = time.perf_counter()
         dc.eigh_tridiagonal(d, e, leaf=leaf)
-        pre = time.perf_counter() - t0
-        # cubic growth aims at 15 s; the size is also capped to stay within
-        # 40 s should the time grow as n^4.5
-        r = 15.0 / max(pre, 1e-3)
-        cap = 40.0 / max(pre, 1e-3)
-        n_sample = int(4000 * min(r ** (1.0 / 3.0), cap ** (1.0 / 4.5))) // 250 * 250
-        n_sample = min(max(n_sample, 4000), 12000)
-        if n_sample & (n_sample - 1) == 0:
-            n_sample -= 250
-    d, e = inputs(family, n_sample)
-    t0 = time.perf_counter()
-    dc.eigh_tridiagonal(d, e, leaf=leaf)
-    dt = time.perf_counter() - t0
+        dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     scale = (n_full / n_sample) ** 3
-    sizing = (f" (size chosen from a {pre:.2f} s solve at n=4000)" if pre is not None else "")
+    steps = "".join(f", n={m}: {t:.2f} s" for m, t in visited[:-1])
+    sizing = f" (smaller samples first{steps})" if len(visited) > 1 else ""
     return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": f"full oracle solve of the {family} matrix at n={n_sample} "
                       f"(leaf {leaf}) took {dt:.2f} s; scaled by (n/{n_sample})^3 = "
