@@ -478,104 +478,78 @@ LrRankSummary rank_summary(const Compressed& Cm) {
     return R;
 }
 
-// Products of one compressed merge: layouts from the ranks, the skeleton
-// columns W, the interpolation rows Y, then the skeleton and fused launches.
-// Its layout, W, Y and task buffers are the arena's, reused by the next
-// merge after these launches in stream order.
-hipError_t finish_product(Arena& A, const Compressed& Cm, int K, int b, const double* cbase,
-                          const double* coff, const double* scale,
-                          std::vector<LrHalf>& halves, int wrows, int variant, hipStream_t s,
-                          double* flops_out) {
-    hipError_t err = hipSuccess;
-    const int p = Cm.p, rmax = Cm.rmax;
+// Host layout of one compressed merge's products, from the ranks alone (the
+// skeleton columns and y stay on the device): W by output block J,
+// [W_IJ for I != J], r_IJ columns each; the stage-1b column list of block
+// row I, [T_IJ for J != I].  Its uploaded arrays (per-pair offsets) and its
+// device-filled arrays (per W column: skeleton generator, v^(r) row, block
+// column, y; the stage-1b lists) have places in the level's layout slot,
+// and W and Y places in the level's W and Y slots.
+struct MergePlan {
+    int p = 0;
+    std::vector<long long> gstart, woff;
+    std::vector<int> loff, lstart;
+    long long NW = 0;
+    size_t up_off = 0, dev_off = 0;               // bytes, in the layout slot
+    size_t o_wo = 0, o_lo = 0, up_bytes = 0;      // inside the uploaded part
+    size_t o_ry = 0, o_rg = 0, o_rv = 0, o_kj = 0, o_cc = 0, o_wp = 0, dev_bytes = 0;
+    size_t w_off = 0, y_off = 0;                  // elements, in the W and Y slots
+};
+
+void plan_layout(const Compressed& Cm, int K, int b, MergePlan& P) {
+    const int p = Cm.p;
+    P.p = p;
     auto bsz = [&](int I) { return std::min(b, K - I * b); };
     // Skeleton size of block (I, J): its rank, or every column if kept dense.
     auto rk = [&](int I, int J) {
         const int r = Cm.rank[(size_t)I * p + J];
         return r == -2 ? bsz(J) : r;
     };
-
-    // Layouts from the ranks alone (the skeleton columns and y stay on the
-    // device): W by output block J, [W_IJ for I != J], r_IJ columns each;
-    // the stage-1b column list of block row I, [T_IJ for J != I].
-    std::vector<long long> gstart(p + 1, 0), woff((size_t)p * p, 0);
-    std::vector<int> loff((size_t)p * p, 0), lstart(p + 1, 0);
+    P.gstart.assign(p + 1, 0);
+    P.woff.assign((size_t)p * p, 0);
+    P.loff.assign((size_t)p * p, 0);
+    P.lstart.assign(p + 1, 0);
     for (int J = 0; J < p; ++J) {
         long long run = 0;
         for (int I = 0; I < p; ++I)
-            if (I != J && rk(I, J) > 0) { woff[(size_t)I * p + J] = gstart[J] + run; run += rk(I, J); }
-        gstart[J + 1] = gstart[J] + run;
+            if (I != J && rk(I, J) > 0) { P.woff[(size_t)I * p + J] = P.gstart[J] + run; run += rk(I, J); }
+        P.gstart[J + 1] = P.gstart[J] + run;
     }
     for (int I = 0; I < p; ++I) {
         int run = 0;
         for (int J = 0; J < p; ++J)
-            if (I != J && rk(I, J) > 0) { loff[(size_t)I * p + J] = lstart[I] + run; run += rk(I, J); }
-        lstart[I + 1] = lstart[I] + run;
+            if (I != J && rk(I, J) > 0) { P.loff[(size_t)I * p + J] = P.lstart[I] + run; run += rk(I, J); }
+        P.lstart[I + 1] = P.lstart[I] + run;
     }
-    const long long NW = gstart[p];
-    // Device block: per-pair offsets (uploaded), then the per-W-column arrays
-    // that k_layout fills: skeleton generator, v^(r) row, block column, y;
-    // and the stage-1b lists (skeleton generator, W column).
+    P.NW = P.gstart[p];
     const size_t p2 = (size_t)p * p;
-    const size_t nw1 = (size_t)std::max<long long>(NW, 1);
+    const size_t nw1 = (size_t)std::max<long long>(P.NW, 1);
     size_t o = 0;
-    const size_t o_wo = o; o = al(o + p2 * sizeof(long long));
-    const size_t o_lo = o; o = al(o + p2 * sizeof(int));
-    const size_t up_bytes = o;
-    const size_t o_ry = o; o = al(o + nw1 * sizeof(double));
-    const size_t o_rg = o; o = al(o + nw1 * sizeof(int));
-    const size_t o_rv = o; o = al(o + nw1 * sizeof(long long));
-    const size_t o_kj = o; o = al(o + nw1 * sizeof(int));
-    const size_t o_cc = o; o = al(o + nw1 * sizeof(int));
-    const size_t o_wp = o; o = al(o + nw1 * sizeof(int));
-    const size_t small_bytes = o;
-    double* W = nullptr;
-    double* Y = nullptr;
-    char* small = nullptr;
-    if (err == hipSuccess) err = arena_get(A, SL_LAYOUT, small_bytes, &small);
-    if (err == hipSuccess && NW > 0)
-        err = arena_get(A, SL_W, (size_t)wrows * NW * sizeof(double), reinterpret_cast<char**>(&W));
-    if (err == hipSuccess && NW > 0)
-        err = arena_get(A, SL_Y, (size_t)NW * b * sizeof(double), reinterpret_cast<char**>(&Y));
-    std::vector<char> host(up_bytes);
-    std::memcpy(host.data() + o_wo, woff.data(), p2 * sizeof(long long));
-    std::memcpy(host.data() + o_lo, loff.data(), p2 * sizeof(int));
-    if (err == hipSuccess) err = dc_upload(small, host.data(), up_bytes, s);
-    int* const d_ccol = reinterpret_cast<int*>(small + o_cc);
-    int* const d_wpos = reinterpret_cast<int*>(small + o_wp);
-    if (err == hipSuccess && NW > 0) {
-        hipLaunchKernelGGL(k_layout, dim3((unsigned)p2), dim3(128), 0, s, p, b, K, rmax,
-                           Cm.out.rank, Cm.out.pcol, Cm.out.y,
-                           reinterpret_cast<long long*>(small + o_wo),
-                           reinterpret_cast<int*>(small + o_lo),
-                           reinterpret_cast<int*>(small + o_rg),
-                           reinterpret_cast<long long*>(small + o_rv),
-                           reinterpret_cast<int*>(small + o_kj),
-                           reinterpret_cast<double*>(small + o_ry), d_ccol, d_wpos);
-        err = hipGetLastError();
-    }
-    if (err == hipSuccess && NW > 0) {
-        const long long ny = NW * b;
-        hipLaunchKernelGGL(k_build_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, NW,
-                           b, K, reinterpret_cast<double*>(small + o_ry),
-                           reinterpret_cast<int*>(small + o_rg),
-                           reinterpret_cast<long long*>(small + o_rv),
-                           reinterpret_cast<int*>(small + o_kj), Cm.out.vk, cbase, coff, scale, Y);
-        err = hipGetLastError();
-    }
+    P.o_wo = o; o = al(o + p2 * sizeof(long long));
+    P.o_lo = o; o = al(o + p2 * sizeof(int));
+    P.up_bytes = o;
+    o = 0;
+    P.o_ry = o; o = al(o + nw1 * sizeof(double));
+    P.o_rg = o; o = al(o + nw1 * sizeof(int));
+    P.o_rv = o; o = al(o + nw1 * sizeof(long long));
+    P.o_kj = o; o = al(o + nw1 * sizeof(int));
+    P.o_cc = o; o = al(o + nw1 * sizeof(int));
+    P.o_wp = o; o = al(o + nw1 * sizeof(int));
+    P.dev_bytes = o;
+}
 
-    // Task lists: (1b) the skeleton columns into W, then one fused launch
-    // per output block J: the diagonal block A(:, J) U_JJ (generated) and
-    // W_J Y_J (loaded Y) accumulate in the same tile, so C is written once.
-    // The fused stage needs the register kernel (variants 0 and 5).
-    Stage s1b, sf;
-    const int fv = (variant == 2 || variant == 5) ? 5 : 0;
+// The products of one merge as tasks of the level's two launches: (1b) the
+// skeleton columns into W; then per output block J, the diagonal block
+// A(:, J) U_JJ (generated) and W_J Y_J (loaded Y) accumulated in the same
+// tile, so C is written once.
+void add_tasks(const MergePlan& P, int K, int b, const double* cbase, const double* coff,
+               const double* scale, const std::vector<LrHalf>& halves, int wrows,
+               double* W, const double* Y, const int* d_ccol, const int* d_wpos, int fv,
+               int sv, Stage& s1b, Stage& sf, double* flops_out) {
+    const int p = P.p;
     const int BMf = dc_gemm_tile_m(fv), BNf = dc_gemm_tile_n(fv);
-    // The skeleton stage's column count per block row (a sum of ranks) is
-    // rarely a multiple of 128: with the default tile rule it takes 64 x 64
-    // register tiles, which waste less on the last column tile.
-    const int sv = variant == 0 ? 5 : variant;
     const int BMs = dc_gemm_tile_m(sv), BNs = dc_gemm_tile_n(sv);
+    auto bsz = [&](int I) { return std::min(b, K - I * b); };
     double flops = 0.0;
     auto tiles = [&](GemmTask& t, int bm, int bn) {
         t.tiles_m = (t.rows + bm - 1) / bm;
@@ -616,11 +590,11 @@ hipError_t finish_product(Arena& A, const Compressed& Cm, int K, int b, const do
             a.ldc = H.ldc;
             a.cpos = H.cpos;
             a.beta = 0;
-            const long long R = gstart[I + 1] - gstart[I];
+            const long long R = P.gstart[I + 1] - P.gstart[I];
             if (R > 0) {
-                a.A2 = W + H.w_row0 + gstart[I] * (long long)wrows;
+                a.A2 = W + H.w_row0 + P.gstart[I] * (long long)wrows;
                 a.lda2 = wrows;
-                a.B2 = Y + gstart[I] * (long long)b;
+                a.B2 = Y + P.gstart[I] * (long long)b;
                 a.ldb2 = b;
                 a.klen2 = (int)R;
             }
@@ -628,11 +602,11 @@ hipError_t finish_product(Arena& A, const Compressed& Cm, int K, int b, const do
             sf.add(a);
             flops += 2.0 * H.rows * (a.klen + a.klen2) * a.ncol;
             // 1b: skeleton columns of every J != I into W
-            if (lstart[I + 1] > lstart[I]) {
+            if (P.lstart[I + 1] > P.lstart[I]) {
                 GemmTask c = t;
-                c.ccol = d_ccol + lstart[I];
-                c.cpos = d_wpos + lstart[I];
-                c.ncol = lstart[I + 1] - lstart[I];
+                c.ccol = d_ccol + P.lstart[I];
+                c.cpos = d_wpos + P.lstart[I];
+                c.ncol = P.lstart[I + 1] - P.lstart[I];
                 c.C = W + H.w_row0;
                 c.ldc = wrows;
                 c.beta = 0;
@@ -642,7 +616,115 @@ hipError_t finish_product(Arena& A, const Compressed& Cm, int K, int b, const do
             }
         }
     }
-    // Upload the task lists and launch the stages in order.
+    *flops_out = flops;
+}
+
+}  // namespace
+
+hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int variant,
+                               hipStream_t s) {
+    if (ms.empty()) return hipSuccess;
+    Arena& A = arena();
+    hipError_t err = arena_begin(A, s);
+    // Every merge's compression output in its own part of one slot, so that
+    // all of them are launched before their ranks come back together.
+    std::vector<size_t> off(ms.size() + 1, 0);
+    for (size_t i = 0; i < ms.size(); ++i) off[i + 1] = off[i] + al(compress_bytes(ms[i].K, b));
+    char* cdev = nullptr;
+    if (err == hipSuccess) err = arena_get(A, SL_SRRSC, off.back(), &cdev);
+    std::vector<Compressed> Cm(ms.size());
+    std::vector<DcRead> reads;
+    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
+        const LrMerge& M = ms[i];
+        err = compress_launch(M.K, b, tol, M.D, M.zhat, M.cbase, M.coff, M.scale, s, Cm[i],
+                              cdev + off[i]);
+        reads.push_back({Cm[i].rank.data(), Cm[i].out.rank, Cm[i].rank.size() * sizeof(int)});
+    }
+    if (err == hipSuccess) err = dc_readback(reads, s);
+    if (err != hipSuccess) return err;
+
+    // Layouts of every merge, then one place for each in the level's slots:
+    // the layout slot holds all uploaded parts first (one upload), then all
+    // device-filled parts; W and Y hold one region per merge.
+    std::vector<MergePlan> P(ms.size());
+    size_t up_total = 0, dev_total = 0, w_total = 0, y_total = 0;
+    for (size_t i = 0; i < ms.size(); ++i) {
+        ms[i].ranks = rank_summary(Cm[i]);
+        plan_layout(Cm[i], ms[i].K, b, P[i]);
+        P[i].up_off = up_total;
+        up_total += P[i].up_bytes;
+        P[i].w_off = w_total;
+        w_total += (size_t)ms[i].wrows * (size_t)P[i].NW;
+        P[i].y_off = y_total;
+        y_total += (size_t)P[i].NW * b;
+    }
+    for (size_t i = 0; i < ms.size(); ++i) {
+        P[i].dev_off = up_total + dev_total;
+        dev_total += P[i].dev_bytes;
+    }
+    char* small = nullptr;
+    double* W = nullptr;
+    double* Y = nullptr;
+    err = arena_get(A, SL_LAYOUT, up_total + dev_total, &small);
+    if (err == hipSuccess && w_total > 0)
+        err = arena_get(A, SL_W, w_total * sizeof(double), reinterpret_cast<char**>(&W));
+    if (err == hipSuccess && y_total > 0)
+        err = arena_get(A, SL_Y, y_total * sizeof(double), reinterpret_cast<char**>(&Y));
+    std::vector<char> host(up_total);
+    for (size_t i = 0; i < ms.size(); ++i) {
+        const size_t p2 = (size_t)P[i].p * P[i].p;
+        std::memcpy(host.data() + P[i].up_off + P[i].o_wo, P[i].woff.data(),
+                    p2 * sizeof(long long));
+        std::memcpy(host.data() + P[i].up_off + P[i].o_lo, P[i].loff.data(), p2 * sizeof(int));
+    }
+    if (err == hipSuccess) err = dc_upload(small, host.data(), up_total, s);
+
+    // Per merge: the per-column layout and the interpolation rows on the
+    // device, and its tasks in the level's two launches.  The fused stage
+    // needs the register kernel (variants 0 and 5).  The skeleton stage's
+    // column count per block row (a sum of ranks) is rarely a multiple of
+    // 128: with the default tile rule it takes 64 x 64 register tiles, which
+    // waste less on the last column tile.
+    const int fv = (variant == 2 || variant == 5) ? 5 : 0;
+    const int sv = variant == 0 ? 5 : variant;
+    Stage s1b, sf;
+    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
+        const MergePlan& Q = P[i];
+        LrMerge& M = ms[i];
+        char* up = small + Q.up_off;
+        char* dv = small + Q.dev_off;
+        double* Wi = W ? W + Q.w_off : nullptr;
+        double* Yi = Y ? Y + Q.y_off : nullptr;
+        const int* d_ccol = reinterpret_cast<int*>(dv + Q.o_cc);
+        const int* d_wpos = reinterpret_cast<int*>(dv + Q.o_wp);
+        if (Q.NW > 0) {
+            hipLaunchKernelGGL(k_layout, dim3((unsigned)((size_t)Q.p * Q.p)), dim3(128), 0, s,
+                               Q.p, b, M.K, Cm[i].rmax, Cm[i].out.rank, Cm[i].out.pcol,
+                               Cm[i].out.y, reinterpret_cast<long long*>(up + Q.o_wo),
+                               reinterpret_cast<int*>(up + Q.o_lo),
+                               reinterpret_cast<int*>(dv + Q.o_rg),
+                               reinterpret_cast<long long*>(dv + Q.o_rv),
+                               reinterpret_cast<int*>(dv + Q.o_kj),
+                               reinterpret_cast<double*>(dv + Q.o_ry),
+                               reinterpret_cast<int*>(dv + Q.o_cc),
+                               reinterpret_cast<int*>(dv + Q.o_wp));
+            err = hipGetLastError();
+            if (err != hipSuccess) break;
+            const long long ny = Q.NW * b;
+            hipLaunchKernelGGL(k_build_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s,
+                               Q.NW, b, M.K, reinterpret_cast<double*>(dv + Q.o_ry),
+                               reinterpret_cast<int*>(dv + Q.o_rg),
+                               reinterpret_cast<long long*>(dv + Q.o_rv),
+                               reinterpret_cast<int*>(dv + Q.o_kj), Cm[i].out.vk, M.cbase,
+                               M.coff, M.scale, Yi);
+            err = hipGetLastError();
+            if (err != hipSuccess) break;
+        }
+        add_tasks(Q, M.K, b, M.cbase, M.coff, M.scale, M.halves, M.wrows, Wi, Yi, d_ccol,
+                  d_wpos, fv, sv, s1b, sf, &M.flops);
+    }
+
+    // Upload the level's task lists and launch the two stages in order.
     constexpr int NS = 2;
     Stage* stages[NS] = {&s1b, &sf};
     size_t to = 0;
@@ -670,38 +752,6 @@ hipError_t finish_product(Arena& A, const Compressed& Cm, int K, int b, const do
         err = (&S == &sf)
                   ? dc_launch_cauchy_gemm2(td, sd, (int)S.tasks.size(), S.start.back(), fv, s)
                   : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), sv, s);
-    }
-    if (flops_out) *flops_out = flops;
-    return err;
-}
-
-}  // namespace
-
-hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int variant,
-                               hipStream_t s) {
-    if (ms.empty()) return hipSuccess;
-    Arena& A = arena();
-    hipError_t err = arena_begin(A, s);
-    // Every merge's compression output in its own part of one slot, so that
-    // all of them are launched before their ranks come back together.
-    std::vector<size_t> off(ms.size() + 1, 0);
-    for (size_t i = 0; i < ms.size(); ++i) off[i + 1] = off[i] + al(compress_bytes(ms[i].K, b));
-    char* cdev = nullptr;
-    if (err == hipSuccess) err = arena_get(A, SL_SRRSC, off.back(), &cdev);
-    std::vector<Compressed> Cm(ms.size());
-    std::vector<DcRead> reads;
-    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
-        const LrMerge& M = ms[i];
-        err = compress_launch(M.K, b, tol, M.D, M.zhat, M.cbase, M.coff, M.scale, s, Cm[i],
-                              cdev + off[i]);
-        reads.push_back({Cm[i].rank.data(), Cm[i].out.rank, Cm[i].rank.size() * sizeof(int)});
-    }
-    if (err == hipSuccess) err = dc_readback(reads, s);
-    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
-        LrMerge& M = ms[i];
-        M.ranks = rank_summary(Cm[i]);
-        err = finish_product(A, Cm[i], M.K, b, M.cbase, M.coff, M.scale, M.halves, M.wrows,
-                             variant, s, &M.flops);
     }
     const hipError_t e2 = arena_end(A, s);
     return err != hipSuccess ? err : e2;
