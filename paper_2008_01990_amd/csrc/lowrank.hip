@@ -26,7 +26,9 @@
 // whose skeleton is every column (identity interpolation rows).  W is laid
 // out by output block J, so each J reads one contiguous column range of W
 // and of Y.  U and Z never exist as matrices; W and Y are m x (sum of ranks)
-// and (sum of ranks) x b.
+// and (sum of ranks) x b.  The merges of one tree level go together: all
+// compressions first (one read of all ranks), then one launch of step 1 and
+// one of step 2 for every merge of the level.
 #include <algorithm>
 #include <climits>
 #include <cstdint>
