@@ -55,15 +55,27 @@ struct SrrscOut {
     double* vk;       // p*p*b: v^(r) of the block's columns (0 on skeletons)
 };
 
+// One compression of a launch: K nodes in p x p blocks, the generators and
+// the outputs.  A launch runs the blocks of several jobs (the merges of a
+// tree level): job j owns blocks [start[j], start[j + 1]) of the grid.
+struct SrrscJob {
+    int K, p;
+    const double* D;
+    const double* u0;
+    const double* cbase;
+    const double* coff;
+    const double* v0;
+    SrrscOut O;
+};
+
 // One workgroup per block (I, J).  MB: LDS capacity in generators; OFF: the
 // column nodes carry an offset (w_j = cbase_j + coff_j, the merge's (origin,
 // tau) form); STORE: write the skeleton and interpolation generators, else only
 // count the rank (up to rmax).
 template <int MB, int RG, bool OFF, bool STORE>
 __global__ __launch_bounds__(NT)
-void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __restrict__ u0,
-             const double* __restrict__ cbase, const double* __restrict__ coff,
-             const double* __restrict__ v0, double tol, int rmax, SrrscOut O) {
+void k_srrsc(const SrrscJob* __restrict__ jobs, const int* __restrict__ start, int njobs, int b,
+             double tol, int rmax) {
     constexpr int JJ = (MB * RG + NT - 1) / NT;   // columns per thread
     __shared__ double sd[MB], su[MB], swb[MB], sv[MB];
     __shared__ double swo[OFF ? MB : 1];
@@ -71,7 +83,20 @@ void k_srrsc(int K, int b, int p, const double* __restrict__ D, const double* __
     __shared__ int wi[NT / 64];
     __shared__ int spr[STORE ? MAX_R : 1], spc[STORE ? MAX_R : 1];
 
-    const int pair = blockIdx.x;
+    int jlo = 0, jhi = njobs - 1;
+    while (jlo < jhi) {
+        const int mid = (jlo + jhi + 1) >> 1;
+        if (start[mid] <= (int)blockIdx.x) jlo = mid; else jhi = mid - 1;
+    }
+    const SrrscJob& job = jobs[jlo];
+    const int K = job.K, p = job.p;
+    const double* __restrict__ D = job.D;
+    const double* __restrict__ u0 = job.u0;
+    const double* __restrict__ cbase = job.cbase;
+    const double* __restrict__ coff = job.coff;
+    const double* __restrict__ v0 = job.v0;
+    const SrrscOut O = job.O;
+    const int pair = blockIdx.x - start[jlo];
     const int I = pair / p, J = pair - (pair / p) * p;
     const int tid = threadIdx.x;
     if (I == J) {
@@ -306,59 +331,72 @@ struct Compressed {
     SrrscOut out{};
 };
 
-// The SRRSC instance that fits: column offsets present (merge nodes, b up to
-// MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); store or count only.
+// The SRRSC instance for a job list: column offsets present (merge nodes, b
+// up to MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); store or count
+// only.
 template <int MB, int RG, bool OFF>
-hipError_t launch_srrsc_mb(int K, int b, int p, const double* D, const double* zhat,
-                           const double* cbase, const double* coff, const double* scale,
-                           double tol, int rmax, bool store, const SrrscOut& out,
-                           hipStream_t s) {
-    const dim3 g((unsigned)((size_t)p * p)), blk(NT);
+hipError_t launch_srrsc_mb(const SrrscJob* jobs, const int* start, int njobs, int blocks, int b,
+                           double tol, int rmax, bool store, hipStream_t s) {
+    const dim3 g((unsigned)blocks), blk(NT);
     if (store)
-        hipLaunchKernelGGL((k_srrsc<MB, RG, OFF, true>), g, blk, 0, s, K, b, p, D, zhat, cbase,
-                           coff, scale, tol, rmax, out);
+        hipLaunchKernelGGL((k_srrsc<MB, RG, OFF, true>), g, blk, 0, s, jobs, start, njobs, b,
+                           tol, rmax);
     else
-        hipLaunchKernelGGL((k_srrsc<MB, RG, OFF, false>), g, blk, 0, s, K, b, p, D, zhat, cbase,
-                           coff, scale, tol, rmax, out);
+        hipLaunchKernelGGL((k_srrsc<MB, RG, OFF, false>), g, blk, 0, s, jobs, start, njobs, b,
+                           tol, rmax);
     return hipGetLastError();
 }
 
-// The SRRSC instance that fits: column offsets present (merge nodes, b up to
-// MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); the smallest LDS
-// capacity that holds b (two workgroups per CU up to b = 1024), with the rows
-// split among 4 or 2 thread groups when b <= 256 or 512; store or count only.
+// The smallest LDS capacity that holds b (two workgroups per CU up to
+// b = 1024), with the rows split among 4 or 2 thread groups when b <= 256 or
+// 512.
 template <bool OFF>
-hipError_t launch_srrsc_off(int K, int b, int p, const double* D, const double* zhat,
-                            const double* cbase, const double* coff, const double* scale,
-                            double tol, int rmax, bool store, const SrrscOut& out,
-                            hipStream_t s) {
+hipError_t launch_srrsc_off(const SrrscJob* jobs, const int* start, int njobs, int blocks,
+                            int b, double tol, int rmax, bool store, hipStream_t s) {
     if (b <= 256)
-        return launch_srrsc_mb<256, 4, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax,
-                                            store, out, s);
+        return launch_srrsc_mb<256, 4, OFF>(jobs, start, njobs, blocks, b, tol, rmax, store, s);
     if (b <= 512)
-        return launch_srrsc_mb<512, 2, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax,
-                                            store, out, s);
+        return launch_srrsc_mb<512, 2, OFF>(jobs, start, njobs, blocks, b, tol, rmax, store, s);
     if (b <= 1024)
-        return launch_srrsc_mb<1024, 1, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax,
-                                             store, out, s);
+        return launch_srrsc_mb<1024, 1, OFF>(jobs, start, njobs, blocks, b, tol, rmax, store,
+                                             s);
     if (b <= MAX_B_OFF)
-        return launch_srrsc_mb<MAX_B_OFF, 1, OFF>(K, b, p, D, zhat, cbase, coff, scale, tol,
-                                                  rmax, store, out, s);
+        return launch_srrsc_mb<MAX_B_OFF, 1, OFF>(jobs, start, njobs, blocks, b, tol, rmax,
+                                                  store, s);
     if constexpr (!OFF)
-        return launch_srrsc_mb<MAX_B_GEN, 1, false>(K, b, p, D, zhat, cbase, coff, scale, tol,
-                                                    rmax, store, out, s);
+        return launch_srrsc_mb<MAX_B_GEN, 1, false>(jobs, start, njobs, blocks, b, tol, rmax,
+                                                    store, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_srrsc(int K, int b, int p, const double* D, const double* zhat,
-                        const double* cbase, const double* coff, const double* scale,
-                        double tol, int rmax, bool store, const SrrscOut& out, hipStream_t s) {
-    if (coff && b > MAX_B_OFF) return hipErrorInvalidValue;
+hipError_t launch_srrsc(const SrrscJob* jobs, const int* start, int njobs, int blocks, int b,
+                        bool offsets, double tol, int rmax, bool store, hipStream_t s) {
+    if (offsets && b > MAX_B_OFF) return hipErrorInvalidValue;
     if (b > MAX_B_GEN) return hipErrorInvalidValue;
-    return coff ? launch_srrsc_off<true>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax, store,
-                                         out, s)
-                : launch_srrsc_off<false>(K, b, p, D, zhat, cbase, coff, scale, tol, rmax, store,
-                                          out, s);
+    if (blocks <= 0 || njobs <= 0) return hipSuccess;
+    return offsets ? launch_srrsc_off<true>(jobs, start, njobs, blocks, b, tol, rmax, store, s)
+                   : launch_srrsc_off<false>(jobs, start, njobs, blocks, b, tol, rmax, store, s);
+}
+
+// A job list in device memory: `dev` holds job_bytes(n) bytes; the list and
+// the block prefix are uploaded, and the grid's block count returned.
+size_t job_bytes(size_t n) {
+    return al(n * sizeof(SrrscJob)) + al((n + 1) * sizeof(int));
+}
+
+hipError_t upload_jobs(const std::vector<SrrscJob>& jobs, char* dev, hipStream_t s,
+                       const SrrscJob** jobs_dev, const int** start_dev, int* blocks) {
+    const size_t n = jobs.size();
+    std::vector<int> start(n + 1, 0);
+    for (size_t i = 0; i < n; ++i) start[i + 1] = start[i] + jobs[i].p * jobs[i].p;
+    std::vector<char> h(job_bytes(n));
+    const size_t so = al(n * sizeof(SrrscJob));
+    if (n) std::memcpy(h.data(), jobs.data(), n * sizeof(SrrscJob));
+    std::memcpy(h.data() + so, start.data(), (n + 1) * sizeof(int));
+    *jobs_dev = reinterpret_cast<const SrrscJob*>(dev);
+    *start_dev = reinterpret_cast<const int*>(dev + so);
+    *blocks = start[n];
+    return dc_upload(dev, h.data(), h.size(), s);
 }
 
 // coff == nullptr: plain column nodes w_j = cbase_j.
@@ -370,11 +408,12 @@ size_t compress_bytes(int K, int b) {
            al(p2 * rmax * sizeof(double)) + al(p2 * (size_t)b * sizeof(double));
 }
 
-// SRRSC of every off-diagonal block into `dev` (compress_bytes(K, b) bytes);
-// the caller reads the ranks back (Cm.rank is sized for them).
-hipError_t compress_launch(int K, int b, double tol, const double* D, const double* zhat,
-                           const double* cbase, const double* coff, const double* scale,
-                           hipStream_t s, Compressed& Cm, char* dev) {
+// The SRRSC job of every off-diagonal block, its output in `dev`
+// (compress_bytes(K, b) bytes); the caller launches it and reads the ranks
+// back (Cm.rank is sized for them).
+SrrscJob compress_prepare(int K, int b, const double* D, const double* zhat,
+                          const double* cbase, const double* coff, const double* scale,
+                          Compressed& Cm, char* dev) {
     Cm.b = b;
     Cm.p = (K + b - 1) / b;
     Cm.rmax = std::min(MAX_R, std::max(1, b / 2));
@@ -384,16 +423,14 @@ hipError_t compress_launch(int K, int b, double tol, const double* D, const doub
     const size_t o_prow = o; o = al(o + p2 * Cm.rmax * sizeof(int));
     const size_t o_pcol = o; o = al(o + p2 * Cm.rmax * sizeof(int));
     const size_t o_y = o; o = al(o + p2 * Cm.rmax * sizeof(double));
-    hipError_t err = hipSuccess;
     Cm.dev = dev;
     Cm.out.rank = reinterpret_cast<int*>(Cm.dev + o_rank);
     Cm.out.prow = reinterpret_cast<int*>(Cm.dev + o_prow);
     Cm.out.pcol = reinterpret_cast<int*>(Cm.dev + o_pcol);
     Cm.out.y = reinterpret_cast<double*>(Cm.dev + o_y);
     Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o);
-    err = launch_srrsc(K, b, Cm.p, D, zhat, cbase, coff, scale, tol, Cm.rmax, true, Cm.out, s);
     Cm.rank.resize(p2);
-    return err;
+    return SrrscJob{K, Cm.p, D, zhat, cbase, coff, scale, Cm.out};
 }
 
 // Device-side task list of one launch, with its tile prefix.
@@ -630,18 +667,32 @@ hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int 
     hipError_t err = arena_begin(A, s);
     // Every merge's compression output in its own part of one slot, so that
     // all of them are launched before their ranks come back together.
+    // One launch runs the blocks of every merge; its job list follows the
+    // outputs in the same slot.
+    const bool offsets = ms[0].coff != nullptr;
+    for (const LrMerge& M : ms)
+        if ((M.coff != nullptr) != offsets) return hipErrorInvalidValue;
     std::vector<size_t> off(ms.size() + 1, 0);
     for (size_t i = 0; i < ms.size(); ++i) off[i + 1] = off[i] + al(compress_bytes(ms[i].K, b));
     char* cdev = nullptr;
-    if (err == hipSuccess) err = arena_get(A, SL_SRRSC, off.back(), &cdev);
+    if (err == hipSuccess)
+        err = arena_get(A, SL_SRRSC, off.back() + job_bytes(ms.size()), &cdev);
     std::vector<Compressed> Cm(ms.size());
+    std::vector<SrrscJob> jobs;
     std::vector<DcRead> reads;
     for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
         const LrMerge& M = ms[i];
-        err = compress_launch(M.K, b, tol, M.D, M.zhat, M.cbase, M.coff, M.scale, s, Cm[i],
-                              cdev + off[i]);
+        jobs.push_back(compress_prepare(M.K, b, M.D, M.zhat, M.cbase, M.coff, M.scale, Cm[i],
+                                        cdev + off[i]));
         reads.push_back({Cm[i].rank.data(), Cm[i].out.rank, Cm[i].rank.size() * sizeof(int)});
     }
+    const SrrscJob* jd = nullptr;
+    const int* sd = nullptr;
+    int blocks = 0;
+    if (err == hipSuccess) err = upload_jobs(jobs, cdev + off.back(), s, &jd, &sd, &blocks);
+    if (err == hipSuccess)
+        err = launch_srrsc(jd, sd, (int)jobs.size(), blocks, b, offsets, tol, Cm[0].rmax, true,
+                           s);
     if (err == hipSuccess) err = dc_readback(reads, s);
     if (err != hipSuccess) return err;
 
@@ -856,30 +907,46 @@ extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
     }
     const int p = (K + lr_block - 1) / lr_block;
     const size_t p2 = (size_t)p * p;
+    const SrrscJob* jd = nullptr;
+    const int* sd = nullptr;
+    int blocks = 0;
     if (rank_cap == 0) {
         // the ranks the low-rank product itself uses
         Compressed Cm;
         char* cdev = nullptr;
+        const size_t cb_bytes = al(compress_bytes(K, lr_block));
         if (err == hipSuccess)
-            err = hipMallocAsync((void**)&cdev, compress_bytes(K, lr_block), stream);
-        if (err == hipSuccess)
-            err = compress_launch(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, stream, Cm,
-                                  cdev);
+            err = hipMallocAsync((void**)&cdev, cb_bytes + job_bytes(1), stream);
+        if (err == hipSuccess) {
+            const std::vector<SrrscJob> jobs{
+                compress_prepare(K, lr_block, Dbar, zhat, cb, co, scale, Cm, cdev)};
+            err = upload_jobs(jobs, cdev + cb_bytes, stream, &jd, &sd, &blocks);
+            if (err == hipSuccess)
+                err = launch_srrsc(jd, sd, 1, blocks, lr_block, co != nullptr, lr_tol, Cm.rmax,
+                                   true, stream);
+        }
         if (err == hipSuccess)
             err = dc_readback({{ranks_host, Cm.out.rank, p2 * sizeof(int)}}, stream);
         if (cdev) hipFreeAsync(cdev, stream);
     } else {
         // count only, up to rank_cap
-        int* rk = nullptr;
-        if (err == hipSuccess) err = hipMallocAsync((void**)&rk, p2 * sizeof(int), stream);
-        SrrscOut out{};
-        out.rank = rk;
+        char* rdev = nullptr;
+        const size_t rk_bytes = al(p2 * sizeof(int));
         if (err == hipSuccess)
-            err = launch_srrsc(K, lr_block, p, Dbar, zhat, cb, co, scale, lr_tol,
-                               std::min(rank_cap, lr_block), false, out, stream);
+            err = hipMallocAsync((void**)&rdev, rk_bytes + job_bytes(1), stream);
+        if (err == hipSuccess) {
+            SrrscOut out{};
+            out.rank = reinterpret_cast<int*>(rdev);
+            const std::vector<SrrscJob> jobs{SrrscJob{K, p, Dbar, zhat, cb, co, scale, out}};
+            err = upload_jobs(jobs, rdev + rk_bytes, stream, &jd, &sd, &blocks);
+            if (err == hipSuccess)
+                err = launch_srrsc(jd, sd, 1, blocks, lr_block, co != nullptr, lr_tol,
+                                   std::min(rank_cap, lr_block), false, stream);
+        }
         if (err == hipSuccess)
-            err = hipMemcpyAsync(ranks_host, rk, p2 * sizeof(int), hipMemcpyDeviceToHost, stream);
-        if (rk) hipFreeAsync(rk, stream);
+            err = hipMemcpyAsync(ranks_host, rdev, p2 * sizeof(int), hipMemcpyDeviceToHost,
+                                 stream);
+        if (rdev) hipFreeAsync(rdev, stream);
     }
     if (nodes) hipFreeAsync(nodes, stream);
     hipError_t e2 = hipStreamSynchronize(stream);
