@@ -68,10 +68,12 @@ def closed_form(family, n):
     return 2.0 - 2.0 * np.cos(k * np.pi / (n + 1))
 
 
-def gpu_accuracy(d, e, lam, Qbuf, family):
+def gpu_accuracy(d, e, lam, Qbuf, family, paper=True):
     """Eigenvalue error, residual and orthogonality of the last solve (GPU,
-    plain torch ops independent of the solver's kernels)."""
-    import numpy as np
+    plain torch ops independent of the solver's kernels), plus the paper's own
+    measures: ||I - Q Q^T||_max (Example 2) and ||A - Q Lambda Q^T||_c /
+    ||A||_2, the largest column 2-norm of the reconstruction error (Example 3),
+    with ||A||_2 from the closed-form spectrum."""
     import torch
     n = d.numel()
     ref = torch.tensor(closed_form(family, n), device="cuda")
@@ -88,17 +90,47 @@ def gpu_accuracy(d, e, lam, Qbuf, family):
     G.diagonal().sub_(1.0)
     orth = float(G.abs().max().item())
     del G
-    return {"eig_err_rel": eig, "residual": res, "orthogonality": orth}
+    out = {"eig_err_rel": eig, "residual": res, "orthogonality": orth}
+    if not paper:
+        return out
+    G = Qbuf.t() @ Qbuf                            # = Q Q^T (rows)
+    G.diagonal().sub_(1.0)
+    out["paper_orthogonality_rows"] = float(G.abs().max().item())
+    del G
+    # A - Q Lambda Q^T in column slabs: column j of A is tridiagonal
+    QL = Q * lam[None, :]
+    col_max = 0.0
+    step = 8192
+    for c0 in range(0, n, step):
+        c1 = min(n, c0 + step)
+        Rs = -(QL @ Qbuf[:, c0:c1])                 # -(Q Lambda Q^T)[:, c0:c1]
+        j = torch.arange(c0, c1, device="cuda")
+        Rs[j, j - c0] += d[c0:c1]
+        jm = j[j > 0]
+        Rs[jm - 1, jm - c0] += e[jm - 1]
+        jp = j[j < n - 1]
+        Rs[jp + 1, jp - c0] += e[jp]
+        col_max = max(col_max, float(torch.linalg.norm(Rs, dim=0).max().item()))
+        del Rs
+    del QL
+    out["paper_residual_colnorm"] = col_max / float(tn)
+    return out
 
 
 def cpu_baseline(family, n_full, n_sample, leaf):
-    """The oracle on the host cores: a full solve at n_sample, scaled by the
-    cubic flop ratio of divide and conquer to the benchmark's order.  With
-    n_sample = 0 the sample grows until it takes at least 10 s: solves at
-    n = 4000 and up (at most 1.5x per step, multiples of 250, capped at
-    16000), the last one reported.  Host speed and how the oracle's time
-    grows with n differ from box to box; orders with a large power-of-two
-    factor make the host BLAS thrash its caches, so none is used."""
+    """The oracle on the host cores, timed on a bounded sample: full solves
+    of the same family at growing orders n = 4000, ... (at most 1.5x per
+    step, multiples of 250, never a power of two, capped at 16000) until one
+    takes at least 10 s.  The time is carried to the benchmark's order with
+    the growth exponent measured between the last samples.  That exponent
+    rises toward 3 with n (the cubic merge product takes over from the
+    quadratic steps), so the carried figure understates the oracle's time at
+    n_full: it is a lower bound on the CPU time, i.e. it favours the CPU.  The
+    cubic carry, (n_full / n)^3, is an upper bound and is reported beside it.
+    Orders with a large power-of-two factor make the host BLAS thrash its
+    caches, so none is used.  n_sample > 0: one solve at that order, cubic
+    carry only."""
+    import math
     from threadpoolctl import threadpool_info
     from oracle import dc
     visited = []
@@ -125,14 +157,28 @@ def cpu_baseline(family, n_full, n_sample, leaf):
         t0 = time.perf_counter()
         dc.eigh_tridiagonal(d, e, leaf=leaf)
         dt = time.perf_counter() - t0
+        visited.append((n_sample, dt))
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    scale = (n_full / n_sample) ** 3
-    steps = "".join(f", n={m}: {t:.2f} s" for m, t in visited[:-1])
-    sizing = f" (smaller samples first{steps})" if len(visited) > 1 else ""
-    return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"full oracle solve of the {family} matrix at n={n_sample} "
-                      f"(leaf {leaf}) took {dt:.2f} s; scaled by (n/{n_sample})^3 = "
-                      f"{scale:.0f} to n={n_full}{sizing}",
+    cubic = dt * (n_full / n_sample) ** 3
+    if len(visited) >= 2:
+        # least-squares slope of log t over log n on the last three samples
+        pts = visited[-3:]
+        xs = [math.log(m) for m, _ in pts]
+        ys = [math.log(t) for _, t in pts]
+        xm, ym = sum(xs) / len(xs), sum(ys) / len(ys)
+        expo = sum((x - xm) * (y - ym) for x, y in zip(xs, ys)) / \
+            sum((x - xm) ** 2 for x in xs)
+        expo = min(3.0, max(1.0, expo))
+    else:
+        expo = 3.0
+    value = dt * (n_full / n_sample) ** expo
+    steps = ", ".join(f"n={m}: {t:.2f} s" for m, t in visited)
+    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"full oracle solves of the {family} matrix (leaf {leaf}): {steps}; "
+                      f"carried from n={n_sample} to n={n_full} with the measured growth "
+                      f"exponent {expo:.2f} (a lower bound on the oracle's time there: the "
+                      f"exponent rises toward 3 with n); the cubic carry gives {cubic:.1f} s",
+            "value_cubic_upper": cubic, "growth_exponent": expo,
             "sample_seconds": dt, "sample_n": n_sample}
 
 

@@ -20,10 +20,16 @@
  *  - Calls are asynchronous on the caller's stream.  Argument errors are
  *    detected synchronously on the host: the call returns -i for the i-th
  *    (1-based) invalid argument and launches nothing.  Errors the device
- *    detects are written to a device status word:
+ *    detects are written to a device status word (decoded by
+ *    dc_status_string; return codes are decoded by dc_strerror):
  *        0        success
- *        j > 0    secular root / leaf block j (1-based) did not converge
+ *        j > 0    an iteration did not converge; j - 1 is a row of the
+ *                 problem: the first row of the leaf block whose QR sweeps
+ *                 ran out, or the merge's first row plus the index of the
+ *                 first secular root that reached max_iter (for dc_secular
+ *                 alone: the root's index)
  *        -1000    a non-finite value in the input
+ *        -2000    equal eigenvalues met by the adjoint (dc_stedc_backward)
  *    The short forms keep that word in library-owned memory per stream
  *    (read it with dc_last_info after synchronising); the _ex forms write it
  *    to the caller's info_dev.
@@ -294,8 +300,12 @@ int dc_stedc_backward_rank1(int n, const double* lam, const double* Q, int ldq,
 /* Status word of the last short-form call on `stream`; synchronises it. */
 int dc_last_info(hipStream_t stream);
 
-/* Human-readable text for a return or status code. */
+/* Human-readable text for a return code: 0, -i (bad argument i) or a
+ * positive HIP runtime error code. */
 const char* dc_strerror(int code);
+
+/* Human-readable text for a device status word (0, j > 0, -1000, -2000). */
+const char* dc_status_string(int status);
 
 /*
  * dc_stats -- per-merge record of the last dc_stedc / dc_stedc_ex /

@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-* ``orthogonality``: max |Q^T Q - I| (the paper reports ||I - Q Q^T||_max).
+* ``orthogonality``: max |Q^T Q - I| (columns).
+* ``paper_orthogonality``: ||I - Q Q^T||_max, the paper's Example 2 measure.
 * ``residual``: ||T Q - Q diag(lam)||_F / (n ||T||), ||T|| := max |lam|.
 * ``eig_error``: max |lam - lam_ref| / ||T||.
 * ``paper_residual``: ||A - Q Lambda Q^T||_c / ||A||_2, ||X||_c the largest
@@ -41,10 +42,18 @@ def eig_error(lam, lam_ref):
 
 
 def paper_residual(d, e, lam, Q):
-    """||A - Q Lambda Q^T||_c / ||A||_2, formed densely (small n only)."""
-    d = np.asarray(d)
-    e = np.asarray(e)
+    """||A - Q Lambda Q^T||_c / ||A||_2 (the paper's Example 3 measure), with
+    ||X||_c the largest column 2-norm and ||A||_2 the spectral norm of the
+    tridiagonal A = T(d, e), both formed densely (small n only)."""
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
     A = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
-    R = A - (Q * lam[None, :]) @ Q.T
+    R = A - (Q * np.asarray(lam)[None, :]) @ Q.T
     col = np.sqrt((R * R).sum(axis=0)).max()
-    return float(col / (np.abs(lam).max() or 1.0))
+    return float(col / (np.linalg.norm(A, 2) or 1.0))
+
+
+def paper_orthogonality(Q):
+    """||I - Q Q^T||_max (the paper's Example 2 measure; rows, not columns)."""
+    n = Q.shape[0]
+    return float(np.abs(Q @ Q.T - np.eye(n)).max()) if n else 0.0

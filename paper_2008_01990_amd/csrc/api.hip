@@ -79,11 +79,18 @@ extern "C" int dc_last_info(hipStream_t stream) {
 
 extern "C" const char* dc_strerror(int code) {
     if (code == 0) return "success";
-    if (code == DC_STATUS_NONFINITE) return "non-finite value in the input";
-    if (code == DC_STATUS_EQUAL_EIG) return "equal eigenvalues: adjoint term dropped";
     if (code < 0) return "invalid argument (-code is its 1-based position)";
-    if (code > 0 && code < 1000) return hipGetErrorString((hipError_t)code);
-    return "a secular root or leaf block did not converge";
+    return hipGetErrorString((hipError_t)code);
+}
+
+extern "C" const char* dc_status_string(int status) {
+    if (status == 0) return "success";
+    if (status == DC_STATUS_NONFINITE) return "non-finite value in the input";
+    if (status == DC_STATUS_EQUAL_EIG) return "equal eigenvalues: adjoint term dropped";
+    if (status > 0)
+        return "an iteration did not converge (status - 1: first row of the leaf block, "
+               "or the merge's first row plus the secular root's index, in the problem)";
+    return "unknown status";
 }
 
 extern "C" int dc_secular(int K, const double* Dbar, const double* zbar, double rho, int* org,

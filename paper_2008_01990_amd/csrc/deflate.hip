@@ -186,7 +186,7 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
     Q.z = S.zbar + base;
     Q.K_p = &cnt->K;
     Q.K = 0;
-    Q.pad_ = 0;
+    Q.row0 = N.off;
     Q.rho_p = S.rho2 + slot;
     Q.rho = 0.0;
     Q.org = S.org + base;

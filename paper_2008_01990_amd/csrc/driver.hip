@@ -573,7 +573,7 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         DC_TRY(prof_mark(li, 3, s));
         DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
         DC_TRY(prof_mark(li, 4, s));
-        if (o.lr_tol > 0.0 && Lv.max_m > o.lr_min_k)
+        if (o.lr_tol > 0.0 && Lv.max_m >= o.lr_min_k)
             DC_TRY(lowrank_level(P, probs, S, Lv.first, Lv.nm, o, s));
         DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
                                      2 * Lv.nm, Lv.tiles, Lv.variant, s));

@@ -182,7 +182,7 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         ev = set_lane(ev, hi - 1, x);
         if (zrow) Z[hi * LD + lane] = zc;
     }
-    if (failed && lane == 0) dc_set_info(P.info, 1 + P.row0 + off);
+    if (failed && lane == 0) dc_set_info(P.info, 1 + off);
     dv *= unscale;
     if (lane < nl) sd[lane] = dv;
     __syncthreads();

@@ -244,7 +244,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                 if (!done) {
                     if (iters > max_iter) {
                         done = true;
-                        dc_set_info(T.info, j + 1);
+                        dc_set_info(T.info, T.row0 + j + 1);
                     } else {
                         // Pole offsets in the (possibly new) origin frame.
                         const double Dn = (org == j) ? (last ? De1 : De0) : De1;

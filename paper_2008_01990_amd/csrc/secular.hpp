@@ -8,7 +8,8 @@ struct SecTask {
     const double* z;      // weights
     const int* K_p;       // device size, or null (= K)
     int K;
-    int pad_;
+    int row0;             // first row of the merge inside its problem: a root j
+                          // that does not converge reports status row0 + j + 1
     const double* rho_p;  // device rho, or null (= rho)
     double rho;
     int* org;             // out: origin pole of each root

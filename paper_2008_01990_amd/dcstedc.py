@@ -12,6 +12,7 @@ come back as the transpose of a row-major (n, ld) buffer.
 
 import ctypes
 import os
+import warnings
 
 import torch
 
@@ -60,6 +61,7 @@ SIGNATURES = [
     ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
     ("dc_last_info", c_int, [P]),
     ("dc_strerror", ctypes.c_char_p, [c_int]),
+    ("dc_status_string", ctypes.c_char_p, [c_int]),
     ("dc_last_stats", c_int, [ctypes.POINTER(MergeStat), c_int]),
     ("dc_profile_enable", c_int, [c_int]),
     ("dc_profile_read", c_int, [P, c_int]),
@@ -101,6 +103,11 @@ def _check(rc, what):
     if rc != 0:
         msg = load().dc_strerror(rc).decode()
         raise DcError(f"{what} returned {rc}: {msg}")
+
+
+def status_string(status):
+    """Text of a device status word (dc_status_string)."""
+    return load().dc_status_string(int(status)).decode()
 
 
 def _stream():
@@ -205,7 +212,7 @@ def stedc(d, e, **kw):
     lam, Q = s(d, e)
     st = s.status()
     if st != 0:
-        raise DcError(f"device status {st}: {load().dc_strerror(st).decode()}")
+        raise DcError(f"device status {st}: {status_string(st)}")
     return lam, Q
 
 
@@ -262,7 +269,7 @@ def secular(D, z, rho, max_iter=200):
            "dc_secular")
     st = int(info.item())
     if st != 0:
-        raise DcError(f"dc_secular device status {st}")
+        raise DcError(f"dc_secular device status {st}: {status_string(st)}")
     return org, tau, zhat, scale
 
 
@@ -369,7 +376,7 @@ class EighTridiagonal(torch.autograd.Function):
         s.solve_into(lam, ee, Qbuf)
         st = s.status()
         if st != 0:
-            raise DcError(f"device status {st}: {load().dc_strerror(st).decode()}")
+            raise DcError(f"device status {st}: {status_string(st)}")
         ctx.save_for_backward(lam, Qbuf)
         return lam.clone(), from_colmajor(Qbuf, n)
 
@@ -379,6 +386,13 @@ class EighTridiagonal(torch.autograd.Function):
         lb = lam_bar.contiguous() if lam_bar is not None else None
         qb = Q_bar.t().contiguous() if Q_bar is not None else None
         d_bar, e_bar = backward(lam, Qbuf, lb, qb)
+        st = backward_status()                 # waits for the backward kernels
+        if st == -2000:
+            warnings.warn("eigh_tridiagonal backward: equal eigenvalues, the terms "
+                          "1 / (lam_j - lam_i) of such pairs were dropped "
+                          "(the gradient is not defined there)", RuntimeWarning)
+        elif st != 0:
+            raise DcError(f"dc_stedc_backward device status {st}: {status_string(st)}")
         return d_bar, e_bar, None, None, None, None
 
 

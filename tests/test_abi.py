@@ -62,6 +62,12 @@ def test_host_side_argument_checks_need_no_gpu():
                                       fake, None) == -9
     assert lib.dc_autotune(-1, None) == -1
     assert lib.dc_strerror(0) == b"success"
+    # return codes and status words have separate decoders: a positive
+    # return code is a HIP error, a positive status a non-convergence
+    assert b"converge" not in lib.dc_strerror(1)
+    assert b"converge" in lib.dc_status_string(1)
+    assert b"non-finite" in lib.dc_status_string(-1000)
+    assert b"equal eigenvalues" in lib.dc_status_string(-2000)
     o = dcstedc.DcOpts()
     lib.dc_opts_default(ctypes.byref(o))
     assert o.leaf == 32 and o.lr_tol == 0.0

@@ -109,3 +109,30 @@ def test_autograd_against_finite_differences(lib):
             ad.append(grad[idx])
     fd, ad = np.array(fd), np.array(ad)
     assert _rel(ad, fd) <= 1e-6
+
+
+def test_equal_eigenvalues_set_status_and_warn(lib):
+    # The adjoint of a decomposition with two equal eigenvalues has no
+    # F_ij = 1 / (lam_j - lam_i) for that pair: the term is dropped and the
+    # status word says so (-2000); the autograd backward turns it into a
+    # warning.  lam = 1, 2, 2, 3, ... with an orthogonal Q from a QR.
+    n = 64
+    announce("adjoint equal eigenvalues status")
+    rng = np.random.default_rng(9)
+    lam = cuda(np.concatenate([[1.0, 2.0, 2.0], 3.0 + np.arange(n - 3)]))
+    Q = cuda(np.linalg.qr(rng.standard_normal((n, n)))[0])
+    Qbar = cuda(rng.standard_normal((n, n)))
+    lib.backward(lam, Q.t().contiguous(), None, Qbar.t().contiguous())
+    assert lib.backward_status() == -2000
+    assert "equal eigenvalues" in lib.status_string(-2000)
+    # distinct eigenvalues: clean status
+    lib.backward(lam + cuda(np.arange(n) * 1e-3), Q.t().contiguous(), None,
+                 Qbar.t().contiguous())
+    assert lib.backward_status() == 0
+    # through autograd: a diagonal matrix with a repeated entry has exactly
+    # equal eigenvalues, and the backward warns
+    d = cuda(np.array([1.0, 2.0, 2.0, 3.0, 5.0])).requires_grad_(True)
+    e = cuda(np.zeros(4)).requires_grad_(True)
+    lamg, Qg = lib.eigh_tridiagonal(d, e, leaf=32)
+    with pytest.warns(RuntimeWarning, match="equal eigenvalues"):
+        (Qg.sum(0) ** 2).sum().backward()

@@ -26,8 +26,11 @@ def _gens(K, seed):
     return D, secular.solve_rank_one(D, z, rho)
 
 
+# (2048, 4096, 256): p = 16 blocks per side, 240 compressed blocks in one
+# job, block rows whose skeleton columns span several product tiles.
 @pytest.mark.parametrize("m,K,b,tol,seed", [(700, 1000, 256, 1e-10, 0),
-                                           (333, 777, 128, 1e-8, 1)])
+                                           (333, 777, 128, 1e-8, 1),
+                                           (2048, 4096, 256, 1e-10, 2)])
 def test_lowrank_merge_update_within_tolerance(lib, m, K, b, tol, seed):
     announce(f"lowrank merge_update m={m} K={K} b={b} tol={tol}")
     D, (org, tau, zhat, s) = _gens(K, seed)
@@ -190,3 +193,46 @@ def test_lowrank_solve_at_extreme_scales(lib, k):
     assert any(r["path"] == 1 for r in lib.last_stats())
     assert np.array_equal(host(lam_s), lam * f)
     assert np.array_equal(host(Q_s), Q)
+
+
+def test_lowrank_solve_level_jobs_against_oracle(lib):
+    # 1-2-1 Toeplitz n = 8192, b = 256, switch at K >= 2048: the two merges
+    # of level 1 (K = 4096, p = 16 each) share one compression launch (a job
+    # list of two) and one skeleton and one fused launch; the root (K = 4096)
+    # follows.  Compared with the oracle's own low-rank solve at the same
+    # block size and switch: eigenvalues within 1e-11 ||T|| (each side's U is
+    # within tol of the exact U entry by entry, so eigenvalues move at the
+    # 1e-10 scale at most), residual and orthogonality within 1e-9.
+    n = 8192
+    d, e = W.toeplitz(n)
+    kw = dict(leaf=64, lr_tol=1e-10, lr_block=256, lr_min_k=2048)
+    announce("lowrank stedc toeplitz n=8192 vs oracle low-rank solve")
+    lam, Q = lib.stedc(cuda(d), cuda(e), **kw)
+    stats = lib.last_stats()
+    lr = [r for r in stats if r["path"] == 1]
+    assert len(lr) == 3 and all(r["K"] >= 2048 for r in lr)
+    assert sum(r["level"] == 1 for r in lr) == 2
+    lam, Q = host(lam), host(Q)
+    lo, Qo = dc.eigh_tridiagonal(d, e, **kw)
+    k = np.arange(1, n + 1)
+    assert metrics.eig_error(lam, 2 - 2 * np.cos(k * np.pi / (n + 1))) <= 1e-13
+    assert np.abs(lam - lo).max() <= 1e-11 * np.abs(lo).max()
+    assert metrics.orthogonality(Q) <= 1e-9
+    assert metrics.residual(d, e, lam, Q) <= 1e-9
+    assert metrics.orthogonality(Qo) <= 1e-9
+
+
+def test_switch_at_exactly_lr_min_k(lib):
+    # Algorithm 3's switch is K >= lr_min_k per merge.  1-2-1 Toeplitz
+    # n = 2048: the two level-1 merges (m = 1024) do not deflate (K = m), so
+    # with lr_min_k = 1024 they take the low-rank product although no merge
+    # of their level is larger than the switch.
+    d, e = W.toeplitz(2048)
+    announce("lowrank switch at K == lr_min_k")
+    lam, Q = lib.stedc(cuda(d), cuda(e), leaf=64, lr_tol=1e-10, lr_block=256, lr_min_k=1024)
+    lvl1 = [r for r in lib.last_stats() if r["level"] == 1]
+    assert len(lvl1) == 2 and all(r["m"] == 1024 and r["K"] == 1024 for r in lvl1)
+    assert all(r["path"] == 1 for r in lvl1)
+    lam, Q = host(lam), host(Q)
+    assert metrics.orthogonality(Q) <= 1e-9
+    assert metrics.residual(d, e, lam, Q) <= 1e-9

@@ -28,8 +28,10 @@ def _bound(Qnd, U):
     return 4 * U.shape[0] * EPS * (np.abs(Qnd) @ np.abs(U)) + 1e-300
 
 
+# (4096, 4096): 32 x 32 tiles of 128 x 128, more than 8 groups of 64 tiles,
+# so the tile order within the task is the transposed (spread) one.
 @pytest.mark.parametrize("m,K,seed", [(517, 300, 0), (256, 128, 1), (1, 1, 2), (33, 7, 3),
-                                      (1000, 515, 4)])
+                                      (1000, 515, 4), (4096, 4096, 5), (4100, 3001, 6)])
 def test_plain_merge_update_matches_oracle(lib, m, K, seed):
     announce(f"merge_update m={m} K={K} seed={seed}")
     D, z, rho = W.random_secular(K, seed=seed)

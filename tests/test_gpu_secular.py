@@ -17,9 +17,11 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
 
 
+# K = 3000 and 4097: several 1024-pole chunks per sweep (and a ragged last one)
 @pytest.mark.parametrize("K,seed,cluster", [(1, 0, False), (2, 1, False), (63, 2, False),
                                             (700, 3, False), (300, 4, True), (200, 5, True),
-                                            (256, 6, False)])
+                                            (256, 6, False), (3000, 7, False),
+                                            (4097, 8, True)])
 def test_secular_matches_oracle(lib, K, seed, cluster):
     announce(f"secular K={K} seed={seed} cluster={cluster}")
     D, z, rho = W.random_secular(K, seed=seed, cluster=cluster)
@@ -38,3 +40,23 @@ def test_secular_matches_oracle(lib, K, seed, cluster):
     assert np.allclose(g_s, o_s, rtol=1e-12, atol=0)
     U = secular.cauchy_matrix(D, g_org, g_tau, g_zhat, g_s)
     assert np.abs(U.T @ U - np.eye(K)).max() <= 1e-13
+
+
+def test_secular_max_iter_one_sets_status(lib):
+    # A one-iteration cap: the kernel stops the unconverged roots and the
+    # status word holds the first one's 1-based index.
+    K = 500
+    D, z, rho = W.random_secular(K, seed=11)
+    announce("secular max_iter=1 status")
+    Dd, zd = cuda(D), cuda(z)
+    org = torch.empty(K, dtype=torch.int32, device="cuda")
+    tau, zhat, s = (torch.empty(K, dtype=torch.float64, device="cuda") for _ in range(3))
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L = lib.load()
+    rc = L.dc_secular(K, lib._ptr(Dd), lib._ptr(zd), float(rho), lib._ptr(org), lib._ptr(tau),
+                      lib._ptr(zhat), lib._ptr(s), lib._ptr(info), 1, lib._stream())
+    assert rc == 0
+    st = int(info.item())
+    assert 1 <= st <= K, st
+    with pytest.raises(lib.DcError):
+        lib.secular(D, z, rho, max_iter=1)
