@@ -297,6 +297,25 @@ int dc_stedc_backward_rank1(int n, const double* lam, const double* Q, int ldq,
                             const double* g, double* d_bar, double* e_bar,
                             hipStream_t stream);
 
+/*
+ * dc_stedc_backward_rank1_noalloc -- dc_stedc_backward_rank1 for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * training or serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and result, plus the caller's device status word info_dev
+ * (cleared, then -2000 on equal eigenvalues).  It allocates nothing: its
+ * scratch (the partial band sums, Q^T u and a flag) is a fixed 16 MiB device
+ * array per GPU, held until the process ends, which limits n to 4712
+ * (dc_stedc_backward_rank1_noalloc_max_bytes() gives the size; a larger n
+ * returns -1 and launches nothing).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (on different streams or host threads) race
+ * and must be ordered by the caller.
+ */
+int dc_stedc_backward_rank1_noalloc(int n, const double* lam, const double* Q, int ldq,
+                                    const double* lam_bar, const double* u,
+                                    const double* g, double* d_bar, double* e_bar,
+                                    int* info_dev, hipStream_t stream);
+size_t dc_stedc_backward_rank1_noalloc_max_bytes(void);
+
 /* Status word of the last short-form call on `stream`; synchronises it. */
 int dc_last_info(hipStream_t stream);
 

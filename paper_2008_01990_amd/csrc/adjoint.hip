@@ -22,6 +22,8 @@
 // Nothing of the forward tree is stored or recomputed: the final (lam, Q) is
 // all the adjoint reads.
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -428,4 +430,80 @@ extern "C" int dc_stedc_backward_rank1(int n, const double* lam, const double* Q
                            o_parts, o_flag, status, stream);
     hipError_t e2 = hipFreeAsync(tmp, stream);
     return (int)(err != hipSuccess ? err : e2);
+}
+
+// ---- Allocation-free rank-one adjoint ----
+// The scratch of dc_stedc_backward_rank1 (the partial band sums, a = Q^T u
+// and the equal-eigenvalue flag) in one fixed device array.  On the host its
+// name is only a stand-in for the symbol: kernels receive the device address
+// that hipGetSymbolAddress returns, looked up once per device.
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH = (size_t)16 << 20;     // 16 MiB per device
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;
+
+hipError_t scratch_address(char** out) {
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return err;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+    *out = static_cast<char*>(p);
+    return hipSuccess;
+}
+
+// Scratch bytes of the rank-one adjoint of order n (flag, partial sums, a).
+size_t rank1_scratch_bytes(int n, size_t* o_parts, size_t* o_a) {
+    size_t o = al(sizeof(int));
+    *o_parts = o;
+    o = al(o + parts_bytes(n));
+    *o_a = o;
+    return al(o + (size_t)n * sizeof(double));
+}
+
+}  // namespace
+
+extern "C" size_t dc_stedc_backward_rank1_noalloc_max_bytes(void) { return NOALLOC_SCRATCH; }
+
+extern "C" int dc_stedc_backward_rank1_noalloc(int n, const double* lam, const double* Q,
+                                               int ldq, const double* lam_bar,
+                                               const double* u, const double* g,
+                                               double* d_bar, double* e_bar, int* info_dev,
+                                               hipStream_t stream) {
+    if (n < 0) return -1;
+    if (!info_dev) return -10;
+    if (n == 0) return (int)dc_fill_int(info_dev, 1, 0, stream);
+    if (!lam) return -2;
+    if (!Q) return -3;
+    if (ldq < n) return -4;
+    if (!u) return -6;
+    if (!g) return -7;
+    if (!d_bar) return -8;
+    if (n > 1 && !e_bar) return -9;
+    size_t o_parts = 0, o_a = 0;
+    if (rank1_scratch_bytes(n, &o_parts, &o_a) > NOALLOC_SCRATCH) return -1;
+    char* tmp = nullptr;
+    hipError_t err = scratch_address(&tmp);
+    if (err != hipSuccess) return (int)err;
+    err = dc_fill_int(info_dev, 1, 0, stream);
+    if (err != hipSuccess) return (int)err;
+    double* a = reinterpret_cast<double*>(tmp + o_a);
+    hipLaunchKernelGGL(k_gemv_t, dim3((n + 3) / 4), dim3(256), 0, stream, Q, (long long)ldq, u,
+                       a, n);
+    err = hipGetLastError();
+    if (err == hipSuccess)
+        err = band_product(n, lam, Q, ldq, lam_bar, nullptr, 0, a, g, d_bar, e_bar, tmp,
+                           o_parts, 0, info_dev, stream);
+    return (int)err;
 }

@@ -59,6 +59,8 @@ SIGNATURES = [
     ("dc_autotune_lowrank", c_int, [c_int, P, c_int, P, P]),
     ("dc_stedc_backward", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P]),
     ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
+    ("dc_stedc_backward_rank1_noalloc", c_int, [c_int, P, P, c_int, P, P, P, P, P, P, P]),
+    ("dc_stedc_backward_rank1_noalloc_max_bytes", c_size_t, []),
     ("dc_last_info", c_int, [P]),
     ("dc_strerror", ctypes.c_char_p, [c_int]),
     ("dc_status_string", ctypes.c_char_p, [c_int]),
