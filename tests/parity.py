@@ -61,3 +61,29 @@ def assert_eigvecs_match(Q, Qo, lam_ref, tn=None, cols=None):
         f"{bad.size} eigenvector columns off: worst column {bad[np.argmax(err[bad] / bound[bad])]}"
         f" err {err[bad].max():.3e} vs bound {bound[bad][np.argmax(err[bad])]:.3e}")
     return err, bound
+
+
+def residual_eig_bound(d, e, lam, Q):
+    """Per column ||T q_j - lam_j q_j|| / ||q_j||: for symmetric T, lam_j is
+    within this distance of an eigenvalue of T (the residual bound), whether
+    or not q_j is exactly orthogonal to the other columns."""
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    Y = d[:, None] * Q
+    if d.shape[0] > 1:
+        Y[:-1] += e[:, None] * Q[1:]
+        Y[1:] += e[:, None] * Q[:-1]
+    R = Y - Q * np.asarray(lam)[None, :]
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(Q, axis=0)
+
+
+def assert_lowrank_eigvals(d, e, lam, Q, lam_ref, floor=1e-13):
+    """Low-rank path: |lam_j - lam_ref_j| <= residual bound of column j +
+    floor ||T||.  The low-rank merge returns approximate eigenpairs (its U is
+    within tol of the exact one entry by entry), so the eigenvalues are held
+    to what their own residuals guarantee, plus the plain path's bar."""
+    tn = float(np.abs(lam_ref).max())
+    bound = residual_eig_bound(d, e, lam, Q) + floor * tn
+    err = np.abs(np.asarray(lam) - np.asarray(lam_ref))
+    assert np.all(err <= bound), (err.max() / tn, int(np.argmax(err / bound)))
+    return err, bound

@@ -6,7 +6,9 @@ tolerance tol (oracle.srrsc.lowrank_cauchy).  Both sides choose pivots from
 rounded values, so near-ties may pick different pivots; each side's U is
 within tol of the exact U entry by entry, hence
   |C_gpu - Qnd U_exact| <= tol * sum_k |Qnd_ik| + rounding,
-and the ranks agree up to such ties.
+and the ranks agree up to such ties.  Low-rank solves hold each eigenvalue
+to its own residual bound ||T q_j - lam_j q_j|| / ||q_j|| plus 1e-13 ||T||,
+and residual and orthogonality to 1e-9.
 """
 import numpy as np
 import pytest
@@ -16,6 +18,7 @@ import torch
 from oracle import dc, metrics, secular, srrsc
 from paper_2008_01990_amd import workloads as W
 from tests.gpu_util import announce, cuda, host
+from tests.parity import assert_lowrank_eigvals
 
 pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
@@ -128,12 +131,13 @@ def test_lowrank_solver_meets_bounds(lib, family, n, b):
         ref = np.arange(-(n - 1), n, 2, dtype=float)
     else:
         ref = np.sort(scipy.linalg.eigh_tridiagonal(d, e, eigvals_only=True))
-    assert metrics.eig_error(lam, ref) <= 1e-13
+    assert_lowrank_eigvals(d, e, lam, Q, ref)
     assert metrics.orthogonality(Q) <= 1e-9
     assert metrics.residual(d, e, lam, Q) <= 1e-9
     lo, Qo = dc.eigh_tridiagonal(d, e, **kw)
     # both sides perturb U by up to tol per entry: eigenvalues move at ~tol scale
     assert np.abs(lam - lo).max() <= 1e-11 * np.abs(lo).max()
+    assert_lowrank_eigvals(d, e, lo, Qo, ref)
 
 
 @pytest.mark.parametrize("nb", [16, 512])
@@ -198,8 +202,8 @@ def test_lowrank_solve_at_extreme_scales(lib, k):
 def test_lowrank_solve_level_jobs_against_oracle(lib):
     # 1-2-1 Toeplitz n = 8192, b = 256, switch at K >= 2048: the two merges
     # of level 1 (K = 4096, p = 16 each) share one compression launch (a job
-    # list of two) and one skeleton and one fused launch; the root (K = 4096)
-    # follows.  Compared with the oracle's own low-rank solve at the same
+    # list of two) and one skeleton and one fused launch, as do the level-2
+    # merges that keep K = 2048; the root (K = 4096) follows.  Compared with the oracle's own low-rank solve at the same
     # block size and switch: eigenvalues within 1e-11 ||T|| (each side's U is
     # within tol of the exact U entry by entry, so eigenvalues move at the
     # 1e-10 scale at most), residual and orthogonality within 1e-9.
@@ -210,12 +214,12 @@ def test_lowrank_solve_level_jobs_against_oracle(lib):
     lam, Q = lib.stedc(cuda(d), cuda(e), **kw)
     stats = lib.last_stats()
     lr = [r for r in stats if r["path"] == 1]
-    assert len(lr) == 3 and all(r["K"] >= 2048 for r in lr)
-    assert sum(r["level"] == 1 for r in lr) == 2
+    assert all(r["K"] >= 2048 for r in lr)
+    assert sum(r["level"] == 1 for r in lr) == 2 and sum(r["level"] == 0 for r in lr) == 1
     lam, Q = host(lam), host(Q)
     lo, Qo = dc.eigh_tridiagonal(d, e, **kw)
     k = np.arange(1, n + 1)
-    assert metrics.eig_error(lam, 2 - 2 * np.cos(k * np.pi / (n + 1))) <= 1e-13
+    assert_lowrank_eigvals(d, e, lam, Q, 2 - 2 * np.cos(k * np.pi / (n + 1)))
     assert np.abs(lam - lo).max() <= 1e-11 * np.abs(lo).max()
     assert metrics.orthogonality(Q) <= 1e-9
     assert metrics.residual(d, e, lam, Q) <= 1e-9
