@@ -648,12 +648,13 @@ def main():
         for _ in range(args.warmup):
             lr_step()
         L.profile_enable(True)
-        lprof = []
+        lprof, lrprof = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             lr_step()
             lprof.append(L.profile_read())
+            lrprof.append(L.profile_read_lowrank())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         L.profile_enable(False)
@@ -672,13 +673,29 @@ def main():
             "root_product_ms": lr_top_ms,
             "root_product_speedup_vs_plain": top["product_ms"] / lr_top_ms,
             "merges": [dict(m=r["m"], K=r["K"], path=r["path"], flops=r["flops"],
+                            flops_skeleton=r["lr_flops_skeleton"],
+                            flops_fused=r["lr_flops_fused"],
                             blocks=r["lr_blocks"], dense=r["lr_dense"], rank_max=r["lr_rank_max"],
                             rank_mean=r["lr_rank_sum"] / max(r["lr_blocks"] - r["lr_dense"], 1))
                        for r in lstats if r["path"] == 1],
-            # the root merge's plain algorithmic flops over the low-rank
-            # product phase's time (compression included)
-            "root_plain_equivalent_tflops": flops_lvl[-1] / (lr_top_ms * 1e-3) / 1e12,
         }
+        # Roofline of the two MFMA launches of the low-rank product, summed
+        # over the levels that take it: executed flops (the skeleton columns
+        # W = A(:, I) U(I, T); the diagonal blocks plus the interpolation
+        # rows, 2 m (b^2 + b r) per block column) over their HIP-event times.
+        fl = {"skeleton": sum(r["lr_flops_skeleton"] for r in lstats if r["path"] == 1),
+              "fused": sum(r["lr_flops_fused"] for r in lstats if r["path"] == 1)}
+        stages = {}
+        for st in ("compress", "skeleton", "fused"):
+            t_ms = sum(sum(lv[st] for lv in p) for p in lrprof) / len(lrprof)
+            rec = {"ms": t_ms}
+            if st in fl:
+                tf = fl[st] / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
+                rec.update({"executed_flops": fl[st], "tflops": tf,
+                            "frac": tf / PEAK_FP64_MFMA_TFLOPS, "bound": "mfma",
+                            "peak": PEAK_FP64_MFMA_TFLOPS})
+            stages[st] = rec
+        out["lowrank"]["stages"] = stages
         if not args.no_accuracy:
             out["lowrank"]["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)
         if not args.no_extra:

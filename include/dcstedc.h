@@ -339,6 +339,10 @@ typedef struct dc_merge_stat {
     /* low-rank merges: off-diagonal blocks, sum and maximum of the ranks of
        the compressed ones, blocks kept dense (0 on the plain path) */
     int lr_blocks, lr_rank_sum, lr_rank_max, lr_dense;
+    /* low-rank merges: executed flops of the skeleton-column product and of
+       the fused product (diagonal blocks plus interpolation rows); their sum
+       is flops */
+    double lr_flops_skeleton, lr_flops_fused;
 } dc_merge_stat;
 
 /* Copies up to cap records into out (HOST); returns the number available. */
@@ -355,6 +359,11 @@ int dc_last_stats(dc_merge_stat* out, int cap);
  */
 int dc_profile_enable(int on);
 int dc_profile_read(double* ms, int cap);
+/* With profiling on: for each level, three durations in milliseconds of its
+ * low-rank product phase (compression and planning, skeleton-column
+ * product, fused product), 0 for levels without a low-rank merge; returns
+ * the number of levels. */
+int dc_profile_read_lowrank(double* ms, int cap);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,8 @@
 // (of every problem of a batch) form one level, processed as one launch per
 // phase:
 //   deflate -> rotate -> secular roots / Loewner / scales -> assemble
-//   -> generated-Cauchy product (top and bottom row halves) -> deflated copy.
+//   -> deflated copy -> [low-rank pipeline] -> generated-Cauchy product
+//   (top and bottom row halves).
 // Leaves run first, all in one launch.  A node's eigenvectors live in the
 // caller's Q when its depth is even and in the workspace partner B1 when it
 // is odd, so each merge reads its children from one buffer and writes the
@@ -14,8 +15,13 @@
 //
 // Nothing here synchronises with the device after the plan exists: the
 // level loop only launches kernels, with data-dependent sizes (the deflated
-// K of each merge) read by the kernels from device memory and grids sized
-// for the worst case.
+// K of each merge, the low-rank ranks) read by the kernels from device memory
+// and grids sized for the worst case or walking device-held tile counts.
+//
+// Merges whose order reaches the low-rank switch are candidates: each has
+// low-rank regions in the workspace sized by its order, and its skeleton
+// columns W go into its children's square of the ping-pong buffer, which is
+// dead once the deflated columns have been copied out of it.
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
@@ -41,6 +47,44 @@ struct Level {
     int off_tile, off_sec, off_row, off_copy, off_gather, off_rot;   // prefix offsets
 };
 
+// Low-rank candidates of one plan for one (block size, switch): merges whose
+// order reaches the switch and exceeds one block (and spans at most
+// DC_LR_MAX_PMAX blocks), in level order.  The
+// device table and the per-level SRRSC block prefixes are uploaded once; the
+// workspace offsets are relative to the low-rank part of the workspace.
+constexpr int DC_LR_MAX_PMAX = 3072;
+
+struct LrCand {
+    int merge;          // index of the merge (slot)
+    int pmax;           // ceil(m / b)
+    int task0;          // first task of the candidate in the task lists
+    int pad_;
+    long long reg;      // byte offset of its regions
+};
+
+struct LrLevel {
+    int first = 0, njobs = 0;      // candidates of the level
+    int srrsc_blocks = 0;          // sum of pmax^2
+    int start_off = 0;             // its SRRSC prefix in d_start (njobs + 1 ints)
+    int task0 = 0, ntasks = 0;     // its tasks in the task lists
+    int ts_off = 0;                // its tile prefix scratch (2 (ntasks + 1) ints)
+    int max_pmax = 0;
+};
+
+struct LrPlan {
+    int b = 0, min_k = 0;
+    std::vector<LrCand> cands;
+    std::vector<LrLevel> levels;   // one per plan level
+    std::vector<int> cand_of_merge;
+    size_t o_jobs = 0, o_tskel = 0, o_tfused = 0, o_ts = 0, o_tot = 0, o_reg = 0, bytes = 0;
+    LrCand* d_cands = nullptr;
+    int* d_start = nullptr;
+    ~LrPlan() {
+        if (d_cands) hipFree(d_cands);
+        if (d_start) hipFree(d_start);
+    }
+};
+
 struct Plan {
     std::vector<int> sizes;
     int leaf, tile;
@@ -54,6 +98,7 @@ struct Plan {
     Node* d_nodes = nullptr;            // leaves then merges
     int* d_prefix = nullptr;
     int device = -1;
+    std::map<std::pair<int, int>, std::unique_ptr<LrPlan>> lr;   // by (b, min_k)
     ~Plan() {
         if (d_nodes) hipFree(d_nodes);
         if (d_prefix) hipFree(d_prefix);
@@ -252,13 +297,66 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 // Workspace layout.
 struct Layout {
     size_t bytes = 0;
-    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, bufs;
+    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, bufs, lr;
     int nd = 16, ni = 14;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout layout(const Plan& P) {
+// Candidates, tasks and regions of the low-rank path for block b and switch
+// min_k (host side; the device tables are uploaded by get_lr_plan).
+std::unique_ptr<LrPlan> make_lr(const Plan& P, int b, int min_k, std::vector<int>* starts) {
+    auto L = std::make_unique<LrPlan>();
+    L->b = b;
+    L->min_k = min_k;
+    L->cand_of_merge.assign(P.merges.size(), -1);
+    L->levels.resize(P.levels.size());
+    int ntask = 0, ts = 0;
+    size_t reg = 0;
+    for (size_t li = 0; li < P.levels.size(); ++li) {
+        const Level& Lv = P.levels[li];
+        LrLevel& LL = L->levels[li];
+        LL.first = (int)L->cands.size();
+        LL.task0 = ntask;
+        LL.start_off = starts ? (int)starts->size() : 0;
+        int acc = 0;
+        for (int i = 0; i < Lv.nm; ++i) {
+            const Node& N = P.merges[Lv.first + i];
+            const int m = N.n1 + N.n2;
+            // (the planning kernel keeps 4 pmax ints of its block grid in LDS)
+            if (m < min_k || m <= b || (m + b - 1) / b > DC_LR_MAX_PMAX) continue;
+            LrCand c{};
+            c.merge = Lv.first + i;
+            c.pmax = (m + b - 1) / b;
+            c.task0 = ntask;
+            c.reg = (long long)reg;
+            reg += align256(dc_lowrank_region_bytes(c.pmax, b, m));
+            ntask += 2 * c.pmax;
+            if (starts) starts->push_back(acc);
+            acc += c.pmax * c.pmax;
+            LL.max_pmax = std::max(LL.max_pmax, c.pmax);
+            L->cand_of_merge[c.merge] = (int)L->cands.size();
+            L->cands.push_back(c);
+        }
+        LL.njobs = (int)L->cands.size() - LL.first;
+        if (starts && LL.njobs > 0) starts->push_back(acc);
+        LL.srrsc_blocks = acc;
+        LL.ntasks = ntask - LL.task0;
+        LL.ts_off = ts;
+        if (LL.njobs > 0) ts += 2 * (LL.ntasks + 1);
+    }
+    size_t o = 0;
+    L->o_jobs = o; o = align256(o + L->cands.size() * sizeof(LrJob));
+    L->o_tskel = o; o = align256(o + (size_t)ntask * sizeof(GemmTask));
+    L->o_tfused = o; o = align256(o + (size_t)ntask * sizeof(GemmTask));
+    L->o_ts = o; o = align256(o + (size_t)ts * sizeof(int));
+    L->o_tot = o; o = align256(o + 32 * P.levels.size() * sizeof(int));
+    L->o_reg = o; o += reg;
+    L->bytes = L->cands.empty() ? 0 : o;
+    return L;
+}
+
+Layout layout(const Plan& P, const LrPlan* LP = nullptr) {
     Layout L;
     size_t o = 0;
     const size_t nm = std::max<size_t>(P.merges.size(), 1);
@@ -272,8 +370,38 @@ Layout layout(const Plan& P) {
     L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
     L.ints = o; o = align256(o + L.ni * R * sizeof(int));
     L.bufs = o; o = align256(o + (P.buf_elems + P.pan_elems) * sizeof(double));
+    L.lr = o; o = align256(o + (LP ? LP->bytes : 0));
     L.bytes = o;
     return L;
+}
+
+// The low-rank tables of (plan, b, min_k), made and uploaded on first use
+// (synchronously: call the workspace query before capturing a graph).
+hipError_t get_lr_plan(Plan& P, int b, int min_k, LrPlan** out) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto key = std::make_pair(b, min_k);
+    auto it = P.lr.find(key);
+    if (it != P.lr.end()) {
+        *out = it->second.get();
+        return hipSuccess;
+    }
+    std::vector<int> starts;
+    auto L = make_lr(P, b, min_k, &starts);
+    hipError_t err = hipSuccess;
+    if (!L->cands.empty()) {
+        err = hipMalloc(&L->d_cands, L->cands.size() * sizeof(LrCand));
+        if (err == hipSuccess)
+            err = hipMemcpy(L->d_cands, L->cands.data(), L->cands.size() * sizeof(LrCand),
+                            hipMemcpyHostToDevice);
+        if (err == hipSuccess) err = hipMalloc(&L->d_start, starts.size() * sizeof(int));
+        if (err == hipSuccess)
+            err = hipMemcpy(L->d_start, starts.data(), starts.size() * sizeof(int),
+                            hipMemcpyHostToDevice);
+    }
+    if (err != hipSuccess) return err;
+    *out = L.get();
+    P.lr[key] = std::move(L);
+    return hipSuccess;
 }
 
 Scratch carve(const Plan& P, const Layout& L, char* w) {
@@ -302,244 +430,133 @@ __global__ void k_fill_int(int* p, int n, int v) {
 }
 
 // Optional instrumentation: HIP events on the caller's stream at the phase
-// boundaries of every level (deflate, rotate, secular, assemble, product,
-// deflated copy).  Off by default; never enabled under graph capture.
+// boundaries of every level, in launch order (deflate, rotate, secular,
+// assemble, deflated copy, product), and inside the product phase of a level
+// with low-rank merges (before the compression, the skeleton launch and the
+// fused launch, and after it).  Off by default; never enabled under graph
+// capture.
 constexpr int NPHASE = 6;
+constexpr int MARK_COPY = 4, MARK_PRODUCT = 5;   // marks before those phases
 bool g_prof = false;
-std::vector<hipEvent_t> g_ev;
+std::vector<hipEvent_t> g_ev, g_lr_ev;
+std::vector<char> g_lr_rec;            // level recorded its low-rank events
 int g_ev_levels = 0;
 
-hipError_t prof_mark(int level, int phase, hipStream_t s) {
-    if (!g_prof) return hipSuccess;
-    const size_t idx = (size_t)level * (NPHASE + 1) + phase;
-    while (g_ev.size() <= idx) {
+hipError_t prof_event(std::vector<hipEvent_t>& v, size_t idx, hipEvent_t* out) {
+    while (v.size() <= idx) {
         hipEvent_t ev;
         hipError_t err = hipEventCreate(&ev);
         if (err != hipSuccess) return err;
-        g_ev.push_back(ev);
+        v.push_back(ev);
     }
-    return hipEventRecord(g_ev[idx], s);
+    *out = v[idx];
+    return hipSuccess;
+}
+
+hipError_t prof_mark(int level, int phase, hipStream_t s) {
+    if (!g_prof) return hipSuccess;
+    hipEvent_t ev;
+    hipError_t err = prof_event(g_ev, (size_t)level * (NPHASE + 1) + phase, &ev);
+    return err == hipSuccess ? hipEventRecord(ev, s) : err;
+}
+
+// The four low-rank events of a level (null when not profiling).
+hipError_t prof_lr_events(int level, hipEvent_t* ev4, bool* on) {
+    *on = g_prof;
+    if (!g_prof) return hipSuccess;
+    for (int k = 0; k < 4; ++k) {
+        hipError_t err = prof_event(g_lr_ev, (size_t)level * 4 + k, &ev4[k]);
+        if (err != hipSuccess) return err;
+    }
+    if (g_lr_rec.size() <= (size_t)level) g_lr_rec.resize(level + 1, 0);
+    g_lr_rec[level] = 1;
+    return hipSuccess;
 }
 
 }  // namespace
 
-// Byte copies between device memory and mapped pinned host memory, as
-// kernels on the caller's stream (the runtime's host copies wait for their
-// completion before returning, which costs a host wake-up per copy).
-__global__ void k_copy_bytes(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src,
-                             size_t n) {
-    const size_t i0 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
-    if (i0 + 8 <= n && ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 7) == 0) {
-        *reinterpret_cast<uint64_t*>(dst + i0) = *reinterpret_cast<const uint64_t*>(src + i0);
-    } else {
-        for (size_t i = i0; i < n && i < i0 + 8; ++i) dst[i] = src[i];
-    }
-}
-
-// Stores seq into a pinned host word once every earlier kernel of the stream
-// has finished (stream order), for the host to spin on.
-__global__ void k_post_flag(volatile unsigned long long* flag, unsigned long long seq) {
-    if (threadIdx.x == 0) *flag = seq;
-}
-
-static hipError_t copy_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const size_t threads = (n + 7) / 8;
-    hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                       static_cast<unsigned char*>(dst), static_cast<const unsigned char*>(src),
-                       n);
-    return hipGetLastError();
-}
-
-// A pinned host buffer and its device-side address.
-static hipError_t pinned_alloc(size_t n, char** host, char** dev) {
-    hipError_t err = hipHostMalloc((void**)host, n, hipHostMallocMapped | hipHostMallocCoherent);
-    if (err != hipSuccess) return err;
-    err = hipHostGetDevicePointer((void**)dev, *host, 0);
-    if (err != hipSuccess) {
-        (void)hipHostFree(*host);
-        *host = nullptr;
-    }
-    return err;
-}
-
-hipError_t dc_readback(const std::vector<DcRead>& reads, hipStream_t s) {
-    thread_local char* pin = nullptr;
-    thread_local char* pin_dev = nullptr;
-    thread_local size_t cap = 0;
-    thread_local unsigned long long seq = 0;
-    size_t total = 256;                // the first 256 bytes hold the flag word
-    for (const DcRead& r : reads) total += (r.n + 255) & ~size_t(255);
-    if (total == 0) return hipSuccess;
-    hipError_t err = hipSuccess;
-    if (total > cap) {
-        // the previous batch is complete (every call waits before returning)
-        if (pin) (void)hipHostFree(pin);
-        pin = pin_dev = nullptr;
-        cap = 0;
-        const size_t want = std::max(total, size_t(1) << 20);
-        err = pinned_alloc(want, &pin, &pin_dev);
-        if (err != hipSuccess) return err;
-        *reinterpret_cast<volatile unsigned long long*>(pin) = 0;
-        cap = want;
-    }
-    size_t off = 256;
-    for (const DcRead& r : reads) {
-        err = copy_bytes(pin_dev + off, r.src, r.n, s);
-        if (err != hipSuccess) return err;
-        off += (r.n + 255) & ~size_t(255);
-    }
-    // Spin on the flag word: it is posted right after the copies finish.
-    // The stream is queried now and then, so a failed stream still returns.
-    volatile unsigned long long* flag = reinterpret_cast<volatile unsigned long long*>(pin);
-    const unsigned long long want = ++seq;
-    hipLaunchKernelGGL(k_post_flag, dim3(1), dim3(64), 0, s,
-                       reinterpret_cast<volatile unsigned long long*>(pin_dev), want);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    for (unsigned long spins = 1; *flag != want; ++spins) {
-        if (spins % 4096 == 0) {
-            err = hipStreamQuery(s);
-            if (err == hipSuccess) break;        // every kernel is done
-            if (err != hipErrorNotReady) return err;
-        }
-    }
-    off = 256;
-    for (const DcRead& r : reads) {
-        if (r.n > 0) std::memcpy(r.dst, pin + off, r.n);
-        off += (r.n + 255) & ~size_t(255);
-    }
-    return hipSuccess;
-}
-
-hipError_t dc_upload(void* dst, const void* src, size_t n, hipStream_t s) {
-    struct Chunk {
-        char* p;
-        char* dev;
-        size_t cap;
-        hipEvent_t ev;
-        bool used;
-    };
-    thread_local std::vector<Chunk> chunks;
-    if (n == 0) return hipSuccess;
-    Chunk* c = nullptr;
-    for (Chunk& k : chunks)
-        if (k.cap >= n && (!k.used || hipEventQuery(k.ev) == hipSuccess)) { c = &k; break; }
-    if (!c) {
-        Chunk k{nullptr, nullptr, std::max(n, size_t(1) << 20), nullptr, false};
-        hipError_t err = pinned_alloc(k.cap, &k.p, &k.dev);
-        if (err != hipSuccess) return err;
-        err = hipEventCreateWithFlags(&k.ev, hipEventDisableTiming);
-        if (err != hipSuccess) {
-            (void)hipHostFree(k.p);
-            return err;
-        }
-        chunks.push_back(k);
-        c = &chunks.back();
-    }
-    std::memcpy(c->p, src, n);
-    hipError_t err = copy_bytes(dst, c->dev, n, s);
-    if (err == hipSuccess) err = hipEventRecord(c->ev, s);
-    c->used = true;
-    return err;
-}
-
 namespace {
 
-// Per-merge product record of the last solve on this host thread:
-// path (0 plain, 1 low rank) and executed flops of low-rank merges.
-thread_local std::vector<int> t_path;
-thread_local std::vector<double> t_lr_flops;
-thread_local std::vector<LrRankSummary> t_lr_ranks;
-
-// Algorithm 3's switch: every merge of the level whose deflated size reaches
-// lr_min_k (and exceeds one block) gets the structured low-rank product; its
-// plain product tasks are then disabled.  Reads the level's sizes on the host.
-hipError_t lowrank_level(const Plan& P, const std::vector<Prob>& probs, const Scratch& S,
-                         int first, int nm, const dc_opts& o, hipStream_t s) {
-    std::vector<MergeCnt> cnt(nm);
-    hipError_t err = dc_readback({{cnt.data(), S.cnt + first, nm * sizeof(MergeCnt)}}, s);
-    if (err != hipSuccess) return err;
-    const int b = std::min(o.lr_block, dc_lowrank_max_block(true));
-    // The row lists of every merge that switches, fetched in one round trip.
-    std::vector<std::vector<LrHalf>> lr_halves(nm);
-    std::vector<DcRead> reads;
-    for (int i = 0; i < nm; ++i) {
-        const Node& N = P.merges[first + i];
-        const MergeCnt& C = cnt[i];
-        if (C.K < o.lr_min_k || C.K <= b) continue;
-        const Prob& pr = probs[N.prob];
-        const long long base = (long long)pr.row0 + N.off;
-        lr_halves[i].resize(2);
-        for (int h = 0; h < 2; ++h) {
-            LrHalf& H = lr_halves[i][h];
-            const int cntk = h ? C.nbot : C.ntop;
-            H.klist.resize(cntk);
-            if (cntk > 0)
-                reads.push_back({H.klist.data(), (h ? S.kbot : S.ktop) + base,
-                                 cntk * sizeof(int)});
-        }
+// The low-rank jobs of every candidate of the plan: the call's pointers
+// (problem buffers, scratch, workspace) and the candidate's regions.  W is
+// the candidate's square of its children's buffer.
+__global__ void k_lr_build(const LrCand* __restrict__ cands, int ncand,
+                           const Node* __restrict__ merges, Scratch S, char* regbase,
+                           LrJob* jobs, GemmTask* tskel, GemmTask* tfused, int b, int min_k) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncand) return;
+    const LrCand C = cands[c];
+    const Node N = merges[C.merge];
+    const Prob P = S.probs[N.prob];
+    const long long base = (long long)P.row0 + N.off;
+    const int m = N.n1 + N.n2;
+    long long ldo, ldi;
+    double* Qo = node_buf(P, N.depth, ldo);
+    double* Qi = node_buf(P, N.depth + 1, ldi);
+    MergeCnt* cnt = S.cnt + N.slot;
+    LrJob J;
+    memset(&J, 0, sizeof(J));
+    J.K_p = &cnt->K;
+    J.pmax = C.pmax;
+    J.min_k = min_k;
+    J.nh = 2;
+    J.D = S.Dbar + base;
+    J.zhat = S.zhat + base;
+    J.cbase = S.cbase + base;
+    J.coff = S.tau + base;
+    J.scale = S.scale + base;
+    for (int h = 0; h < 2; ++h) {
+        LrHalf& H = J.h[h];
+        const int r0 = h ? N.n1 : 0;
+        H.A = P.B2 + (long long)N.off * P.ld2 + N.off + r0;
+        H.lda = P.ld2;
+        H.rows = h ? N.n2 : N.n1;
+        H.r0 = r0;
+        H.klist = (h ? S.kbot : S.ktop) + base;
+        H.klen_p = h ? &cnt->nbot : &cnt->ntop;
+        H.gD = (h ? S.gDb : S.gDt) + base;
+        H.gz = (h ? S.gzb : S.gzt) + base;
+        H.C = Qo + (long long)N.off * ldo + N.off + r0;
+        H.ldc = ldo;
+        H.cpos = S.pos_root + base;
     }
-    err = dc_readback(reads, s);
-    if (err != hipSuccess) return err;
-    // Every switching merge of the level together: their compressions run
-    // back to back and their ranks come back in one round trip.
-    std::vector<LrMerge> ms;
-    std::vector<int> which;
-    for (int i = 0; i < nm; ++i) {
-        if (lr_halves[i].empty()) continue;
-        const Node& N = P.merges[first + i];
-        const MergeCnt& C = cnt[i];
-        const Prob& pr = probs[N.prob];
-        const long long base = (long long)pr.row0 + N.off;
-        long long ldo;
-        double* Qo = node_buf(pr, N.depth, ldo);
-        std::vector<LrHalf>& halves = lr_halves[i];
-        for (int h = 0; h < 2; ++h) {
-            LrHalf& H = halves[h];
-            const int r0 = h ? N.n1 : 0;
-            H.A = pr.B2 + (long long)N.off * pr.ld2 + N.off + r0;
-            H.lda = pr.ld2;
-            H.rows = h ? N.n2 : N.n1;
-            H.gD = (h ? S.gDb : S.gDt) + base;
-            H.gz = (h ? S.gzb : S.gzt) + base;
-            H.C = Qo + (long long)N.off * ldo + N.off + r0;
-            H.ldc = ldo;
-            H.cpos = S.pos_root + base;
-            H.w_row0 = r0;
-        }
-        LrMerge M;
-        M.K = C.K;
-        M.D = S.Dbar + base;
-        M.zhat = S.zhat + base;
-        M.cbase = S.cbase + base;
-        M.coff = S.tau + base;
-        M.scale = S.scale + base;
-        M.halves = std::move(halves);
-        M.wrows = N.n1 + N.n2;
-        ms.push_back(std::move(M));
-        which.push_back(i);
-    }
-    err = dc_lowrank_products(b, o.lr_tol, ms, 0, s);
-    if (err != hipSuccess) return err;
-    for (size_t q = 0; q < ms.size(); ++q) {
-        const Node& N = P.merges[first + which[q]];
-        err = dc_disable_tasks(S.gtask + 2 * N.slot, 2, &S.cnt[N.slot].pad_[0], s);
-        if (err != hipSuccess) return err;
-        t_path[N.slot] = 1;
-        t_lr_flops[N.slot] = ms[q].flops;
-        t_lr_ranks[N.slot] = ms[q].ranks;
-    }
-    return hipSuccess;
+    J.W = Qi + (long long)N.off * ldi + N.off;
+    J.ldw = ldi;
+    J.wrows = m;
+    J.wcap = m;
+    J.plain = S.gtask + 2 * N.slot;
+    J.zero = &cnt->pad_[0];
+    J.tskel = tskel + C.task0;
+    J.tfused = tfused + C.task0;
+    dc_lowrank_carve(J, regbase + C.reg, b, m);
+    jobs[c] = J;
 }
 
-hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
-                    const dc_opts& o, hipStream_t s) {
-    t_path.assign(P.merges.size(), 0);
-    t_lr_flops.assign(P.merges.size(), 0.0);
-    t_lr_ranks.assign(P.merges.size(), LrRankSummary{});
-    const Layout L = layout(P);
+// Algorithm 3's switch and the structured product for the candidates of one
+// level, all on the device (graph-capturable).
+hipError_t lowrank_level(const LrPlan& LP, int li, char* lrbase, double tol, hipStream_t s) {
+    const LrLevel& LL = LP.levels[li];
+    LrJob* jobs = reinterpret_cast<LrJob*>(lrbase + LP.o_jobs) + LL.first;
+    GemmTask* tskel = reinterpret_cast<GemmTask*>(lrbase + LP.o_tskel) + LL.task0;
+    GemmTask* tfused = reinterpret_cast<GemmTask*>(lrbase + LP.o_tfused) + LL.task0;
+    int* ts = reinterpret_cast<int*>(lrbase + LP.o_ts) + LL.ts_off;
+    int* tot = reinterpret_cast<int*>(lrbase + LP.o_tot) + 32 * li;
+    hipError_t err = dc_lowrank_decide(jobs, LL.njobs, LP.b, s);
+    if (err != hipSuccess) return err;
+    hipEvent_t ev[4];
+    bool prof = false;
+    err = prof_lr_events(li, ev, &prof);
+    if (err != hipSuccess) return err;
+    return dc_lowrank_level(jobs, LL.njobs, LP.d_start + LL.start_off, LL.srrsc_blocks, tskel,
+                            tfused, LL.ntasks, ts, tot, LP.b, tol, LL.max_pmax, true, s,
+                            prof ? ev : nullptr);
+}
+
+hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& probs,
+                    char* work, const dc_opts& o, hipStream_t s) {
+    const Layout L = layout(P, LP);
     Scratch S = carve(P, L, work);
+    char* lrbase = work + L.lr;
     hipError_t err = dc_launch_set_probs(probs.data(), (int)probs.size(), S.probs, s);
     if (err != hipSuccess) return err;
     // Exact power-of-two scaling of every problem to max(|d|, |e|) in [1, 2)
@@ -553,9 +570,22 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
         err = dc_launch_build(d_merges + Lv.first, Lv.nm, Lv.bm, Lv.bn, S, s);
         if (err != hipSuccess) return err;
     }
+    const bool lr = LP && o.lr_tol > 0.0 && !LP->cands.empty();
+    if (lr) {
+        const int nc = (int)LP->cands.size();
+        hipLaunchKernelGGL(k_lr_build, dim3((nc + 63) / 64), dim3(64), 0, s, LP->d_cands, nc,
+                           d_merges, S, lrbase + LP->o_reg,
+                           reinterpret_cast<LrJob*>(lrbase + LP->o_jobs),
+                           reinterpret_cast<GemmTask*>(lrbase + LP->o_tskel),
+                           reinterpret_cast<GemmTask*>(lrbase + LP->o_tfused), LP->b,
+                           LP->min_k);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
     err = dc_launch_leaf(d_leaves, (int)P.leaves.size(), P.leaf, S, s);
     if (err != hipSuccess) return err;
     g_ev_levels = (int)P.levels.size();
+    if (g_prof) g_lr_rec.assign(P.levels.size(), 0);
     for (int li = 0; li < (int)P.levels.size(); ++li) {
         const Level& Lv = P.levels[li];
         const Node* mg = d_merges + Lv.first;
@@ -572,21 +602,24 @@ hipError_t run_plan(const Plan& P, const std::vector<Prob>& probs, char* work,
                                  Lv.sec_blocks, Lv.max_m, o.max_iter, s));
         DC_TRY(prof_mark(li, 3, s));
         DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
-        DC_TRY(prof_mark(li, 4, s));
-        if (o.lr_tol > 0.0 && Lv.max_m >= o.lr_min_k)
-            DC_TRY(lowrank_level(P, probs, S, Lv.first, Lv.nm, o, s));
-        DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
-                                     2 * Lv.nm, Lv.tiles, Lv.variant, s));
-        DC_TRY(prof_mark(li, 5, s));
+        // The deflated columns leave the children's buffer before the
+        // product, whose low-rank form keeps its skeleton columns there.
+        DC_TRY(prof_mark(li, MARK_COPY, s));
         DC_TRY(dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks,
                                        S, s));
-        DC_TRY(prof_mark(li, 6, s));
+        DC_TRY(prof_mark(li, MARK_PRODUCT, s));
+        if (lr && LP->levels[li].njobs > 0)
+            DC_TRY(lowrank_level(*LP, li, lrbase, o.lr_tol, s));
+        DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
+                                     2 * Lv.nm, Lv.tiles, Lv.variant, s));
+        DC_TRY(prof_mark(li, NPHASE, s));
 #undef DC_TRY
     }
     return dc_launch_scale((int)probs.size(), true, S, s);
 }
 
 thread_local const Plan* t_last_plan = nullptr;
+thread_local const LrPlan* t_last_lr = nullptr;
 thread_local char* t_last_work = nullptr;
 
 }  // namespace
@@ -654,13 +687,37 @@ static int check_opts(const dc_opts& o) {
     return 0;
 }
 
+// Low-rank part of the workspace: for the block size and switch the caller
+// fixed, or, for fields left automatic, the largest over the values the tuner
+// may choose (so that a later tuning never outgrows a workspace sized now).
+// The tables of the pair a solve would use now are uploaded (before any
+// graph capture).
+static hipError_t lr_workspace(Plan& P, const dc_opts* opt, const dc_opts& o, size_t* bytes) {
+    *bytes = 0;
+    if (!(o.lr_tol > 0.0)) return hipSuccess;
+    std::vector<int> bs, ks;
+    if (opt && opt->lr_block > 0) bs = {opt->lr_block};
+    else bs = {128, 256, 512, o.lr_block};
+    if (opt && opt->lr_min_k > 0) ks = {opt->lr_min_k};
+    else ks = {1024, 2048, 4096, o.lr_min_k};
+    for (int b : bs)
+        for (int k : ks) {
+            if (b > dc_lowrank_max_block(true)) continue;
+            *bytes = std::max(*bytes, make_lr(P, b, k, nullptr)->bytes);
+        }
+    LrPlan* LP = nullptr;
+    return get_lr_plan(P, o.lr_block, o.lr_min_k, &LP);
+}
+
 extern "C" size_t dc_stedc_workspace(int n, const dc_opts* opt) {
     if (n < 0) return 0;
-    const dc_opts o = dc_resolve_opts(opt);
+    const dc_opts o = resolve_for(opt, {n});
     if (check_opts(o)) return 0;
     Plan* P = nullptr;
     if (get_plan({n}, o.leaf, o.gemm_tile, &P) != hipSuccess) return 0;
-    return layout(*P).bytes;
+    size_t lrb = 0;
+    if (lr_workspace(*P, opt, o, &lrb) != hipSuccess) return 0;
+    return layout(*P).bytes + align256(lrb);
 }
 
 extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void* work,
@@ -677,7 +734,12 @@ extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void
     Plan* P = nullptr;
     hipError_t err = get_plan({n}, o.leaf, o.gemm_tile, &P);
     if (err != hipSuccess) return (int)err;
-    const Layout L = layout(*P);
+    LrPlan* LP = nullptr;
+    if (o.lr_tol > 0.0) {
+        err = get_lr_plan(*P, o.lr_block, o.lr_min_k, &LP);
+        if (err != hipSuccess) return (int)err;
+    }
+    const Layout L = layout(*P, LP);
     if (!work || lwork < L.bytes) return -7;
     if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -6;
     err = (hipError_t)dc_fill_int(info_dev, 1, 0, stream);
@@ -696,22 +758,25 @@ extern "C" int dc_stedc_ex(int n, double* d, double* e, double* Q, int ldq, void
     pr.n = n;
     pr.row0 = 0;
     pr.info = info_dev;
-    err = run_plan(*P, {pr}, w, o, stream);
+    err = run_plan(*P, LP, {pr}, w, o, stream);
     t_last_plan = P;
+    t_last_lr = LP;
     t_last_work = w;
     return (int)err;
 }
 
 extern "C" size_t dc_stedc_batched_workspace(int count, const int* n_host, const dc_opts* opt) {
     if (count < 0 || (count > 0 && !n_host)) return 0;
-    const dc_opts o = dc_resolve_opts(opt);
-    if (check_opts(o)) return 0;
     std::vector<int> sizes(n_host, n_host + count);
     for (int v : sizes)
         if (v < 0) return 0;
+    const dc_opts o = resolve_for(opt, sizes);
+    if (check_opts(o)) return 0;
     Plan* P = nullptr;
     if (get_plan(sizes, o.leaf, o.gemm_tile, &P) != hipSuccess) return 0;
-    return layout(*P).bytes;
+    size_t lrb = 0;
+    if (lr_workspace(*P, opt, o, &lrb) != hipSuccess) return 0;
+    return layout(*P).bytes + align256(lrb);
 }
 
 // Per-problem pointers of a batch over the workspace `w` laid out as L.
@@ -779,25 +844,30 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
     Plan* P = nullptr;
     hipError_t err = get_plan(sizes, o.leaf, o.gemm_tile, &P);
     if (err != hipSuccess) return (int)err;
-    const Layout L = layout(*P);
+    LrPlan* LP = nullptr;
+    if (o.lr_tol > 0.0) {
+        err = get_lr_plan(*P, o.lr_block, o.lr_min_k, &LP);
+        if (err != hipSuccess) return (int)err;
+    }
+    const Layout L = layout(*P, LP);
     if (!work || lwork < L.bytes) return -8;
     if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return -7;
     char* w = static_cast<char*>(work);
     const std::vector<Prob> probs = batch_probs(*P, L, w, d, e, Q, ldq_host, info_dev);
     t_last_plan = P;                     // for dc_last_stats
+    t_last_lr = LP;
     t_last_work = w;
-    // The low-rank switch reads sizes on the host and cannot be captured.
-    if (!use_graph || o.lr_tol > 0.0) {
+    if (!use_graph) {
         err = (hipError_t)dc_fill_int(info_dev, count, 0, stream);
         if (err != hipSuccess) return (int)err;
-        return (int)run_plan(*P, probs, w, o, stream);
+        return (int)run_plan(*P, LP, probs, w, o, stream);
     }
-    t_path.assign(P->merges.size(), 0);   // a replayed schedule is all plain
-    t_lr_flops.assign(P->merges.size(), 0.0);
-    t_lr_ranks.assign(P->merges.size(), LrRankSummary{});
-    // Graph path: capture the whole level schedule once per signature.
-    std::vector<uintptr_t> key{(uintptr_t)P, (uintptr_t)work, (uintptr_t)info_dev,
-                               (uintptr_t)o.max_iter};
+    // Graph path: capture the whole level schedule once per signature (the
+    // low-rank tolerance, block size and switch are part of it).
+    uint64_t tol_bits = 0;
+    std::memcpy(&tol_bits, &o.lr_tol, sizeof(tol_bits));
+    std::vector<uintptr_t> key{(uintptr_t)P,          (uintptr_t)LP,         (uintptr_t)work,
+                               (uintptr_t)info_dev,   (uintptr_t)o.max_iter, (uintptr_t)tol_bits};
     for (int p = 0; p < count; ++p) {
         key.push_back((uintptr_t)d[p]);
         key.push_back((uintptr_t)e[p]);
@@ -817,7 +887,7 @@ int dc_batched_impl(int count, const int* n_host, double* const* d, double* cons
             const bool prof = g_prof;
             g_prof = false;                  // no event records inside the graph
             hipError_t e1 = dc_fill_int(info_dev, count, 0, cap);
-            if (e1 == hipSuccess) e1 = run_plan(*P, G->probs, w, o, cap);
+            if (e1 == hipSuccess) e1 = run_plan(*P, LP, G->probs, w, o, cap);
             g_prof = prof;
             hipGraph_t graph = nullptr;
             err = hipStreamEndCapture(cap, &graph);
@@ -851,37 +921,54 @@ extern "C" int dc_stedc_batched_eager(int count, const int* n_host, double* cons
 extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
     const Plan* P = t_last_plan;
     if (!P || !t_last_work) return 0;
-    const Layout L = layout(*P);
+    const LrPlan* LP = t_last_lr;
+    const Layout L = layout(*P, LP);
     std::vector<MergeCnt> cnt(P->merges.size());
     if (!cnt.empty() &&
         hipMemcpy(cnt.data(), t_last_work + L.cnt, cnt.size() * sizeof(MergeCnt),
                   hipMemcpyDeviceToHost) != hipSuccess)
         return 0;
+    // low-rank records of the candidates (the job holds each record's place)
+    std::vector<LrRec> rec(LP ? LP->cands.size() : 0);
+    for (size_t c = 0; c < rec.size(); ++c) {
+        const LrCand& C = LP->cands[c];
+        const Node& N = P->merges[C.merge];
+        LrJob J;
+        std::memset(&J, 0, sizeof(J));
+        J.pmax = C.pmax;
+        dc_lowrank_carve(J, t_last_work + L.lr + LP->o_reg + C.reg, LP->b, N.n1 + N.n2);
+        if (hipMemcpy(&rec[c], J.rec, sizeof(LrRec), hipMemcpyDeviceToHost) != hipSuccess)
+            return 0;
+    }
     const int nmr = (int)P->merges.size();
-    int li = 0;
     for (int lv = 0; lv < (int)P->levels.size(); ++lv) {
         const Level& Lv = P->levels[lv];
         for (int i = 0; i < Lv.nm; ++i) {
             const int g = Lv.first + i;
-            if (out && g < cap) {
-                const Node& N = P->merges[g];
-                dc_merge_stat& r = out[g];
-                r.level = (int)P->levels.size() - 1 - lv;
-                r.m = N.n1 + N.n2;
-                r.K = cnt[g].K;
-                r.nrot = cnt[g].nrot;
-                const bool lr = g < (int)t_path.size() && t_path[g] == 1;
-                r.path = lr ? 1 : 0;
-                const LrRankSummary rk = lr ? t_lr_ranks[g] : LrRankSummary{};
-                r.lr_blocks = rk.blocks;
-                r.lr_rank_sum = rk.rank_sum;
-                r.lr_rank_max = rk.rank_max;
-                r.lr_dense = rk.dense;
-                r.flops = lr ? t_lr_flops[g]
-                             : 2.0 * ((double)N.n1 * cnt[g].ntop + (double)N.n2 * cnt[g].nbot) *
-                                   cnt[g].K;
+            if (!out || g >= cap) continue;
+            const Node& N = P->merges[g];
+            dc_merge_stat& r = out[g];
+            std::memset(&r, 0, sizeof(r));
+            r.level = (int)P->levels.size() - 1 - lv;
+            r.m = N.n1 + N.n2;
+            r.K = cnt[g].K;
+            r.nrot = cnt[g].nrot;
+            const int c = LP ? LP->cand_of_merge[g] : -1;
+            const bool lr = c >= 0 && rec[c].active == 1;
+            r.path = lr ? 1 : 0;
+            if (lr) {
+                const LrRec& R = rec[c];
+                r.lr_blocks = R.blocks;
+                r.lr_rank_sum = R.rank_sum;
+                r.lr_rank_max = R.rank_max;
+                r.lr_dense = R.dense;
+                r.lr_flops_skeleton = R.flops_skel;
+                r.lr_flops_fused = R.flops_fused;
+                r.flops = R.flops_skel + R.flops_fused;
+            } else {
+                r.flops = 2.0 * ((double)N.n1 * cnt[g].ntop + (double)N.n2 * cnt[g].nbot) *
+                          cnt[g].K;
             }
-            ++li;
         }
     }
     return nmr;
@@ -895,14 +982,40 @@ extern "C" int dc_profile_enable(int on) {
 extern "C" int dc_profile_read(double* ms, int cap) {
     if (!g_prof) return 0;
     const int nl = g_ev_levels;
+    // marks in launch order; the reported order puts the product before the copy
+    static const int from[NPHASE] = {0, 1, 2, 3, MARK_PRODUCT, MARK_COPY};
+    static const int to[NPHASE] = {1, 2, 3, MARK_COPY, NPHASE, MARK_PRODUCT};
     for (int li = 0; li < nl; ++li) {
         for (int ph = 0; ph < NPHASE; ++ph) {
             const int k = li * NPHASE + ph;
             if (!ms || k >= cap) continue;
             float t = 0.0f;
-            const size_t a = (size_t)li * (NPHASE + 1) + ph;
-            if (hipEventSynchronize(g_ev[a + 1]) != hipSuccess ||
-                hipEventElapsedTime(&t, g_ev[a], g_ev[a + 1]) != hipSuccess)
+            const size_t a = (size_t)li * (NPHASE + 1);
+            if (hipEventSynchronize(g_ev[a + to[ph]]) != hipSuccess ||
+                hipEventElapsedTime(&t, g_ev[a + from[ph]], g_ev[a + to[ph]]) != hipSuccess)
+                t = -1.0f;
+            ms[k] = t;
+        }
+    }
+    return nl;
+}
+
+extern "C" int dc_profile_read_lowrank(double* ms, int cap) {
+    if (!g_prof) return 0;
+    const int nl = g_ev_levels;
+    for (int li = 0; li < nl; ++li) {
+        const bool on = li < (int)g_lr_rec.size() && g_lr_rec[li];
+        for (int ph = 0; ph < 3; ++ph) {
+            const int k = li * 3 + ph;
+            if (!ms || k >= cap) continue;
+            float t = 0.0f;
+            if (!on) {
+                ms[k] = 0.0;
+                continue;
+            }
+            const size_t a = (size_t)li * 4 + ph;
+            if (hipEventSynchronize(g_lr_ev[a + 1]) != hipSuccess ||
+                hipEventElapsedTime(&t, g_lr_ev[a], g_lr_ev[a + 1]) != hipSuccess)
                 t = -1.0f;
             ms[k] = t;
         }
@@ -1101,12 +1214,16 @@ extern "C" int dc_autotune_batched(int count, const int* n_host, double* const* 
         for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
             err = restore_d();
             if (err == hipSuccess) err = dc_fill_int(info_dev, count, 0, stream);
-            if (err == hipSuccess) err = run_plan(*Pv, probs, w, o, stream);
+            // the plain product on every level (the tile variants are its)
+            dc_opts op = o;
+            op.lr_tol = 0.0;
+            if (err == hipSuccess) err = run_plan(*Pv, nullptr, probs, w, op, stream);
             for (int li = 0; li < nl && err == hipSuccess; ++li) {
-                const size_t a = (size_t)li * (NPHASE + 1) + 4;
+                const size_t a = (size_t)li * (NPHASE + 1);
                 float t = 0.0f;
-                err = hipEventSynchronize(g_ev[a + 1]);
-                if (err == hipSuccess) err = hipEventElapsedTime(&t, g_ev[a], g_ev[a + 1]);
+                err = hipEventSynchronize(g_ev[a + NPHASE]);
+                if (err == hipSuccess)
+                    err = hipEventElapsedTime(&t, g_ev[a + MARK_PRODUCT], g_ev[a + NPHASE]);
                 float& best = ms[(size_t)li * DC_TILE_VARIANTS + v];
                 best = std::min(best, t);
             }
@@ -1153,7 +1270,11 @@ extern "C" int dc_autotune_batched(int count, const int* n_host, double* const* 
                     err = restore_d();
                     if (err == hipSuccess) err = dc_fill_int(info_dev, count, 0, stream);
                     if (err == hipSuccess) err = hipEventRecord(e0, stream);
-                    if (err == hipSuccess) err = run_plan(*PT, probs, w, oc, stream);
+                    LrPlan* LPT = nullptr;
+                    if (err == hipSuccess) err = get_lr_plan(*PT, b, k, &LPT);
+                    if (err == hipSuccess && lwork < layout(*PT, LPT).bytes)
+                        err = hipErrorInvalidValue;
+                    if (err == hipSuccess) err = run_plan(*PT, LPT, probs, w, oc, stream);
                     if (err == hipSuccess) err = hipEventRecord(e1, stream);
                     if (err == hipSuccess) err = hipEventSynchronize(e1);
                     float ms1 = 0.0f;

@@ -1,5 +1,6 @@
 // Structured low-rank merge product: SRRSC compression of the off-diagonal
-// blocks of U from their Cauchy generators, then two generated products.
+// blocks of U from their Cauchy generators, then two generated products,
+// planned and launched on the device.
 //
 // Compression (section "SRRSC low-rank approximation"): U is cut into
 // contiguous b x b blocks of the sorted order (block data distribution, which
@@ -25,15 +26,21 @@
 // and loaded.  C is written once.  A block kept dense is carried as a block
 // whose skeleton is every column (identity interpolation rows).  W is laid
 // out by output block J, so each J reads one contiguous column range of W
-// and of Y.  U and Z never exist as matrices; W and Y are m x (sum of ranks)
-// and (sum of ranks) x b.  The merges of one tree level go together: all
-// compressions first (one read of all ranks), then one launch of step 1 and
-// one of step 2 for every merge of the level.
+// and of Y.  U and Z never exist as matrices.
+//
+// Everything after the deflated size K is known runs on the device, so the
+// host never waits: a decision kernel applies Algorithm 3's switch (K >=
+// min_k), the compression runs on a grid bounded by the merge's order, a
+// planning workgroup per merge turns the ranks into W's column layout, the
+// interpolation-row generators and the two launches' task lists (and switches
+// the plain product off, or leaves it on when W would not fit), and the two
+// products walk their tiles with persistent grids that read the tile counts
+// from device memory.  The merges of one tree level go together through every
+// stage.
 #include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
-#include <map>
 #include <vector>
 
 #include "dc_internal.hpp"
@@ -47,34 +54,13 @@ constexpr int MAX_B_OFF = 2048;   // block size limit with column offsets (merge
 constexpr int MAX_B_GEN = 4096;   // block size limit with plain column nodes
 constexpr int MAX_R = 128;
 
-struct SrrscOut {
-    int* rank;        // p*p: rank, -1 on the diagonal, -2 kept dense
-    int* prow;        // p*p*rmax, local pivot rows
-    int* pcol;        // p*p*rmax, local skeleton columns
-    double* y;        // p*p*rmax
-    double* vk;       // p*p*b: v^(r) of the block's columns (0 on skeletons)
-};
-
-// One compression of a launch: K nodes in p x p blocks, the generators and
-// the outputs.  A launch runs the blocks of several jobs (the merges of a
-// tree level): job j owns blocks [start[j], start[j + 1]) of the grid.
-struct SrrscJob {
-    int K, p;
-    const double* D;
-    const double* u0;
-    const double* cbase;
-    const double* coff;
-    const double* v0;
-    SrrscOut O;
-};
-
 // One workgroup per block (I, J).  MB: LDS capacity in generators; OFF: the
 // column nodes carry an offset (w_j = cbase_j + coff_j, the merge's (origin,
 // tau) form); STORE: write the skeleton and interpolation generators, else only
 // count the rank (up to rmax).
 template <int MB, int RG, bool OFF, bool STORE>
 __global__ __launch_bounds__(NT)
-void k_srrsc(const SrrscJob* __restrict__ jobs, const int* __restrict__ start, int njobs, int b,
+void k_srrsc(const LrJob* __restrict__ jobs, const int* __restrict__ start, int njobs, int b,
              double tol, int rmax) {
     constexpr int JJ = (MB * RG + NT - 1) / NT;   // columns per thread
     __shared__ double sd[MB], su[MB], swb[MB], sv[MB];
@@ -88,19 +74,22 @@ void k_srrsc(const SrrscJob* __restrict__ jobs, const int* __restrict__ start, i
         const int mid = (jlo + jhi + 1) >> 1;
         if (start[mid] <= (int)blockIdx.x) jlo = mid; else jhi = mid - 1;
     }
-    const SrrscJob& job = jobs[jlo];
-    const int K = job.K, p = job.p;
+    const LrJob& job = jobs[jlo];
+    // the grid covers pmax x pmax blocks per job; this call's K has p blocks
+    // per side (p = 0: the merge keeps the plain product)
+    const int K = job.K_dev, p = job.p, pmax = job.pmax;
     const double* __restrict__ D = job.D;
-    const double* __restrict__ u0 = job.u0;
+    const double* __restrict__ u0 = job.zhat;
     const double* __restrict__ cbase = job.cbase;
     const double* __restrict__ coff = job.coff;
-    const double* __restrict__ v0 = job.v0;
-    const SrrscOut O = job.O;
-    const int pair = blockIdx.x - start[jlo];
-    const int I = pair / p, J = pair - (pair / p) * p;
+    const double* __restrict__ v0 = job.scale;
+    const int loc = blockIdx.x - start[jlo];
+    const int I = loc / pmax, J = loc - (loc / pmax) * pmax;
+    if (I >= p || J >= p) return;
+    const int pair = I * pmax + J;       // output index of block (I, J)
     const int tid = threadIdx.x;
     if (I == J) {
-        if (tid == 0) O.rank[pair] = -1;
+        if (tid == 0) job.rank[pair] = -1;
         return;
     }
     const int r0 = I * b, c0 = J * b;
@@ -216,11 +205,11 @@ void k_srrsc(const SrrscJob* __restrict__ jobs, const int* __restrict__ start, i
         ++k;
         __syncthreads();
     }
-    if (tid == 0) O.rank[pair] = dense ? -2 : k;
+    if (tid == 0) job.rank[pair] = dense ? -2 : k;
     if constexpr (STORE) {
         if (dense) {
             // every column becomes a skeleton column: v^(r) = 0 throughout
-            for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = 0.0;
+            for (int j = tid; j < bj; j += NT) job.vk[(long long)pair * b + j] = 0.0;
             return;
         }
         const long long pb = (long long)pair * rmax;
@@ -237,11 +226,11 @@ void k_srrsc(const SrrscJob* __restrict__ jobs, const int* __restrict__ start, i
                 y *= num * dc_rcp(den);
             }
             y *= ((sd[spr[a]] - wba) - woa) * dc_rcp(v0[c0 + ja]);
-            O.y[pb + a] = y;
-            O.prow[pb + a] = spr[a];
-            O.pcol[pb + a] = ja;
+            job.y[pb + a] = y;
+            job.prow[pb + a] = spr[a];
+            job.pcol[pb + a] = ja;
         }
-        for (int j = tid; j < bj; j += NT) O.vk[(long long)pair * b + j] = sv[j];
+        for (int j = tid; j < bj; j += NT) job.vk[(long long)pair * b + j] = sv[j];
     }
 }
 
@@ -258,84 +247,350 @@ __global__ void k_nodes(int K, const double* D, const int* org, const double* ta
     }
 }
 
+// Algorithm 3's switch per merge: the low-rank product when K >= min_k and K
+// exceeds one block; p = 0 keeps the plain product.
+__global__ void k_lr_decide(LrJob* jobs, int njobs, int b) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    LrJob& J = jobs[j];
+    const int K = J.K_p ? *J.K_p : J.K;
+    J.K_dev = K;
+    J.p = (K >= J.min_k && K > b) ? min((K + b - 1) / b, J.pmax) : 0;
+}
+
+__device__ __forceinline__ int lower_bound_dev(const int* a, int n, int v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void empty_task(GemmTask& t) {
+    t.tiles_m = 0;
+    t.tiles_n = 0;
+}
+
+// Exclusive prefix of in[0, n) into out[0, n] (out[n] = total) over one
+// workgroup of NT threads; wsum (NT / 64) and carry are LDS scratch.
+__device__ void block_scan_excl(const int* in, int* out, int n, int* wsum, int* carry) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) *carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += NT) {
+        const int t = base + tid;
+        const int v = t < n ? in[t] : 0;
+        int x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        int before = *carry;
+        for (int q = 0; q < w; ++q) before += wsum[q];
+        if (t < n) out[t] = before + x - v;
+        __syncthreads();
+        if (tid == NT - 1) *carry = before + x;
+        __syncthreads();
+    }
+    if (tid == 0) out[n] = *carry;
+    __syncthreads();
+}
+
+// One workgroup per merge of the level.  From the block ranks: the skeleton
+// size of every block (its rank, or all its columns when kept dense), W's
+// column layout by output block J (woff) and the skeleton column lists by
+// block row I, the per-column generators of the interpolation rows, the
+// tasks of both product launches, the flop and rank record, and the switch
+// of the plain product.  When the skeleton columns would not fit W the merge
+// keeps the plain product.  Block columns (and rows) are walked in segments
+// of a few blocks by several threads each, whose offsets come from segment
+// sums, so no thread follows a dependent chain through all p blocks.
+__global__ __launch_bounds__(NT)
+void k_lr_plan(LrJob* __restrict__ jobs, int b, int rmax, int bms, int bns, int bmf, int bnf) {
+    extern __shared__ int sm[];
+    __shared__ unsigned long long s_rsum;
+    __shared__ int s_rmax, s_dense, s_carry;
+    __shared__ int s_wsum[NT / 64];
+    __shared__ double s_fs, s_ff;
+    LrJob& J = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int pmax = J.pmax, p = J.p, K = J.K_dev;
+    const int ntask = J.nh * pmax;
+    const int* __restrict__ rank = J.rank;
+    auto bsz = [&](int I) { return min(b, K - I * b); };
+    auto skel = [&](int I, int c) {
+        const int r = rank[I * pmax + c];
+        return r == -2 ? bsz(c) : (r < 0 ? 0 : r);
+    };
+    int* rs = sm;                  // skeleton columns per block row (p)
+    int* cs = sm + pmax;           // per block column (p)
+    int* ls = sm + 2 * pmax;       // exclusive prefix of rs (p + 1)
+    int* gs = ls + pmax + 1;       // exclusive prefix of cs (p + 1)
+    int* seg = gs + pmax + 1;      // segment sums (NT)
+    if (tid == 0) {
+        s_rsum = 0;
+        s_rmax = 0;
+        s_dense = 0;
+        s_fs = 0.0;
+        s_ff = 0.0;
+    }
+    for (int i = tid; i < p; i += NT) {
+        rs[i] = 0;
+        cs[i] = 0;
+    }
+    __syncthreads();
+    {
+        unsigned long long rsum = 0;
+        int rmx = 0, dn = 0;
+        for (int q = tid; q < p * p; q += NT) {
+            const int I = q / p, c = q - (q / p) * p;
+            if (I == c) continue;
+            const int rr = rank[I * pmax + c];
+            const bool dense = rr == -2;
+            const int r = dense ? bsz(c) : rr;
+            if (dense) ++dn; else { rsum += rr; rmx = max(rmx, rr); }
+            if (r > 0) {
+                atomicAdd(&rs[I], r);
+                atomicAdd(&cs[c], r);
+            }
+        }
+        if (rsum) atomicAdd(&s_rsum, rsum);
+        if (rmx) atomicMax(&s_rmax, rmx);
+        if (dn) atomicAdd(&s_dense, dn);
+    }
+    __syncthreads();
+    block_scan_excl(rs, ls, p, s_wsum, &s_carry);
+    block_scan_excl(cs, gs, p, s_wsum, &s_carry);
+    const int nw = p > 0 ? gs[p] : 0;
+    const bool active = p > 0 && nw <= J.wcap;
+    if (!active) {
+        for (int t = tid; t < ntask; t += NT) {
+            empty_task(J.tskel[t]);
+            empty_task(J.tfused[t]);
+        }
+        if (tid == 0) *J.rec = LrRec{0, nw, 0, 0, 0, 0, 0.0, 0.0};
+        return;
+    }
+    // T threads per block column (or row), each over L consecutive blocks.
+    const int T = p >= NT ? 1 : min(64, NT / p);
+    const int L = (p + T - 1) / T;
+    // W's columns by output block c: block (I, c) at woff, its skeleton
+    // generators, the v^(r) row of the block, the block column and y.
+    for (int q = tid; q < p * T; q += NT) {
+        const int c = q / T, sg = q - (q / T) * T;
+        int a = 0;
+        for (int I = sg * L; I < min(p, sg * L + L); ++I)
+            if (I != c) a += skel(I, c);
+        if (T > 1) seg[q] = a;
+    }
+    __syncthreads();
+    for (int q = tid; q < p * T; q += NT) {
+        const int c = q / T, sg = q - (q / T) * T;
+        int run = gs[c];
+        for (int u = 0; u < sg; ++u) run += seg[c * T + u];
+        for (int I = sg * L; I < min(p, sg * L + L); ++I) {
+            if (I == c) continue;
+            const int pair = I * pmax + c;
+            const int rr = rank[pair];
+            const bool dense = rr == -2;
+            const int r = dense ? bsz(c) : rr;
+            J.woff[pair] = run;
+            for (int a = 0; a < r; ++a) {
+                const int col = run + a;
+                J.rgen[col] = c * b + (dense ? a : J.pcol[(long long)pair * rmax + a]);
+                J.rvo[col] = (long long)pair * b;
+                J.kJ[col] = c;
+                J.ry[col] = dense ? 0.0 : J.y[(long long)pair * rmax + a];
+            }
+            run += r;
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // Skeleton column lists by block row I: generator and W column.
+    for (int q = tid; q < p * T; q += NT) {
+        const int I = q / T, sg = q - (q / T) * T;
+        int a = 0;
+        for (int c = sg * L; c < min(p, sg * L + L); ++c)
+            if (c != I) a += skel(I, c);
+        if (T > 1) seg[q] = a;
+    }
+    __syncthreads();
+    for (int q = tid; q < p * T; q += NT) {
+        const int I = q / T, sg = q - (q / T) * T;
+        int run = ls[I];
+        for (int u = 0; u < sg; ++u) run += seg[I * T + u];
+        for (int c = sg * L; c < min(p, sg * L + L); ++c) {
+            if (c == I) continue;
+            const int pair = I * pmax + c;
+            const int rr = rank[pair];
+            const bool dense = rr == -2;
+            const int r = dense ? bsz(c) : rr;
+            const int w0 = J.woff[pair];
+            for (int a = 0; a < r; ++a) {
+                J.ccol[run + a] = c * b + (dense ? a : J.pcol[(long long)pair * rmax + a]);
+                J.wpos[run + a] = w0 + a;
+            }
+            run += r;
+        }
+    }
+    // Tasks: per row half and block row I, the fused task (diagonal block
+    // generated, then W's columns of block I against Y) and the skeleton task.
+    double fs = 0.0, ff = 0.0;
+    for (int t = tid; t < ntask; t += NT) {
+        const int hh = t / pmax, I = t - hh * pmax;
+        if (I >= p) {
+            empty_task(J.tskel[t]);
+            empty_task(J.tfused[t]);
+            continue;
+        }
+        const LrHalf& H = J.h[hh];
+        int lo, hi;
+        if (H.klist) {
+            const int n = H.klen_p ? *H.klen_p : H.klen;
+            lo = lower_bound_dev(H.klist, n, I * b);
+            hi = lower_bound_dev(H.klist, n, I * b + b);
+        } else {
+            lo = I * b;
+            hi = I * b + bsz(I);
+        }
+        GemmTask base;
+        memset(&base, 0, sizeof(base));
+        base.A = H.A + (long long)lo * H.lda;
+        base.lda = H.lda;
+        base.klen = hi - lo;
+        base.rows = H.rows;
+        base.rD = H.gD + lo;
+        base.rz = H.gz + lo;
+        base.cbase = J.cbase;
+        base.coff = J.coff;
+        base.cs = J.scale;
+        GemmTask a = base;
+        a.col_off = I * b;
+        a.ncol = bsz(I);
+        a.C = H.C;
+        a.ldc = H.ldc;
+        a.cpos = H.cpos;
+        const int R = gs[I + 1] - gs[I];
+        if (R > 0) {
+            a.A2 = J.W + H.r0 + (long long)gs[I] * J.ldw;
+            a.lda2 = J.ldw;
+            a.B2 = J.Y + (long long)gs[I] * b;
+            a.ldb2 = b;
+            a.klen2 = R;
+        }
+        a.tiles_m = H.rows > 0 ? (H.rows + bmf - 1) / bmf : 0;
+        a.tiles_n = (a.ncol + bnf - 1) / bnf;
+        J.tfused[t] = a;
+        ff += 2.0 * H.rows * (double)(a.klen + a.klen2) * a.ncol;
+        GemmTask c = base;
+        const int ncs = ls[I + 1] - ls[I];
+        c.ccol = J.ccol + ls[I];
+        c.cpos = J.wpos + ls[I];
+        c.ncol = ncs;
+        c.C = J.W + H.r0;
+        c.ldc = J.ldw;
+        c.tiles_m = (H.rows > 0 && ncs > 0) ? (H.rows + bms - 1) / bms : 0;
+        c.tiles_n = (ncs + bns - 1) / bns;
+        J.tskel[t] = c;
+        fs += 2.0 * H.rows * (double)c.klen * ncs;
+    }
+    fs = dc_wave_sum(fs);
+    ff = dc_wave_sum(ff);
+    if ((tid & 63) == 0) {
+        atomicAdd(&s_fs, fs);
+        atomicAdd(&s_ff, ff);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int h = 0; h < J.nh && J.plain; ++h) J.plain[h].ncol_p = J.zero;
+        *J.rec = LrRec{1, nw, p * (p - 1), (int)s_rsum, s_rmax, s_dense, s_fs, s_ff};
+    }
+}
+
 // Interpolation rows [I Z_IJ] P^T of the low-rank blocks, one row per W
 // column k (Theorem 2, eq. geneZ): for output column c of block column
 // J = kJ[k], generator g = J b + c, the entry is 1 on the skeleton column
 // itself (g == rgen[k]) and y_k v^(r)_c / (w_h - w_g) otherwise.  Stored
 // row-major, Y[k b + c], divided by the column scale s_g that the product's
-// epilogue multiplies back; 0 past the block's last column.
-__global__ void k_build_y(long long nw, int b, int K, const double* __restrict__ ry,
-                          const int* __restrict__ rgen, const long long* __restrict__ rvo,
-                          const int* __restrict__ kJ, const double* __restrict__ vk,
-                          const double* __restrict__ cbase, const double* __restrict__ coff,
-                          const double* __restrict__ scale, double* __restrict__ Y) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nw * b) return;
-    const long long k = idx / b;
-    const int c = (int)(idx - k * b);
-    const int g = kJ[k] * b + c;
-    if (g >= K) {
-        Y[idx] = 0.0;
-        return;
-    }
-    const int h = rgen[k];
-    double v = 1.0;
-    if (h != g) {
-        const double den = (cbase[h] - cbase[g]) + (coff ? coff[h] - coff[g] : 0.0);
-        v = ry[k] * vk[rvo[k] + c] / den;
-    }
-    Y[idx] = v / scale[g];
-}
-
-// Column layout of the low-rank product from the SRRSC output, one
-// workgroup per block pair (I, J), I != J, whose skeleton has r columns (its
-// rank, or every column of block J when kept dense): W column woff + a and
-// stage-1b list slot loff + a (a < r) get the skeleton column's generator
-// index, the pair's v^(r) row offset, the block column J and y_a (0 for a
-// dense block, whose interpolation rows are the identity).
-__global__ void k_layout(int p, int b, int K, int rmax, const int* __restrict__ rank,
-                         const int* __restrict__ pcol, const double* __restrict__ y,
-                         const long long* __restrict__ woff, const int* __restrict__ loff,
-                         int* __restrict__ rgen, long long* __restrict__ rvo,
-                         int* __restrict__ kJ, double* __restrict__ ry,
-                         int* __restrict__ ccol, int* __restrict__ wpos) {
-    const int pair = blockIdx.x;
-    const int I = pair / p, J = pair - (pair / p) * p;
-    if (I == J) return;
-    const int rk = rank[pair];
-    const bool dense = rk == -2;
-    const int r = dense ? min(b, K - J * b) : rk;
-    for (int a = threadIdx.x; a < r; a += blockDim.x) {
-        const long long col = woff[pair] + a;
-        const int h = J * b + (dense ? a : pcol[(long long)pair * rmax + a]);
-        rgen[col] = h;
-        rvo[col] = (long long)pair * b;
-        kJ[col] = J;
-        ry[col] = dense ? 0.0 : y[(long long)pair * rmax + a];
-        ccol[loff[pair] + a] = h;
-        wpos[loff[pair] + a] = (int)col;
+// epilogue multiplies back; 0 past the block's last column.  blockIdx.y is
+// the merge; the blocks stride over its nw b entries.
+__global__ void k_build_y(const LrJob* __restrict__ jobs, int b) {
+    const LrJob& J = jobs[blockIdx.y];
+    if (J.p == 0 || !J.rec->active) return;
+    const long long total = (long long)J.rec->nw * b;
+    const int K = J.K_dev;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long k = idx / b;
+        const int c = (int)(idx - k * b);
+        const int g = J.kJ[k] * b + c;
+        if (g >= K) {
+            J.Y[idx] = 0.0;
+            continue;
+        }
+        const int h = J.rgen[k];
+        double v = 1.0;
+        if (h != g) {
+            const double den = (J.cbase[h] - J.cbase[g]) + (J.coff ? J.coff[h] - J.coff[g] : 0.0);
+            v = J.ry[k] * J.vk[J.rvo[k] + c] / den;
+        }
+        J.Y[idx] = v / J.scale[g];
     }
 }
 
-__global__ void k_disable_tasks(GemmTask* tasks, int n, const int* zero) {
-    const int i = threadIdx.x;
-    if (i < n) tasks[i].ncol_p = zero;
+// Exclusive prefix of the tiles of a level's tasks (skeleton list, then
+// fused list), the two totals, and the two launches' claim counters (8 each,
+// at totals + 8 and totals + 16) cleared.
+__global__ __launch_bounds__(NT)
+void k_lr_scan(const GemmTask* __restrict__ tskel, const GemmTask* __restrict__ tfused,
+               int ntasks, int* __restrict__ tile_start, int* __restrict__ totals) {
+    __shared__ int wsum[NT / 64];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid >= 8 && tid < 24) totals[tid] = 0;
+    for (int st = 0; st < 2; ++st) {
+        const GemmTask* T = st ? tfused : tskel;
+        int* out = tile_start + st * (ntasks + 1);
+        if (tid == 0) carry = 0;
+        __syncthreads();
+        for (int base = 0; base < ntasks; base += NT) {
+            const int t = base + tid;
+            const int v = t < ntasks ? T[t].tiles_m * T[t].tiles_n : 0;
+            int x = v;                                  // inclusive scan in the wave
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(x, off, 64);
+                if (lane >= off) x += y;
+            }
+            if (lane == 63) wsum[w] = x;
+            __syncthreads();
+            int before = carry;
+            for (int q = 0; q < w; ++q) before += wsum[q];
+            if (t < ntasks) out[t] = before + x - v;
+            __syncthreads();
+            if (tid == NT - 1) carry = before + x;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            out[ntasks] = carry;
+            totals[st] = carry;
+        }
+        __syncthreads();
+    }
 }
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Compressed {
-    int p = 0, b = 0, rmax = 0;
-    std::vector<int> rank;
-    char* dev = nullptr;          // device block holding SrrscOut arrays (not owned)
-    SrrscOut out{};
-};
 
 // The SRRSC instance for a job list: column offsets present (merge nodes, b
 // up to MAX_B_OFF) or plain column nodes (b up to MAX_B_GEN); store or count
 // only.
 template <int MB, int RG, bool OFF>
-hipError_t launch_srrsc_mb(const SrrscJob* jobs, const int* start, int njobs, int blocks, int b,
+hipError_t launch_srrsc_mb(const LrJob* jobs, const int* start, int njobs, int blocks, int b,
                            double tol, int rmax, bool store, hipStream_t s) {
     const dim3 g((unsigned)blocks), blk(NT);
     if (store)
@@ -351,7 +606,7 @@ hipError_t launch_srrsc_mb(const SrrscJob* jobs, const int* start, int njobs, in
 // b = 1024), with the rows split among 4 or 2 thread groups when b <= 256 or
 // 512.
 template <bool OFF>
-hipError_t launch_srrsc_off(const SrrscJob* jobs, const int* start, int njobs, int blocks,
+hipError_t launch_srrsc_off(const LrJob* jobs, const int* start, int njobs, int blocks,
                             int b, double tol, int rmax, bool store, hipStream_t s) {
     if (b <= 256)
         return launch_srrsc_mb<256, 4, OFF>(jobs, start, njobs, blocks, b, tol, rmax, store, s);
@@ -369,7 +624,7 @@ hipError_t launch_srrsc_off(const SrrscJob* jobs, const int* start, int njobs, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_srrsc(const SrrscJob* jobs, const int* start, int njobs, int blocks, int b,
+hipError_t launch_srrsc(const LrJob* jobs, const int* start, int njobs, int blocks, int b,
                         bool offsets, double tol, int rmax, bool store, hipStream_t s) {
     if (offsets && b > MAX_B_OFF) return hipErrorInvalidValue;
     if (b > MAX_B_GEN) return hipErrorInvalidValue;
@@ -378,455 +633,68 @@ hipError_t launch_srrsc(const SrrscJob* jobs, const int* start, int njobs, int b
                    : launch_srrsc_off<false>(jobs, start, njobs, blocks, b, tol, rmax, store, s);
 }
 
-// A job list in device memory: `dev` holds job_bytes(n) bytes; the list and
-// the block prefix are uploaded, and the grid's block count returned.
-size_t job_bytes(size_t n) {
-    return al(n * sizeof(SrrscJob)) + al((n + 1) * sizeof(int));
-}
-
-hipError_t upload_jobs(const std::vector<SrrscJob>& jobs, char* dev, hipStream_t s,
-                       const SrrscJob** jobs_dev, const int** start_dev, int* blocks) {
-    const size_t n = jobs.size();
-    std::vector<int> start(n + 1, 0);
-    for (size_t i = 0; i < n; ++i) start[i + 1] = start[i] + jobs[i].p * jobs[i].p;
-    std::vector<char> h(job_bytes(n));
-    const size_t so = al(n * sizeof(SrrscJob));
-    if (n) std::memcpy(h.data(), jobs.data(), n * sizeof(SrrscJob));
-    std::memcpy(h.data() + so, start.data(), (n + 1) * sizeof(int));
-    *jobs_dev = reinterpret_cast<const SrrscJob*>(dev);
-    *start_dev = reinterpret_cast<const int*>(dev + so);
-    *blocks = start[n];
-    return dc_upload(dev, h.data(), h.size(), s);
-}
-
-// coff == nullptr: plain column nodes w_j = cbase_j.
-// Bytes of the SRRSC output of a K-node problem in b x b blocks.
-size_t compress_bytes(int K, int b) {
-    const size_t p = (K + b - 1) / b, p2 = p * p;
-    const size_t rmax = std::min(MAX_R, std::max(1, b / 2));
-    return al(p2 * sizeof(int)) + 2 * al(p2 * rmax * sizeof(int)) +
-           al(p2 * rmax * sizeof(double)) + al(p2 * (size_t)b * sizeof(double));
-}
-
-// The SRRSC job of every off-diagonal block, its output in `dev`
-// (compress_bytes(K, b) bytes); the caller launches it and reads the ranks
-// back (Cm.rank is sized for them).
-SrrscJob compress_prepare(int K, int b, const double* D, const double* zhat,
-                          const double* cbase, const double* coff, const double* scale,
-                          Compressed& Cm, char* dev) {
-    Cm.b = b;
-    Cm.p = (K + b - 1) / b;
-    Cm.rmax = std::min(MAX_R, std::max(1, b / 2));
-    const size_t p2 = (size_t)Cm.p * Cm.p;
-    size_t o = 0;
-    const size_t o_rank = o; o = al(o + p2 * sizeof(int));
-    const size_t o_prow = o; o = al(o + p2 * Cm.rmax * sizeof(int));
-    const size_t o_pcol = o; o = al(o + p2 * Cm.rmax * sizeof(int));
-    const size_t o_y = o; o = al(o + p2 * Cm.rmax * sizeof(double));
-    Cm.dev = dev;
-    Cm.out.rank = reinterpret_cast<int*>(Cm.dev + o_rank);
-    Cm.out.prow = reinterpret_cast<int*>(Cm.dev + o_prow);
-    Cm.out.pcol = reinterpret_cast<int*>(Cm.dev + o_pcol);
-    Cm.out.y = reinterpret_cast<double*>(Cm.dev + o_y);
-    Cm.out.vk = reinterpret_cast<double*>(Cm.dev + o);
-    Cm.rank.resize(p2);
-    return SrrscJob{K, Cm.p, D, zhat, cbase, coff, scale, Cm.out};
-}
-
-// Device-side task list of one launch, with its tile prefix.
-struct Stage {
-    std::vector<GemmTask> tasks;
-    std::vector<int> start{0};
-    void add(const GemmTask& t) {
-        if (t.tiles_m * t.tiles_n == 0) return;
-        tasks.push_back(t);
-        start.push_back(start.back() + t.tiles_m * t.tiles_n);
-    }
-};
+// Tile shapes of the two product launches (register kernel variants): the
+// fused launch takes 128 x 128 tiles of 128 x 32 waves; the skeleton launch
+// takes 64 x 64 one-wave tiles (its k-range is one block, b, and its column
+// counts are sums of ranks: there the 128-row waves ran at 39% of peak
+// against 58-65% for 64 x 64, whose generated entries feed twice as many
+// MFMAs per loaded A value).
+constexpr int FUSED_VARIANT = 0;
+constexpr int SKEL_VARIANT = 5;
 
 }  // namespace
 
-// Device buffers of the low-rank product, kept per host thread and device
-// for the process and grown on demand: stream-ordered allocation, and above
-// all freeing, cost several hundred microseconds of host time per merge.
-// Each use is ordered after the previous one: on the same stream by stream
-// order, on another stream through an event recorded after the last use.
-enum { SL_SRRSC, SL_LAYOUT, SL_W, SL_Y, SL_TASKS, NSLOT };
-struct Arena {
-    char* p[NSLOT] = {};
-    size_t cap[NSLOT] = {};
-    hipEvent_t ev = nullptr;
-    hipStream_t last = nullptr;
-    bool used = false;
-};
+int dc_lowrank_max_block(bool offsets) { return offsets ? MAX_B_OFF : MAX_B_GEN; }
+int dc_lowrank_rmax(int b) { return std::min(MAX_R, std::max(1, b / 2)); }
 
-Arena& arena() {
-    thread_local std::map<int, Arena> per_device;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    return per_device[dev];
+size_t dc_lowrank_region_bytes(int pmax, int b, int wcap) {
+    const size_t p2 = (size_t)pmax * pmax;
+    const size_t rmax = dc_lowrank_rmax(b);
+    const size_t w = std::max(wcap, 1);
+    return al(p2 * sizeof(int)) * 2 + 2 * al(p2 * rmax * sizeof(int)) +
+           al(p2 * rmax * sizeof(double)) + al(p2 * (size_t)b * sizeof(double)) +
+           al(w * (size_t)b * sizeof(double)) + 4 * al(w * sizeof(int)) +
+           al(w * sizeof(long long)) + al(w * sizeof(double)) + al(sizeof(LrRec));
 }
 
-hipError_t arena_begin(Arena& A, hipStream_t s) {
-    return (A.used && A.last != s) ? hipStreamWaitEvent(s, A.ev, 0) : hipSuccess;
+hipError_t dc_lowrank_decide(LrJob* jobs_dev, int njobs, int b, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lr_decide, dim3((njobs + 63) / 64), dim3(64), 0, s, jobs_dev, njobs, b);
+    return hipGetLastError();
 }
 
-hipError_t arena_get(Arena& A, int slot, size_t n, char** out) {
-    if (n > A.cap[slot]) {
-        if (A.p[slot]) {
-            // earlier work may still read the old buffer (rare: growth)
-            hipError_t err = hipDeviceSynchronize();
-            if (err == hipSuccess) err = hipFree(A.p[slot]);
-            if (err != hipSuccess) return err;
-            A.p[slot] = nullptr;
-            A.cap[slot] = 0;
-        }
-        const size_t want = n + n / 4;
-        hipError_t err = hipMalloc((void**)&A.p[slot], want);
-        if (err != hipSuccess) return err;
-        A.cap[slot] = want;
-    }
-    *out = A.p[slot];
-    return hipSuccess;
-}
-
-hipError_t arena_end(Arena& A, hipStream_t s) {
-    if (!A.ev) {
-        hipError_t err = hipEventCreateWithFlags(&A.ev, hipEventDisableTiming);
-        if (err != hipSuccess) return err;
-    }
-    A.last = s;
-    A.used = true;
-    return hipEventRecord(A.ev, s);
-}
-
-namespace {
-
-LrRankSummary rank_summary(const Compressed& Cm) {
-    LrRankSummary R;
-    const int p = Cm.p;
-    for (int I = 0; I < p; ++I)
-        for (int J = 0; J < p; ++J) {
-            if (I == J) continue;
-            const int r = Cm.rank[(size_t)I * p + J];
-            ++R.blocks;
-            if (r == -2) { ++R.dense; continue; }
-            R.rank_sum += r;
-            R.rank_max = std::max(R.rank_max, r);
-        }
-    return R;
-}
-
-// Host layout of one compressed merge's products, from the ranks alone (the
-// skeleton columns and y stay on the device): W by output block J,
-// [W_IJ for I != J], r_IJ columns each; the stage-1b column list of block
-// row I, [T_IJ for J != I].  Its uploaded arrays (per-pair offsets) and its
-// device-filled arrays (per W column: skeleton generator, v^(r) row, block
-// column, y; the stage-1b lists) have places in the level's layout slot,
-// and W and Y places in the level's W and Y slots.
-struct MergePlan {
-    int p = 0;
-    std::vector<long long> gstart, woff;
-    std::vector<int> loff, lstart;
-    long long NW = 0;
-    size_t up_off = 0, dev_off = 0;               // bytes, in the layout slot
-    size_t o_wo = 0, o_lo = 0, up_bytes = 0;      // inside the uploaded part
-    size_t o_ry = 0, o_rg = 0, o_rv = 0, o_kj = 0, o_cc = 0, o_wp = 0, dev_bytes = 0;
-    size_t w_off = 0, y_off = 0;                  // elements, in the W and Y slots
-};
-
-void plan_layout(const Compressed& Cm, int K, int b, MergePlan& P) {
-    const int p = Cm.p;
-    P.p = p;
-    auto bsz = [&](int I) { return std::min(b, K - I * b); };
-    // Skeleton size of block (I, J): its rank, or every column if kept dense.
-    auto rk = [&](int I, int J) {
-        const int r = Cm.rank[(size_t)I * p + J];
-        return r == -2 ? bsz(J) : r;
-    };
-    P.gstart.assign(p + 1, 0);
-    P.woff.assign((size_t)p * p, 0);
-    P.loff.assign((size_t)p * p, 0);
-    P.lstart.assign(p + 1, 0);
-    for (int J = 0; J < p; ++J) {
-        long long run = 0;
-        for (int I = 0; I < p; ++I)
-            if (I != J && rk(I, J) > 0) { P.woff[(size_t)I * p + J] = P.gstart[J] + run; run += rk(I, J); }
-        P.gstart[J + 1] = P.gstart[J] + run;
-    }
-    for (int I = 0; I < p; ++I) {
-        int run = 0;
-        for (int J = 0; J < p; ++J)
-            if (I != J && rk(I, J) > 0) { P.loff[(size_t)I * p + J] = P.lstart[I] + run; run += rk(I, J); }
-        P.lstart[I + 1] = P.lstart[I] + run;
-    }
-    P.NW = P.gstart[p];
-    const size_t p2 = (size_t)p * p;
-    const size_t nw1 = (size_t)std::max<long long>(P.NW, 1);
-    size_t o = 0;
-    P.o_wo = o; o = al(o + p2 * sizeof(long long));
-    P.o_lo = o; o = al(o + p2 * sizeof(int));
-    P.up_bytes = o;
-    o = 0;
-    P.o_ry = o; o = al(o + nw1 * sizeof(double));
-    P.o_rg = o; o = al(o + nw1 * sizeof(int));
-    P.o_rv = o; o = al(o + nw1 * sizeof(long long));
-    P.o_kj = o; o = al(o + nw1 * sizeof(int));
-    P.o_cc = o; o = al(o + nw1 * sizeof(int));
-    P.o_wp = o; o = al(o + nw1 * sizeof(int));
-    P.dev_bytes = o;
-}
-
-// The products of one merge as tasks of the level's two launches: (1b) the
-// skeleton columns into W; then per output block J, the diagonal block
-// A(:, J) U_JJ (generated) and W_J Y_J (loaded Y) accumulated in the same
-// tile, so C is written once.
-void add_tasks(const MergePlan& P, int K, int b, const double* cbase, const double* coff,
-               const double* scale, const std::vector<LrHalf>& halves, int wrows,
-               double* W, const double* Y, const int* d_ccol, const int* d_wpos, int fv,
-               int sv, Stage& s1b, Stage& sf, double* flops_out) {
-    const int p = P.p;
-    const int BMf = dc_gemm_tile_m(fv), BNf = dc_gemm_tile_n(fv);
-    const int BMs = dc_gemm_tile_m(sv), BNs = dc_gemm_tile_n(sv);
-    auto bsz = [&](int I) { return std::min(b, K - I * b); };
-    double flops = 0.0;
-    auto tiles = [&](GemmTask& t, int bm, int bn) {
-        t.tiles_m = (t.rows + bm - 1) / bm;
-        t.tiles_n = (t.ncol + bn - 1) / bn;
-    };
-    for (const LrHalf& H : halves) {
-        if (H.rows <= 0) continue;
-        std::vector<int> lo(p), hi(p);
-        for (int I = 0; I < p; ++I) {
-            if (H.klist.empty()) {
-                lo[I] = I * b;
-                hi[I] = I * b + bsz(I);
-            } else {
-                lo[I] = (int)(std::lower_bound(H.klist.begin(), H.klist.end(), I * b) -
-                              H.klist.begin());
-                hi[I] = (int)(std::lower_bound(H.klist.begin(), H.klist.end(), I * b + b) -
-                              H.klist.begin());
-            }
-        }
-        GemmTask base;
-        std::memset(&base, 0, sizeof(base));
-        base.lda = H.lda;
-        base.rows = H.rows;
-        base.cbase = cbase;
-        base.coff = coff;
-        base.cs = scale;
-        for (int I = 0; I < p; ++I) {
-            GemmTask t = base;
-            t.A = H.A + (long long)lo[I] * H.lda;
-            t.klen = hi[I] - lo[I];
-            t.rD = H.gD + lo[I];
-            t.rz = H.gz + lo[I];
-            // diagonal block straight into C, plus the interpolation phase
-            GemmTask a = t;
-            a.col_off = I * b;
-            a.ncol = bsz(I);
-            a.C = H.C;
-            a.ldc = H.ldc;
-            a.cpos = H.cpos;
-            a.beta = 0;
-            const long long R = P.gstart[I + 1] - P.gstart[I];
-            if (R > 0) {
-                a.A2 = W + H.w_row0 + P.gstart[I] * (long long)wrows;
-                a.lda2 = wrows;
-                a.B2 = Y + P.gstart[I] * (long long)b;
-                a.ldb2 = b;
-                a.klen2 = (int)R;
-            }
-            tiles(a, BMf, BNf);
-            sf.add(a);
-            flops += 2.0 * H.rows * (a.klen + a.klen2) * a.ncol;
-            // 1b: skeleton columns of every J != I into W
-            if (P.lstart[I + 1] > P.lstart[I]) {
-                GemmTask c = t;
-                c.ccol = d_ccol + P.lstart[I];
-                c.cpos = d_wpos + P.lstart[I];
-                c.ncol = P.lstart[I + 1] - P.lstart[I];
-                c.C = W + H.w_row0;
-                c.ldc = wrows;
-                c.beta = 0;
-                tiles(c, BMs, BNs);
-                s1b.add(c);
-                flops += 2.0 * H.rows * c.klen * c.ncol;
-            }
-        }
-    }
-    *flops_out = flops;
-}
-
-}  // namespace
-
-hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int variant,
-                               hipStream_t s) {
-    if (ms.empty()) return hipSuccess;
-    Arena& A = arena();
-    hipError_t err = arena_begin(A, s);
-    // Every merge's compression output in its own part of one slot, so that
-    // all of them are launched before their ranks come back together.
-    // One launch runs the blocks of every merge; its job list follows the
-    // outputs in the same slot.
-    const bool offsets = ms[0].coff != nullptr;
-    for (const LrMerge& M : ms)
-        if ((M.coff != nullptr) != offsets) return hipErrorInvalidValue;
-    std::vector<size_t> off(ms.size() + 1, 0);
-    for (size_t i = 0; i < ms.size(); ++i) off[i + 1] = off[i] + al(compress_bytes(ms[i].K, b));
-    char* cdev = nullptr;
+hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
+                            int srrsc_blocks, GemmTask* tskel, GemmTask* tfused, int ntasks,
+                            int* tile_start, int* totals, int b, double tol, int max_pmax,
+                            bool offsets, hipStream_t s, const hipEvent_t* ev) {
+    if (njobs <= 0) return hipSuccess;
+    const int rmax = dc_lowrank_rmax(b);
+    hipError_t err = ev ? hipEventRecord(ev[0], s) : hipSuccess;
     if (err == hipSuccess)
-        err = arena_get(A, SL_SRRSC, off.back() + job_bytes(ms.size()), &cdev);
-    std::vector<Compressed> Cm(ms.size());
-    std::vector<SrrscJob> jobs;
-    std::vector<DcRead> reads;
-    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
-        const LrMerge& M = ms[i];
-        jobs.push_back(compress_prepare(M.K, b, M.D, M.zhat, M.cbase, M.coff, M.scale, Cm[i],
-                                        cdev + off[i]));
-        reads.push_back({Cm[i].rank.data(), Cm[i].out.rank, Cm[i].rank.size() * sizeof(int)});
-    }
-    const SrrscJob* jd = nullptr;
-    const int* sd = nullptr;
-    int blocks = 0;
-    if (err == hipSuccess) err = upload_jobs(jobs, cdev + off.back(), s, &jd, &sd, &blocks);
-    if (err == hipSuccess)
-        err = launch_srrsc(jd, sd, (int)jobs.size(), blocks, b, offsets, tol, Cm[0].rmax, true,
-                           s);
-    if (err == hipSuccess) err = dc_readback(reads, s);
+        err = launch_srrsc(jobs_dev, srrsc_start, njobs, srrsc_blocks, b, offsets, tol, rmax,
+                           true, s);
     if (err != hipSuccess) return err;
-
-    // Layouts of every merge, then one place for each in the level's slots:
-    // the layout slot holds all uploaded parts first (one upload), then all
-    // device-filled parts; W and Y hold one region per merge.
-    std::vector<MergePlan> P(ms.size());
-    size_t up_total = 0, dev_total = 0, w_total = 0, y_total = 0;
-    for (size_t i = 0; i < ms.size(); ++i) {
-        ms[i].ranks = rank_summary(Cm[i]);
-        plan_layout(Cm[i], ms[i].K, b, P[i]);
-        P[i].up_off = up_total;
-        up_total += P[i].up_bytes;
-        P[i].w_off = w_total;
-        w_total += (size_t)ms[i].wrows * (size_t)P[i].NW;
-        P[i].y_off = y_total;
-        y_total += (size_t)P[i].NW * b;
-    }
-    for (size_t i = 0; i < ms.size(); ++i) {
-        P[i].dev_off = up_total + dev_total;
-        dev_total += P[i].dev_bytes;
-    }
-    char* small = nullptr;
-    double* W = nullptr;
-    double* Y = nullptr;
-    err = arena_get(A, SL_LAYOUT, up_total + dev_total, &small);
-    if (err == hipSuccess && w_total > 0)
-        err = arena_get(A, SL_W, w_total * sizeof(double), reinterpret_cast<char**>(&W));
-    if (err == hipSuccess && y_total > 0)
-        err = arena_get(A, SL_Y, y_total * sizeof(double), reinterpret_cast<char**>(&Y));
-    std::vector<char> host(up_total);
-    for (size_t i = 0; i < ms.size(); ++i) {
-        const size_t p2 = (size_t)P[i].p * P[i].p;
-        std::memcpy(host.data() + P[i].up_off + P[i].o_wo, P[i].woff.data(),
-                    p2 * sizeof(long long));
-        std::memcpy(host.data() + P[i].up_off + P[i].o_lo, P[i].loff.data(), p2 * sizeof(int));
-    }
-    if (err == hipSuccess) err = dc_upload(small, host.data(), up_total, s);
-
-    // Per merge: the per-column layout and the interpolation rows on the
-    // device, and its tasks in the level's two launches.  The fused stage
-    // needs the register kernel (variants 0 and 5).  The skeleton stage's
-    // column count per block row (a sum of ranks) is rarely a multiple of
-    // 128: with the default tile rule it takes 64 x 64 register tiles, which
-    // waste less on the last column tile.
-    const int fv = (variant == 2 || variant == 5) ? 5 : 0;
-    const int sv = variant == 0 ? 5 : variant;
-    Stage s1b, sf;
-    for (size_t i = 0; i < ms.size() && err == hipSuccess; ++i) {
-        const MergePlan& Q = P[i];
-        LrMerge& M = ms[i];
-        char* up = small + Q.up_off;
-        char* dv = small + Q.dev_off;
-        double* Wi = W ? W + Q.w_off : nullptr;
-        double* Yi = Y ? Y + Q.y_off : nullptr;
-        const int* d_ccol = reinterpret_cast<int*>(dv + Q.o_cc);
-        const int* d_wpos = reinterpret_cast<int*>(dv + Q.o_wp);
-        if (Q.NW > 0) {
-            hipLaunchKernelGGL(k_layout, dim3((unsigned)((size_t)Q.p * Q.p)), dim3(128), 0, s,
-                               Q.p, b, M.K, Cm[i].rmax, Cm[i].out.rank, Cm[i].out.pcol,
-                               Cm[i].out.y, reinterpret_cast<long long*>(up + Q.o_wo),
-                               reinterpret_cast<int*>(up + Q.o_lo),
-                               reinterpret_cast<int*>(dv + Q.o_rg),
-                               reinterpret_cast<long long*>(dv + Q.o_rv),
-                               reinterpret_cast<int*>(dv + Q.o_kj),
-                               reinterpret_cast<double*>(dv + Q.o_ry),
-                               reinterpret_cast<int*>(dv + Q.o_cc),
-                               reinterpret_cast<int*>(dv + Q.o_wp));
-            err = hipGetLastError();
-            if (err != hipSuccess) break;
-            const long long ny = Q.NW * b;
-            hipLaunchKernelGGL(k_build_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s,
-                               Q.NW, b, M.K, reinterpret_cast<double*>(dv + Q.o_ry),
-                               reinterpret_cast<int*>(dv + Q.o_rg),
-                               reinterpret_cast<long long*>(dv + Q.o_rv),
-                               reinterpret_cast<int*>(dv + Q.o_kj), Cm[i].out.vk, M.cbase,
-                               M.coff, M.scale, Yi);
-            err = hipGetLastError();
-            if (err != hipSuccess) break;
-        }
-        add_tasks(Q, M.K, b, M.cbase, M.coff, M.scale, M.halves, M.wrows, Wi, Yi, d_ccol,
-                  d_wpos, fv, sv, s1b, sf, &M.flops);
-    }
-
-    // Upload the level's task lists and launch the two stages in order.
-    constexpr int NS = 2;
-    Stage* stages[NS] = {&s1b, &sf};
-    size_t to = 0;
-    std::vector<size_t> tof(NS), sof(NS);
-    for (int i = 0; i < NS; ++i) {
-        tof[i] = to; to = al(to + std::max<size_t>(stages[i]->tasks.size(), 1) * sizeof(GemmTask));
-        sof[i] = to; to = al(to + stages[i]->start.size() * sizeof(int));
-    }
-    char* tdev = nullptr;
-    std::vector<char> th(to);
-    for (int i = 0; i < NS; ++i) {
-        if (!stages[i]->tasks.empty())
-            std::memcpy(th.data() + tof[i], stages[i]->tasks.data(),
-                        stages[i]->tasks.size() * sizeof(GemmTask));
-        std::memcpy(th.data() + sof[i], stages[i]->start.data(),
-                    stages[i]->start.size() * sizeof(int));
-    }
-    if (err == hipSuccess) err = arena_get(A, SL_TASKS, to, &tdev);
-    if (err == hipSuccess) err = dc_upload(tdev, th.data(), to, s);
-    for (int i = 0; i < NS && err == hipSuccess; ++i) {
-        const Stage& S = *stages[i];
-        if (S.tasks.empty()) continue;
-        const GemmTask* td = reinterpret_cast<GemmTask*>(tdev + tof[i]);
-        const int* sd = reinterpret_cast<int*>(tdev + sof[i]);
-        err = (&S == &sf)
-                  ? dc_launch_cauchy_gemm2(td, sd, (int)S.tasks.size(), S.start.back(), fv, s)
-                  : dc_launch_cauchy_gemm(td, sd, (int)S.tasks.size(), S.start.back(), sv, s);
-    }
-    const hipError_t e2 = arena_end(A, s);
-    return err != hipSuccess ? err : e2;
-}
-
-hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
-                              const double* cbase, const double* coff, const double* scale,
-                              std::vector<LrHalf>& halves, int wrows, int variant,
-                              hipStream_t s, double* flops_out, LrRankSummary* ranks_out) {
-    std::vector<LrMerge> ms(1);
-    LrMerge& M = ms[0];
-    M.K = K;
-    M.D = D;
-    M.zhat = zhat;
-    M.cbase = cbase;
-    M.coff = coff;
-    M.scale = scale;
-    M.halves = halves;
-    M.wrows = wrows;
-    const hipError_t err = dc_lowrank_products(b, tol, ms, variant, s);
-    if (flops_out) *flops_out = M.flops;
-    if (ranks_out) *ranks_out = M.ranks;
+    const size_t lds = (size_t)(4 * max_pmax + 2 + NT) * sizeof(int);
+    hipLaunchKernelGGL(k_lr_plan, dim3(njobs), dim3(NT), lds, s, jobs_dev, b, rmax,
+                       dc_gemm_tile_m(SKEL_VARIANT), dc_gemm_tile_n(SKEL_VARIANT),
+                       dc_gemm_tile_m(FUSED_VARIANT), dc_gemm_tile_n(FUSED_VARIANT));
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_build_y, dim3(256, njobs), dim3(256), 0, s, jobs_dev, b);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_lr_scan, dim3(1), dim3(NT), 0, s, tskel, tfused, ntasks, tile_start,
+                       totals);
+    err = hipGetLastError();
+    if (err == hipSuccess && ev) err = hipEventRecord(ev[1], s);
+    if (err == hipSuccess)
+        err = dc_launch_cauchy_gemm_dev(tskel, tile_start, ntasks, totals, totals + 8,
+                                        SKEL_VARIANT, false, s);
+    if (err == hipSuccess && ev) err = hipEventRecord(ev[2], s);
+    if (err == hipSuccess)
+        err = dc_launch_cauchy_gemm_dev(tfused, tile_start + ntasks + 1, ntasks, totals + 1,
+                                        totals + 16, FUSED_VARIANT, true, s);
+    if (err == hipSuccess && ev) err = hipEventRecord(ev[3], s);
     return err;
 }
 
@@ -837,47 +705,113 @@ hipError_t dc_node_arrays(int K, const double* Dbar, const int* org, const doubl
     return hipGetLastError();
 }
 
-hipError_t dc_disable_tasks(GemmTask* tasks, int n, const int* zero, hipStream_t s) {
-    hipLaunchKernelGGL(k_disable_tasks, dim3(1), dim3(64), 0, s, tasks, n, zero);
-    return hipGetLastError();
-}
-
-int dc_lowrank_max_block(bool offsets) { return offsets ? MAX_B_OFF : MAX_B_GEN; }
-
+// Stand-alone low-rank product C = Qnd U (one merge, one row half): the same
+// device pipeline on a temporary, stream-ordered region (W is m x K; when
+// the skeleton columns exceed it, the plain product launched behind the
+// pipeline, which the planning kernel otherwise switches off, runs instead).
 hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
                              const int* org, const double* tau, const double* zhat,
                              const double* scale, double* C, long long ldc, double lr_tol,
                              int lr_block, hipStream_t stream) {
-    if (lr_block > dc_lowrank_max_block(org != nullptr)) return hipErrorInvalidValue;
-    // Merge generators become (base, offset) column nodes; plain column nodes
-    // (org == NULL) are used as they are.
+    const int b = lr_block;
+    if (b > dc_lowrank_max_block(org != nullptr)) return hipErrorInvalidValue;
+    const int pmax = (K + b - 1) / b;
+    const int wcap = K;
+    // temporary: nodes | job | plain task | srrsc prefix | zero | tasks |
+    // tile prefix | totals | regions | W
+    size_t o = 0;
+    const size_t o_nodes = o; o = al(o + (org ? 2 * (size_t)K * sizeof(double) : 0));
+    const size_t o_job = o; o = al(o + sizeof(LrJob));
+    const size_t o_plain = o; o = al(o + sizeof(GemmTask));
+    const size_t o_small = o; o = al(o + 40 * sizeof(int));
+    const size_t o_tasks = o; o = al(o + 2 * (size_t)pmax * sizeof(GemmTask));
+    const size_t o_ts = o; o = al(o + 2 * ((size_t)pmax + 1) * sizeof(int));
+    const size_t o_reg = o; o = al(o + dc_lowrank_region_bytes(pmax, b, wcap));
+    const size_t o_w = o; o = al(o + (size_t)m * wcap * sizeof(double));
+    char* tmp = nullptr;
+    hipError_t err = hipMallocAsync((void**)&tmp, o, stream);
+    if (err != hipSuccess) return err;
     const double* cb = tau;
     const double* co = nullptr;
-    double* nodes = nullptr;
-    hipError_t err = hipSuccess;
     if (org) {
-        err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
-        if (err != hipSuccess) return err;
+        double* nodes = reinterpret_cast<double*>(tmp + o_nodes);
         err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
         cb = nodes;
         co = nodes + K;
     }
-    std::vector<LrHalf> halves(1);
-    LrHalf& H = halves[0];
+    // small: [0, p^2] SRRSC prefix, a zero, the plain task's tile prefix at
+    // 4, the totals and claim counters at 8 (24 ints)
+    int* small = reinterpret_cast<int*>(tmp + o_small);
+    GemmTask* plain = reinterpret_cast<GemmTask*>(tmp + o_plain);
+    LrJob J;
+    std::memset(&J, 0, sizeof(J));
+    J.K_p = nullptr;
+    J.K = K;
+    J.pmax = pmax;
+    J.min_k = 0;
+    J.nh = 1;
+    J.D = Dbar;
+    J.zhat = zhat;
+    J.cbase = cb;
+    J.coff = co;
+    J.scale = scale;
+    LrHalf& H = J.h[0];
     H.A = Qnd;
     H.lda = ldq;
     H.rows = m;
+    H.r0 = 0;
+    H.klist = nullptr;
+    H.klen_p = nullptr;
+    H.klen = K;
     H.gD = Dbar;
     H.gz = zhat;
     H.C = C;
     H.ldc = ldc;
     H.cpos = nullptr;
-    H.w_row0 = 0;
+    J.W = reinterpret_cast<double*>(tmp + o_w);
+    J.ldw = m;
+    J.wrows = m;
+    J.wcap = wcap;
+    J.plain = plain;
+    J.zero = small + 2;
+    J.tskel = reinterpret_cast<GemmTask*>(tmp + o_tasks);
+    J.tfused = J.tskel + pmax;
+    J.K_dev = K;
+    J.p = pmax;
+    dc_lowrank_carve(J, tmp + o_reg, b, wcap);
+    // The plain product behind the pipeline (switched off by the planning
+    // kernel unless the skeleton columns overflow W).
+    GemmTask T;
+    std::memset(&T, 0, sizeof(T));
+    const int bm = dc_gemm_tile_m(0), bn = dc_gemm_tile_n(0);
+    T.A = Qnd;
+    T.lda = ldq;
+    T.klen = K;
+    T.rows = m;
+    T.rD = Dbar;
+    T.rz = zhat;
+    T.cbase = cb;
+    T.coff = co;
+    T.cs = scale;
+    T.ncol = K;
+    T.C = C;
+    T.ldc = ldc;
+    T.tiles_m = (m + bm - 1) / bm;
+    T.tiles_n = (K + bn - 1) / bn;
+    const int small_h[8] = {0, pmax * pmax, 0, 0, 0, T.tiles_m * T.tiles_n, 0, 0};
+    if (err == hipSuccess) err = dc_write_blob(tmp + o_job, &J, sizeof(J), stream);
+    if (err == hipSuccess) err = dc_write_blob(plain, &T, sizeof(T), stream);
+    if (err == hipSuccess) err = dc_write_blob(small, small_h, sizeof(small_h), stream);
+    int* ts = reinterpret_cast<int*>(tmp + o_ts);
     if (err == hipSuccess)
-        err = dc_lowrank_product(K, lr_block, lr_tol, Dbar, zhat, cb, co, scale, halves, m, 0,
-                                 stream, nullptr);
-    if (nodes) hipFreeAsync(nodes, stream);
-    return err;
+        err = dc_lowrank_level(reinterpret_cast<LrJob*>(tmp + o_job), 1, small, pmax * pmax,
+                               J.tskel, J.tfused, pmax, ts, small + 8, b, lr_tol, pmax,
+                               co != nullptr, stream, nullptr);
+    // plain fallback: tile prefix {0, tiles} at small[4..5]
+    if (err == hipSuccess)
+        err = dc_launch_cauchy_gemm(plain, small + 4, 1, T.tiles_m * T.tiles_n, 0, stream);
+    const hipError_t e2 = hipFreeAsync(tmp, stream);
+    return err != hipSuccess ? err : e2;
 }
 
 extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
@@ -894,61 +828,53 @@ extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
     if (lr_block > dc_lowrank_max_block(org != nullptr)) return -8;
     if (rank_cap < 0) return -9;
     if (!ranks_host) return -10;
+    const int b = lr_block;
+    const int p = (K + b - 1) / b;
+    const size_t p2 = (size_t)p * p;
+    // rank_cap 0: the ranks the low-rank product itself uses (full SRRSC
+    // output); > 0: count only, up to rank_cap
+    const size_t reg = rank_cap == 0 ? dc_lowrank_region_bytes(p, b, 1) : al(p2 * sizeof(int));
+    size_t o = 0;
+    const size_t o_nodes = o; o = al(o + (org ? 2 * (size_t)K * sizeof(double) : 0));
+    const size_t o_job = o; o = al(o + sizeof(LrJob));
+    const size_t o_start = o; o = al(o + 2 * sizeof(int));
+    const size_t o_reg = o; o = al(o + reg);
+    char* tmp = nullptr;
+    hipError_t err = hipMallocAsync((void**)&tmp, o, stream);
+    if (err != hipSuccess) return (int)err;
     const double* cb = tau;
     const double* co = nullptr;
-    double* nodes = nullptr;
-    hipError_t err = hipSuccess;
     if (org) {
-        err = hipMallocAsync((void**)&nodes, 2 * (size_t)K * sizeof(double), stream);
-        if (err != hipSuccess) return (int)err;
+        double* nodes = reinterpret_cast<double*>(tmp + o_nodes);
         err = dc_node_arrays(K, Dbar, org, tau, nodes, nodes + K, stream);
         cb = nodes;
         co = nodes + K;
     }
-    const int p = (K + lr_block - 1) / lr_block;
-    const size_t p2 = (size_t)p * p;
-    const SrrscJob* jd = nullptr;
-    const int* sd = nullptr;
-    int blocks = 0;
-    if (rank_cap == 0) {
-        // the ranks the low-rank product itself uses
-        Compressed Cm;
-        char* cdev = nullptr;
-        const size_t cb_bytes = al(compress_bytes(K, lr_block));
-        if (err == hipSuccess)
-            err = hipMallocAsync((void**)&cdev, cb_bytes + job_bytes(1), stream);
-        if (err == hipSuccess) {
-            const std::vector<SrrscJob> jobs{
-                compress_prepare(K, lr_block, Dbar, zhat, cb, co, scale, Cm, cdev)};
-            err = upload_jobs(jobs, cdev + cb_bytes, stream, &jd, &sd, &blocks);
-            if (err == hipSuccess)
-                err = launch_srrsc(jd, sd, 1, blocks, lr_block, co != nullptr, lr_tol, Cm.rmax,
-                                   true, stream);
-        }
-        if (err == hipSuccess)
-            err = dc_readback({{ranks_host, Cm.out.rank, p2 * sizeof(int)}}, stream);
-        if (cdev) hipFreeAsync(cdev, stream);
-    } else {
-        // count only, up to rank_cap
-        char* rdev = nullptr;
-        const size_t rk_bytes = al(p2 * sizeof(int));
-        if (err == hipSuccess)
-            err = hipMallocAsync((void**)&rdev, rk_bytes + job_bytes(1), stream);
-        if (err == hipSuccess) {
-            SrrscOut out{};
-            out.rank = reinterpret_cast<int*>(rdev);
-            const std::vector<SrrscJob> jobs{SrrscJob{K, p, Dbar, zhat, cb, co, scale, out}};
-            err = upload_jobs(jobs, rdev + rk_bytes, stream, &jd, &sd, &blocks);
-            if (err == hipSuccess)
-                err = launch_srrsc(jd, sd, 1, blocks, lr_block, co != nullptr, lr_tol,
-                                   std::min(rank_cap, lr_block), false, stream);
-        }
-        if (err == hipSuccess)
-            err = hipMemcpyAsync(ranks_host, rdev, p2 * sizeof(int), hipMemcpyDeviceToHost,
-                                 stream);
-        if (rdev) hipFreeAsync(rdev, stream);
-    }
-    if (nodes) hipFreeAsync(nodes, stream);
-    hipError_t e2 = hipStreamSynchronize(stream);
-    return (int)(err != hipSuccess ? err : e2);
+    LrJob J;
+    std::memset(&J, 0, sizeof(J));
+    J.K = K;
+    J.K_dev = K;
+    J.pmax = p;
+    J.p = p;
+    J.D = Dbar;
+    J.zhat = zhat;
+    J.cbase = cb;
+    J.coff = co;
+    J.scale = scale;
+    if (rank_cap == 0) dc_lowrank_carve(J, tmp + o_reg, b, 1);
+    else J.rank = reinterpret_cast<int*>(tmp + o_reg);
+    const int st[2] = {0, (int)p2};
+    if (err == hipSuccess) err = dc_write_blob(tmp + o_job, &J, sizeof(J), stream);
+    if (err == hipSuccess) err = dc_write_blob(tmp + o_start, st, sizeof(st), stream);
+    if (err == hipSuccess)
+        err = launch_srrsc(reinterpret_cast<LrJob*>(tmp + o_job),
+                           reinterpret_cast<int*>(tmp + o_start), 1, (int)p2, b, co != nullptr,
+                           lr_tol, rank_cap == 0 ? dc_lowrank_rmax(b) : std::min(rank_cap, b),
+                           rank_cap == 0, stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(ranks_host, J.rank, p2 * sizeof(int), hipMemcpyDeviceToHost,
+                             stream);
+    const hipError_t e2 = hipFreeAsync(tmp, stream);
+    const hipError_t e3 = hipStreamSynchronize(stream);
+    return (int)(err != hipSuccess ? err : (e2 != hipSuccess ? e2 : e3));
 }

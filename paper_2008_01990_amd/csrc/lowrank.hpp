@@ -1,4 +1,6 @@
-// Structured low-rank merge product (SRRSC compression + generated products).
+// Structured low-rank merge product (SRRSC compression + generated products),
+// planned and launched on the device: no host read sits between its kernels,
+// so a tree level that takes it can be captured in a graph.
 #pragma once
 #include <vector>
 
@@ -6,61 +8,124 @@
 
 // One row half of a merge product: C[rows, :] = A[rows, panel] * U[panel, :],
 // where panel column t holds the basis column of survivor klist[t] (klist
-// ascending; empty means the identity 0..K-1) and gD / gz are the row
+// ascending; null means the identity 0..K-1) and gD / gz are the row
 // generators in panel order.
 struct LrHalf {
-    const double* A = nullptr;
-    long long lda = 0;
-    int rows = 0;
-    std::vector<int> klist;
-    const double* gD = nullptr;
-    const double* gz = nullptr;
-    double* C = nullptr;
-    long long ldc = 0;
-    const int* cpos = nullptr;   // output column of generator g (null: g)
-    long long w_row0 = 0;        // row offset of this half inside W
+    const double* A;
+    long long lda;
+    int rows;
+    int r0;               // first row of the half inside the merge (and W)
+    const int* klist;     // survivor list of the half, or null (= 0..K-1)
+    const int* klen_p;    // device length of klist, or null (= klen)
+    int klen;
+    const double* gD;
+    const double* gz;
+    double* C;
+    long long ldc;
+    const int* cpos;      // output column of generator g (null: g)
 };
 
-// Low-rank product over the given halves (host-synchronising: reads the
-// ranks).  cbase/coff are the column nodes w_j = cbase_j + coff_j (coff null:
-// plain nodes w_j = cbase_j), scale the column scales.  wrows
-// is the row count of the skeleton panel W (sum of the halves' rows).
-// Ranks of the off-diagonal blocks of one low-rank product: block count,
-// sum and maximum of the ranks of the compressed blocks, blocks kept dense.
-struct LrRankSummary {
-    int blocks = 0, rank_sum = 0, rank_max = 0, dense = 0;
+// Per-merge record of the low-rank path, written on the device.
+struct LrRec {
+    int active;           // 1: the merge took the low-rank product
+    int nw;               // W columns: sum of the skeleton sizes
+    int blocks, rank_sum, rank_max, dense;   // off-diagonal blocks
+    double flops_skel, flops_fused;          // executed product flops
 };
 
-hipError_t dc_lowrank_product(int K, int b, double tol, const double* D, const double* zhat,
-                              const double* cbase, const double* coff, const double* scale,
-                              std::vector<LrHalf>& halves, int wrows, int variant,
-                              hipStream_t s, double* flops_out,
-                              LrRankSummary* ranks_out = nullptr);
-
-// One merge of dc_lowrank_products: its generators and halves as for
-// dc_lowrank_product; flops and ranks are filled in.
-struct LrMerge {
-    int K = 0;
-    const double* D = nullptr;
-    const double* zhat = nullptr;
-    const double* cbase = nullptr;
-    const double* coff = nullptr;
-    const double* scale = nullptr;
-    std::vector<LrHalf> halves;
-    int wrows = 0;
-    double flops = 0.0;
-    LrRankSummary ranks;
+// Everything the device pipeline of one low-rank merge reads and writes.
+// The driver fills these on the device (they hold the call's pointers);
+// the stand-alone entry points fill them on the host.
+struct LrJob {
+    const int* K_p;       // device K, or null (= K)
+    int K;
+    int pmax;             // block grid bound: ceil(max K / b)
+    int min_k;            // take the low-rank product when K >= min_k and K > b
+    int nh;               // number of row halves (1 or 2)
+    const double *D, *zhat, *cbase, *coff, *scale;   // generators (coff null: plain nodes)
+    LrHalf h[2];
+    double* W;            // skeleton columns: wrows x wcap, leading dimension ldw
+    long long ldw;
+    int wrows, wcap;
+    GemmTask* plain;      // nh plain product tasks, disabled when the merge switches
+    const int* zero;      // an int 0 for the disabled tasks' column count
+    // SRRSC output (pmax^2 blocks, rmax skeleton columns each)
+    int* rank;
+    int* prow;
+    int* pcol;
+    double* y;
+    double* vk;           // pmax^2 x b: v^(r) of each block's columns
+    int* woff;            // pmax^2: first W column of block (I, J)
+    // per W column (wcap): interpolation rows and the skeleton column lists
+    double* Y;            // wcap x b, row-major
+    int* rgen;
+    long long* rvo;
+    int* kJ;
+    double* ry;
+    int* ccol;
+    int* wpos;
+    GemmTask* tskel;      // nh * pmax skeleton tasks
+    GemmTask* tfused;     // nh * pmax fused tasks
+    LrRec* rec;
+    // set on the device before compression
+    int K_dev, p;         // this call's K and block count (p = 0: plain path)
 };
-
-// Low-rank products of several merges (one tree level) on one stream: every
-// compression is launched first and all ranks are read in one round trip,
-// then each merge's products follow in turn (host-synchronising once).
-hipError_t dc_lowrank_products(int b, double tol, std::vector<LrMerge>& ms, int variant,
-                               hipStream_t s);
 
 // Largest block size b of the compression: with column offsets (merge nodes)
 // or with plain column nodes.
 int dc_lowrank_max_block(bool offsets);
+// Skeleton-column cap of one block: min(128, b / 2).
+int dc_lowrank_rmax(int b);
+
+// Device bytes of one merge's low-rank regions (SRRSC output, layout, Y,
+// record) for block grid pmax, block b and W capacity wcap.
+size_t dc_lowrank_region_bytes(int pmax, int b, int wcap);
+// Points the job's region pointers into `dev` (dc_lowrank_region_bytes;
+// J.pmax must be set).
+__host__ __device__ inline void dc_lowrank_carve(LrJob& J, char* dev, int b, int wcap) {
+    const size_t p2 = (size_t)J.pmax * J.pmax;
+    const size_t rmax = b / 2 < 128 ? (b / 2 > 1 ? b / 2 : 1) : 128;
+    const size_t w = wcap > 1 ? wcap : 1;
+    auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t o = 0;
+    J.rank = reinterpret_cast<int*>(dev + o); o = a(o + p2 * sizeof(int));
+    J.woff = reinterpret_cast<int*>(dev + o); o = a(o + p2 * sizeof(int));
+    J.prow = reinterpret_cast<int*>(dev + o); o = a(o + p2 * rmax * sizeof(int));
+    J.pcol = reinterpret_cast<int*>(dev + o); o = a(o + p2 * rmax * sizeof(int));
+    J.y = reinterpret_cast<double*>(dev + o); o = a(o + p2 * rmax * sizeof(double));
+    J.vk = reinterpret_cast<double*>(dev + o); o = a(o + p2 * (size_t)b * sizeof(double));
+    J.Y = reinterpret_cast<double*>(dev + o); o = a(o + w * (size_t)b * sizeof(double));
+    J.rgen = reinterpret_cast<int*>(dev + o); o = a(o + w * sizeof(int));
+    J.kJ = reinterpret_cast<int*>(dev + o); o = a(o + w * sizeof(int));
+    J.ccol = reinterpret_cast<int*>(dev + o); o = a(o + w * sizeof(int));
+    J.wpos = reinterpret_cast<int*>(dev + o); o = a(o + w * sizeof(int));
+    J.rvo = reinterpret_cast<long long*>(dev + o); o = a(o + w * sizeof(long long));
+    J.ry = reinterpret_cast<double*>(dev + o); o = a(o + w * sizeof(double));
+    J.rec = reinterpret_cast<LrRec*>(dev + o);
+}
+
+
+// Algorithm 3's switch on the device: sets K_dev and p (0: plain product)
+// of every job from its device K.
+hipError_t dc_lowrank_decide(LrJob* jobs_dev, int njobs, int b, hipStream_t s);
+
+// The pipeline over njobs jobs in device memory (one tree level), after
+// K_dev and p are set:
+//   SRRSC on the pmax^2 block grid of every job -> layout, tasks, records and
+//   the plain-task switch-off -> interpolation rows -> skeleton product into
+//   W -> fused product into C.
+// srrsc_start: device prefix of pmax^2 over the jobs (njobs + 1), srrsc_blocks
+// its total; tskel / tfused: the level's task lists (job j's nh * pmax tasks
+// at its own offset), ntasks in all; tile_start: device scratch of
+// 2 (ntasks + 1) ints; totals: 24 ints (the two tile totals, then the two
+// launches' claim counters at totals + 8 and + 16); max_pmax: largest pmax;
+// offsets: the column nodes carry offsets (merge generators).  ev (optional,
+// 4 events) is recorded before the compression, before the skeleton product,
+// before the fused product and after it.
+hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
+                            int srrsc_blocks, GemmTask* tskel, GemmTask* tfused, int ntasks,
+                            int* tile_start, int* totals, int b, double tol, int max_pmax,
+                            bool offsets, hipStream_t s, const hipEvent_t* ev);
 
 hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
                              const int* org, const double* tau, const double* zhat,
@@ -72,4 +137,3 @@ hipError_t dc_plain_update(int m, int K, const double* Qnd, long long ldq, const
                            int variant, hipStream_t stream);
 hipError_t dc_node_arrays(int K, const double* Dbar, const int* org, const double* tau,
                           double* cbase, double* coff, hipStream_t s);
-hipError_t dc_disable_tasks(GemmTask* tasks, int n, const int* zero, hipStream_t s);

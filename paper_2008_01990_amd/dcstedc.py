@@ -34,7 +34,8 @@ class DcOpts(ctypes.Structure):
 class MergeStat(ctypes.Structure):
     _fields_ = [("level", c_int), ("m", c_int), ("K", c_int), ("nrot", c_int),
                 ("path", c_int), ("flops", c_double), ("lr_blocks", c_int),
-                ("lr_rank_sum", c_int), ("lr_rank_max", c_int), ("lr_dense", c_int)]
+                ("lr_rank_sum", c_int), ("lr_rank_max", c_int), ("lr_dense", c_int),
+                ("lr_flops_skeleton", c_double), ("lr_flops_fused", c_double)]
 
 
 # (name, restype, argtypes) of every exported entry point.
@@ -67,6 +68,7 @@ SIGNATURES = [
     ("dc_last_stats", c_int, [ctypes.POINTER(MergeStat), c_int]),
     ("dc_profile_enable", c_int, [c_int]),
     ("dc_profile_read", c_int, [P, c_int]),
+    ("dc_profile_read_lowrank", c_int, [P, c_int]),
 ]
 
 # Extra (non-header) hooks used by tests and the benchmark.
@@ -237,7 +239,8 @@ def last_stats():
     lib.dc_last_stats(arr, cnt)
     return [dict(level=r.level, m=r.m, K=r.K, nrot=r.nrot, path=r.path, flops=r.flops,
                  lr_blocks=r.lr_blocks, lr_rank_sum=r.lr_rank_sum, lr_rank_max=r.lr_rank_max,
-                 lr_dense=r.lr_dense) for r in arr[:cnt]]
+                 lr_dense=r.lr_dense, lr_flops_skeleton=r.lr_flops_skeleton,
+                 lr_flops_fused=r.lr_flops_fused) for r in arr[:cnt]]
 
 
 PHASES = ("deflate", "rotate", "secular", "assemble", "product", "copy")
@@ -254,6 +257,19 @@ def profile_read():
     buf = (ctypes.c_double * max(6 * nl, 1))()
     lib.dc_profile_read(ctypes.cast(buf, ctypes.c_void_p), 6 * nl)
     return [dict(zip(PHASES, buf[6 * i:6 * i + 6])) for i in range(nl)]
+
+
+LR_PHASES = ("compress", "skeleton", "fused")
+
+
+def profile_read_lowrank():
+    """Per level (deepest first): dict of low-rank stage -> milliseconds
+    (0 on levels without a low-rank merge)."""
+    lib = load()
+    nl = lib.dc_profile_read_lowrank(None, 0)
+    buf = (ctypes.c_double * max(3 * nl, 1))()
+    lib.dc_profile_read_lowrank(ctypes.cast(buf, ctypes.c_void_p), 3 * nl)
+    return [dict(zip(LR_PHASES, buf[3 * i:3 * i + 3])) for i in range(nl)]
 
 
 def secular(D, z, rho, max_iter=200):

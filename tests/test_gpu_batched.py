@@ -53,9 +53,10 @@ def test_batched_matches_oracle(lib, graph):
 
 def test_batched_lowrank_matches_oracle_within_tolerance(lib):
     # Several problems whose merges of one level take the low-rank product
-    # together (one read of the level's sizes and row lists, the low-rank
-    # buffers reused across merges of different problems); the graph request
-    # falls back to the eager schedule on this path.  Bars of the low-rank
+    # together (one compression launch, one skeleton and one fused launch for
+    # the level, all planned on the device).  The batch is captured in a
+    # graph with the low-rank path included; its replays, with other work in
+    # between, equal the eager schedule bit for bit.  Bars of the low-rank
     # path at tol 1e-10: 1e-9 on residual and orthogonality.
     # (random tridiagonals deflate to K ~ 100 and never switch: 1-2-1
     # Toeplitz and Clement matrices keep most of each merge)
@@ -64,21 +65,31 @@ def test_batched_lowrank_matches_oracle_within_tolerance(lib):
     probs = [tuple(np.asarray(x) for x in g(n)) for g, n in zip(gens, sizes)]
     announce(f"batched lowrank sizes={sizes}")
     B = lib.BatchedSolver(sizes, leaf=32, lr_tol=1e-10, lr_block=128, lr_min_k=512)
-    for graph in (False, True):
-        B.load_inputs(probs)
-        B.solve(graph=graph)
-        torch.cuda.synchronize()
-        assert all(v == 0 for v in B.status())
-        for p, (d, e) in enumerate(probs):
-            lam, Q = B.result(p)
-            lam, Q = host(lam), host(Q)
-            lo = np.sort(dc.eigh_tridiagonal(np.asarray(d), np.asarray(e), leaf=32)[0])
-            tn = max(np.abs(lo).max(), 1e-300)
-            assert np.abs(lam - lo).max() <= 1e-9 * tn
-            assert metrics.orthogonality(Q) <= 1e-9
-            assert metrics.residual(np.asarray(d), np.asarray(e), lam, Q) <= 1e-9
+    B.load_inputs(probs)
+    B.solve(graph=False)
+    torch.cuda.synchronize()
+    eager = [(host(B.result(p)[0]).copy(), host(B.result(p)[1]).copy())
+             for p in range(len(sizes))]
     stats = lib.last_stats()
     assert sum(r["path"] == 1 for r in stats) >= 4    # several low-rank merges
+    for rep in range(3):
+        B.restore()
+        scratch = torch.randn(700, 700, device="cuda", dtype=torch.float64)
+        float((scratch @ scratch).sum())
+        B.solve(graph=True)
+        torch.cuda.synchronize()
+        assert all(v == 0 for v in B.status())
+        for p in range(len(sizes)):
+            lam, Q = B.result(p)
+            assert np.array_equal(host(lam), eager[p][0])
+            assert np.array_equal(host(Q), eager[p][1])
+    for p, (d, e) in enumerate(probs):
+        lam, Q = eager[p]
+        lo = np.sort(dc.eigh_tridiagonal(np.asarray(d), np.asarray(e), leaf=32)[0])
+        tn = max(np.abs(lo).max(), 1e-300)
+        assert np.abs(lam - lo).max() <= 1e-9 * tn
+        assert metrics.orthogonality(Q) <= 1e-9
+        assert metrics.residual(np.asarray(d), np.asarray(e), lam, Q) <= 1e-9
 
 
 def test_graph_replays_equal_eager(lib):

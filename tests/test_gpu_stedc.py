@@ -296,6 +296,53 @@ def test_ex_form_captured_in_a_graph(lib):
     _check_against_oracle(np.asarray(d), np.asarray(e), lam, Q, 32)
 
 
+def test_ex_form_lowrank_captured_in_a_graph(lib):
+    # The low-rank path plans on the device (Algorithm 3's switch, the
+    # compression, the layouts and task lists of the structured product), so
+    # dc_stedc_ex with lr_tol > 0 also allocates nothing and never waits on
+    # the host: captured once, replayed with new inputs and other work in
+    # between, it equals the eager solve bit for bit.
+    import torch
+    n = 3000
+    kw = dict(leaf=32, lr_tol=1e-10, lr_block=256, lr_min_k=1024)
+    rng = np.random.default_rng(93)
+    s = lib.Solver(n, **kw)                    # builds the plan and tables before capture
+    d_in = cuda(np.zeros(n))
+    e_in = cuda(np.zeros(n - 1))
+    dd = torch.empty_like(d_in)
+    Qg = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dd.copy_(d_in)
+        s.solve_into(dd, e_in, Qg)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dd.copy_(d_in)
+        s.solve_into(dd, e_in, Qg)
+    for rep in range(3):
+        announce(f"stedc_ex low-rank graph replay {rep}")
+        # perturbed 1-2-1 matrices keep most of every merge (K ~ m)
+        d = 2.0 + 1e-3 * rng.standard_normal(n)
+        e = -1.0 + 1e-3 * rng.standard_normal(n - 1)
+        d_in.copy_(cuda(d))
+        e_in.copy_(cuda(e))
+        scratch = torch.randn(800, 800, dtype=torch.float64, device="cuda")
+        float((scratch @ scratch).sum())
+        g.replay()
+        torch.cuda.synchronize()
+        lam_g, Q_g = host(dd).copy(), host(Qg).copy()
+        assert s.status() == 0
+        lam, Q = _solve(lib, d, e, **kw)
+        assert any(r["path"] == 1 for r in lib.last_stats())
+        assert np.array_equal(lam_g, lam)
+        assert np.array_equal(Q_g.T, Q)
+    assert metrics.orthogonality(Q) <= 1e-9
+    assert metrics.residual(d, e, lam, Q) <= 1e-9
+
+
 def test_concurrent_solves_from_two_threads(lib):
     # Two host threads, each with its own stream and workspace, one on the
     # plain path and one on the low-rank path (per-thread low-rank buffers
