@@ -509,94 +509,28 @@ __device__ __forceinline__ void reg_tile(const GemmTask& T, int local) {
 }
 
 
+// total_p (optional): the tile count in device memory (task lists built on
+// the device; the grid then covers an upper bound and the rest exit).
 template <int FM, int FN, int WGM, int WGN, int RING, int OCC, bool P2>
 __global__ __launch_bounds__(WGM * WGN * 64, OCC)
 void k_cauchy_gemm_reg(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
-                       int ntasks, int total_tiles) {
+                       int ntasks, int total_tiles, const int* __restrict__ total_p) {
     constexpr int G = reg_group<WGM * WGN, OCC>();
     const int t = xcd_tile<G>(blockIdx.x);
-    if (t >= total_tiles) return;
+    if (t >= (total_p ? *total_p : total_tiles)) return;
     const int ti = find_task(tile_start, ntasks, t);
     reg_tile<FM, FN, WGM, WGN, RING, P2>(
         tasks[ti], spread_local<G>(t - tile_start[ti], tile_start[ti + 1] - tile_start[ti]));
 }
 
-// The same tiles with the tile count in device memory (task lists built on
-// the device): a grid of co-resident workgroups, a multiple of 8 G, takes
-// tiles from one counter per XCD (ctr[8], zero before the launch).  A
-// workgroup on XCD x turns its k-th claim into virtual id x + 8 k, whose
-// tile lies in the groups the direct launch gives that XCD, so the tiles
-// that share A panels stay on one L2; claiming instead of a fixed stride
-// lets a workgroup that drew cheap tiles take more (tile costs vary with
-// the task's k-range).  Claims of one XCD give increasing tiles, so the
-// first one past the end ends a workgroup's walk.  Multi-wave workgroups
-// share each claim through LDS (one barrier per tile).
-template <int FM, int FN, int WGM, int WGN, int RING, int OCC, bool P2>
-__global__ __launch_bounds__(WGM * WGN * 64, OCC)
-void k_cauchy_gemm_reg_dev(const GemmTask* __restrict__ tasks, const int* __restrict__ tile_start,
-                           int ntasks, const int* __restrict__ total_p, int* __restrict__ ctr) {
-    constexpr int G = reg_group<WGM * WGN, OCC>();
-    constexpr bool MULTI = WGM * WGN > 1;
-    __shared__ int claim[MULTI ? 2 : 1];
-    const int total = *total_p;
-    const int x = blockIdx.x & 7;
-    for (int it = 0;; ++it) {
-        int k;
-        if constexpr (MULTI) {
-            if (threadIdx.x == 0) claim[it & 1] = atomicAdd(ctr + x, 1);
-            __syncthreads();
-            k = claim[it & 1];
-        } else {
-            k = (threadIdx.x & 63) == 0 ? atomicAdd(ctr + x, 1) : 0;
-            k = __shfl(k, 0, 64);
-        }
-        const int t = xcd_tile<G>(x + 8 * k);
-        if (t >= total) break;
-        const int ti = find_task(tile_start, ntasks, t);
-        reg_tile<FM, FN, WGM, WGN, RING, P2>(
-            tasks[ti], spread_local<G>(t - tile_start[ti], tile_start[ti + 1] - tile_start[ti]));
-    }
-}
-
 template <int FM, int FN, int WGM, int WGN, int RING, int OCC = 2, bool P2 = false>
 hipError_t launch_reg(const GemmTask* tasks, const int* tile_start, int ntasks, int total,
-                      hipStream_t s) {
+                      hipStream_t s, const int* total_p = nullptr) {
     constexpr int G8 = 8 * reg_group<WGM * WGN, OCC>();
     const int grid = (total + G8 - 1) / G8 * G8;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((k_cauchy_gemm_reg<FM, FN, WGM, WGN, RING, OCC, P2>), dim3(grid),
-                       dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total);
-    return hipGetLastError();
-}
-
-// Co-resident workgroups of a register-kernel instance on the current device
-// (compute units x OCC waves per SIMD x 4 SIMDs / waves per workgroup),
-// rounded up to a multiple of 8 G.
-template <int WAVES, int OCC>
-int resident_grid() {
-    static int cus[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (cus[dev] == 0) {
-        int c = 0;
-        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            c <= 0)
-            c = 256;
-        cus[dev] = c;
-    }
-    constexpr int G8 = 8 * reg_group<WAVES, OCC>();
-    const int per_cu = (4 * OCC) / WAVES > 0 ? (4 * OCC) / WAVES : 1;
-    const int want = cus[dev] * per_cu;
-    return (want + G8 - 1) / G8 * G8;
-}
-
-template <int FM, int FN, int WGM, int WGN, int RING, int OCC = 2, bool P2 = false>
-hipError_t launch_reg_dev(const GemmTask* tasks, const int* tile_start, int ntasks,
-                          const int* total_p, int* ctr, hipStream_t s) {
-    if (ntasks <= 0) return hipSuccess;
-    const int grid = resident_grid<WGM * WGN, OCC>();
-    hipLaunchKernelGGL((k_cauchy_gemm_reg_dev<FM, FN, WGM, WGN, RING, OCC, P2>), dim3(grid),
-                       dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total_p, ctr);
+                       dim3(WGM * WGN * 64), 0, s, tasks, tile_start, ntasks, total, total_p);
     return hipGetLastError();
 }
 
@@ -659,18 +593,19 @@ hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks, const int* tile_start, 
     return hipErrorInvalidValue;
 }
 
-hipError_t dc_launch_cauchy_gemm_dev(const GemmTask* tasks, const int* tile_start, int ntasks,
-                                     const int* total_p, int* ctr, int variant, bool two_phase,
-                                     hipStream_t s) {
+hipError_t dc_launch_cauchy_gemm_bounded(const GemmTask* tasks, const int* tile_start,
+                                         int ntasks, int max_tiles, const int* total_p,
+                                         int variant, bool two_phase, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
     if (variant == 5)
-        return two_phase ? launch_reg_dev<4, 4, 1, 1, 4, 2, true>(tasks, tile_start, ntasks,
-                                                                  total_p, ctr, s)
-                         : launch_reg_dev<4, 4, 1, 1, 4, 2, false>(tasks, tile_start, ntasks,
-                                                                   total_p, ctr, s);
+        return two_phase ? launch_reg<4, 4, 1, 1, 4, 2, true>(tasks, tile_start, ntasks,
+                                                              max_tiles, s, total_p)
+                         : launch_reg<4, 4, 1, 1, 4, 2, false>(tasks, tile_start, ntasks,
+                                                               max_tiles, s, total_p);
     if (variant == 0)
-        return two_phase ? launch_reg_dev<8, 2, 1, 4, 3, 2, true>(tasks, tile_start, ntasks,
-                                                                  total_p, ctr, s)
-                         : launch_reg_dev<8, 2, 1, 4, 3, 2, false>(tasks, tile_start, ntasks,
-                                                                   total_p, ctr, s);
+        return two_phase ? launch_reg<8, 2, 1, 4, 3, 2, true>(tasks, tile_start, ntasks,
+                                                              max_tiles, s, total_p)
+                         : launch_reg<8, 2, 1, 4, 3, 2, false>(tasks, tile_start, ntasks,
+                                                               max_tiles, s, total_p);
     return hipErrorInvalidValue;
 }

@@ -118,13 +118,13 @@ hipError_t dc_launch_cauchy_gemm(const GemmTask* tasks_dev, const int* tile_star
 hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks_dev, const int* tile_start_dev,
                                   int ntasks, int total_tiles, int variant,
                                   hipStream_t stream);
-// Tasks and tile prefix built on the device, total tile count in device
-// memory: a grid of co-resident workgroups claims the tiles from eight
-// device counters (ctr, zero before the launch) (register kernel: variant 0
-// or 5; two_phase as dc_launch_cauchy_gemm2).
-hipError_t dc_launch_cauchy_gemm_dev(const GemmTask* tasks_dev, const int* tile_start_dev,
-                                     int ntasks, const int* total_tiles_dev, int* ctr,
-                                     int variant, bool two_phase, hipStream_t stream);
+// Tasks built on the device, with the tile prefix and the total tile count
+// in device memory: a direct launch over max_tiles (an upper bound known on
+// the host) in which the tiles past the total exit at once (register
+// kernel, variant 0 or 5).
+hipError_t dc_launch_cauchy_gemm_bounded(const GemmTask* tasks_dev, const int* tile_start_dev,
+                                         int ntasks, int max_tiles, const int* total_tiles_dev,
+                                         int variant, bool two_phase, hipStream_t stream);
 // Number of merge-product tile variants (0 .. DC_TILE_VARIANTS - 1).
 constexpr int DC_TILE_VARIANTS = 6;
 int dc_gemm_tile_m(int variant);

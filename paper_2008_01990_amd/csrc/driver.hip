@@ -69,6 +69,7 @@ struct LrLevel {
     int task0 = 0, ntasks = 0;     // its tasks in the task lists
     int ts_off = 0;                // its tile prefix scratch (2 (ntasks + 1) ints)
     int max_pmax = 0;
+    int tiles_skel = 0, tiles_fused = 0;   // tile bounds of its two launches
 };
 
 struct LrPlan {
@@ -335,6 +336,10 @@ std::unique_ptr<LrPlan> make_lr(const Plan& P, int b, int min_k, std::vector<int
             if (starts) starts->push_back(acc);
             acc += c.pmax * c.pmax;
             LL.max_pmax = std::max(LL.max_pmax, c.pmax);
+            for (int rows : {N.n1, N.n2}) {
+                LL.tiles_skel += dc_lowrank_max_skel_tiles(rows, m, c.pmax);
+                LL.tiles_fused += dc_lowrank_max_fused_tiles(rows, m, b, c.pmax);
+            }
             L->cand_of_merge[c.merge] = (int)L->cands.size();
             L->cands.push_back(c);
         }
@@ -350,7 +355,7 @@ std::unique_ptr<LrPlan> make_lr(const Plan& P, int b, int min_k, std::vector<int
     L->o_tskel = o; o = align256(o + (size_t)ntask * sizeof(GemmTask));
     L->o_tfused = o; o = align256(o + (size_t)ntask * sizeof(GemmTask));
     L->o_ts = o; o = align256(o + (size_t)ts * sizeof(int));
-    L->o_tot = o; o = align256(o + 32 * P.levels.size() * sizeof(int));
+    L->o_tot = o; o = align256(o + 2 * P.levels.size() * sizeof(int));
     L->o_reg = o; o += reg;
     L->bytes = L->cands.empty() ? 0 : o;
     return L;
@@ -540,7 +545,7 @@ hipError_t lowrank_level(const LrPlan& LP, int li, char* lrbase, double tol, hip
     GemmTask* tskel = reinterpret_cast<GemmTask*>(lrbase + LP.o_tskel) + LL.task0;
     GemmTask* tfused = reinterpret_cast<GemmTask*>(lrbase + LP.o_tfused) + LL.task0;
     int* ts = reinterpret_cast<int*>(lrbase + LP.o_ts) + LL.ts_off;
-    int* tot = reinterpret_cast<int*>(lrbase + LP.o_tot) + 32 * li;
+    int* tot = reinterpret_cast<int*>(lrbase + LP.o_tot) + 2 * li;
     hipError_t err = dc_lowrank_decide(jobs, LL.njobs, LP.b, s);
     if (err != hipSuccess) return err;
     hipEvent_t ev[4];
@@ -548,8 +553,8 @@ hipError_t lowrank_level(const LrPlan& LP, int li, char* lrbase, double tol, hip
     err = prof_lr_events(li, ev, &prof);
     if (err != hipSuccess) return err;
     return dc_lowrank_level(jobs, LL.njobs, LP.d_start + LL.start_off, LL.srrsc_blocks, tskel,
-                            tfused, LL.ntasks, ts, tot, LP.b, tol, LL.max_pmax, true, s,
-                            prof ? ev : nullptr);
+                            tfused, LL.ntasks, ts, tot, LP.b, tol, LL.max_pmax,
+                            LL.tiles_skel, LL.tiles_fused, true, s, prof ? ev : nullptr);
 }
 
 hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& probs,
@@ -1214,10 +1219,12 @@ extern "C" int dc_autotune_batched(int count, const int* n_host, double* const* 
         for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
             err = restore_d();
             if (err == hipSuccess) err = dc_fill_int(info_dev, count, 0, stream);
-            // the plain product on every level (the tile variants are its)
-            dc_opts op = o;
-            op.lr_tol = 0.0;
-            if (err == hipSuccess) err = run_plan(*Pv, nullptr, probs, w, op, stream);
+            // levels that switch to the low-rank product keep it (the tile
+            // variants are the plain product's, timed where it runs)
+            LrPlan* LPv = nullptr;
+            if (err == hipSuccess && o.lr_tol > 0.0)
+                err = get_lr_plan(*Pv, o.lr_block, o.lr_min_k, &LPv);
+            if (err == hipSuccess) err = run_plan(*Pv, LPv, probs, w, o, stream);
             for (int li = 0; li < nl && err == hipSuccess; ++li) {
                 const size_t a = (size_t)li * (NPHASE + 1);
                 float t = 0.0f;

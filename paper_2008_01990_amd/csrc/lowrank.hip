@@ -544,15 +544,13 @@ __global__ void k_build_y(const LrJob* __restrict__ jobs, int b) {
 }
 
 // Exclusive prefix of the tiles of a level's tasks (skeleton list, then
-// fused list), the two totals, and the two launches' claim counters (8 each,
-// at totals + 8 and totals + 16) cleared.
+// fused list) and the two totals.
 __global__ __launch_bounds__(NT)
 void k_lr_scan(const GemmTask* __restrict__ tskel, const GemmTask* __restrict__ tfused,
                int ntasks, int* __restrict__ tile_start, int* __restrict__ totals) {
     __shared__ int wsum[NT / 64];
     __shared__ int carry;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid >= 8 && tid < 24) totals[tid] = 0;
     for (int st = 0; st < 2; ++st) {
         const GemmTask* T = st ? tfused : tskel;
         int* out = tile_start + st * (ntasks + 1);
@@ -634,17 +632,38 @@ hipError_t launch_srrsc(const LrJob* jobs, const int* start, int njobs, int bloc
 }
 
 // Tile shapes of the two product launches (register kernel variants): the
-// fused launch takes 128 x 128 tiles of 128 x 32 waves; the skeleton launch
-// takes 64 x 64 one-wave tiles (its k-range is one block, b, and its column
-// counts are sums of ranks: there the 128-row waves ran at 39% of peak
-// against 58-65% for 64 x 64, whose generated entries feed twice as many
-// MFMAs per loaded A value).
+// fused launch takes 128 x 128 tiles of 128 x 32 waves; the skeleton launch,
+// whose k-range is one block (b) and whose column counts are sums of ranks,
+// takes 64 x 64 one-wave tiles: such a wave feeds each generated entry to
+// twice as many MFMAs per loaded A value as a 128 x 32 one (those ran the
+// skeleton columns at 39% of peak, 64 x 64 at 58-65%), and one-wave groups
+// leave no slot idle where a row panel's last column tile is partial.  The
+// Both launches are direct, over tile-count bounds known on the host: the
+// fused launch's count depends only on the block count p <= pmax; the
+// skeleton's on the ranks, and is bounded through W's capacity: a row half's
+// column tiles over its p block rows number at most (wcap + 63 pmax) / 64.
+// The tiles past the device's count exit at once (a launch of 65536 empty
+// workgroups takes about 0.06 ms); grids of resident waves that walked or
+// claimed the skeleton tiles instead fetched 1.5x as much (their tiles
+// sharing an A panel ran less together) and ran 7-9% longer.
 constexpr int FUSED_VARIANT = 0;
 constexpr int SKEL_VARIANT = 5;
 
 }  // namespace
 
 int dc_lowrank_max_block(bool offsets) { return offsets ? MAX_B_OFF : MAX_B_GEN; }
+
+int dc_lowrank_max_skel_tiles(int rows, int wcap, int pmax) {
+    const int bm = dc_gemm_tile_m(SKEL_VARIANT), bn = dc_gemm_tile_n(SKEL_VARIANT);
+    return ((rows + bm - 1) / bm) * ((wcap + (bn - 1) * pmax) / bn);
+}
+
+int dc_lowrank_max_fused_tiles(int rows, int m, int b, int pmax) {
+    const int bm = dc_gemm_tile_m(FUSED_VARIANT), bn = dc_gemm_tile_n(FUSED_VARIANT);
+    int t = 0;
+    for (int I = 0; I < pmax; ++I) t += (std::min(b, m - I * b) + bn - 1) / bn;
+    return t * ((rows + bm - 1) / bm);
+}
 int dc_lowrank_rmax(int b) { return std::min(MAX_R, std::max(1, b / 2)); }
 
 size_t dc_lowrank_region_bytes(int pmax, int b, int wcap) {
@@ -666,7 +685,8 @@ hipError_t dc_lowrank_decide(LrJob* jobs_dev, int njobs, int b, hipStream_t s) {
 hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
                             int srrsc_blocks, GemmTask* tskel, GemmTask* tfused, int ntasks,
                             int* tile_start, int* totals, int b, double tol, int max_pmax,
-                            bool offsets, hipStream_t s, const hipEvent_t* ev) {
+                            int max_tiles_skel, int max_tiles_fused, bool offsets,
+                            hipStream_t s, const hipEvent_t* ev) {
     if (njobs <= 0) return hipSuccess;
     const int rmax = dc_lowrank_rmax(b);
     hipError_t err = ev ? hipEventRecord(ev[0], s) : hipSuccess;
@@ -688,12 +708,12 @@ hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
     err = hipGetLastError();
     if (err == hipSuccess && ev) err = hipEventRecord(ev[1], s);
     if (err == hipSuccess)
-        err = dc_launch_cauchy_gemm_dev(tskel, tile_start, ntasks, totals, totals + 8,
-                                        SKEL_VARIANT, false, s);
+        err = dc_launch_cauchy_gemm_bounded(tskel, tile_start, ntasks, max_tiles_skel, totals,
+                                            SKEL_VARIANT, false, s);
     if (err == hipSuccess && ev) err = hipEventRecord(ev[2], s);
     if (err == hipSuccess)
-        err = dc_launch_cauchy_gemm_dev(tfused, tile_start + ntasks + 1, ntasks, totals + 1,
-                                        totals + 16, FUSED_VARIANT, true, s);
+        err = dc_launch_cauchy_gemm_bounded(tfused, tile_start + ntasks + 1, ntasks,
+                                            max_tiles_fused, totals + 1, FUSED_VARIANT, true, s);
     if (err == hipSuccess && ev) err = hipEventRecord(ev[3], s);
     return err;
 }
@@ -723,7 +743,7 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     const size_t o_nodes = o; o = al(o + (org ? 2 * (size_t)K * sizeof(double) : 0));
     const size_t o_job = o; o = al(o + sizeof(LrJob));
     const size_t o_plain = o; o = al(o + sizeof(GemmTask));
-    const size_t o_small = o; o = al(o + 40 * sizeof(int));
+    const size_t o_small = o; o = al(o + 16 * sizeof(int));
     const size_t o_tasks = o; o = al(o + 2 * (size_t)pmax * sizeof(GemmTask));
     const size_t o_ts = o; o = al(o + 2 * ((size_t)pmax + 1) * sizeof(int));
     const size_t o_reg = o; o = al(o + dc_lowrank_region_bytes(pmax, b, wcap));
@@ -740,7 +760,7 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
         co = nodes + K;
     }
     // small: [0, p^2] SRRSC prefix, a zero, the plain task's tile prefix at
-    // 4, the totals and claim counters at 8 (24 ints)
+    // 4, the two launches' tile totals at 8
     int* small = reinterpret_cast<int*>(tmp + o_small);
     GemmTask* plain = reinterpret_cast<GemmTask*>(tmp + o_plain);
     LrJob J;
@@ -806,7 +826,9 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     if (err == hipSuccess)
         err = dc_lowrank_level(reinterpret_cast<LrJob*>(tmp + o_job), 1, small, pmax * pmax,
                                J.tskel, J.tfused, pmax, ts, small + 8, b, lr_tol, pmax,
-                               co != nullptr, stream, nullptr);
+                               dc_lowrank_max_skel_tiles(m, wcap, pmax),
+                               dc_lowrank_max_fused_tiles(m, K, b, pmax), co != nullptr,
+                               stream, nullptr);
     // plain fallback: tile prefix {0, tiles} at small[4..5]
     if (err == hipSuccess)
         err = dc_launch_cauchy_gemm(plain, small + 4, 1, T.tiles_m * T.tiles_n, 0, stream);

@@ -117,15 +117,24 @@ hipError_t dc_lowrank_decide(LrJob* jobs_dev, int njobs, int b, hipStream_t s);
 // srrsc_start: device prefix of pmax^2 over the jobs (njobs + 1), srrsc_blocks
 // its total; tskel / tfused: the level's task lists (job j's nh * pmax tasks
 // at its own offset), ntasks in all; tile_start: device scratch of
-// 2 (ntasks + 1) ints; totals: 24 ints (the two tile totals, then the two
-// launches' claim counters at totals + 8 and + 16); max_pmax: largest pmax;
+// 2 (ntasks + 1) ints; totals: 2 ints; max_pmax: largest pmax;
+// max_tiles_skel / max_tiles_fused: upper bounds of the two launches' tiles
+// (the sums of dc_lowrank_max_skel_tiles / _fused_tiles over the jobs'
+// halves);
 // offsets: the column nodes carry offsets (merge generators).  ev (optional,
 // 4 events) is recorded before the compression, before the skeleton product,
 // before the fused product and after it.
 hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
                             int srrsc_blocks, GemmTask* tskel, GemmTask* tfused, int ntasks,
                             int* tile_start, int* totals, int b, double tol, int max_pmax,
-                            bool offsets, hipStream_t s, const hipEvent_t* ev);
+                            int max_tiles_skel, int max_tiles_fused, bool offsets,
+                            hipStream_t s, const hipEvent_t* ev);
+// Upper bound of the skeleton launch's tiles for one row half of `rows` rows
+// whose W holds at most wcap columns, over pmax blocks.
+int dc_lowrank_max_skel_tiles(int rows, int wcap, int pmax);
+// Upper bound of the fused launch's tiles for one row half of `rows` rows of
+// a merge of order m (K <= m) over pmax blocks of b.
+int dc_lowrank_max_fused_tiles(int rows, int m, int b, int pmax);
 
 hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, const double* Dbar,
                              const int* org, const double* tau, const double* zhat,
