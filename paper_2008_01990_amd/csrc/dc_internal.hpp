@@ -58,10 +58,13 @@ struct Scratch {
     int *perm;                  // sorted position -> local column
     int *surv, *stype;          // survivor -> local column, row-type bits
     int *org;                   // root origin (K)
-    int *dcol, *dtype;          // deflated -> local column, row-type bits
+    int *dcol, *dtype;          // deflated -> local column, row-type bits (1 top rows,
+                                //   2 bottom rows; 8: deflated by rotation t = dtype >> 4)
     int *rp, *ri, *rt;          // rotation column pair and row-type bits (p | i << 2)
     int *rch;                   // first rotation of each rotation chain
     int *ktop, *kbot;           // generator lists of the top and bottom row halves
+    int *ptop, *pbot;           // place of each survivor in those lists
+    int *rdk;                   // deflated-list entry of the column rotation t deflates
     int *pos_root, *pos_defl;   // output column of each root / deflated pair
     MergeCnt* cnt;              // per merge slot
     double* rho2;               // per merge slot: 2 |e_k|

@@ -460,11 +460,12 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
                 S.rc[base + orr] = c;
                 S.rs[base + orr] = sn;
                 S.rt[base + orr] = st.typ | (ti << 2);
-                ++orr;
                 const int trig = SI[k + 1];
                 tV[trig] = dv;
                 tC[trig] = st.col;
-                tT[trig] = nx.typ;                     // typ_p | typ_i
+                // typ_p | typ_i, the rotation flag and the rotation's index
+                tT[trig] = nx.typ | 8 | (orr << 4);
+                ++orr;
             } else {
                 put_surv(st, os++, orr - 1);
             }
@@ -537,15 +538,20 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         S.rho2[N.slot] = rho2;
     }
     __syncthreads();
+    // Each rotation's deflated column: its entry in the final deflated list
+    // (the rotation kernel writes it straight to its output column).
+    for (int k = tid; k < nd; k += NT) {
+        const int t = S.dtype[base + k];
+        if (t & 8) S.rdk[base + (t >> 4)] = k;
+    }
 
     // Order-preserving lists of survivors touching the top / bottom rows
-    // (the survivor panel's columns), and each survivor's place in them
-    // (pos_root / pos_defl are free until the eigenvalue order is formed).
+    // (the survivor panel's columns), and each survivor's place in them.
     const int lane = tid & 63, wv = tid >> 6;
     for (int half = 0; half < 2; ++half) {
         const int bit = half ? 2 : 1;
         int* out = (half ? S.kbot : S.ktop) + base;
-        int* inv = (half ? S.pos_defl : S.pos_root) + base;
+        int* inv = (half ? S.pbot : S.ptop) + base;
         int running = 0;
         for (int c0 = 0; c0 < K; c0 += NT) {
             const int j = c0 + tid;
@@ -578,8 +584,11 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
 // whose first elements the walk records.  A thread owns one row of the merge
 // block and DC_ROT_CHAINS chains: the first rotation of every chain is loaded
 // up front, each chain is then carried through in registers, and only final
-// column values are stored.  Entries outside a column's row type are
-// structural zeros.
+// column values are stored: the column each rotation deflates goes straight
+// to its output column (the eigenvalue order is formed before the rotations
+// run), zero outside its row type, and the column that ends a chain to the
+// survivor panel.  The children's basis is only read.  Entries outside a
+// column's row type are structural zeros.
 __device__ __forceinline__ void rot_apply(int ty, int rbit, double c, double s, double& qp,
                                           double& qi) {
     const bool inp = (ty & rbit) != 0;
@@ -608,15 +617,18 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     if (r >= m) return;
     const Prob P = S.probs[N.prob];
     const long long base = (long long)P.row0 + N.off;
-    long long ld;
-    double* Qi = node_buf(P, N.depth + 1, ld);
-    double* row = Qi + (long long)N.off * ld + N.off + r;
+    long long ld, ldo;
+    const double* Qi = node_buf(P, N.depth + 1, ld);
+    double* Qo = node_buf(P, N.depth, ldo);
+    const double* row = Qi + (long long)N.off * ld + N.off + r;
+    double* orow = Qo + (long long)N.off * ldo + N.off + r;
     const int rbit = r < N.n1 ? 1 : 2;
     const int* __restrict__ rt = S.rt + base;
-    const int* __restrict__ rp = S.rp + base;
     const int* __restrict__ rend = S.perm + base;
-    const int* __restrict__ ptop = S.pos_root + base;
-    const int* __restrict__ pbot = S.pos_defl + base;
+    const int* __restrict__ ptop = S.ptop + base;
+    const int* __restrict__ pbot = S.pbot + base;
+    const int* __restrict__ rdk = S.rdk + base;
+    const int* __restrict__ pdef = S.pos_defl + base;
     double* panel = P.B2 + (long long)N.off * P.ld2 + N.off + r;
     const int* __restrict__ ri = S.ri + base;
     const double* __restrict__ rc = S.rc + base;
@@ -638,7 +650,7 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
         const bool live = t0[q] < t1[q];
         const int t = live ? t0[q] : 0;
         ty0[q] = live ? rt[t] : 0;
-        p0[q] = rp[t];
+        p0[q] = S.rp[base + t];
         i0[q] = ri[t];
         c0[q] = rc[t];
         s0[q] = rs[t];
@@ -656,7 +668,9 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
         double a = vp[q], b = vi[q];
         int ty = ty0[q], col_i = i0[q];
         rot_apply(ty, rbit, c0[q], s0[q], a, b);
-        if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)p0[q] * ld] = a;
+        // the deflated column of rotation t, in its output column (0 outside
+        // its row type, whose rows rot_apply leaves at 0)
+        orow[(long long)pdef[rdk[t0[q]]] * ldo] = a;
         // the rest of a longer chain: the previous second column is this
         // rotation's first one
         for (int t = t0[q] + 1; t < t1[q]; ++t) {
@@ -665,7 +679,7 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
             a = b;
             b = ((ty >> 2) & rbit) ? row[(long long)col_i * ld] : 0.0;
             rot_apply(ty, rbit, rc[t], rs[t], a, b);
-            if ((ty & rbit) || ((ty >> 2) & rbit)) row[(long long)rp[t] * ld] = a;
+            orow[(long long)pdef[rdk[t]] * ldo] = a;
         }
         // The chain's last column is a survivor: it goes straight to its
         // column of the survivor panel (the gather skips it).
@@ -754,8 +768,8 @@ void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start
     }
 }
 
-// Deflated eigenvectors: the (rotated) basis column itself, zero-filled
-// outside its row type, written to its final position.
+// Deflated eigenvectors not produced by a rotation: the basis column itself,
+// zero-filled outside its row type, written to its final position.
 __global__ __launch_bounds__(256)
 void k_copy_deflated(const Node* __restrict__ merges, const int* __restrict__ blk_start,
                      int nm, Scratch S) {
@@ -773,6 +787,7 @@ void k_copy_deflated(const Node* __restrict__ merges, const int* __restrict__ bl
     for (int k = k0; k < min(C.ndefl, k0 + DC_COLS_PER_BLOCK); ++k) {
         const int src = S.dcol[base + k];
         const int ty = S.dtype[base + k];
+        if (ty & 8) continue;                // written by the rotation kernel
         const int dst = S.pos_defl[base + k];
         const double* a = Qi + (long long)(N.off + src) * ldi + N.off;
         double* o = Qo + (long long)(N.off + dst) * ldo + N.off;

@@ -5,9 +5,9 @@
 // `leaf` rows.  Merges are grouped by tree depth; all merges of one depth
 // (of every problem of a batch) form one level, processed as one launch per
 // phase:
-//   deflate -> rotate -> secular roots / Loewner / scales -> assemble
-//   -> deflated copy -> [low-rank pipeline] -> generated-Cauchy product
-//   (top and bottom row halves).
+//   deflate -> secular roots / Loewner / scales -> assemble (eigenvalue
+//   order) -> rotate and gather -> deflated copy -> [low-rank pipeline]
+//   -> generated-Cauchy product (top and bottom row halves).
 // Leaves run first, all in one launch.  A node's eigenvectors live in the
 // caller's Q when its depth is even and in the workspace partner B1 when it
 // is odd, so each merge reads its children from one buffer and writes the
@@ -299,7 +299,7 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 struct Layout {
     size_t bytes = 0;
     size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, bufs, lr;
-    int nd = 16, ni = 14;
+    int nd = 16, ni = 17;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -418,7 +418,8 @@ Scratch carve(const Plan& P, const Layout& L, char* w) {
     for (int i = 0; i < L.nd; ++i) *dp[i] = db + i * R;
     int* ib = reinterpret_cast<int*>(w + L.ints);
     int** ip[] = {&S.perm, &S.surv, &S.stype, &S.org, &S.dcol, &S.dtype, &S.rp, &S.ri,
-                  &S.rt, &S.ktop, &S.kbot, &S.pos_root, &S.pos_defl, &S.rch};
+                  &S.rt, &S.ktop, &S.kbot, &S.pos_root, &S.pos_defl, &S.rch, &S.ptop,
+                  &S.pbot, &S.rdk};
     for (int i = 0; i < L.ni; ++i) *ip[i] = ib + i * R;
     S.cnt = reinterpret_cast<MergeCnt*>(w + L.cnt);
     S.rho2 = reinterpret_cast<double*>(w + L.rho2);
@@ -435,13 +436,15 @@ __global__ void k_fill_int(int* p, int n, int v) {
 }
 
 // Optional instrumentation: HIP events on the caller's stream at the phase
-// boundaries of every level, in launch order (deflate, rotate, secular,
-// assemble, deflated copy, product), and inside the product phase of a level
+// boundaries of every level, in launch order (deflate, secular, assemble,
+// rotate and gather, deflated copy, product), and inside the product phase of a level
 // with low-rank merges (before the compression, the skeleton launch and the
 // fused launch, and after it).  Off by default; never enabled under graph
 // capture.
 constexpr int NPHASE = 6;
-constexpr int MARK_COPY = 4, MARK_PRODUCT = 5;   // marks before those phases
+// marks before the phases in launch order: 0 deflate, 1 secular, 2 assemble,
+// 3 rotate (and gather), 4 deflated copy, 5 product; NPHASE after it
+constexpr int MARK_ROTATE = 3, MARK_COPY = 4, MARK_PRODUCT = 5;
 bool g_prof = false;
 std::vector<hipEvent_t> g_ev, g_lr_ev;
 std::vector<char> g_lr_rec;            // level recorded its low-rank events
@@ -599,16 +602,19 @@ hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& pr
         DC_TRY(dc_launch_deflate(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, Lv.max_m,
                                  S, s));
         DC_TRY(prof_mark(li, 1, s));
+        DC_TRY(dc_launch_secular(S.stask + Lv.first, P.d_prefix + Lv.off_sec, Lv.nm,
+                                 Lv.sec_blocks, Lv.max_m, o.max_iter, s));
+        DC_TRY(prof_mark(li, 2, s));
+        DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
+        // With the eigenvalue order formed, the rotations write the columns
+        // they deflate straight to their output columns and the survivors
+        // that end their chains to the panel; the gather packs the others.
+        DC_TRY(prof_mark(li, MARK_ROTATE, s));
         DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_rot, Lv.nm, Lv.rot_blocks, S, s));
         DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks, S,
                                 s));
-        DC_TRY(prof_mark(li, 2, s));
-        DC_TRY(dc_launch_secular(S.stask + Lv.first, P.d_prefix + Lv.off_sec, Lv.nm,
-                                 Lv.sec_blocks, Lv.max_m, o.max_iter, s));
-        DC_TRY(prof_mark(li, 3, s));
-        DC_TRY(dc_launch_assemble(mg, P.d_prefix + Lv.off_row, Lv.nm, Lv.row_blocks, S, s));
-        // The deflated columns leave the children's buffer before the
-        // product, whose low-rank form keeps its skeleton columns there.
+        // The remaining deflated columns leave the children's buffer before
+        // the product, whose low-rank form keeps its skeleton columns there.
         DC_TRY(prof_mark(li, MARK_COPY, s));
         DC_TRY(dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks,
                                        S, s));
@@ -987,9 +993,9 @@ extern "C" int dc_profile_enable(int on) {
 extern "C" int dc_profile_read(double* ms, int cap) {
     if (!g_prof) return 0;
     const int nl = g_ev_levels;
-    // marks in launch order; the reported order puts the product before the copy
-    static const int from[NPHASE] = {0, 1, 2, 3, MARK_PRODUCT, MARK_COPY};
-    static const int to[NPHASE] = {1, 2, 3, MARK_COPY, NPHASE, MARK_PRODUCT};
+    // reported order: deflate, rotate (and gather), secular, assemble, product, copy
+    static const int from[NPHASE] = {0, MARK_ROTATE, 1, 2, MARK_PRODUCT, MARK_COPY};
+    static const int to[NPHASE] = {1, MARK_COPY, 2, MARK_ROTATE, NPHASE, MARK_PRODUCT};
     for (int li = 0; li < nl; ++li) {
         for (int ph = 0; ph < NPHASE; ++ph) {
             const int k = li * NPHASE + ph;
