@@ -38,13 +38,10 @@
  *    with caller workspace allocate nothing and may be captured in a graph.
  *  - Host threads: solves may be issued from several threads (on separate
  *    streams, with separate workspaces).  The tree plans, captured graphs
- *    and tuning tables are shared under locks; the low-rank buffers, the
- *    pinned staging for host reads and uploads, and the records read by
+ *    and tuning tables are shared under locks; the records read by
  *    dc_last_stats belong to the calling thread.  The instrumentation
  *    (dc_profile_enable / dc_profile_read) and dc_autotune_batched, which
  *    uses it, are process-wide: call them while no other thread solves.
- *  - Where the host must read device results before its next launch (the
- *    low-rank switch), the calling thread waits by polling, not sleeping.
  */
 #ifndef DCSTEDC_H
 #define DCSTEDC_H
@@ -107,14 +104,15 @@ size_t dc_stedc_workspace(int n, const dc_opts* opt);
  *   work, lwork  device workspace of at least dc_stedc_workspace(n, opt)
  *                bytes, 256-byte aligned
  *   info_dev     device int; receives the status (see above)
- * With opt->lr_tol == 0 it allocates nothing and performs no host
- * synchronisation (graph-capturable).  With lr_tol > 0, each merge that takes
- * the low-rank product reads its sizes and ranks on the host (the calling
- * thread waits for the stream at those points): not graph-capturable.  Its
- * device temporaries (SRRSC output, W = m x sum of ranks, the interpolation
- * rows, layouts and task lists) are kept per host thread and device for
- * reuse until the process ends, grown as needed; reuse from another stream
- * is ordered after the last use by an event.
+ * It allocates nothing and performs no host synchronisation, with or
+ * without the low-rank product (graph-capturable): with opt->lr_tol > 0 the
+ * switch of Algorithm 3, the SRRSC compression, W's layout and the product
+ * task lists are decided and built on the device, in regions of the
+ * workspace (dc_stedc_workspace includes them for the options' lr_block and
+ * lr_min_k, or for every automatic choice when those are 0); W itself
+ * occupies the merge's square in the buffer that holds its children's
+ * eigenvectors (Q or its ping-pong partner in the workspace), free once the
+ * deflated columns are out.
  * The first call for a given (n, options) builds and uploads the tree plan
  * synchronously; call dc_stedc_workspace first (it builds the plan) before
  * capturing.
@@ -171,8 +169,8 @@ int dc_secular(int K, const double* Dbar, const double* zbar, double rho,
  *                3(b)-(c)); diagonal blocks stay exact.
  *   lr_block     block size for lr_tol > 0 (<= 0: default 256); at most
  *                2048 with org, 4096 with org == NULL (else returns -13)
- * With lr_tol > 0 it uses the per-thread low-rank buffers described at
- * dc_stedc_ex and waits for the stream once (to read the ranks).
+ * With lr_tol > 0 it allocates its temporaries stream-ordered
+ * (hipMallocAsync / hipFreeAsync on the stream) and does not wait for it.
  */
 int dc_merge_update(int m, int K, const double* Qnd, int ldq,
                     const double* Dbar, const int* org, const double* tau,

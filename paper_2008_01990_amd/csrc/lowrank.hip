@@ -631,13 +631,15 @@ hipError_t launch_srrsc(const LrJob* jobs, const int* start, int njobs, int bloc
                    : launch_srrsc_off<false>(jobs, start, njobs, blocks, b, tol, rmax, store, s);
 }
 
-// Tile shapes of the two product launches (register kernel variants): the
-// fused launch takes 128 x 128 tiles of 128 x 32 waves; the skeleton launch,
-// whose k-range is one block (b) and whose column counts are sums of ranks,
-// takes 64 x 64 one-wave tiles: such a wave feeds each generated entry to
-// twice as many MFMAs per loaded A value as a 128 x 32 one (those ran the
-// skeleton columns at 39% of peak, 64 x 64 at 58-65%), and one-wave groups
-// leave no slot idle where a row panel's last column tile is partial.  The
+// Tile shape of the two product launches (register kernel variant 5): 64 x 64
+// one-wave tiles.  The k-ranges are short (one block b, plus the skeleton
+// columns of the block column in the fused launch's second phase), so the
+// tile's cost is dominated by generating U and loading A: a 64 x 64 wave
+// feeds each generated entry to twice as many MFMAs per loaded A value as a
+// 128 x 32 one (those ran the skeleton columns at 39% of peak, 64 x 64 at
+// 58-65%; the fused launch took 2% less time on 64 x 64 tiles than on
+// 128 x 128 tiles of 128 x 32 waves), and one-wave groups leave no slot idle
+// where a row panel's last column tile is partial.
 // Both launches are direct, over tile-count bounds known on the host: the
 // fused launch's count depends only on the block count p <= pmax; the
 // skeleton's on the ranks, and is bounded through W's capacity: a row half's
@@ -646,7 +648,7 @@ hipError_t launch_srrsc(const LrJob* jobs, const int* start, int njobs, int bloc
 // workgroups takes about 0.06 ms); grids of resident waves that walked or
 // claimed the skeleton tiles instead fetched 1.5x as much (their tiles
 // sharing an A panel ran less together) and ran 7-9% longer.
-constexpr int FUSED_VARIANT = 0;
+constexpr int FUSED_VARIANT = 5;
 constexpr int SKEL_VARIANT = 5;
 
 }  // namespace
