@@ -225,6 +225,56 @@ def _events(fn, reps, torch):
     return best
 
 
+def merge_traffic(r):
+    """Algorithmic HBM bytes and flops of one merge (a dc_last_stats record)
+    as the level's kernels move them.  Read once, over its child's rows (taken
+    as m / 2, the mean of n1 and n2): every survivor's column and every column
+    of a rotation chain (K + nrot columns) and, at a root merge, every other
+    deflated column.  Written once: the survivor panel (n1 ntop + n2 nbot
+    entries, read again by the product), each column deflated by a rotation
+    (m rows), the product's m K entries and, at a root merge, the other
+    deflated columns (m rows, zeros included).  Below the root the columns
+    deflated without a rotation stay where they are and cost nothing."""
+    m, n1, K, nrot = r["m"], r["n1"], r["K"], r["nrot"]
+    n2 = m - n1
+    root = r["level"] == 0
+    panel = 8.0 * (n1 * r["ntop"] + n2 * r["nbot"])
+    rest = m - K - nrot if root else 0
+    move = (8.0 * 0.5 * m * (K + nrot + rest) + panel + 8.0 * m * nrot + 8.0 * m * rest)
+    prod_b = panel + 8.0 * m * K
+    prod_f = 2.0 * (n1 * r["ntop"] + n2 * r["nbot"]) * K
+    return move, prod_b, prod_f
+
+
+def level_traffic(stats, prof_levels, phases):
+    """Per tree level (deepest first, as dc_profile_read orders them): the
+    event-timed phases and the algorithmic bytes of the data-movement phases
+    (rotations, gather and deflated copy) and of the product."""
+    nlev = len(prof_levels)
+    move = [0.0] * nlev
+    pb = [0.0] * nlev
+    pf = [0.0] * nlev
+    for r in stats:
+        li = nlev - 1 - r["level"]
+        a, b, c = merge_traffic(r)
+        move[li] += a
+        pb[li] += b
+        pf[li] += c
+    out = []
+    for li in range(nlev):
+        ph = prof_levels[li]
+        mv_ms = ph["rotate"] + ph["copy"]
+        # the product is bound by the larger of its HBM and MFMA times
+        floor_ms = max(pb[li] / (PEAK_HBM_GBS * 1e9), pf[li] / (PEAK_FP64_MFMA_TFLOPS * 1e12)) * 1e3
+        out.append({"level_from_root": nlev - 1 - li,
+                    "phase_ms": {k: ph[k] for k in phases},
+                    "move_bytes": move[li],
+                    "move_gbs": move[li] / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else 0.0,
+                    "product_bytes": pb[li], "product_flops": pf[li],
+                    "product_floor_ms": floor_ms})
+    return out
+
+
 def example1(L, torch, sizes=(8192, 16384, 32768), tol=1e-10, b=1024):
     """Example 1 on one GPU: C = A B with A random (N(0,1)) and B Example 0's
     Cauchy-like matrix B_ij = u_i v_j / (d_i - w_j) given by its generators.
@@ -356,13 +406,56 @@ def batched_config(L, torch):
     t_meas = time.perf_counter() - t0
     tg = _time(lambda: step(True), 5, torch)
     te = _time(lambda: step(False), 5, torch)
+    # One eager solve with phase events, for the bytes-moved accounting.
+    L.profile_enable(True)
+    B.restore()
+    B.solve(graph=False)
+    prof = L.profile_read()
+    L.profile_enable(False)
+    stats = L.last_stats()
+    lv = level_traffic(stats, prof, L.PHASES)
+    ph = {k: sum(x["phase_ms"][k] for x in lv) for k in L.PHASES}
+    move_b = sum(x["move_bytes"] for x in lv)
+    prod_b = sum(x["product_bytes"] for x in lv)
+    prod_f = sum(x["product_flops"] for x in lv)
+    prod_floor = sum(x["product_floor_ms"] for x in lv)
+    # leaves: each writes its nb x nb block; the tree halves a problem until
+    # its blocks hold at most `leaf` rows, so sum nb^2 ~ n * (n / 2^depth)
+    leaf_b = 0.0
+    for n in sizes:
+        nb = float(n)
+        while nb > 32:
+            nb /= 2.0
+        leaf_b += 8.0 * n * nb
+    total_b = move_b + prod_b + leaf_b
+    move_ms = ph["rotate"] + ph["copy"]
+    other_ms = te * 1e3 - sum(ph.values())
     res["batched_256_loguniform_64_4096"] = {
         "seconds_graph": tg, "seconds_eager": te, "seconds_graph_default_tiles": tg_rule,
         "seconds_graph_bucket_tuned": tg_bucket, "bucket_autotune_seconds": t_tune,
         "bucket_variant_by_size": {f"<={1 << b}": v for b, v in enumerate(table) if 6 <= b <= 12},
         "measured_autotune_seconds": t_meas, "measured_variant_by_level": levels,
         "problems": len(sizes), "sum_n": int(sum(sizes)),
-        "status_ok": all(v == 0 for v in B.status())}
+        "status_ok": all(v == 0 for v in B.status()),
+        # whole batch against HBM: algorithmic bytes (merge_traffic per merge,
+        # plus the leaf blocks) over the graph-replay time
+        "roofline": {"bound": "hbm", "achieved": total_b / tg / 1e9, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": total_b / tg / 1e9 / PEAK_HBM_GBS,
+                     "traffic": None, "bytes": total_b,
+                     "floor_ms": total_b / (PEAK_HBM_GBS * 1e9) * 1e3},
+        "phases": {
+            "data_movement": {"ms": move_ms, "bytes": move_b,
+                              "gbs": move_b / (move_ms * 1e-3) / 1e9 if move_ms > 0 else 0.0,
+                              "frac": move_b / (move_ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+                              if move_ms > 0 else 0.0,
+                              "rotate_gather_ms": ph["rotate"], "copy_ms": ph["copy"]},
+            "product": {"ms": ph["product"], "bytes": prod_b, "flops": prod_f,
+                        "floor_ms": prod_floor,
+                        "frac": prod_floor / ph["product"] if ph["product"] > 0 else 0.0},
+            "secular_ms": ph["secular"], "deflate_ms": ph["deflate"],
+            "assemble_ms": ph["assemble"],
+            "leaves_and_setup": {"ms": other_ms, "leaf_bytes": leaf_b}},
+        "levels": lv}
     del B
     L.autotune(0)
     torch.cuda.empty_cache()
@@ -620,18 +713,15 @@ def main():
         "merges_top": [dict(m=r["m"], K=r["K"], nrot=r["nrot"]) for r in stats
                        if r["level"] <= 1],
     }
-    # HBM-bound phases of the root merge: the deflated-column copy moves
-    # 16 m (m - K) bytes; the rotations of pairs from opposite halves read one
-    # column and write two per row, 24 m nrot bytes (the survivors they produce
-    # go straight to the panel, so the gather has nothing left at this root).
+    # HBM-bound phases of the root merge (rotations, gather and deflated
+    # copy): the algorithmic bytes of merge_traffic over their event times.
     root = [r for r in stats if r["level"] == 0][0]
-    cp_b = 16.0 * root["m"] * (root["m"] - root["K"])
-    rot_b = 24.0 * root["m"] * root["nrot"]
+    mv_b = merge_traffic(root)[0]
+    mv_ms = top["phase_ms"]["rotate"] + top["phase_ms"]["copy"]
     out["root_hbm_phases"] = {
-        "copy": {"ms": top["phase_ms"]["copy"], "bytes": cp_b,
-                 "gbs": cp_b / (top["phase_ms"]["copy"] * 1e-3) / 1e9 if top["phase_ms"]["copy"] > 0 else 0.0},
-        "rotate_gather": {"ms": top["phase_ms"]["rotate"], "bytes": rot_b,
-                          "gbs": rot_b / (top["phase_ms"]["rotate"] * 1e-3) / 1e9 if top["phase_ms"]["rotate"] > 0 else 0.0},
+        "data_movement": {"ms": mv_ms, "rotate_gather_ms": top["phase_ms"]["rotate"],
+                          "copy_ms": top["phase_ms"]["copy"], "bytes": mv_b,
+                          "gbs": mv_b / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else 0.0},
         "peak_gbs": PEAK_HBM_GBS}
     if not args.no_accuracy:
         out["accuracy"] = gpu_accuracy(d_in, e, d, Qbuf, args.family)

@@ -110,9 +110,8 @@ size_t dc_stedc_workspace(int n, const dc_opts* opt);
  * task lists are decided and built on the device, in regions of the
  * workspace (dc_stedc_workspace includes them for the options' lr_block and
  * lr_min_k, or for every automatic choice when those are 0); W itself
- * occupies the merge's square in the buffer that holds its children's
- * eigenvectors (Q or its ping-pong partner in the workspace), free once the
- * deflated columns are out.
+ * occupies the merge's square of Q below the root (Q is written only by the
+ * root merge) and of the workspace basis at the root.
  * The first call for a given (n, options) builds and uploads the tree plan
  * synchronously; call dc_stedc_workspace first (it builds the plan) before
  * capturing.
@@ -341,6 +340,10 @@ typedef struct dc_merge_stat {
        the fused product (diagonal blocks plus interpolation rows); their sum
        is flops */
     double lr_flops_skeleton, lr_flops_fused;
+    /* rows of the first child (the second has m - n1); survivors with
+       non-zeros in the first child's rows and in the second's; problem index
+       (0 for dc_stedc / dc_stedc_ex) */
+    int n1, ntop, nbot, prob;
 } dc_merge_stat;
 
 /* Copies up to cap records into out (HOST); returns the number available. */

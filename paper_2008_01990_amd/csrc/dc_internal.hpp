@@ -15,7 +15,7 @@ struct Prob {
     const double* e;    // off-diagonal (n - 1)
     double* Q;          // output eigenvectors, column-major
     long long ldq;
-    double* B1;         // ping-pong partner of Q inside the workspace
+    double* B1;         // working basis of every merge below the root (workspace)
     long long ld1;
     double* B2;         // packed survivor panels of the merge products
     long long ld2;
@@ -30,7 +30,7 @@ struct Node {
     int prob;
     int off;            // first row inside its problem
     int n1, n2;
-    int depth;          // 0 at the root; parity selects Q (even) or B1 (odd)
+    int depth;          // 0 at the root (writes Q); below it the basis lives in B1
     int slot;           // merge index across the plan (per-merge scalars)
 };
 
@@ -65,6 +65,15 @@ struct Scratch {
     int *ktop, *kbot;           // generator lists of the top and bottom row halves
     int *ptop, *pbot;           // place of each survivor in those lists
     int *rdk;                   // deflated-list entry of the column rotation t deflates
+    // Resident columns below the root.  The eigenvector of a node's sorted
+    // eigenvalue j lives in column cmap[off + j] of B1 (a column of the
+    // node's own range [off, off + m)) and holds data only in rows
+    // [rng[off + j].x, rng[off + j].y); the other rows of the node's range
+    // are structural zeros (stale memory, never read).  A merge reads its
+    // children's map and ranges (parity of depth + 1) and writes its own
+    // (parity of depth).
+    int *cmap0, *cmap1;
+    int2 *rng0, *rng1;
     int *pos_root, *pos_defl;   // output column of each root / deflated pair
     MergeCnt* cnt;              // per merge slot
     double* rho2;               // per merge slot: 2 |e_k|
@@ -74,10 +83,20 @@ struct Scratch {
     SecTask* stask;             // one per merge slot
 };
 
+// Output buffer of a node: the caller's Q at the root, B1 below it (the
+// children of every merge are therefore in B1).
 __host__ __device__ inline double* node_buf(const Prob& P, int depth, long long& ld) {
-    if (depth & 1) { ld = P.ld1; return P.B1; }
+    if (depth > 0) { ld = P.ld1; return P.B1; }
     ld = P.ldq;
     return P.Q;
+}
+
+__host__ __device__ inline int* node_cmap(const Scratch& S, int depth) {
+    return (depth & 1) ? S.cmap1 : S.cmap0;
+}
+
+__host__ __device__ inline int2* node_rng(const Scratch& S, int depth) {
+    return (depth & 1) ? S.rng1 : S.rng0;
 }
 
 // Kernel launchers (deflate.hip / leaf.hip).

@@ -20,10 +20,18 @@
 // Every column of the merge block carries row-type bits: 1 if it may be
 // non-zero in the top rows [0, n1), 2 in the bottom rows [n1, m).  Columns of
 // Q_1 start as 1, of Q_2 as 2; a rotation of two columns gives both the union.
-// Memory outside a column's type is never read (it holds stale data of other
-// tree levels), and the product then runs separately on the top rows (k over
-// survivors of type 1|3) and on the bottom rows (type 2|3): the structural
-// zeros of diag(Q_1, Q_2) cost no flops.
+// The product runs separately on the top rows (k over survivors of type 1|3)
+// and on the bottom rows (type 2|3): the structural zeros of diag(Q_1, Q_2)
+// cost no flops.
+//
+// Below the root the children's eigenvectors are resident columns of B1: the
+// eigenvector of local column c (the child's sorted eigenvalue c, or c - n1)
+// is column cmap[c] of B1, with data only in rows rng[c] of that column; the
+// other rows are structural zeros and are never read.  A merge below the
+// root moves no deflated column: it overwrites the columns it deflates by
+// rotation in place, gives its product columns the places of its survivors
+// (packed into the panel first), and records its own map and ranges.  The
+// root merge writes the caller's Q in eigenvalue order.
 #include "dc_internal.hpp"
 
 namespace {
@@ -223,15 +231,21 @@ void k_merge_sort(const Node* __restrict__ merges, const int* __restrict__ blk_s
     const double ek = P.e[N.off + n1 - 1];            // its sign only: scale-free
     const double sigma = ek < 0.0 ? -1.0 : 1.0;
     const double rs2 = 0.70710678118654752440;
+    // the child's last (top) or first (bottom) row of the column, 0 outside
+    // its rows
+    const int col = node_cmap(S, N.depth + 1)[base + i];
+    const int2 rg = node_rng(S, N.depth + 1)[base + i];
+    const int row = i < n1 ? N.off + n1 - 1 : N.off + n1;
+    const double q = row >= rg.x && row < rg.y ? Qi[(long long)col * ldi + row] : 0.0;
     double Dv, zv;
     int pos;
     if (i < n1) {
         Dv = L1[i];
-        zv = Qi[(long long)(N.off + i) * ldi + N.off + n1 - 1] * rs2;
+        zv = q * rs2;
         pos = i + count_lt(L2, n2, Dv);
     } else {
         Dv = L2[i - n1];
-        zv = sigma * Qi[(long long)(N.off + i) * ldi + N.off + n1] * rs2;
+        zv = sigma * q * rs2;
         pos = (i - n1) + count_le(L1, n1, Dv);
     }
     S.Ds[base + pos] = Dv;
@@ -584,11 +598,12 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
 // whose first elements the walk records.  A thread owns one row of the merge
 // block and DC_ROT_CHAINS chains: the first rotation of every chain is loaded
 // up front, each chain is then carried through in registers, and only final
-// column values are stored: the column each rotation deflates goes straight
-// to its output column (the eigenvalue order is formed before the rotations
-// run), zero outside its row type, and the column that ends a chain to the
-// survivor panel.  The children's basis is only read.  Entries outside a
-// column's row type are structural zeros.
+// column values are stored: the column each rotation deflates goes, zero
+// outside its row type, to its output column at the root (the eigenvalue
+// order is formed before the rotations run) and over the column it came from
+// below the root (read by this thread, in this row, before), and the column
+// that ends a chain to the survivor panel.  Entries outside a column's rows
+// are structural zeros.
 __device__ __forceinline__ void rot_apply(int ty, int rbit, double c, double s, double& qp,
                                           double& qi) {
     const bool inp = (ty & rbit) != 0;
@@ -620,8 +635,17 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     long long ld, ldo;
     const double* Qi = node_buf(P, N.depth + 1, ld);
     double* Qo = node_buf(P, N.depth, ldo);
-    const double* row = Qi + (long long)N.off * ld + N.off + r;
-    double* orow = Qo + (long long)N.off * ldo + N.off + r;
+    const bool root = N.depth == 0;
+    const int ra = N.off + r;                     // row of the problem
+    const double* row = Qi + ra;
+    const int* __restrict__ cmap = node_cmap(S, N.depth + 1) + base;
+    const int2* __restrict__ rng = node_rng(S, N.depth + 1) + base;
+    // local column c in this row (0 outside its rows)
+    auto child = [&](int c) {
+        const int col = cmap[c];
+        const int2 rg = rng[c];
+        return ra >= rg.x && ra < rg.y ? row[(long long)col * ld] : 0.0;
+    };
     const int rbit = r < N.n1 ? 1 : 2;
     const int* __restrict__ rt = S.rt + base;
     const int* __restrict__ rend = S.perm + base;
@@ -630,6 +654,11 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     const int* __restrict__ rdk = S.rdk + base;
     const int* __restrict__ pdef = S.pos_defl + base;
     double* panel = P.B2 + (long long)N.off * P.ld2 + N.off + r;
+    // the column rotation t deflates (local column p of the pair)
+    auto put = [&](int t, int p, double v) {
+        const long long col = root ? N.off + pdef[rdk[t]] : cmap[p];
+        Qo[col * ldo + ra] = v;
+    };
     const int* __restrict__ ri = S.ri + base;
     const double* __restrict__ rc = S.rc + base;
     const double* __restrict__ rs = S.rs + base;
@@ -659,8 +688,8 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     double vp[DC_ROT_CHAINS], vi[DC_ROT_CHAINS];
 #pragma unroll
     for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        vp[q] = (ty0[q] & rbit) ? row[(long long)p0[q] * ld] : 0.0;
-        vi[q] = ((ty0[q] >> 2) & rbit) ? row[(long long)i0[q] * ld] : 0.0;
+        vp[q] = (ty0[q] & rbit) ? child(p0[q]) : 0.0;
+        vi[q] = ((ty0[q] >> 2) & rbit) ? child(i0[q]) : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < DC_ROT_CHAINS; ++q) {
@@ -668,18 +697,19 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
         double a = vp[q], b = vi[q];
         int ty = ty0[q], col_i = i0[q];
         rot_apply(ty, rbit, c0[q], s0[q], a, b);
-        // the deflated column of rotation t, in its output column (0 outside
-        // its row type, whose rows rot_apply leaves at 0)
-        orow[(long long)pdef[rdk[t0[q]]] * ldo] = a;
+        // the deflated column of rotation t (0 outside its row type, whose
+        // rows rot_apply leaves at 0)
+        put(t0[q], p0[q], a);
         // the rest of a longer chain: the previous second column is this
         // rotation's first one
         for (int t = t0[q] + 1; t < t1[q]; ++t) {
+            const int col_p = col_i;
             ty = rt[t];
             col_i = ri[t];
             a = b;
-            b = ((ty >> 2) & rbit) ? row[(long long)col_i * ld] : 0.0;
+            b = ((ty >> 2) & rbit) ? child(col_i) : 0.0;
             rot_apply(ty, rbit, rc[t], rs[t], a, b);
-            orow[(long long)pdef[rdk[t]] * ldo] = a;
+            put(t, col_p, a);
         }
         // The chain's last column is a survivor: it goes straight to its
         // column of the survivor panel (the gather skips it).
@@ -691,7 +721,11 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
 
 // Final ascending order of the merged eigenvalues: roots (ascending by
 // interlacing) and deflated values (ascending) meet by a merge path; ties
-// place the root first.  Writes the eigenvalues into the lam array.
+// place the root first.  Writes the eigenvalues into the lam array.  At the
+// root, root j's product column is its place in that order; below it, the
+// column of survivor j (free once the panel holds it), and the merge's map
+// sends each place to its column, with the column's rows: the merge's for
+// product columns and columns deflated by rotation, the child's otherwise.
 __global__ __launch_bounds__(DC_ROWS_PER_BLOCK)
 void k_assemble(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
                 Scratch S) {
@@ -716,16 +750,32 @@ void k_assemble(const Node* __restrict__ merges, const int* __restrict__ blk_sta
         S.gDb[base + x] = S.Dbar[base + g];
         S.gzb[base + x] = S.zhat[base + g];
     }
+    const int* cin = node_cmap(S, N.depth + 1) + base;
+    int* cout = node_cmap(S, N.depth) + base;
+    int2* rout = node_rng(S, N.depth) + base;
+    const int2 whole = make_int2(N.off, N.off + m);
     if (x < C.K) {
         const double v = lr[x];
         const int pos = x + count_lt(dd, C.ndefl, v);
-        S.pos_root[base + x] = pos;
+        if (N.depth > 0) {
+            const int col = cin[S.surv[base + x]];
+            S.pos_root[base + x] = col - N.off;
+            cout[pos] = col;
+            rout[pos] = whole;
+        } else {
+            S.pos_root[base + x] = pos;
+        }
         P.d[N.off + pos] = v;
     } else {
         const int k = x - C.K;
         const double v = dd[k];
         const int pos = k + count_le(lr, C.K, v);
         S.pos_defl[base + k] = pos;
+        if (N.depth > 0) {
+            const int c = S.dcol[base + k];
+            cout[pos] = cin[c];
+            rout[pos] = (S.dtype[base + k] & 8) ? whole : node_rng(S, N.depth + 1)[base + c];
+        }
         P.d[N.off + pos] = v;
     }
 }
@@ -745,31 +795,37 @@ void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start
     const long long base = (long long)P.row0 + N.off;
     long long ldi;
     const double* Qi = node_buf(P, N.depth + 1, ldi);
-    const double* blk = Qi + (long long)N.off * ldi + N.off;
+    const int* cmap = node_cmap(S, N.depth + 1) + base;
     double* G = P.B2 + (long long)N.off * P.ld2 + N.off;
+    // rows [r0, r0 + nr) of the merge block of survivor ks into panel column
+    // t, zero outside the column's rows
+    auto pack = [&](int ks, int t, int r0, int nr) {
+        const int c = S.surv[base + ks];
+        const int col = cmap[c];
+        const int2 rg = node_rng(S, N.depth + 1)[base + c];
+        const int lo = rg.x - N.off - r0;
+        const int hi = rg.y - N.off - r0;
+        const double* a = Qi + (long long)col * ldi + N.off + r0;
+        double* o = G + (long long)t * P.ld2 + r0;
+        for (int r = threadIdx.x; r < nr; r += 256) o[r] = r >= lo && r < hi ? a[r] : 0.0;
+    };
     for (int t = t0; t < t0 + DC_GATHER_COLS; ++t) {
         // (survivors that end a rotation chain were written by the rotation)
         if (t < C.ntop) {
             const int ks = S.ktop[base + t];
-            if (!(S.stype[base + ks] & 4)) {
-                const double* a = blk + (long long)S.surv[base + ks] * ldi;
-                double* o = G + (long long)t * P.ld2;
-                for (int r = threadIdx.x; r < N.n1; r += 256) o[r] = a[r];
-            }
+            if (!(S.stype[base + ks] & 4)) pack(ks, t, 0, N.n1);
         }
         if (t < C.nbot) {
             const int ks = S.kbot[base + t];
-            if (!(S.stype[base + ks] & 4)) {
-                const double* a = blk + (long long)S.surv[base + ks] * ldi + N.n1;
-                double* o = G + (long long)t * P.ld2 + N.n1;
-                for (int r = threadIdx.x; r < N.n2; r += 256) o[r] = a[r];
-            }
+            if (!(S.stype[base + ks] & 4)) pack(ks, t, N.n1, N.n2);
         }
     }
 }
 
-// Deflated eigenvectors not produced by a rotation: the basis column itself,
-// zero-filled outside its row type, written to its final position.
+// Deflated eigenvectors of the root merges not produced by a rotation: the
+// basis column itself, zero outside its rows, written to its place in Q.
+// (Below the root deflated columns do not move; the level loop launches this
+// only for the roots.)
 __global__ __launch_bounds__(256)
 void k_copy_deflated(const Node* __restrict__ merges, const int* __restrict__ blk_start,
                      int nm, Scratch S) {
@@ -777,24 +833,26 @@ void k_copy_deflated(const Node* __restrict__ merges, const int* __restrict__ bl
     const Node N = merges[mi];
     const MergeCnt C = S.cnt[N.slot];
     const int k0 = (blockIdx.x - blk_start[mi]) * DC_COLS_PER_BLOCK;
-    if (k0 >= C.ndefl) return;
+    if (N.depth > 0 || k0 >= C.ndefl) return;
     const Prob P = S.probs[N.prob];
     const long long base = (long long)P.row0 + N.off;
     const int m = N.n1 + N.n2;
+    const int* cmap = node_cmap(S, 1) + base;
+    const int2* rng = node_rng(S, 1) + base;
     long long ldi, ldo;
-    const double* Qi = node_buf(P, N.depth + 1, ldi);
-    double* Qo = node_buf(P, N.depth, ldo);
+    const double* Qi = node_buf(P, 1, ldi);
+    double* Qo = node_buf(P, 0, ldo);
     for (int k = k0; k < min(C.ndefl, k0 + DC_COLS_PER_BLOCK); ++k) {
-        const int src = S.dcol[base + k];
         const int ty = S.dtype[base + k];
         if (ty & 8) continue;                // written by the rotation kernel
+        const int c = S.dcol[base + k];
+        const int col = cmap[c];
+        const int lo = rng[c].x - N.off;
+        const int hi = rng[c].y - N.off;
         const int dst = S.pos_defl[base + k];
-        const double* a = Qi + (long long)(N.off + src) * ldi + N.off;
+        const double* a = Qi + (long long)col * ldi + N.off;
         double* o = Qo + (long long)(N.off + dst) * ldo + N.off;
-        for (int r = threadIdx.x; r < m; r += 256) {
-            const int rbit = r < N.n1 ? 1 : 2;
-            o[r] = (ty & rbit) ? a[r] : 0.0;
-        }
+        for (int r = threadIdx.x; r < m; r += 256) o[r] = r >= lo && r < hi ? a[r] : 0.0;
     }
 }
 

@@ -8,10 +8,14 @@
 //   deflate -> secular roots / Loewner / scales -> assemble (eigenvalue
 //   order) -> rotate and gather -> deflated copy -> [low-rank pipeline]
 //   -> generated-Cauchy product (top and bottom row halves).
-// Leaves run first, all in one launch.  A node's eigenvectors live in the
-// caller's Q when its depth is even and in the workspace partner B1 when it
-// is odd, so each merge reads its children from one buffer and writes the
-// other, and the root lands in Q.
+// Leaves run first, all in one launch.  Below the root, eigenvectors stay
+// where they were formed, in the workspace basis B1: a merge writes the
+// columns it deflates by rotation over the columns they came from and its
+// product columns over the columns of the survivors (already packed into the
+// product panel); the columns it deflates untouched do not move.  A map per
+// node (sorted eigenvalue -> column of B1) and a row range per column record
+// the layout.  Only the root merge writes Q, in eigenvalue order: the
+// permutation is materialised once.
 //
 // Nothing here synchronises with the device after the plan exists: the
 // level loop only launches kernels, with data-dependent sizes (the deflated
@@ -20,8 +24,8 @@
 //
 // Merges whose order reaches the low-rank switch are candidates: each has
 // low-rank regions in the workspace sized by its order, and its skeleton
-// columns W go into its children's square of the ping-pong buffer, which is
-// dead once the deflated columns have been copied out of it.
+// columns W go into its square of the buffer it does not write (Q below the
+// root, B1 at the root once the deflated columns are in Q).
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
@@ -43,6 +47,7 @@ struct Level {
     int tiles;          // worst-case product tiles
     int sec_blocks, row_blocks, copy_blocks, gather_blocks, rot_blocks;
     int max_m;          // largest merge of the level
+    int depth;          // tree depth of its merges (0: the roots, which write Q)
     int variant, bm, bn;   // product tile shape of the level
     int off_tile, off_sec, off_row, off_copy, off_gather, off_rot;   // prefix offsets
 };
@@ -94,7 +99,7 @@ struct Plan {
     std::vector<int> prefix;            // all per-level prefix sums
     std::vector<long long> row0, buf_off, pan_off;
     long long rows = 0;                 // sum of n
-    long long buf_elems = 0;            // sum of n^2 (odd-depth buffers)
+    long long buf_elems = 0;            // sum of n^2 (working bases B1)
     long long pan_elems = 0;            // sum of panel_ld(n) n (survivor panels)
     Node* d_nodes = nullptr;            // leaves then merges
     int* d_prefix = nullptr;
@@ -172,6 +177,7 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
     }
     for (int dep = (int)by_depth.size() - 1; dep >= 0; --dep) {
         Level L{};
+        L.depth = dep;
         L.first = (int)P->merges.size();
         for (Node N : by_depth[dep]) {
             N.slot = (int)P->merges.size();
@@ -298,8 +304,8 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 // Workspace layout.
 struct Layout {
     size_t bytes = 0;
-    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, bufs, lr;
-    int nd = 16, ni = 17;
+    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, rng, bufs, lr;
+    int nd = 16, ni = 19;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -374,6 +380,7 @@ Layout layout(const Plan& P, const LrPlan* LP = nullptr) {
     L.psc = o; o = align256(o + std::max<size_t>(P.sizes.size(), 1) * sizeof(double));
     L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
     L.ints = o; o = align256(o + L.ni * R * sizeof(int));
+    L.rng = o; o = align256(o + 2 * R * sizeof(int2));
     L.bufs = o; o = align256(o + (P.buf_elems + P.pan_elems) * sizeof(double));
     L.lr = o; o = align256(o + (LP ? LP->bytes : 0));
     L.bytes = o;
@@ -419,8 +426,10 @@ Scratch carve(const Plan& P, const Layout& L, char* w) {
     int* ib = reinterpret_cast<int*>(w + L.ints);
     int** ip[] = {&S.perm, &S.surv, &S.stype, &S.org, &S.dcol, &S.dtype, &S.rp, &S.ri,
                   &S.rt, &S.ktop, &S.kbot, &S.pos_root, &S.pos_defl, &S.rch, &S.ptop,
-                  &S.pbot, &S.rdk};
+                  &S.pbot, &S.rdk, &S.cmap0, &S.cmap1};
     for (int i = 0; i < L.ni; ++i) *ip[i] = ib + i * R;
+    S.rng0 = reinterpret_cast<int2*>(w + L.rng);
+    S.rng1 = S.rng0 + R;
     S.cnt = reinterpret_cast<MergeCnt*>(w + L.cnt);
     S.rho2 = reinterpret_cast<double*>(w + L.rho2);
     S.psc = reinterpret_cast<double*>(w + L.psc);
@@ -487,7 +496,9 @@ namespace {
 
 // The low-rank jobs of every candidate of the plan: the call's pointers
 // (problem buffers, scratch, workspace) and the candidate's regions.  W is
-// the candidate's square of its children's buffer.
+// the candidate's square of the buffer it does not write: Q below the root
+// (Q receives nothing before the root merge), B1 at the root (its square is
+// dead once the deflated columns are in Q, before the product runs).
 __global__ void k_lr_build(const LrCand* __restrict__ cands, int ncand,
                            const Node* __restrict__ merges, Scratch S, char* regbase,
                            LrJob* jobs, GemmTask* tskel, GemmTask* tfused, int b, int min_k) {
@@ -498,9 +509,10 @@ __global__ void k_lr_build(const LrCand* __restrict__ cands, int ncand,
     const Prob P = S.probs[N.prob];
     const long long base = (long long)P.row0 + N.off;
     const int m = N.n1 + N.n2;
-    long long ldo, ldi;
+    long long ldo;
     double* Qo = node_buf(P, N.depth, ldo);
-    double* Qi = node_buf(P, N.depth + 1, ldi);
+    const long long ldw = N.depth > 0 ? P.ldq : P.ld1;
+    double* Wb = N.depth > 0 ? P.Q : P.B1;
     MergeCnt* cnt = S.cnt + N.slot;
     LrJob J;
     memset(&J, 0, sizeof(J));
@@ -528,8 +540,8 @@ __global__ void k_lr_build(const LrCand* __restrict__ cands, int ncand,
         H.ldc = ldo;
         H.cpos = S.pos_root + base;
     }
-    J.W = Qi + (long long)N.off * ldi + N.off;
-    J.ldw = ldi;
+    J.W = Wb + (long long)N.off * ldw + N.off;
+    J.ldw = ldw;
     J.wrows = m;
     J.wcap = m;
     J.plain = S.gtask + 2 * N.slot;
@@ -613,11 +625,13 @@ hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& pr
         DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_rot, Lv.nm, Lv.rot_blocks, S, s));
         DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks, S,
                                 s));
-        // The remaining deflated columns leave the children's buffer before
-        // the product, whose low-rank form keeps its skeleton columns there.
+        // At the root the remaining deflated columns go to Q before the
+        // product, whose low-rank form keeps its skeleton columns in B1's
+        // square; below the root they stay where they are.
         DC_TRY(prof_mark(li, MARK_COPY, s));
-        DC_TRY(dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm, Lv.copy_blocks,
-                                       S, s));
+        if (Lv.depth == 0)
+            DC_TRY(dc_launch_copy_deflated(mg, P.d_prefix + Lv.off_copy, Lv.nm,
+                                           Lv.copy_blocks, S, s));
         DC_TRY(prof_mark(li, MARK_PRODUCT, s));
         if (lr && LP->levels[li].njobs > 0)
             DC_TRY(lowrank_level(*LP, li, lrbase, o.lr_tol, s));
@@ -964,6 +978,10 @@ extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
             r.m = N.n1 + N.n2;
             r.K = cnt[g].K;
             r.nrot = cnt[g].nrot;
+            r.n1 = N.n1;
+            r.ntop = cnt[g].ntop;
+            r.nbot = cnt[g].nbot;
+            r.prob = N.prob;
             const int c = LP ? LP->cand_of_merge[g] : -1;
             const bool lr = c >= 0 && rec[c].active == 1;
             r.path = lr ? 1 : 0;

@@ -205,6 +205,12 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         P.d[off + rank[lane]] = dv;
         for (int c = 0; c < nl; ++c)
             Qo[(long long)(off + rank[c]) * ld + off + lane] = Z[c * LD + lane];
+        if (L.depth > 0) {
+            // below the root: eigenvalue j in column off + j, rows of the leaf
+            const long long g = (long long)P.row0 + off + lane;
+            node_cmap(S, L.depth)[g] = off + lane;
+            node_rng(S, L.depth)[g] = make_int2(off, off + nl);
+        }
     }
 }
 

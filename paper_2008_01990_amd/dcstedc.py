@@ -35,7 +35,8 @@ class MergeStat(ctypes.Structure):
     _fields_ = [("level", c_int), ("m", c_int), ("K", c_int), ("nrot", c_int),
                 ("path", c_int), ("flops", c_double), ("lr_blocks", c_int),
                 ("lr_rank_sum", c_int), ("lr_rank_max", c_int), ("lr_dense", c_int),
-                ("lr_flops_skeleton", c_double), ("lr_flops_fused", c_double)]
+                ("lr_flops_skeleton", c_double), ("lr_flops_fused", c_double),
+                ("n1", c_int), ("ntop", c_int), ("nbot", c_int), ("prob", c_int)]
 
 
 # (name, restype, argtypes) of every exported entry point.
@@ -240,7 +241,8 @@ def last_stats():
     return [dict(level=r.level, m=r.m, K=r.K, nrot=r.nrot, path=r.path, flops=r.flops,
                  lr_blocks=r.lr_blocks, lr_rank_sum=r.lr_rank_sum, lr_rank_max=r.lr_rank_max,
                  lr_dense=r.lr_dense, lr_flops_skeleton=r.lr_flops_skeleton,
-                 lr_flops_fused=r.lr_flops_fused) for r in arr[:cnt]]
+                 lr_flops_fused=r.lr_flops_fused, n1=r.n1, ntop=r.ntop, nbot=r.nbot,
+                 prob=r.prob) for r in arr[:cnt]]
 
 
 PHASES = ("deflate", "rotate", "secular", "assemble", "product", "copy")
