@@ -615,6 +615,7 @@ __device__ __forceinline__ void rot_apply(int ty, int rbit, double c, double s, 
     }
 }
 
+template <bool STRIDE>
 __global__ __launch_bounds__(DC_ROWS_PER_BLOCK)
 void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
               Scratch S) {
@@ -624,11 +625,11 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     if (C.nrot == 0) return;
     const int m = N.n1 + N.n2;
     const int nrb = (m + DC_ROWS_PER_BLOCK - 1) / DC_ROWS_PER_BLOCK;
+    const int ngb = dc_rot_group_blocks(m, STRIDE);
     const int local = blockIdx.x - blk_start[mi];
-    const int cg = local / nrb;
-    const int ch0 = cg * DC_ROT_CHAINS;
-    if (ch0 >= C.nchain) return;
-    const int r = (local - cg * nrb) * DC_ROWS_PER_BLOCK + threadIdx.x;
+    const int gb = local / nrb;
+    if (gb * DC_ROT_CHAINS >= C.nchain) return;
+    const int r = (local - gb * nrb) * DC_ROWS_PER_BLOCK + threadIdx.x;
     if (r >= m) return;
     const Prob P = S.probs[N.prob];
     const long long base = (long long)P.row0 + N.off;
@@ -662,61 +663,70 @@ void k_rotate(const Node* __restrict__ merges, const int* __restrict__ blk_start
     const int* __restrict__ ri = S.ri + base;
     const double* __restrict__ rc = S.rc + base;
     const double* __restrict__ rs = S.rs + base;
-    // Every chain's bounds and first rotation are read before any store: the
-    // stores go to Q, which the compiler cannot tell apart from these lists,
-    // and a read after a store would cost one memory round trip per chain.
-    int t0[DC_ROT_CHAINS], t1[DC_ROT_CHAINS], ty0[DC_ROT_CHAINS], p0[DC_ROT_CHAINS],
-        i0[DC_ROT_CHAINS];
-    double c0[DC_ROT_CHAINS], s0[DC_ROT_CHAINS];
+    // Chain groups gb, gb + ngb, ...  In each, every chain's bounds and first
+    // rotation are read before any store: the stores go to Q or B1, which the
+    // compiler cannot tell apart from these lists, and a read after a store
+    // would cost one memory round trip per chain.  The first group is peeled
+    // off the loop: its list reads precede every store of the kernel, so
+    // they can go through the scalar cache (in the loop they cannot).
+    auto group = [&](int cg) __attribute__((always_inline)) {
+        const int ch0 = cg * DC_ROT_CHAINS;
+        int t0[DC_ROT_CHAINS], t1[DC_ROT_CHAINS], ty0[DC_ROT_CHAINS], p0[DC_ROT_CHAINS],
+            i0[DC_ROT_CHAINS];
+        double c0[DC_ROT_CHAINS], s0[DC_ROT_CHAINS];
 #pragma unroll
-    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        const int ch = ch0 + q;
-        t0[q] = ch < C.nchain ? S.rch[base + ch] : 0;
-        t1[q] = ch < C.nchain ? (ch + 1 < C.nchain ? S.rch[base + ch + 1] : C.nrot) : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        const bool live = t0[q] < t1[q];
-        const int t = live ? t0[q] : 0;
-        ty0[q] = live ? rt[t] : 0;
-        p0[q] = S.rp[base + t];
-        i0[q] = ri[t];
-        c0[q] = rc[t];
-        s0[q] = rs[t];
-    }
-    // the first rotation's two columns of every chain: loads issued together
-    double vp[DC_ROT_CHAINS], vi[DC_ROT_CHAINS];
-#pragma unroll
-    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        vp[q] = (ty0[q] & rbit) ? child(p0[q]) : 0.0;
-        vi[q] = ((ty0[q] >> 2) & rbit) ? child(i0[q]) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < DC_ROT_CHAINS; ++q) {
-        if (t0[q] >= t1[q]) continue;
-        double a = vp[q], b = vi[q];
-        int ty = ty0[q], col_i = i0[q];
-        rot_apply(ty, rbit, c0[q], s0[q], a, b);
-        // the deflated column of rotation t (0 outside its row type, whose
-        // rows rot_apply leaves at 0)
-        put(t0[q], p0[q], a);
-        // the rest of a longer chain: the previous second column is this
-        // rotation's first one
-        for (int t = t0[q] + 1; t < t1[q]; ++t) {
-            const int col_p = col_i;
-            ty = rt[t];
-            col_i = ri[t];
-            a = b;
-            b = ((ty >> 2) & rbit) ? child(col_i) : 0.0;
-            rot_apply(ty, rbit, rc[t], rs[t], a, b);
-            put(t, col_p, a);
+        for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+            const int ch = ch0 + q;
+            t0[q] = ch < C.nchain ? S.rch[base + ch] : 0;
+            t1[q] = ch < C.nchain ? (ch + 1 < C.nchain ? S.rch[base + ch + 1] : C.nrot) : 0;
         }
-        // The chain's last column is a survivor: it goes straight to its
-        // column of the survivor panel (the gather skips it).
-        const int ks = rend[t1[q] - 1];
-        if (ks >= 0 && (S.stype[base + ks] & rbit))
-            panel[(long long)(rbit == 1 ? ptop[ks] : pbot[ks]) * P.ld2] = b;
-    }
+#pragma unroll
+        for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+            const bool live = t0[q] < t1[q];
+            const int t = live ? t0[q] : 0;
+            ty0[q] = live ? rt[t] : 0;
+            p0[q] = S.rp[base + t];
+            i0[q] = ri[t];
+            c0[q] = rc[t];
+            s0[q] = rs[t];
+        }
+        // the first rotation's two columns of every chain: loads issued together
+        double vp[DC_ROT_CHAINS], vi[DC_ROT_CHAINS];
+#pragma unroll
+        for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+            vp[q] = (ty0[q] & rbit) ? child(p0[q]) : 0.0;
+            vi[q] = ((ty0[q] >> 2) & rbit) ? child(i0[q]) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < DC_ROT_CHAINS; ++q) {
+            if (t0[q] >= t1[q]) continue;
+            double a = vp[q], b = vi[q];
+            int ty = ty0[q], col_i = i0[q];
+            rot_apply(ty, rbit, c0[q], s0[q], a, b);
+            // the deflated column of rotation t (0 outside its row type, whose
+            // rows rot_apply leaves at 0)
+            put(t0[q], p0[q], a);
+            // the rest of a longer chain: the previous second column is this
+            // rotation's first one
+            for (int t = t0[q] + 1; t < t1[q]; ++t) {
+                const int col_p = col_i;
+                ty = rt[t];
+                col_i = ri[t];
+                a = b;
+                b = ((ty >> 2) & rbit) ? child(col_i) : 0.0;
+                rot_apply(ty, rbit, rc[t], rs[t], a, b);
+                put(t, col_p, a);
+            }
+            // The chain's last column is a survivor: it goes straight to its
+            // column of the survivor panel (the gather skips it).
+            const int ks = rend[t1[q] - 1];
+            if (ks >= 0 && (S.stype[base + ks] & rbit))
+                panel[(long long)(rbit == 1 ? ptop[ks] : pbot[ks]) * P.ld2] = b;
+        }
+    };
+    group(gb);
+    if (STRIDE)
+        for (int cg = gb + ngb; cg * DC_ROT_CHAINS < C.nchain; cg += ngb) group(cg);
 }
 
 // Final ascending order of the merged eigenvalues: roots (ascending by
@@ -785,12 +795,14 @@ void k_assemble(const Node* __restrict__ merges, const int* __restrict__ blk_sta
 // column t of the bottom panel rows [n1, m) of bottom-list entry t.
 __global__ __launch_bounds__(256)
 void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start, int nm,
-              Scratch S) {
+              bool stride, Scratch S) {
     const int mi = block_of(blk_start, nm, blockIdx.x);
     const Node N = merges[mi];
     const MergeCnt C = S.cnt[N.slot];
-    const int t0 = (blockIdx.x - blk_start[mi]) * DC_GATHER_COLS;
-    if (t0 >= max(C.ntop, C.nbot)) return;
+    const int local = blockIdx.x - blk_start[mi];
+    const int ncols = max(C.ntop, C.nbot);
+    if (local * DC_GATHER_COLS >= ncols) return;
+    const int step = dc_gather_blocks(N.n1 + N.n2, stride) * DC_GATHER_COLS;
     const Prob P = S.probs[N.prob];
     const long long base = (long long)P.row0 + N.off;
     long long ldi;
@@ -809,15 +821,17 @@ void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start
         double* o = G + (long long)t * P.ld2 + r0;
         for (int r = threadIdx.x; r < nr; r += 256) o[r] = r >= lo && r < hi ? a[r] : 0.0;
     };
-    for (int t = t0; t < t0 + DC_GATHER_COLS; ++t) {
-        // (survivors that end a rotation chain were written by the rotation)
-        if (t < C.ntop) {
-            const int ks = S.ktop[base + t];
-            if (!(S.stype[base + ks] & 4)) pack(ks, t, 0, N.n1);
-        }
-        if (t < C.nbot) {
-            const int ks = S.kbot[base + t];
-            if (!(S.stype[base + ks] & 4)) pack(ks, t, N.n1, N.n2);
+    for (int t0 = local * DC_GATHER_COLS; t0 < ncols; t0 += step) {
+        for (int t = t0; t < t0 + DC_GATHER_COLS; ++t) {
+            // (survivors that end a rotation chain were written by the rotation)
+            if (t < C.ntop) {
+                const int ks = S.ktop[base + t];
+                if (!(S.stype[base + ks] & 4)) pack(ks, t, 0, N.n1);
+            }
+            if (t < C.nbot) {
+                const int ks = S.kbot[base + t];
+                if (!(S.stype[base + ks] & 4)) pack(ks, t, N.n1, N.n2);
+            }
         }
     }
 }
@@ -893,10 +907,14 @@ hipError_t dc_launch_deflate(const Node* merges, const int* row_start, int nm, i
 }
 
 hipError_t dc_launch_rotate(const Node* merges, const int* blk_start, int nm, int nblk,
-                            Scratch S, hipStream_t s) {
+                            bool stride, Scratch S, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rotate, dim3(nblk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
-                       blk_start, nm, S);
+    if (stride)
+        hipLaunchKernelGGL(k_rotate<true>, dim3(nblk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
+                           blk_start, nm, S);
+    else
+        hipLaunchKernelGGL(k_rotate<false>, dim3(nblk), dim3(DC_ROWS_PER_BLOCK), 0, s, merges,
+                           blk_start, nm, S);
     return hipGetLastError();
 }
 
@@ -909,9 +927,10 @@ hipError_t dc_launch_assemble(const Node* merges, const int* blk_start, int nm, 
 }
 
 hipError_t dc_launch_gather(const Node* merges, const int* blk_start, int nm, int nblk,
-                            Scratch S, hipStream_t s) {
+                            bool stride, Scratch S, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(nblk), dim3(256), 0, s, merges, blk_start, nm, S);
+    hipLaunchKernelGGL(k_gather, dim3(nblk), dim3(256), 0, s, merges, blk_start, nm, stride,
+                       S);
     return hipGetLastError();
 }
 

@@ -48,6 +48,7 @@ struct Level {
     int sec_blocks, row_blocks, copy_blocks, gather_blocks, rot_blocks;
     int max_m;          // largest merge of the level
     int depth;          // tree depth of its merges (0: the roots, which write Q)
+    bool stride;        // gather and rotation workgroups take strided groups
     int variant, bm, bn;   // product tile shape of the level
     int off_tile, off_sec, off_row, off_copy, off_gather, off_rot;   // prefix offsets
 };
@@ -223,21 +224,24 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
         add(DC_ROOTS_PER_BLOCK, L.off_sec, L.sec_blocks);
         add(DC_ROWS_PER_BLOCK, L.off_row, L.row_blocks);
         add(DC_COLS_PER_BLOCK, L.off_copy, L.copy_blocks);
-        add(DC_GATHER_COLS, L.off_gather, L.gather_blocks);
-        // rotations: (row blocks) x (chain groups); at most m/2 chains
-        L.off_rot = (int)pre.size();
-        {
+        auto add_fn = [&](auto blocks_of, int& off, int& total) {
+            off = (int)pre.size();
             int a = 0;
             for (int i = 0; i < L.nm; ++i) {
                 const Node& N = P->merges[L.first + i];
-                const int m = N.n1 + N.n2;
                 pre.push_back(a);
-                a += ((m + DC_ROWS_PER_BLOCK - 1) / DC_ROWS_PER_BLOCK) *
-                     ((m / 2 + DC_ROT_CHAINS - 1) / DC_ROT_CHAINS);
+                a += blocks_of(N.n1 + N.n2);
             }
             pre.push_back(a);
-            L.rot_blocks = a;
-        }
+            total = a;
+        };
+        L.stride = L.max_m < DC_STRIDE_MAX_M;
+        const bool st = L.stride;
+        add_fn([st](int m) { return dc_gather_blocks(m, st); }, L.off_gather, L.gather_blocks);
+        // rotations: (row blocks) x (chain groups); at most m/2 chains
+        add_fn([st](int m) {
+            return ((m + DC_ROWS_PER_BLOCK - 1) / DC_ROWS_PER_BLOCK) * dc_rot_group_blocks(m, st);
+        }, L.off_rot, L.rot_blocks);
         P->levels.push_back(L);
     }
     return P;
@@ -622,9 +626,10 @@ hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& pr
         // they deflate straight to their output columns and the survivors
         // that end their chains to the panel; the gather packs the others.
         DC_TRY(prof_mark(li, MARK_ROTATE, s));
-        DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_rot, Lv.nm, Lv.rot_blocks, S, s));
-        DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks, S,
-                                s));
+        DC_TRY(dc_launch_rotate(mg, P.d_prefix + Lv.off_rot, Lv.nm, Lv.rot_blocks, Lv.stride,
+                                S, s));
+        DC_TRY(dc_launch_gather(mg, P.d_prefix + Lv.off_gather, Lv.nm, Lv.gather_blocks,
+                                Lv.stride, S, s));
         // At the root the remaining deflated columns go to Q before the
         // product, whose low-rank form keeps its skeleton columns in B1's
         // square; below the root they stay where they are.
