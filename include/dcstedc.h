@@ -70,7 +70,7 @@ typedef struct dc_opts {
                         bisection to reach 4-ulp relative accuracy) */
     int gemm_tile;   /* merge-product tile variant for every level:
                         0 = automatic (the tuned choice when one exists,
-                        else 64 x 64 tiles for levels of merges up to 256
+                        else 64 x 64 tiles for levels of merges up to 512
                         rows and the 128 x 128 register kernel above);
                         1 128 x 128 LDS kernel, two workgroups per CU;
                         2 64 x 64 LDS; 3 128 x 128 LDS, k-step 32;
@@ -206,7 +206,7 @@ int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
  * graphs stay as they were).  Allocates and synchronises: not for use inside
  * graph capture.  max_n = 0 clears the device's table and every table made
  * by dc_autotune_batched on it (back to the default rule: 64 x 64 tiles up
- * to 256 rows, 128 x 128 above).  A variant replaces the default rule's
+ * to 512 rows, 128 x 128 above).  A variant replaces the default rule's
  * choice only when it is at least 3 % faster.  Returns 0, -1 for max_n < 0,
  * or a HIP error code.
  */

@@ -155,7 +155,7 @@ int size_bucket(int m) {
 int level_variant(int forced, int max_m, const std::vector<int>* tuned) {
     if (forced > 0) return forced;
     if (tuned && (*tuned)[size_bucket(max_m)] >= 0) return (*tuned)[size_bucket(max_m)];
-    if (max_m <= 256) return 5;
+    if (max_m <= 512) return 5;
     return 0;
 }
 
