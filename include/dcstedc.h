@@ -271,15 +271,35 @@ int dc_autotune_table(int* variant_out, int cap);
  *   d_bar      out (n);  e_bar  out (n-1)
  * Equal eigenvalues make F undefined: such pairs get F_ij = 0 and the status
  * word is set to -2000 (read with dc_last_info).
- * With Q_bar, G^T = Q_bar^T Q is formed first (both operands transposed
- * into temporaries); P = Q M then runs on register tiles with M generated
- * and only the band reduced.  Temporaries (three n x n arrays with Q_bar,
- * O(n^2 / 32) partial sums) are allocated stream-ordered and freed on the
- * stream: not for graph capture.
+ * With Q_bar, G^T = Q_bar^T Q is formed first, by an MFMA product that reads
+ * both operands down their columns (no transposed copies); P = Q M then runs
+ * on register tiles with M generated and only the band reduced.  Temporaries
+ * (G^T, n x n, with Q_bar; O(n^2 / 32) partial sums) are allocated
+ * stream-ordered and freed on the stream: not for graph capture (use
+ * dc_stedc_backward_ex).
  */
 int dc_stedc_backward(int n, const double* lam, const double* Q, int ldq,
                       const double* lam_bar, const double* Q_bar, int ldqb,
                       double* d_bar, double* e_bar, hipStream_t stream);
+
+/* Workspace in bytes that dc_stedc_backward_ex needs for order n, with
+ * (with_qbar != 0) or without a Q_bar. */
+size_t dc_stedc_backward_workspace(int n, int with_qbar);
+
+/*
+ * dc_stedc_backward_ex -- dc_stedc_backward with caller workspace and status
+ * word: the same gradient (same kernels, same result bit for bit).
+ *   work, lwork  device workspace of at least
+ *                dc_stedc_backward_workspace(n, Q_bar != NULL) bytes,
+ *                256-byte aligned (else -10; too small: -11)
+ *   info_dev     device int (else -12); cleared, then -2000 when equal
+ *                eigenvalues were met
+ * It allocates nothing and never waits for the device: graph-capturable.
+ */
+int dc_stedc_backward_ex(int n, const double* lam, const double* Q, int ldq,
+                         const double* lam_bar, const double* Q_bar, int ldqb,
+                         double* d_bar, double* e_bar, void* work, size_t lwork,
+                         int* info_dev, hipStream_t stream);
 
 /*
  * dc_stedc_backward_rank1 -- the same gradient when Q_bar = u g^T has rank

@@ -15,8 +15,9 @@
 // partial row sums are written to small buffers and summed in a fixed order
 // (deterministic).
 //
-//   general Q_bar:  Q^T (explicit transpose, HBM-bound) -> G = Q^T Q_bar (loaded
-//                   MFMA product) -> P = Q M with band epilogue: 4 n^3 flops.
+//   general Q_bar:  G^T = Q_bar^T Q (an MFMA product that reads both operands
+//                   down their columns: no transpose) -> P = Q M with band
+//                   epilogue: 4 n^3 flops.
 //   rank-one Q_bar = u g^T:  G = (Q^T u) g^T is itself Cauchy-like inside F o G,
 //                   so M is generated from (Q^T u, g, lam): 2 n^3 flops.
 // Nothing of the forward tree is stored or recomputed: the final (lam, Q) is
@@ -31,22 +32,24 @@
 
 namespace {
 
-constexpr int TT = 32;
-
-__global__ void k_transpose(const double* __restrict__ A, long long lda, double* __restrict__ B,
-                            long long ldb, int n) {
-    __shared__ double t[TT][TT + 1];
-    const int bx = blockIdx.x * TT, by = blockIdx.y * TT;
-    const int tx = threadIdx.x, ty = threadIdx.y;     // 32 x 8
-    for (int k = ty; k < TT; k += 8) {
-        const int r = bx + tx, c = by + k;
-        if (r < n && c < n) t[k][tx] = A[(long long)c * lda + r];
-    }
-    __syncthreads();
-    for (int k = ty; k < TT; k += 8) {
-        const int r = by + tx, c = bx + k;            // B[r, c] = A[c, r]
-        if (r < n && c < n) B[(long long)c * ldb + r] = t[tx][k];
-    }
+// Tile of workgroup b in a tiles_m x tiles_n grid.  Each XCD (the hardware
+// places workgroup b on XCD b % 8) gets a contiguous range of the order;
+// the order runs over groups of GM tile rows, column by column within a
+// group, so the workgroups an XCD runs together cover a near-square patch
+// (8 rows x 8 columns for 64 of them) and share both operand panels in its
+// L2.  Returns false for grid padding.
+template <int GM>
+__device__ __forceinline__ bool grouped_tile(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int total = tiles_m * tiles_n;
+    const int per_xcd = (total + 7) / 8;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    if (t >= total || (b >> 3) >= per_xcd) return false;
+    const int g = t / (GM * tiles_n);
+    const int rows = min(GM, tiles_m - g * GM);
+    const int w = t - g * GM * tiles_n;
+    tn = w / rows;
+    tm = g * GM + (w - tn * rows);
+    return true;
 }
 
 // a_i = sum_l Q[l, i] u[l]: one wave per column.
@@ -77,6 +80,31 @@ __global__ void k_band_reduce(const double* __restrict__ pd, const double* __res
     if (i + 1 < n) ebar[i] = se;
 }
 
+// distinct = 1 if lam is strictly increasing (then no two eigenvalues are
+// equal and the band kernel's instance without the equality test runs),
+// else 0 (unsorted, equal or NaN entries: the instance with the test).
+__global__ __launch_bounds__(1024)
+void k_check_distinct(const double* __restrict__ lam, int n, int* __restrict__ distinct) {
+    int bad = 0;
+    for (int i = threadIdx.x; i + 1 < n; i += 1024) bad |= !(lam[i] < lam[i + 1]);
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) *distinct = !bad;
+}
+
+// With lam not strictly increasing: flag = 1 if two entries are equal (any
+// order; one thread per entry against all the others).
+__global__ __launch_bounds__(256)
+void k_equal_pairs(const double* __restrict__ lam, int n, const int* __restrict__ distinct,
+                   int* __restrict__ flag) {
+    if (*distinct) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double v = lam[i];
+    bool eq = false;
+    for (int j = 0; j < n; ++j) eq |= j != i && lam[j] == v;
+    if (eq) atomicOr(flag, 1);
+}
+
 __global__ void k_flag_to_status(const int* flag, int* status) {
     if (threadIdx.x == 0 && *flag) dc_set_info(status, DC_STATUS_EQUAL_EIG);
 }
@@ -91,29 +119,30 @@ __global__ void k_fill(double* p, long long n, double v) {
 // k-step of 4 it loads its A operands (16 consecutive rows of Q per MFMA)
 // straight from global memory RING - 1 steps ahead and generates its M
 // operands in registers:
-//     M_kc = lbar_c if k == c, 0 if lam_c == lam_k (the status flag is set),
-//            X_kc / (lam_c - lam_k) otherwise,
+//     M_kc = lbar_c if k == c, 0 if lam_c == lam_k (k_equal_pairs sets the
+//            status flag), X_kc / (lam_c - lam_k) otherwise,
 // X_kc = XR[k ldx + c] (LOADED: G stored row-major) or a_k g_c (rank one).
 // The epilogue reduces each row of the wave's block of P against rows r,
 // r + 1 and r - 1 of Q over its columns and writes one partial sum per
 // (column group, row): the column group is wcol / (16 FN), and exactly one
 // wave writes each (group, row).
-template <int FM, int FN, int WGN, int RING, bool LOADED>
+// DISTINCT: the instance for strictly increasing lam (k_check_distinct),
+// which needs no test for equal eigenvalues: off the diagonal every
+// lam_c - lam_k is non-zero.  Both instances are launched; each returns at
+// once unless the device flag selects it.
+template <int FM, int FN, int WGN, int RING, bool LOADED, bool DISTINCT>
 __global__ __launch_bounds__(WGN * 64, 2)
 void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
                 const double* __restrict__ lam, const double* __restrict__ lbar,
                 const double* __restrict__ XR, long long ldx, const double* __restrict__ av,
                 const double* __restrict__ gv, double* __restrict__ pd, double* __restrict__ pu,
-                double* __restrict__ pl, int tiles_m, int tiles_n, int* __restrict__ flag) {
+                double* __restrict__ pl, int tiles_m, int tiles_n,
+                const int* __restrict__ distinct) {
     constexpr int WR = 16 * FM, WC = 16 * FN, BN = WGN * WC;
     constexpr int PD = RING - 1;
-    // Eight consecutive blocks go to eight XCDs: give each XCD a contiguous
-    // range of tiles (whole tile rows share their panel of Q in its L2).
-    const int total = tiles_m * tiles_n;
-    const int per_xcd = (total + 7) / 8;
-    const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (t >= total) return;
-    const int tm = t / tiles_n, tn = t - (t / tiles_n) * tiles_n;
+    if ((*distinct != 0) != DISTINCT) return;
+    int tm, tn;
+    if (!grouped_tile<8>(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
     const int lane = threadIdx.x & 63, wn = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int row0 = tm * WR;
@@ -137,7 +166,6 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = dc_double4{0.0, 0.0, 0.0, 0.0};
-    bool equal_eig = false;
 
     // SHIFT (n >= WR): the rows move back inside the matrix, one base pointer
     // plus constant offsets; otherwise each row index is clamped.
@@ -176,11 +204,11 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
                     const double den = lc[j] - dk[slot];
                     const double x = LOADED ? xk[slot][j] : xk[slot][0] * gc[j];
                     const bool diag = kk == cix[j];
-                    const bool eq = den == 0.0;
                     double v = x * dc_rcp3(den);
-                    v = eq ? 0.0 : v;
+                    if constexpr (!DISTINCT) v = den == 0.0 ? 0.0 : v;
+                    // (DISTINCT: den is 0 only on the diagonal, replaced here,
+                    // and for k past n or columns past n, never used)
                     v = diag ? lb[j] : v;
-                    equal_eig |= eq && !diag && kok && cval[j];
                     bf[j] = (!MASKED || kok) ? v : 0.0;
                 }
             } else {
@@ -188,10 +216,8 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
                 for (int j = 0; j < FN; ++j) {
                     const double den = lc[j] - dk[slot];
                     const double x = LOADED ? xk[slot][j] : xk[slot][0] * gc[j];
-                    const bool eq = den == 0.0;
                     const double v = x * dc_rcp3(den);
-                    bf[j] = eq ? 0.0 : v;
-                    equal_eig |= eq && cval[j];
+                    bf[j] = (DISTINCT || den != 0.0) ? v : 0.0;
                 }
             }
 #pragma unroll
@@ -259,7 +285,163 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
             }
         }
     }
-    if (equal_eig && flag) atomicOr(flag, 1);
+}
+
+// C = A^T B for column-major A (K x M, lda) and B (K x N, ldb); C is M x N,
+// column-major (ldc).  Both operands are read down their columns, where k
+// is contiguous: within a chunk of 8 values of k, lane (r, q) of a wave
+// (r = lane % 16, q = lane / 16) loads k = 2q and 2q + 1 of its column (one
+// 16-byte load when VEC), and the chunk's two MFMA steps take them in turn.
+// An MFMA step contracts over the k its four lane rows hold; any assignment
+// of k to (lane, step) that both operands share gives the same sum, so no
+// transpose of either operand is needed.  Waves own 16 FM x 16 FN blocks of
+// C (M >= 16 FM, N >= 16 FN); a wave's window is moved back inside the
+// matrix where it would run past it (the rows or columns computed twice are
+// stored once), so every load address is a wave-uniform base plus one
+// per-lane offset.  A ring of RING chunk slots keeps the loads RING - 1
+// chunks ahead.
+typedef double dc_double2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const dc_double2 dc_gdouble2;
+
+template <int FM, int FN, int WGM, int WGN, int RING, bool VEC>
+__global__ __launch_bounds__(WGM * WGN * 64, 2)
+void k_gemm_tn(int M, int N, int K, const double* __restrict__ A, long long lda,
+               const double* __restrict__ B, long long ldb, double* __restrict__ C,
+               long long ldc, int tiles_m, int tiles_n) {
+    constexpr int WR = 16 * FM, WC = 16 * FN, BM = WGM * WR, BN = WGN * WC;
+    constexpr int PD = RING - 1;
+    int tm, tn;
+    if (!grouped_tile<8>(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WGN, wn = wave - (wave / WGN) * WGN;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int i0 = tm * BM + wm * WR, j0 = tn * BN + wn * WC;
+    if (i0 >= M || j0 >= N) return;          // no barriers: waves retire independently
+    const int ib = min(i0, M - WR), jb = min(j0, N - WC);
+    const double* __restrict__ A0 = A + (long long)ib * lda;
+    const double* __restrict__ B0 = B + (long long)jb * ldb;
+    const long long oa = (long long)lr * lda + 2 * lq, ob = (long long)lr * ldb + 2 * lq;
+    dc_double4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = dc_double4{0.0, 0.0, 0.0, 0.0};
+    dc_double2 av[RING][FM], bv[RING][FN];
+    auto ld2 = [&](const double* p) -> dc_double2 {
+        if constexpr (VEC) return *(dc_gdouble2*)p;
+        return dc_double2{dc_ldg(p), dc_ldg(p + 1)};
+    };
+    // chunk c (every k < K)
+    auto issue = [&](int slot, int c) {
+        const int kc = c * 8;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) av[slot][i] = ld2(A0 + (long long)i * 16 * lda + kc + oa);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bv[slot][j] = ld2(B0 + (long long)j * 16 * ldb + kc + ob);
+    };
+    auto compute = [&](int slot) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[slot][i][s], bv[slot][j][s],
+                                                                     acc[i][j], 0, 0, 0);
+    };
+    const int nfull = K / 8;                    // chunks with every k < K
+#pragma unroll
+    for (int c = 0; c < PD; ++c)
+        if (c < nfull) issue(c, c);
+    int c = 0;
+    for (; c + RING + PD <= nfull; c += RING) {
+#pragma unroll
+        for (int j = 0; j < RING; ++j) {
+            issue((j + PD) % RING, c + j + PD);
+            compute(j);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    for (; c < nfull; c += RING) {
+#pragma unroll
+        for (int j = 0; j < RING; ++j) {
+            if (c + j + PD < nfull) issue((j + PD) % RING, c + j + PD);
+            if (c + j < nfull) compute(j);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (nfull * 8 < K) {
+        // the last, partial chunk: k past K reads row K - 1 and counts 0
+        const int k0 = nfull * 8 + 2 * lq;
+        const bool v0 = k0 < K, v1 = k0 + 1 < K;
+        const long long d0 = min(k0, K - 1) - 2 * lq, d1 = min(k0 + 1, K - 1) - 2 * lq;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const double* p = A0 + (long long)i * 16 * lda + oa;
+            av[0][i] = dc_double2{v0 ? dc_ldg(p + d0) : 0.0, v1 ? dc_ldg(p + d1) : 0.0};
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const double* p = B0 + (long long)j * 16 * ldb + ob;
+            bv[0][j] = dc_double2{v0 ? dc_ldg(p + d0) : 0.0, v1 ? dc_ldg(p + d1) : 0.0};
+        }
+        compute(0);
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int col = jb + j * 16 + lr;
+        if (col < j0) continue;
+        double* Cc = C + (long long)col * ldc;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = ib + i * 16 + lq + 4 * v;
+                if (r >= i0) Cc[r] = acc[i][j][v];
+            }
+    }
+}
+
+// The same product for matrices smaller than one wave's window: one thread
+// per entry of C.
+__global__ void k_gemm_tn_small(int M, int N, int K, const double* __restrict__ A, long long lda,
+                                const double* __restrict__ B, long long ldb,
+                                double* __restrict__ C, long long ldc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= M || j >= N) return;
+    const double* a = A + (long long)i * lda;
+    const double* b = B + (long long)j * ldb;
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s = __builtin_fma(a[k], b[k], s);
+    C[(long long)j * ldc + i] = s;
+}
+
+constexpr int TFM = 4, TFN = 4, TWGM = 2, TWGN = 2, TRING = 2;
+
+// G^T = Q_bar^T Q (n x n, column-major, ld n) on the TN kernel.
+hipError_t gemm_tn(int n, const double* Qb, long long ldqb, const double* Q, long long ldq,
+                   double* Gt, hipStream_t s) {
+    constexpr int BM = TWGM * 16 * TFM, BN = TWGN * 16 * TFN;
+    if (n < 16 * TFM || n < 16 * TFN) {
+        hipLaunchKernelGGL(k_gemm_tn_small, dim3((n + 63) / 64, n), dim3(64), 0, s, n, n, n, Qb,
+                           ldqb, Q, ldq, Gt, (long long)n);
+        return hipGetLastError();
+    }
+    const int tiles_m = (n + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+    const int grid = (tiles_m * tiles_n + 7) / 8 * 8;
+    const bool vec = ldqb % 2 == 0 && ldq % 2 == 0 &&
+                     (reinterpret_cast<uintptr_t>(Qb) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_gemm_tn<TFM, TFN, TWGM, TWGN, TRING, true>), dim3(grid),
+                           dim3(TWGM * TWGN * 64), 0, s, n, n, n, Qb, ldqb, Q, ldq, Gt,
+                           (long long)n, tiles_m, tiles_n);
+    else
+        hipLaunchKernelGGL((k_gemm_tn<TFM, TFN, TWGM, TWGN, TRING, false>), dim3(grid),
+                           dim3(TWGM * TWGN * 64), 0, s, n, n, n, Qb, ldqb, Q, ldq, Gt,
+                           (long long)n, tiles_m, tiles_n);
+    return hipGetLastError();
 }
 
 constexpr int BFM = 8, BFN = 2, BWGN = 4, BRING = 3;
@@ -282,18 +464,31 @@ hipError_t band_product(int n, const double* lam, const double* Q, long long ldq
     double* pu = parts + (size_t)nparts * n;
     double* pl = parts + 2 * (size_t)nparts * n;
     int* flag = reinterpret_cast<int*>(tmp + o_flag);
+    int* distinct = flag + 1;                  // (the flag's slot holds 256 bytes)
     hipError_t err = dc_fill_int(flag, 1, 0, s);
     if (err != hipSuccess) return err;
-    const int grid = (tiles_m * tiles_n + 7) / 8 * 8;
-    if (XR)
-        hipLaunchKernelGGL((k_band_reg<BFM, BFN, BWGN, BRING, true>), dim3(grid),
-                           dim3(BWGN * 64), 0, s, n, Q, ldq, lam, lam_bar, XR, ldx, a, g, pd,
-                           pu, pl, tiles_m, tiles_n, flag);
-    else
-        hipLaunchKernelGGL((k_band_reg<BFM, BFN, BWGN, BRING, false>), dim3(grid),
-                           dim3(BWGN * 64), 0, s, n, Q, ldq, lam, lam_bar, XR, ldx, a, g, pd,
-                           pu, pl, tiles_m, tiles_n, flag);
+    hipLaunchKernelGGL(k_check_distinct, dim3(1), dim3(1024), 0, s, lam, n, distinct);
     err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_equal_pairs, dim3((n + 255) / 256), dim3(256), 0, s, lam, n, distinct,
+                       flag);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int grid = (tiles_m * tiles_n + 7) / 8 * 8;
+    auto launch = [&](auto loaded, auto dist) {
+        hipLaunchKernelGGL((k_band_reg<BFM, BFN, BWGN, BRING, decltype(loaded)::value,
+                                       decltype(dist)::value>),
+                           dim3(grid), dim3(BWGN * 64), 0, s, n, Q, ldq, lam, lam_bar, XR, ldx,
+                           a, g, pd, pu, pl, tiles_m, tiles_n, distinct);
+        return hipGetLastError();
+    };
+    if (XR) {
+        err = launch(dc_true_type{}, dc_true_type{});
+        if (err == hipSuccess) err = launch(dc_true_type{}, dc_false_type{});
+    } else {
+        err = launch(dc_false_type{}, dc_true_type{});
+        if (err == hipSuccess) err = launch(dc_false_type{}, dc_false_type{});
+    }
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_band_reduce, dim3((n + 255) / 256), dim3(256), 0, s, pd, pu, pl,
                        nparts, n, d_bar, e_bar);
@@ -309,9 +504,28 @@ size_t parts_bytes(int n) {
 
 }  // namespace
 
-extern "C" int dc_stedc_backward(int n, const double* lam, const double* Q, int ldq,
-                                 const double* lam_bar, const double* Q_bar, int ldqb,
-                                 double* d_bar, double* e_bar, hipStream_t stream) {
+namespace {
+
+// Workspace of the general adjoint: the equal-eigenvalue flag, the partial
+// band sums, a zero vector (the rank-one generators of M when there is no
+// Q_bar) and G^T = Q_bar^T Q (with Q_bar).
+struct BwLayout {
+    size_t flag, parts, zero, g, bytes;
+};
+
+BwLayout bw_layout(int n, bool with_qbar) {
+    BwLayout L;
+    size_t o = 0;
+    L.flag = o; o = al(o + sizeof(int));
+    L.parts = o; o = al(o + parts_bytes(n));
+    L.zero = o; o = al(o + (size_t)n * sizeof(double));
+    L.g = o; o = al(o + (with_qbar ? (size_t)n * n * sizeof(double) : 0));
+    L.bytes = o;
+    return L;
+}
+
+int backward_check(int n, const double* lam, const double* Q, int ldq, const double* Q_bar,
+                   int ldqb, const double* d_bar, const double* e_bar) {
     if (n < 0) return -1;
     if (n == 0) return 0;
     if (!lam) return -2;
@@ -320,79 +534,73 @@ extern "C" int dc_stedc_backward(int n, const double* lam, const double* Q, int 
     if (Q_bar && ldqb < n) return -7;
     if (!d_bar) return -8;
     if (n > 1 && !e_bar) return -9;
+    return 0;
+}
+
+// G^T = Q_bar^T Q on the TN kernel (both operands read down their columns),
+// then P = Q M with the band epilogue.  Launches only.
+hipError_t backward_run(int n, const double* lam, const double* Q, int ldq,
+                        const double* lam_bar, const double* Q_bar, int ldqb, double* d_bar,
+                        double* e_bar, char* w, const BwLayout& L, int* status,
+                        hipStream_t s) {
+    double* zero = reinterpret_cast<double*>(w + L.zero);
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, zero, (long long)n,
+                       0.0);
+    hipError_t err = hipGetLastError();
+    const double* XR = nullptr;
+    if (err == hipSuccess && Q_bar) {
+        double* Gt = reinterpret_cast<double*>(w + L.g);
+        err = gemm_tn(n, Q_bar, ldqb, Q, ldq, Gt, s);
+        XR = Gt;       // G^T column-major is G row-major, as the band kernel reads it
+    }
+    if (err == hipSuccess)
+        // without Q_bar, X = a g^T with a = g = 0: M = diag(lam_bar)
+        err = band_product(n, lam, Q, ldq, lam_bar, XR, n, zero, zero, d_bar, e_bar, w,
+                           L.parts, L.flag, status, s);
+    return err;
+}
+
+}  // namespace
+
+extern "C" size_t dc_stedc_backward_workspace(int n, int with_qbar) {
+    if (n < 0) return 0;
+    return bw_layout(n, with_qbar != 0).bytes;
+}
+
+extern "C" int dc_stedc_backward_ex(int n, const double* lam, const double* Q, int ldq,
+                                    const double* lam_bar, const double* Q_bar, int ldqb,
+                                    double* d_bar, double* e_bar, void* work, size_t lwork,
+                                    int* info_dev, hipStream_t stream) {
+    const int bad = backward_check(n, lam, Q, ldq, Q_bar, ldqb, d_bar, e_bar);
+    if (bad || n < 0) return bad;
+    if (!info_dev) return -12;
+    if (n == 0) return (int)dc_fill_int(info_dev, 1, 0, stream);
+    const BwLayout L = bw_layout(n, Q_bar != nullptr);
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255) != 0) return -10;
+    if (lwork < L.bytes) return -11;
+    hipError_t err = dc_fill_int(info_dev, 1, 0, stream);
+    if (err == hipSuccess)
+        err = backward_run(n, lam, Q, ldq, lam_bar, Q_bar, ldqb, d_bar, e_bar,
+                           static_cast<char*>(work), L, info_dev, stream);
+    return (int)err;
+}
+
+extern "C" int dc_stedc_backward(int n, const double* lam, const double* Q, int ldq,
+                                 const double* lam_bar, const double* Q_bar, int ldqb,
+                                 double* d_bar, double* e_bar, hipStream_t stream) {
+    const int bad = backward_check(n, lam, Q, ldq, Q_bar, ldqb, d_bar, e_bar);
+    if (bad || n <= 0) return bad;
     int* status = nullptr;
     hipError_t err = dc_status_word(stream, &status);
     if (err != hipSuccess) return (int)err;
     err = dc_fill_int(status, 1, 0, stream);
     if (err != hipSuccess) return (int)err;
-    size_t o = 0;
-    const size_t o_task = o; o = al(o + 2048);
-    const size_t o_flag = o; o = al(o + sizeof(int));
-    const size_t o_parts = o; o = al(o + parts_bytes(n));
-    const size_t o_ones = o; o = al(o + (size_t)n * sizeof(double));
-    const size_t o_zero = o; o = al(o + (size_t)n * sizeof(double));
-    const size_t o_qt = o; o = al(o + (Q_bar ? (size_t)n * n * sizeof(double) : 0));
-    const size_t o_qbt = o; o = al(o + (Q_bar ? (size_t)n * n * sizeof(double) : 0));
-    const size_t o_g = o; o = al(o + (Q_bar ? (size_t)n * n * sizeof(double) : 0));
+    const BwLayout L = bw_layout(n, Q_bar != nullptr);
     char* tmp = nullptr;
-    err = hipMallocAsync((void**)&tmp, o, stream);
+    err = hipMallocAsync((void**)&tmp, L.bytes, stream);
     if (err != hipSuccess) return (int)err;
-    double* ones = reinterpret_cast<double*>(tmp + o_ones);
-    double* zero = reinterpret_cast<double*>(tmp + o_zero);
-    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, stream, ones, (long long)n,
-                       1.0);
-    err = hipGetLastError();
-    if (err == hipSuccess) {
-        hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, stream, zero,
-                           (long long)n, 0.0);
-        err = hipGetLastError();
-    }
-    const double* XR = nullptr;
-    if (err == hipSuccess && Q_bar) {
-        // G^T = Q_bar^T Q through the loaded k-phase of the merge product's
-        // register kernel (A2 = Q_bar^T, B2 = Q row-major; no generated phase;
-        // column scales 1): G^T column-major is G row-major.
-        double* Qt = reinterpret_cast<double*>(tmp + o_qt);
-        double* Qbt = reinterpret_cast<double*>(tmp + o_qbt);
-        double* Gt = reinterpret_cast<double*>(tmp + o_g);
-        const dim3 tg((n + TT - 1) / TT, (n + TT - 1) / TT), tb(TT, 8);
-        hipLaunchKernelGGL(k_transpose, tg, tb, 0, stream, Q, (long long)ldq, Qt, (long long)n,
-                           n);
-        err = hipGetLastError();
-        if (err == hipSuccess) {
-            hipLaunchKernelGGL(k_transpose, tg, tb, 0, stream, Q_bar, (long long)ldqb, Qbt,
-                               (long long)n, n);
-            err = hipGetLastError();
-        }
-        GemmTask T;
-        std::memset(&T, 0, sizeof(T));
-        T.klen = 0;
-        T.rows = n;
-        T.ncol = n;
-        T.cbase = ones;
-        T.cs = ones;
-        T.C = Gt;
-        T.ldc = n;
-        T.A2 = Qbt;
-        T.lda2 = n;
-        T.B2 = Qt;
-        T.ldb2 = n;
-        T.klen2 = n;
-        T.tiles_m = (n + dc_gemm_tile_m(0) - 1) / dc_gemm_tile_m(0);
-        T.tiles_n = (n + dc_gemm_tile_n(0) - 1) / dc_gemm_tile_n(0);
-        const int ts[2] = {0, T.tiles_m * T.tiles_n};
-        if (err == hipSuccess) err = dc_write_blob(tmp + o_task, &T, sizeof(T), stream);
-        if (err == hipSuccess) err = dc_write_blob(tmp + o_task + 1024, ts, sizeof(ts), stream);
-        if (err == hipSuccess)
-            err = dc_launch_cauchy_gemm2(reinterpret_cast<GemmTask*>(tmp + o_task),
-                                         reinterpret_cast<int*>(tmp + o_task + 1024), 1, ts[1],
-                                         0, stream);
-        XR = Gt;
-    }
-    if (err == hipSuccess)
-        // without Q_bar, X = a g^T with a = g = 0: M = diag(lam_bar)
-        err = band_product(n, lam, Q, ldq, lam_bar, XR, n, zero, zero, d_bar, e_bar, tmp,
-                           o_parts, o_flag, status, stream);
+    err = backward_run(n, lam, Q, ldq, lam_bar, Q_bar, ldqb, d_bar, e_bar, tmp, L, status,
+                       stream);
     hipError_t e2 = hipFreeAsync(tmp, stream);
     return (int)(err != hipSuccess ? err : e2);
 }

@@ -60,6 +60,9 @@ SIGNATURES = [
     ("dc_autotune_levels", c_int, [c_int, P, c_int, P, c_int]),
     ("dc_autotune_lowrank", c_int, [c_int, P, c_int, P, P]),
     ("dc_stedc_backward", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P]),
+    ("dc_stedc_backward_workspace", c_size_t, [c_int, c_int]),
+    ("dc_stedc_backward_ex", c_int, [c_int, P, P, c_int, P, P, c_int, P, P, P, c_size_t, P,
+                                     P]),
     ("dc_stedc_backward_rank1", c_int, [c_int, P, P, c_int, P, P, P, P, P, P]),
     ("dc_stedc_backward_rank1_noalloc", c_int, [c_int, P, P, c_int, P, P, P, P, P, P, P]),
     ("dc_stedc_backward_rank1_noalloc_max_bytes", c_size_t, []),
@@ -361,6 +364,40 @@ def backward(lam, Qbuf, lam_bar=None, Qbar_cm=None):
     return d_bar, e_bar[:max(n - 1, 0)]
 
 
+def backward_workspace(n, with_qbar):
+    """Workspace tensor (float64, on the GPU) for backward_ex, with room to
+    align its start to 256 bytes."""
+    nbytes = load().dc_stedc_backward_workspace(n, 1 if with_qbar else 0)
+    return torch.empty(max(nbytes, 8) // 8 + 33, dtype=torch.float64, device="cuda")
+
+
+def backward_ex(lam, Qbuf, lam_bar=None, Qbar_cm=None, work=None, info=None, d_bar=None,
+                e_bar=None):
+    """dc_stedc_backward_ex: the same gradient with caller workspace and device
+    status (info, an int32 tensor of one element); allocates nothing itself
+    when work, info and the outputs are given (capturable).  Returns
+    (d_bar, e_bar, info)."""
+    n = lam.numel()
+    if work is None:
+        work = backward_workspace(n, Qbar_cm is not None)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if d_bar is None:
+        d_bar = torch.empty(n, dtype=torch.float64, device="cuda")
+    if e_bar is None:
+        e_bar = torch.empty(max(n - 1, 1), dtype=torch.float64, device="cuda")
+    addr = work.data_ptr()
+    start = (addr + 255) & ~255
+    _check(load().dc_stedc_backward_ex(n, _ptr(lam), _ptr(Qbuf), Qbuf.shape[1],
+                                       _ptr(lam_bar), _ptr(Qbar_cm),
+                                       Qbar_cm.shape[1] if Qbar_cm is not None else n,
+                                       _ptr(d_bar), _ptr(e_bar), ctypes.c_void_p(start),
+                                       work.numel() * 8 - (start - addr), _ptr(info),
+                                       _stream()),
+           "dc_stedc_backward_ex")
+    return d_bar, e_bar[:max(n - 1, 0)], info
+
+
 def backward_rank1(lam, Qbuf, u, g, lam_bar=None):
     """Gradient for Q_bar = u g^T (rank one)."""
     n = lam.numel()
@@ -381,7 +418,7 @@ def backward_status():
 class EighTridiagonal(torch.autograd.Function):
     """(lam, Q) = eig(T(d, e)) with the library's adjoint as backward.
 
-    forward: dc_stedc_ex; backward: dc_stedc_backward on the saved final
+    forward: dc_stedc_ex; backward: dc_stedc_backward_ex on the saved final
     (lam, Q) only -- no per-level state is kept.
     """
 
@@ -405,8 +442,8 @@ class EighTridiagonal(torch.autograd.Function):
         lam, Qbuf = ctx.saved_tensors
         lb = lam_bar.contiguous() if lam_bar is not None else None
         qb = Q_bar.t().contiguous() if Q_bar is not None else None
-        d_bar, e_bar = backward(lam, Qbuf, lb, qb)
-        st = backward_status()                 # waits for the backward kernels
+        d_bar, e_bar, info = backward_ex(lam, Qbuf, lb, qb)
+        st = int(info.item())                  # waits for the backward kernels
         if st == -2000:
             warnings.warn("eigh_tridiagonal backward: equal eigenvalues, the terms "
                           "1 / (lam_j - lam_i) of such pairs were dropped "

@@ -58,6 +58,17 @@ def test_host_side_argument_checks_need_no_gpu():
                                8192, 1e-10, 8192, None) == -13
     assert lib.dc_merge_lowrank_ranks(8192, fake, fake, fake, fake, fake, 1e-10, 4096, 0,
                                       fake, None) == -8
+    # the adjoint's caller-workspace form: status word, then workspace alignment
+    # and size, all before any device work
+    assert lib.dc_stedc_backward_workspace(-1, 0) == 0
+    need = lib.dc_stedc_backward_workspace(4, 1)
+    assert need > 0
+    assert lib.dc_stedc_backward_ex(4, fake, fake, 4, None, fake, 4, fake, fake, fake, need,
+                                    None, None) == -12
+    assert lib.dc_stedc_backward_ex(4, fake, fake, 4, None, fake, 4, fake, fake,
+                                    ctypes.c_void_p(264), need, fake, None) == -10
+    assert lib.dc_stedc_backward_ex(4, fake, fake, 4, None, fake, 4, fake, fake, fake,
+                                    need - 1, fake, None) == -11
     assert lib.dc_merge_lowrank_ranks(8192, fake, None, fake, fake, fake, 1e-10, 1024, -1,
                                       fake, None) == -9
     assert lib.dc_autotune(-1, None) == -1
