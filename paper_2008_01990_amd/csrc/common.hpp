@@ -125,6 +125,11 @@ hipError_t dc_launch_cauchy_gemm2(const GemmTask* tasks_dev, const int* tile_sta
 hipError_t dc_launch_cauchy_gemm_bounded(const GemmTask* tasks_dev, const int* tile_start_dev,
                                          int ntasks, int max_tiles, const int* total_tiles_dev,
                                          int variant, bool two_phase, hipStream_t stream);
+// Tasks whose column counts the device now knows: rewrites each task's
+// tiles_n to ceil(ncol / bn) and writes the exclusive prefix of
+// tiles_m * tiles_n (ntasks + 1 ints) and its sum, for a bounded launch.
+hipError_t dc_launch_tile_scan(GemmTask* tasks, int ntasks, int bn, int* tile_start, int* total,
+                               hipStream_t s);
 // Number of merge-product tile variants (0 .. DC_TILE_VARIANTS - 1).
 constexpr int DC_TILE_VARIANTS = 6;
 int dc_gemm_tile_m(int variant);

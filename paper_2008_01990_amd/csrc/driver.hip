@@ -308,7 +308,7 @@ hipError_t get_plan(const std::vector<int>& sizes, int leaf, int variant, Plan**
 // Workspace layout.
 struct Layout {
     size_t bytes = 0;
-    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, rng, bufs, lr;
+    size_t probs, gtask, stask, cnt, rho2, psc, dbl, ints, rng, tiles, bufs, lr;
     int nd = 16, ni = 19;
 };
 
@@ -385,6 +385,8 @@ Layout layout(const Plan& P, const LrPlan* LP = nullptr) {
     L.dbl = o; o = align256(o + L.nd * R * sizeof(double));
     L.ints = o; o = align256(o + L.ni * R * sizeof(int));
     L.rng = o; o = align256(o + 2 * R * sizeof(int2));
+    // per level: the actual tile prefix of its 2 nm product tasks and the total
+    L.tiles = o; o = align256(o + (2 * nm + 2 * (P.levels.size() + 1)) * sizeof(int));
     L.bufs = o; o = align256(o + (P.buf_elems + P.pan_elems) * sizeof(double));
     L.lr = o; o = align256(o + (LP ? LP->bytes : 0));
     L.bytes = o;
@@ -640,8 +642,24 @@ hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& pr
         DC_TRY(prof_mark(li, MARK_PRODUCT, s));
         if (lr && LP->levels[li].njobs > 0)
             DC_TRY(lowrank_level(*LP, li, lrbase, o.lr_tol, s));
-        DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
-                                     2 * Lv.nm, Lv.tiles, Lv.variant, s));
+        if (Lv.stride && Lv.max_m >= 1024 && (Lv.variant == 0 || Lv.variant == 5)) {
+            // Levels of merges from 1024 to 4095 rows (the top of a batch of
+            // random problems, whose K is a few percent of m): the tiles of
+            // the actual K, compacted on the device; the workgroups of the
+            // worst-case grid past their total exit at once instead of
+            // searching the task list first (batched 256 problems: the two
+            // top levels' products 0.37 -> 0.29 ms; on the levels of
+            // smaller merges the scan's own launch cost more than it saved).
+            int* act = reinterpret_cast<int*>(work + L.tiles) + 2 * Lv.first + 2 * li;
+            DC_TRY(dc_launch_tile_scan(S.gtask + 2 * Lv.first, 2 * Lv.nm, Lv.bn, act,
+                                       act + 2 * Lv.nm + 1, s));
+            DC_TRY(dc_launch_cauchy_gemm_bounded(S.gtask + 2 * Lv.first, act, 2 * Lv.nm,
+                                                 Lv.tiles, act + 2 * Lv.nm + 1, Lv.variant,
+                                                 false, s));
+        } else {
+            DC_TRY(dc_launch_cauchy_gemm(S.gtask + 2 * Lv.first, P.d_prefix + Lv.off_tile,
+                                         2 * Lv.nm, Lv.tiles, Lv.variant, s));
+        }
         DC_TRY(prof_mark(li, NPHASE, s));
 #undef DC_TRY
     }
