@@ -500,6 +500,62 @@ hipError_t prof_lr_events(int level, hipEvent_t* ev4, bool* on) {
 
 namespace {
 
+// Actual tile grids of a level's plain product tasks, once the device knows
+// each merge's K: every task's tiles_n becomes ceil(ncol / bn) (its rows
+// are fixed), and tile_start / *total their exclusive prefix and sum.  One
+// workgroup.
+constexpr int SCAN_NT = 1024;
+__global__ __launch_bounds__(SCAN_NT)
+void k_tile_scan(GemmTask* __restrict__ tasks, int ntasks, int bn, int* __restrict__ tile_start,
+                 int* __restrict__ total) {
+    __shared__ int wsum[SCAN_NT / 64];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < ntasks; base += SCAN_NT) {
+        const int t = base + tid;
+        int v = 0;
+        if (t < ntasks) {
+            GemmTask& T = tasks[t];
+            const int ncol = T.ncol_p ? *T.ncol_p : T.ncol;
+            const int tn = (ncol + bn - 1) / bn;
+            T.tiles_n = tn;
+            v = T.tiles_m * tn;
+        }
+        int x = v;                                      // inclusive scan in the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        int before = carry;
+        for (int q = 0; q < w; ++q) before += wsum[q];
+        if (t < ntasks) tile_start[t] = before + x - v;
+        __syncthreads();
+        if (tid == SCAN_NT - 1) carry = before + x;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        tile_start[ntasks] = carry;
+        *total = carry;
+    }
+}
+
+}  // namespace
+
+hipError_t dc_launch_tile_scan(GemmTask* tasks, int ntasks, int bn, int* tile_start, int* total,
+                               hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(SCAN_NT), 0, s, tasks, ntasks, bn, tile_start,
+                       total);
+    return hipGetLastError();
+}
+
+namespace {
+
 // The low-rank jobs of every candidate of the plan: the call's pointers
 // (problem buffers, scratch, workspace) and the candidate's regions.  W is
 // the candidate's square of the buffer it does not write: Q below the root
