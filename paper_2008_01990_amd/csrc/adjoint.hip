@@ -65,19 +65,39 @@ __global__ void k_gemv_t(const double* __restrict__ Q, long long ldq, const doub
     if (lane == 0) a[col] = s;
 }
 
-__global__ void k_band_reduce(const double* __restrict__ pd, const double* __restrict__ pu,
-                              const double* __restrict__ pl, int nparts, int n,
-                              double* __restrict__ dbar, double* __restrict__ ebar) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// d_bar_i = sum_p pd[p][i], e_bar_i = sum_p (pu[p][i] + pl[p][i+1]) over the
+// column groups p, in a fixed order: a workgroup takes 32 rows; its eight
+// lanes per row sum the groups p = g, g + 8, ... (g = 0..7) in increasing
+// p, and the eight partial sums are added in order of g.
+constexpr int RED_ROWS = 32, RED_SPLIT = 8;
+__global__ __launch_bounds__(RED_ROWS * RED_SPLIT)
+void k_band_reduce(const double* __restrict__ pd, const double* __restrict__ pu,
+                   const double* __restrict__ pl, int nparts, int n,
+                   double* __restrict__ dbar, double* __restrict__ ebar) {
+    __shared__ double sd_g[RED_SPLIT][RED_ROWS], se_g[RED_SPLIT][RED_ROWS];
+    const int r = threadIdx.x % RED_ROWS, g = threadIdx.x / RED_ROWS;
+    const int i = blockIdx.x * RED_ROWS + r;
     double sd = 0.0, se = 0.0;
-    for (int p = 0; p < nparts; ++p) {
-        const long long o = (long long)p * n;
-        sd += pd[o + i];
-        if (i + 1 < n) se += pu[o + i] + pl[o + i + 1];
+    if (i < n) {
+        for (int p = g; p < nparts; p += RED_SPLIT) {
+            const long long o = (long long)p * n;
+            sd += pd[o + i];
+            if (i + 1 < n) se += pu[o + i] + pl[o + i + 1];
+        }
     }
-    dbar[i] = sd;
-    if (i + 1 < n) ebar[i] = se;
+    sd_g[g][r] = sd;
+    se_g[g][r] = se;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        double td = 0.0, te = 0.0;
+#pragma unroll
+        for (int q = 0; q < RED_SPLIT; ++q) {
+            td += sd_g[q][r];
+            te += se_g[q][r];
+        }
+        dbar[i] = td;
+        if (i + 1 < n) ebar[i] = te;
+    }
 }
 
 // distinct = 1 if lam is strictly increasing (then no two eigenvalues are
@@ -232,6 +252,39 @@ void k_band_reg(int n, const double* __restrict__ Q, long long ldq,
 #pragma unroll
         for (int s = 0; s < PD; ++s) issue(s, s);
         int s = 0;
+        if constexpr (SHIFT) {
+            // Steps whose prefetches all lie below n: no clamp, running
+            // pointers instead of an index product per step (the MFMA pipe
+            // waits for integer VALU work as for the generation of M).
+            const long long kstep = 4 * ldq, xstep = 4 * ldx;
+            const double* __restrict__ pa = Ab + (long long)(PD * 4 + lk) * ldq;
+            const double* __restrict__ pl = lam + PD * 4 + lk;
+            const double* __restrict__ px = LOADED ? XR + (long long)(PD * 4 + lk) * ldx : av + PD * 4 + lk;
+            int xc[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) xc[j] = min(cix[j], n - 1);
+            for (; s + 2 * RING - 1 <= nfull; s += RING) {
+#pragma unroll
+                for (int j = 0; j < RING; ++j) {
+                    const int sl = (j + PD) % RING;
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) a[sl][i] = dc_ldg(pa + i * 16);
+                    dk[sl] = dc_ldg(pl);
+                    if constexpr (LOADED) {
+#pragma unroll
+                        for (int q = 0; q < FN; ++q) xk[sl][q] = dc_ldg(px + xc[q]);
+                        px += xstep;
+                    } else {
+                        xk[sl][0] = dc_ldg(px);
+                        px += 4;
+                    }
+                    pa += kstep;
+                    pl += 4;
+                    compute(j, s + j, dc_false_type{});
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
         for (; s + RING <= nfull; s += RING) {
 #pragma unroll
             for (int j = 0; j < RING; ++j) {
@@ -490,8 +543,8 @@ hipError_t band_product(int n, const double* lam, const double* Q, long long ldq
         if (err == hipSuccess) err = launch(dc_false_type{}, dc_false_type{});
     }
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_band_reduce, dim3((n + 255) / 256), dim3(256), 0, s, pd, pu, pl,
-                       nparts, n, d_bar, e_bar);
+    hipLaunchKernelGGL(k_band_reduce, dim3((n + RED_ROWS - 1) / RED_ROWS),
+                       dim3(RED_ROWS * RED_SPLIT), 0, s, pd, pu, pl, nparts, n, d_bar, e_bar);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_flag_to_status, dim3(1), dim3(64), 0, s, flag, status);
@@ -544,9 +597,12 @@ hipError_t backward_run(int n, const double* lam, const double* Q, int ldq,
                         double* e_bar, char* w, const BwLayout& L, int* status,
                         hipStream_t s) {
     double* zero = reinterpret_cast<double*>(w + L.zero);
-    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, zero, (long long)n,
-                       0.0);
-    hipError_t err = hipGetLastError();
+    hipError_t err = hipSuccess;
+    if (!Q_bar) {
+        hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, zero, (long long)n,
+                           0.0);
+        err = hipGetLastError();
+    }
     const double* XR = nullptr;
     if (err == hipSuccess && Q_bar) {
         double* Gt = reinterpret_cast<double*>(w + L.g);

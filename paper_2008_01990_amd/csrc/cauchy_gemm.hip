@@ -407,6 +407,33 @@ __device__ __forceinline__ void reg_tile(const GemmTask& T, int local) {
 #pragma unroll
             for (int s = 0; s < PD; ++s) issue(s, s);
             int s = 0;
+            if constexpr (SHIFT) {
+                // Steps whose prefetches all lie below klen: no clamp, and
+                // running pointers (one 64-bit add per step for the A rows,
+                // one each for the row generators) instead of an index
+                // product per step; the integer VALU work of a step was ten
+                // instructions, which the MFMA pipe waits for as it waits
+                // for U's generation.
+                const long long kstep = 4 * lda;
+                const double* __restrict__ pa = Ab + (long long)(PD * 4 + lk) * lda;
+                const double* __restrict__ pdd = rD + PD * 4 + lk;
+                const double* __restrict__ pzz = rz + PD * 4 + lk;
+                for (; s + 2 * RING - 1 <= nfull; s += RING) {
+#pragma unroll
+                    for (int j = 0; j < RING; ++j) {
+                        const int sl = (j + PD) % RING;
+#pragma unroll
+                        for (int i = 0; i < FM; ++i) a[sl][i] = dc_ldg(pa + i * 16);
+                        dd[sl] = dc_ldg(pdd);
+                        zz[sl] = dc_ldg(pzz);
+                        pa += kstep;
+                        pdd += 4;
+                        pzz += 4;
+                        compute(j, s + j, dc_false_type{});
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
             for (; s + RING <= nfull; s += RING) {
 #pragma unroll
                 for (int j = 0; j < RING; ++j) {
@@ -464,6 +491,29 @@ __device__ __forceinline__ void reg_tile(const GemmTask& T, int local) {
 #pragma unroll
             for (int s = 0; s < PD; ++s) issue2(s, s);
             int s = 0;
+            if constexpr (SHIFT) {
+                // as in the generated phase: unclamped steps on running pointers
+                const long long kstep = 4 * lda2, bstep = 4 * ldb2;
+                const double* __restrict__ pa = Ab2 + (long long)(PD * 4 + lk) * lda2;
+                const double* __restrict__ pb = B2 + (long long)(PD * 4 + lk) * ldb2;
+                int bc[FN];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bc[j] = min(wcol + j * 16 + lr, ncol - 1);
+                for (; s + 2 * RING - 1 <= nfull; s += RING) {
+#pragma unroll
+                    for (int j = 0; j < RING; ++j) {
+                        const int sl = (j + PD) % RING;
+#pragma unroll
+                        for (int i = 0; i < FM; ++i) a[sl][i] = dc_ldg(pa + i * 16);
+#pragma unroll
+                        for (int q = 0; q < FN; ++q) b2[sl][q] = dc_ldg(pb + bc[q]);
+                        pa += kstep;
+                        pb += bstep;
+                        compute2(j, s + j, dc_false_type{});
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
             for (; s + RING <= nfull; s += RING) {
 #pragma unroll
                 for (int j = 0; j < RING; ++j) {
