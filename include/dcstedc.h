@@ -169,7 +169,11 @@ int dc_secular(int K, const double* Dbar, const double* zbar, double rho,
  *   lr_block     block size for lr_tol > 0 (<= 0: default 256); at most
  *                2048 with org, 4096 with org == NULL (else returns -13)
  * With lr_tol > 0 it allocates its temporaries stream-ordered
- * (hipMallocAsync / hipFreeAsync on the stream) and does not wait for it.
+ * (hipMallocAsync / hipFreeAsync on the stream) and waits for the stream
+ * once, after the compression, to size the skeleton columns W (m x the sum
+ * of the ranks, a block kept dense counting its width) exactly; when W
+ * would take more than half the free device memory the plain product runs
+ * instead.
  */
 int dc_merge_update(int m, int K, const double* Qnd, int ldq,
                     const double* Dbar, const int* org, const double* tau,

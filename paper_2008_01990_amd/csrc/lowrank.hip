@@ -684,23 +684,26 @@ hipError_t dc_lowrank_decide(LrJob* jobs_dev, int njobs, int b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
-                            int srrsc_blocks, GemmTask* tskel, GemmTask* tfused, int ntasks,
-                            int* tile_start, int* totals, int b, double tol, int max_pmax,
-                            int max_tiles_skel, int max_tiles_fused, bool offsets,
-                            hipStream_t s, const hipEvent_t* ev) {
-    if (njobs <= 0) return hipSuccess;
+namespace {
+
+// The two halves of a level's pipeline: the SRRSC compression, then the
+// planning, interpolation rows and the two product launches.
+hipError_t lowrank_compress(LrJob* jobs_dev, int njobs, const int* srrsc_start,
+                            int srrsc_blocks, int b, double tol, bool offsets, hipStream_t s) {
+    return launch_srrsc(jobs_dev, srrsc_start, njobs, srrsc_blocks, b, offsets, tol,
+                        dc_lowrank_rmax(b), true, s);
+}
+
+hipError_t lowrank_products(LrJob* jobs_dev, int njobs, GemmTask* tskel, GemmTask* tfused,
+                            int ntasks, int* tile_start, int* totals, int b, int max_pmax,
+                            int max_tiles_skel, int max_tiles_fused, hipStream_t s,
+                            const hipEvent_t* ev) {
     const int rmax = dc_lowrank_rmax(b);
-    hipError_t err = ev ? hipEventRecord(ev[0], s) : hipSuccess;
-    if (err == hipSuccess)
-        err = launch_srrsc(jobs_dev, srrsc_start, njobs, srrsc_blocks, b, offsets, tol, rmax,
-                           true, s);
-    if (err != hipSuccess) return err;
     const size_t lds = (size_t)(4 * max_pmax + 2 + NT) * sizeof(int);
     hipLaunchKernelGGL(k_lr_plan, dim3(njobs), dim3(NT), lds, s, jobs_dev, b, rmax,
                        dc_gemm_tile_m(SKEL_VARIANT), dc_gemm_tile_n(SKEL_VARIANT),
                        dc_gemm_tile_m(FUSED_VARIANT), dc_gemm_tile_n(FUSED_VARIANT));
-    err = hipGetLastError();
+    hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_build_y, dim3(256, njobs), dim3(256), 0, s, jobs_dev, b);
     err = hipGetLastError();
@@ -717,6 +720,23 @@ hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
         err = dc_launch_cauchy_gemm_bounded(tfused, tile_start + ntasks + 1, ntasks,
                                             max_tiles_fused, totals + 1, FUSED_VARIANT, true, s);
     if (err == hipSuccess && ev) err = hipEventRecord(ev[3], s);
+    return err;
+}
+
+}  // namespace
+
+hipError_t dc_lowrank_level(LrJob* jobs_dev, int njobs, const int* srrsc_start,
+                            int srrsc_blocks, GemmTask* tskel, GemmTask* tfused, int ntasks,
+                            int* tile_start, int* totals, int b, double tol, int max_pmax,
+                            int max_tiles_skel, int max_tiles_fused, bool offsets,
+                            hipStream_t s, const hipEvent_t* ev) {
+    if (njobs <= 0) return hipSuccess;
+    hipError_t err = ev ? hipEventRecord(ev[0], s) : hipSuccess;
+    if (err == hipSuccess)
+        err = lowrank_compress(jobs_dev, njobs, srrsc_start, srrsc_blocks, b, tol, offsets, s);
+    if (err == hipSuccess)
+        err = lowrank_products(jobs_dev, njobs, tskel, tfused, ntasks, tile_start, totals, b,
+                               max_pmax, max_tiles_skel, max_tiles_fused, s, ev);
     return err;
 }
 
@@ -738,9 +758,13 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     const int b = lr_block;
     if (b > dc_lowrank_max_block(org != nullptr)) return hipErrorInvalidValue;
     const int pmax = (K + b - 1) / b;
-    const int wcap = K;
-    // temporary: nodes | job | plain task | srrsc prefix | zero | tasks |
-    // tile prefix | totals | regions | W
+    // Two passes with one host wait between them: the compression, whose
+    // ranks give the exact number of skeleton columns NW (blocks of
+    // near-full rank, as in a block-cyclic order, need several times K of
+    // them), then W (m x NW), the interpolation rows and the column layout,
+    // allocated at that size, and the products.
+    // temporary 1: nodes | job | plain task | srrsc prefix | zero | tasks |
+    // tile prefix | totals | SRRSC regions
     size_t o = 0;
     const size_t o_nodes = o; o = al(o + (org ? 2 * (size_t)K * sizeof(double) : 0));
     const size_t o_job = o; o = al(o + sizeof(LrJob));
@@ -748,8 +772,7 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     const size_t o_small = o; o = al(o + 16 * sizeof(int));
     const size_t o_tasks = o; o = al(o + 2 * (size_t)pmax * sizeof(GemmTask));
     const size_t o_ts = o; o = al(o + 2 * ((size_t)pmax + 1) * sizeof(int));
-    const size_t o_reg = o; o = al(o + dc_lowrank_region_bytes(pmax, b, wcap));
-    const size_t o_w = o; o = al(o + (size_t)m * wcap * sizeof(double));
+    const size_t o_reg = o; o = al(o + dc_lowrank_region_bytes(pmax, b, 1));
     char* tmp = nullptr;
     hipError_t err = hipMallocAsync((void**)&tmp, o, stream);
     if (err != hipSuccess) return err;
@@ -790,19 +813,17 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     H.C = C;
     H.ldc = ldc;
     H.cpos = nullptr;
-    J.W = reinterpret_cast<double*>(tmp + o_w);
     J.ldw = m;
     J.wrows = m;
-    J.wcap = wcap;
     J.plain = plain;
     J.zero = small + 2;
     J.tskel = reinterpret_cast<GemmTask*>(tmp + o_tasks);
     J.tfused = J.tskel + pmax;
     J.K_dev = K;
     J.p = pmax;
-    dc_lowrank_carve(J, tmp + o_reg, b, wcap);
+    dc_lowrank_carve(J, tmp + o_reg, b, 1);
     // The plain product behind the pipeline (switched off by the planning
-    // kernel unless the skeleton columns overflow W).
+    // kernel unless the skeleton columns do not fit W).
     GemmTask T;
     std::memset(&T, 0, sizeof(T));
     const int bm = dc_gemm_tile_m(0), bn = dc_gemm_tile_n(0);
@@ -821,21 +842,68 @@ hipError_t dc_lowrank_update(int m, int K, const double* Qnd, long long ldq, con
     T.tiles_m = (m + bm - 1) / bm;
     T.tiles_n = (K + bn - 1) / bn;
     const int small_h[8] = {0, pmax * pmax, 0, 0, 0, T.tiles_m * T.tiles_n, 0, 0};
-    if (err == hipSuccess) err = dc_write_blob(tmp + o_job, &J, sizeof(J), stream);
+    LrJob* jd = reinterpret_cast<LrJob*>(tmp + o_job);
+    if (err == hipSuccess) err = dc_write_blob(jd, &J, sizeof(J), stream);
     if (err == hipSuccess) err = dc_write_blob(plain, &T, sizeof(T), stream);
     if (err == hipSuccess) err = dc_write_blob(small, small_h, sizeof(small_h), stream);
+    if (err == hipSuccess) err = lowrank_compress(jd, 1, small, pmax * pmax, b, lr_tol,
+                                                  co != nullptr, stream);
+    // NW exactly as the planning kernel counts it: a rank, or the block's
+    // width where it is kept dense (-2)
+    std::vector<int> rk((size_t)pmax * pmax);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(rk.data(), J.rank, rk.size() * sizeof(int), hipMemcpyDeviceToHost,
+                             stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    long long nw = 0;
+    for (int I = 0; I < pmax; ++I)
+        for (int c = 0; c < pmax; ++c) {
+            if (I == c) continue;
+            const int r = rk[(size_t)I * pmax + c];
+            nw += r == -2 ? std::min(b, K - c * b) : std::max(r, 0);
+        }
+    // temporary 2: W and the per-W-column arrays at NW columns (none when
+    // they would not fit in half the free memory: the plain product runs)
+    size_t free_b = 0, total_b = 0;
+    const size_t per_col = (size_t)m * sizeof(double) + (size_t)b * sizeof(double) + 64;
+    const bool fits = err == hipSuccess && nw > 0 && nw < INT32_MAX &&
+                      hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                      (size_t)nw * per_col <= free_b / 2;
+    const int wcap = fits ? (int)nw : 0;
+    char* tmp2 = nullptr;
+    if (err == hipSuccess && fits) {
+        size_t o2 = 0;
+        const size_t o_y = o2; o2 = al(o2 + (size_t)wcap * b * sizeof(double));
+        const size_t o_i = o2; o2 = al(o2 + 4 * (size_t)wcap * sizeof(int));
+        const size_t o_v = o2; o2 = al(o2 + (size_t)wcap * sizeof(long long));
+        const size_t o_r = o2; o2 = al(o2 + (size_t)wcap * sizeof(double));
+        const size_t o_w2 = o2; o2 = al(o2 + (size_t)m * wcap * sizeof(double));
+        err = hipMallocAsync((void**)&tmp2, o2, stream);
+        if (err == hipSuccess) {
+            J.Y = reinterpret_cast<double*>(tmp2 + o_y);
+            int* ib = reinterpret_cast<int*>(tmp2 + o_i);
+            J.rgen = ib;
+            J.kJ = ib + wcap;
+            J.ccol = ib + 2 * (size_t)wcap;
+            J.wpos = ib + 3 * (size_t)wcap;
+            J.rvo = reinterpret_cast<long long*>(tmp2 + o_v);
+            J.ry = reinterpret_cast<double*>(tmp2 + o_r);
+            J.W = reinterpret_cast<double*>(tmp2 + o_w2);
+        }
+    }
+    J.wcap = wcap;
+    if (err == hipSuccess) err = dc_write_blob(jd, &J, sizeof(J), stream);
     int* ts = reinterpret_cast<int*>(tmp + o_ts);
     if (err == hipSuccess)
-        err = dc_lowrank_level(reinterpret_cast<LrJob*>(tmp + o_job), 1, small, pmax * pmax,
-                               J.tskel, J.tfused, pmax, ts, small + 8, b, lr_tol, pmax,
-                               dc_lowrank_max_skel_tiles(m, wcap, pmax),
-                               dc_lowrank_max_fused_tiles(m, K, b, pmax), co != nullptr,
-                               stream, nullptr);
+        err = lowrank_products(jd, 1, J.tskel, J.tfused, pmax, ts, small + 8, b, pmax,
+                               dc_lowrank_max_skel_tiles(m, std::max(wcap, 1), pmax),
+                               dc_lowrank_max_fused_tiles(m, K, b, pmax), stream, nullptr);
     // plain fallback: tile prefix {0, tiles} at small[4..5]
     if (err == hipSuccess)
         err = dc_launch_cauchy_gemm(plain, small + 4, 1, T.tiles_m * T.tiles_n, 0, stream);
+    const hipError_t e3 = tmp2 ? hipFreeAsync(tmp2, stream) : hipSuccess;
     const hipError_t e2 = hipFreeAsync(tmp, stream);
-    return err != hipSuccess ? err : e2;
+    return err != hipSuccess ? err : (e2 != hipSuccess ? e2 : e3);
 }
 
 extern "C" int dc_merge_lowrank_ranks(int K, const double* Dbar, const int* org,
