@@ -180,6 +180,15 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         s_tau[lane] = tau;
         s_do[lane] = valid ? D[org] : 0.0;
     }
+    // When every pole fits in one chunk it is staged once for all the
+    // iterations (most merges of a batch of small problems).
+    const bool one_chunk = K <= CH;
+    if (one_chunk)
+        for (int i = tid; i < K; i += NW * 64) {
+            sD[i] = D[i];
+            const double zi = z[i];
+            sz2[i] = zi * zi;
+        }
     __syncthreads();
 
     for (int it = 0;; ++it) {
@@ -187,18 +196,24 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         Sums p{0.0, 0.0, 0.0, 0.0};
         const double Do = s_do[lane];
         const double tcur = s_tau[lane];
-        for (int c0 = 0; c0 < K; c0 += CH) {
-            const int cn = min(CH, K - c0);
-            __syncthreads();
-            for (int i = tid; i < cn; i += NW * 64) {
-                sD[i] = D[c0 + i];
-                const double zi = z[c0 + i];
-                sz2[i] = zi * zi;
+        if (one_chunk) {
+            const int per = (K + NW - 1) / NW;    // the poles split over all waves
+            const int a = min(K, w * per), b = min(K, a + per);
+            if (valid) chunk_sums(sD, sz2, 0, a, b, Do, tcur, e0, e1, p);
+        } else {
+            for (int c0 = 0; c0 < K; c0 += CH) {
+                const int cn = min(CH, K - c0);
+                __syncthreads();
+                for (int i = tid; i < cn; i += NW * 64) {
+                    sD[i] = D[c0 + i];
+                    const double zi = z[c0 + i];
+                    sz2[i] = zi * zi;
+                }
+                __syncthreads();
+                const int per = (cn + NW - 1) / NW;   // the chunk split over all waves
+                const int a = min(cn, w * per), b = min(cn, a + per);
+                if (valid) chunk_sums(sD, sz2, c0, a, b, Do, tcur, e0, e1, p);
             }
-            __syncthreads();
-            const int per = (cn + NW - 1) / NW;   // the chunk split over all waves
-            const int a = min(cn, w * per), b = min(cn, a + per);
-            if (valid) chunk_sums(sD, sz2, c0, a, b, Do, tcur, e0, e1, p);
         }
         red[0][w][lane] = p.psi;
         red[1][w][lane] = p.dpsi;
