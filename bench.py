@@ -710,7 +710,9 @@ def main():
                           if sec_ms > 0 else 0.0,
                           "fp64_valu_fma_per_s_peak": PEAK_FP64_MFMA_TFLOPS * 1e12 / 2},
         "levels": levels,
-        "merges_top": [dict(m=r["m"], K=r["K"], nrot=r["nrot"]) for r in stats
+        "merges_top": [dict(m=r["m"], K=r["K"], nrot=r["nrot"],
+                            secular_iters_mean=r["sec_iters_sum"] / max(r["K"], 1),
+                            secular_iters_max=r["sec_iters_max"]) for r in stats
                        if r["level"] <= 1],
     }
     # HBM-bound phases of the root merge (rotations, gather and deflated
@@ -763,6 +765,8 @@ def main():
             "root_product_ms": lr_top_ms,
             "root_product_speedup_vs_plain": top["product_ms"] / lr_top_ms,
             "merges": [dict(m=r["m"], K=r["K"], path=r["path"], flops=r["flops"],
+                            secular_iters_mean=r["sec_iters_sum"] / max(r["K"], 1),
+                            secular_iters_max=r["sec_iters_max"],
                             flops_skeleton=r["lr_flops_skeleton"],
                             flops_fused=r["lr_flops_fused"],
                             blocks=r["lr_blocks"], dense=r["lr_dense"], rank_max=r["lr_rank_max"],

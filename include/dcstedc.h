@@ -368,6 +368,8 @@ typedef struct dc_merge_stat {
        non-zeros in the first child's rows and in the second's; problem index
        (0 for dc_stedc / dc_stedc_ex) */
     int n1, ntop, nbot, prob;
+    /* secular iterations of the merge's K roots: sum and maximum */
+    int sec_iters_sum, sec_iters_max;
 } dc_merge_stat;
 
 /* Copies up to cap records into out (HOST); returns the number available. */

@@ -43,6 +43,7 @@ struct MergeCnt {
     int nbot;           // survivors with non-zeros in the bottom rows
     int nchain;         // rotation chains (a chain shares columns only inside itself)
     int pad_[2];        // pad_[0] stays 0: a disabled product task points here
+    int sec_iters[2];   // secular iterations of the merge's roots: sum, maximum
 };
 
 // Per-row scratch (indexed by prob.row0 + node.off + local index) and

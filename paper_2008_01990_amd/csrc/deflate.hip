@@ -204,6 +204,7 @@ __global__ void k_build(const Node* __restrict__ merges, int nm, int bm, int bn,
     Q.zhat = S.zhat + base;
     Q.scale = S.scale + base;
     Q.info = P.info;
+    Q.iters = cnt->sec_iters;
     S.stask[slot] = Q;
 }
 
@@ -297,6 +298,8 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
             cnt->nbot = 0;
             cnt->nchain = 0;
             cnt->pad_[0] = 0;
+            cnt->sec_iters[0] = 0;
+            cnt->sec_iters[1] = 0;
             S.rho2[N.slot] = 0.0;
         }
         return;
@@ -549,6 +552,8 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         cnt->ndefl = nd;
         cnt->nchain = nch;
         cnt->pad_[0] = 0;
+        cnt->sec_iters[0] = 0;
+        cnt->sec_iters[1] = 0;
         S.rho2[N.slot] = rho2;
     }
     __syncthreads();

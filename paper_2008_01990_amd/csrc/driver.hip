@@ -1061,6 +1061,8 @@ extern "C" int dc_last_stats(dc_merge_stat* out, int cap) {
             r.ntop = cnt[g].ntop;
             r.nbot = cnt[g].nbot;
             r.prob = N.prob;
+            r.sec_iters_sum = cnt[g].sec_iters[0];
+            r.sec_iters_max = cnt[g].sec_iters[1];
             const int c = LP ? LP->cand_of_merge[g] : -1;
             const bool lr = c >= 0 && rec[c].active == 1;
             r.path = lr ? 1 : 0;

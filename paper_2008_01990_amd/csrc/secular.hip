@@ -304,6 +304,20 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
         __syncthreads();
         if (!s_live) break;
     }
+    if (w == 0 && T.iters) {
+        // per-merge iteration statistics (lanes past K count 0): a wave
+        // reduction with every lane active, one atomic per wave
+        int isum = iters, imax = iters;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            isum += __shfl_xor(isum, off, 64);
+            imax = max(imax, __shfl_xor(imax, off, 64));
+        }
+        if (lane == 0) {
+            atomicAdd(T.iters, isum);
+            atomicMax(T.iters + 1, imax);
+        }
+    }
     if (w == 0 && valid) {
         const double base = (org == j) ? (last ? De1 : De0) : De1;
         T.org[j] = org;

@@ -19,6 +19,8 @@ struct SecTask {
     double* zhat;         // out: Loewner weights
     double* scale;        // out: column scales
     int* info;            // status word, or null
+    int* iters;           // out (optional): [0] sum, [1] maximum of the roots'
+                          // iteration counts (accumulated: cleared by the caller)
 };
 
 // block_start: exclusive prefix sum (ntasks + 1 entries, device) of

@@ -36,7 +36,8 @@ class MergeStat(ctypes.Structure):
                 ("path", c_int), ("flops", c_double), ("lr_blocks", c_int),
                 ("lr_rank_sum", c_int), ("lr_rank_max", c_int), ("lr_dense", c_int),
                 ("lr_flops_skeleton", c_double), ("lr_flops_fused", c_double),
-                ("n1", c_int), ("ntop", c_int), ("nbot", c_int), ("prob", c_int)]
+                ("n1", c_int), ("ntop", c_int), ("nbot", c_int), ("prob", c_int),
+                ("sec_iters_sum", c_int), ("sec_iters_max", c_int)]
 
 
 # (name, restype, argtypes) of every exported entry point.
@@ -245,7 +246,8 @@ def last_stats():
                  lr_blocks=r.lr_blocks, lr_rank_sum=r.lr_rank_sum, lr_rank_max=r.lr_rank_max,
                  lr_dense=r.lr_dense, lr_flops_skeleton=r.lr_flops_skeleton,
                  lr_flops_fused=r.lr_flops_fused, n1=r.n1, ntop=r.ntop, nbot=r.nbot,
-                 prob=r.prob) for r in arr[:cnt]]
+                 prob=r.prob, sec_iters_sum=r.sec_iters_sum,
+                 sec_iters_max=r.sec_iters_max) for r in arr[:cnt]]
 
 
 PHASES = ("deflate", "rotate", "secular", "assemble", "product", "copy")
