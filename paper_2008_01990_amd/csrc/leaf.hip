@@ -1,11 +1,13 @@
 // Leaf eigensolver: Algorithm 1's "apply the QR algorithm" on every block of
-// at most 64 rows, one wave per leaf.
+// at most 64 rows; a wave holds 64 / LD leaves of at most LD rows each.
 //
 // Implicit symmetric tridiagonal QR with a Wilkinson shift (Golub & Van Loan,
-// section 8.3).  The tridiagonal lives in registers, entry i in lane i; the
-// bulge chase is a chain of Givens steps that every lane evaluates
-// identically, reading entries ahead of the chase with readlane and carrying
-// the entries the chase has touched in registers, while lane r applies each
+// section 8.3).  The tridiagonal lives in registers, entry i in lane i of the
+// leaf's lane group; the bulge chase is a chain of Givens steps that every
+// lane of the group evaluates identically, reading entries ahead of the chase
+// across the group (readlane for a whole-wave group, a lane permute
+// otherwise) and carrying the entries the chase has touched in registers,
+// while lane r applies each
 // rotation to row r of the eigenvector block (one LDS read and one write per
 // step: the column the chase leaves behind).  The leaf is scaled by a power of
 // two (exact) so that x^2 + y^2 of a rotation neither overflows nor
@@ -30,86 +32,117 @@ __device__ __forceinline__ double lane_value(double v, int k) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ double set_lane(double v, int k, double x) {
-    return (int)threadIdx.x == k ? x : v;
-}
-
-// Givens rotation c = x / r, s = y / r, r = sqrt(x^2 + y^2), so that
-// c x + s y = r and c y - s x = 0.  The reciprocal square root is the
-// hardware estimate refined by two Newton steps q <- q (3 - t q^2) / 2 when t
-// lies well inside the exponent range; hypot and divisions otherwise.
+// Givens rotation with c >= 0 and r carrying the sign of x, so that
+// c x + s y = r and c y - s x = 0 (r = x, c = 1, s = 0 when y = 0).  The
+// reciprocal square root of t = x^2 + y^2 is the hardware estimate refined
+// by two Newton steps q <- q (3 - t q^2) / 2.  That branch-free form is
+// taken by the whole wave unless one of its lanes has t outside the safe
+// exponent range (t = 0 included); those waves take the per-lane path, with
+// hypot and divisions for such lanes.
 __device__ __forceinline__ void givens(double x, double y, double& c, double& s, double& r) {
-    if (y == 0.0) {
-        c = 1.0;
-        s = 0.0;
-        r = x;
-        return;
-    }
     const double t = __builtin_fma(x, x, y * y);
-    if (t > 0x1p-960 && t < 0x1p960) {
+    const bool fast = t > 0x1p-960 && t < 0x1p960;
+    auto refined = [&]() {
         const double h = 0.5 * t;
         double q = __builtin_amdgcn_rsq(t);
         double e = __builtin_fma(-h * q, q, 0.5);
         q = __builtin_fma(q, e, q);
         e = __builtin_fma(-h * q, q, 0.5);
         q = __builtin_fma(q, e, q);
+        q = copysign(q, x);
         c = x * q;
         s = y * q;
         r = t * q;
+    };
+    if (__builtin_expect(__ballot(!fast) == 0ull, 1)) {
+        refined();
+    } else if (y == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        r = x;
+    } else if (fast) {
+        refined();
     } else {
-        r = hypot(x, y);
+        r = copysign(hypot(x, y), x);
         c = x / r;
         s = y / r;
     }
 }
 
 // LD: leaf size bound and row stride of the eigenvector block in LDS (16,
-// 32 or 64): a block sized for the plan's leaves lets more of them share a
-// compute unit, which hides the chase's latency.
+// 32 or 64).  A wave holds 64 / LD leaves, lane group g = lane / LD solving
+// leaf blockIdx.x * (64 / LD) + g with row r = lane % LD: the chase's scalar
+// chain is then evaluated once per group instead of once per wave (its cost is
+// instruction issue, shared by the waves of a SIMD), and entries ahead of the
+// chase are read across the group with a lane permute.  A group that needs
+// no sweep waits for the others' chases with its lanes masked off, so every
+// pass of the sweep loop deflates first and chases at most once per group.
+template <int LD>
+__device__ __forceinline__ double grp_value(double v, int k) {
+    if constexpr (LD == 64) return lane_value(v, k);
+    else return __shfl(v, k, LD);
+}
+
 template <int LD>
 __global__ __launch_bounds__(64)
-void k_leaf(const Node* __restrict__ leaves, Scratch S) {
-    __shared__ double Z[LD * LD];   // column-major, LD rows
-    __shared__ double sd[LD];
-    __shared__ int rank[LD];
+void k_leaf(const Node* __restrict__ leaves, int nleaves, Scratch S) {
+    constexpr int NPW = 64 / LD;                // leaves per wave
+    __shared__ double Zall[NPW * LD * LD];      // per group: column-major, LD rows
+    __shared__ double sdall[NPW * LD];
+    __shared__ int rankall[NPW * LD];
 
-    const Node L = leaves[blockIdx.x];
-    const Prob P = S.probs[L.prob];
-    const double esc = S.psc[L.prob];        // d is scaled in place, e on read
-    const int nl = L.n1;
     const int lane = threadIdx.x;
-    const bool zrow = LD == 64 || lane < LD;   // lane holds a row of the block
-    const int off = L.off;
+    const int grp = lane / LD, r = lane - (lane / LD) * LD;
+    const int li = blockIdx.x * NPW + grp;
+    double* __restrict__ Z = Zall + grp * LD * LD;
+    double* __restrict__ sd = sdall + grp * LD;
+    int* __restrict__ rank = rankall + grp * LD;
+    // the group's bits of a wave ballot
+    auto gbits = [&](unsigned long long m) {
+        return LD == 64 ? m : (m >> (grp * LD)) & ((1ull << (LD & 63)) - 1ull);
+    };
+
+    Node L = {};
+    Prob P = {};
+    double esc = 1.0;
+    int nl = 0;
+    if (li < nleaves) {
+        L = leaves[li];
+        P = S.probs[L.prob];
+        esc = S.psc[L.prob];                    // d is scaled in place, e on read
+        nl = L.n1;
+    }
+    const int off = nl > 0 ? L.off : 0;
 
     // Load, apply the tear corrections, check for non-finite input.
     bool bad = false;
     double dv = 0.0, ev = 0.0;
-    if (lane < nl) {
-        dv = P.d[off + lane];
+    if (r < nl) {
+        dv = P.d[off + r];
         bad |= !isfinite(dv);
-        if (lane == 0 && off > 0) {
+        if (r == 0 && off > 0) {
             const double x = P.e[off - 1] * esc;
             bad |= !isfinite(x);
             dv -= fabs(x);
         }
-        if (lane == nl - 1 && off + nl < P.n) {
+        if (r == nl - 1 && off + nl < P.n) {
             const double x = P.e[off + nl - 1] * esc;
             bad |= !isfinite(x);
             dv -= fabs(x);
         }
-        if (lane < nl - 1) {
-            ev = P.e[off + lane] * esc;
+        if (r < nl - 1) {
+            ev = P.e[off + r] * esc;
             bad |= !isfinite(ev);
         }
     }
-    if (__ballot(bad) != 0ull && lane == 0) dc_set_info(P.info, DC_STATUS_NONFINITE);
-    if (zrow)
-        for (int c = 0; c < nl; ++c) Z[c * LD + lane] = (c == lane) ? 1.0 : 0.0;
+    if (gbits(__ballot(bad)) != 0ull && r == 0) dc_set_info(P.info, DC_STATUS_NONFINITE);
+    for (int c = 0; c < nl; ++c) Z[c * LD + r] = (c == r) ? 1.0 : 0.0;
 
     // ||T||_inf of the leaf, then an exact power-of-two scale to [1, 2).
-    const double eprev = __shfl_up(ev, 1, 64);
-    double rowsum = lane < nl ? fabs(dv) + fabs(ev) + (lane > 0 ? fabs(eprev) : 0.0) : 0.0;
-    double anorm = lane_value(dc_wave_max(rowsum), 0);
+    const double eprev = __shfl_up(ev, 1, LD);
+    double anorm = r < nl ? fabs(dv) + fabs(ev) + (r > 0 ? fabs(eprev) : 0.0) : 0.0;
+#pragma unroll
+    for (int o = LD / 2; o > 0; o >>= 1) anorm = fmax(anorm, __shfl_xor(anorm, o, 64));
     double unscale = 1.0;
     if (anorm > 0.0 && anorm < INFINITY) {
         const int ex = (int)((__double_as_longlong(anorm) >> 52) & 0x7ff) - 1023;
@@ -122,55 +155,58 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
         }
     }
     const double thresh = EPS * anorm;
+    auto set_row = [&](double v, int k, double x) { return r == k ? x : v; };
 
     int hi = nl - 1;
     int sweeps = 0;
     bool failed = false;
-    while (hi > 0) {
-        const double ehi = lane_value(ev, hi - 1);
-        if (fabs(ehi) <= thresh) {
-            ev = set_lane(ev, hi - 1, 0.0);
+    while (true) {
+        // deflate at the bottom until the last off-diagonal is not negligible
+        while (hi > 0 && fabs(grp_value<LD>(ev, hi - 1)) <= thresh) {
+            ev = set_row(ev, hi - 1, 0.0);
             --hi;
             sweeps = 0;
-            continue;
         }
+        if (hi <= 0) break;
+        const double ehi = grp_value<LD>(ev, hi - 1);
         // lo: one past the last negligible off-diagonal below hi - 1
-        const unsigned long long small = __ballot(lane < hi - 1 && fabs(ev) <= thresh);
+        const unsigned long long small = gbits(__ballot(r < hi - 1 && fabs(ev) <= thresh));
         const int lo = small ? 64 - __builtin_clzll(small) : 0;
-        if (lo > 0) ev = set_lane(ev, lo - 1, 0.0);
+        if (lo > 0) ev = set_row(ev, lo - 1, 0.0);
         if (++sweeps > MAX_SWEEPS) { failed = true; break; }
-        const double dhi = lane_value(dv, hi);
-        const double delta = 0.5 * (lane_value(dv, hi - 1) - dhi);
+        const double dhi = grp_value<LD>(dv, hi);
+        const double delta = 0.5 * (grp_value<LD>(dv, hi - 1) - dhi);
         const double sgn = delta >= 0.0 ? 1.0 : -1.0;
         const double mu = dhi - ehi * ehi / (delta + sgn * hypot(delta, ehi));
 
         // Entries ahead of the chase are read from the sweep's starting
         // values (d0, e0); the chase writes its finished entries into dv, ev.
         const double d0 = dv, e0 = ev;
-        double a = lane_value(d0, lo);           // current d[k]
-        double f = lane_value(e0, lo);           // current e[k]
+        double a = grp_value<LD>(d0, lo);        // current d[k]
+        double f = grp_value<LD>(e0, lo);        // current e[k]
         double x = a - mu, y = f;
-        double zc = zrow ? Z[lo * LD + lane] : 0.0;   // current column k, this row
-        double g = lane_value(d0, lo + 1);
-        double en = lo + 1 < hi ? lane_value(e0, lo + 1) : 0.0;
-        double zn = zrow ? Z[(lo + 1) * LD + lane] : 0.0;
+        double zc = Z[lo * LD + r];              // current column k, this row
+        double g = grp_value<LD>(d0, lo + 1);
+        // Reads ahead are clamped inside the block.  Past hi they feed only
+        // values the sweep never uses: g and zn after the last step, and en
+        // (the bulge and f) at the last step.
+        double en = grp_value<LD>(e0, min(lo + 1, LD - 1));
+        double zn = Z[(lo + 1) * LD + r];
         for (int k = lo; k < hi; ++k) {
-            double g2 = 0.0, en2 = 0.0, zn2 = 0.0;
-            if (k + 2 <= hi) {
-                g2 = lane_value(d0, k + 2);
-                zn2 = zrow ? Z[(k + 2) * LD + lane] : 0.0;
-            }
-            if (k + 2 < hi) en2 = lane_value(e0, k + 2);
-            double c, s, r;
-            givens(x, y, c, s, r);
-            if (k > lo) ev = set_lane(ev, k - 1, r);
+            const int k2 = min(k + 2, LD - 1);
+            const double g2 = grp_value<LD>(d0, k2);
+            const double en2 = grp_value<LD>(e0, k2);
+            const double zn2 = Z[k2 * LD + r];
+            double c, s, rr;
+            givens(x, y, c, s, rr);
+            if (k > lo) ev = set_row(ev, k - 1, rr);
             const double cc = c * c, ss = s * s, cs = c * s;
-            dv = set_lane(dv, k, cc * a + 2.0 * cs * f + ss * g);
+            dv = set_row(dv, k, cc * a + 2.0 * cs * f + ss * g);
             const double gn = ss * a - 2.0 * cs * f + cc * g;
             const double fn = cs * (g - a) + (cc - ss) * f;
-            if (zrow) Z[k * LD + lane] = c * zc + s * zn;
+            Z[k * LD + r] = c * zc + s * zn;
             zc = -s * zc + c * zn;
-            y = s * en;                           // the bulge (0 at the last step)
+            y = s * en;                           // the bulge
             f = c * en;
             x = fn;
             a = gn;
@@ -178,37 +214,37 @@ void k_leaf(const Node* __restrict__ leaves, Scratch S) {
             en = en2;
             zn = zn2;
         }
-        dv = set_lane(dv, hi, a);
-        ev = set_lane(ev, hi - 1, x);
-        if (zrow) Z[hi * LD + lane] = zc;
+        dv = set_row(dv, hi, a);
+        ev = set_row(ev, hi - 1, x);
+        Z[hi * LD + r] = zc;
     }
-    if (failed && lane == 0) dc_set_info(P.info, 1 + off);
+    if (failed && r == 0) dc_set_info(P.info, 1 + off);
     dv *= unscale;
-    if (lane < nl) sd[lane] = dv;
+    if (r < nl) sd[r] = dv;
     __syncthreads();
 
     // Ascending order: rank of each eigenvalue, ties by index; NaN ranks as
     // +inf so the ranks always form a permutation.
-    if (lane < nl) {
+    if (r < nl) {
         const double v = isnan(dv) ? INFINITY : dv;
-        int r = 0;
+        int q = 0;
         for (int k = 0; k < nl; ++k) {
             const double u = isnan(sd[k]) ? INFINITY : sd[k];
-            r += (u < v) || (u == v && k < lane);
+            q += (u < v) || (u == v && k < r);
         }
-        rank[lane] = r;
+        rank[r] = q;
     }
     __syncthreads();
-    long long ld;
-    double* Qo = node_buf(P, L.depth, ld);
-    if (lane < nl) {
-        P.d[off + rank[lane]] = dv;
+    if (r < nl) {
+        long long ld;
+        double* Qo = node_buf(P, L.depth, ld);
+        P.d[off + rank[r]] = dv;
         for (int c = 0; c < nl; ++c)
-            Qo[(long long)(off + rank[c]) * ld + off + lane] = Z[c * LD + lane];
+            Qo[(long long)(off + rank[c]) * ld + off + r] = Z[c * LD + r];
         if (L.depth > 0) {
             // below the root: eigenvalue j in column off + j, rows of the leaf
-            const long long g = (long long)P.row0 + off + lane;
-            node_cmap(S, L.depth)[g] = off + lane;
+            const long long g = (long long)P.row0 + off + r;
+            node_cmap(S, L.depth)[g] = off + r;
             node_rng(S, L.depth)[g] = make_int2(off, off + nl);
         }
     }
@@ -265,10 +301,12 @@ hipError_t dc_launch_leaf(const Node* leaves, int nleaves, int max_leaf, Scratch
                           hipStream_t s) {
     if (nleaves <= 0) return hipSuccess;
     if (max_leaf <= 16)
-        hipLaunchKernelGGL(k_leaf<16>, dim3(nleaves), dim3(64), 0, s, leaves, S);
+        hipLaunchKernelGGL(k_leaf<16>, dim3((nleaves + 3) / 4), dim3(64), 0, s, leaves,
+                           nleaves, S);
     else if (max_leaf <= 32)
-        hipLaunchKernelGGL(k_leaf<32>, dim3(nleaves), dim3(64), 0, s, leaves, S);
+        hipLaunchKernelGGL(k_leaf<32>, dim3((nleaves + 1) / 2), dim3(64), 0, s, leaves,
+                           nleaves, S);
     else
-        hipLaunchKernelGGL(k_leaf<64>, dim3(nleaves), dim3(64), 0, s, leaves, S);
+        hipLaunchKernelGGL(k_leaf<64>, dim3(nleaves), dim3(64), 0, s, leaves, nleaves, S);
     return hipGetLastError();
 }
