@@ -24,14 +24,6 @@ namespace {
 constexpr double EPS = 2.220446049250313e-16;
 constexpr int MAX_SWEEPS = 40;
 
-// Value of v in lane k (k wave-uniform).
-__device__ __forceinline__ double lane_value(double v, int k) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, k);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 // Givens rotation with c >= 0 and r carrying the sign of x, so that
 // c x + s y = r and c y - s x = 0 (r = x, c = 1, s = 0 when y = 0).  The
 // reciprocal square root of t = x^2 + y^2 is the hardware estimate refined
@@ -73,21 +65,19 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
 // 32 or 64).  A wave holds 64 / LD leaves, lane group g = lane / LD solving
 // leaf blockIdx.x * (64 / LD) + g with row r = lane % LD: the chase's scalar
 // chain is then evaluated once per group instead of once per wave (its cost is
-// instruction issue, shared by the waves of a SIMD), and entries ahead of the
-// chase are read across the group with a lane permute.  A group that needs
-// no sweep waits for the others' chases with its lanes masked off, so every
-// pass of the sweep loop deflates first and chases at most once per group.
-template <int LD>
-__device__ __forceinline__ double grp_value(double v, int k) {
-    if constexpr (LD == 64) return lane_value(v, k);
-    else return __shfl(v, k, LD);
-}
-
+// instruction issue, shared by the waves of a SIMD).  The tridiagonal lives in
+// LDS as pairs (e[k-1], d[k]): the chase reads entries ahead of it with one
+// broadcast load per step and lane 0 of the group writes each finished pair
+// back, so no register selects or lane permutes sit in the step.  A group that
+// needs no sweep waits for the others' chases with its lanes masked off, so
+// every pass of the sweep loop deflates first and chases at most once per
+// group.
 template <int LD>
 __global__ __launch_bounds__(64)
 void k_leaf(const Node* __restrict__ leaves, int nleaves, Scratch S) {
     constexpr int NPW = 64 / LD;                // leaves per wave
     __shared__ double Zall[NPW * LD * LD];      // per group: column-major, LD rows
+    __shared__ double2 tdall[NPW * LD];         // per group: (e[k-1], d[k])
     __shared__ double sdall[NPW * LD];
     __shared__ int rankall[NPW * LD];
 
@@ -95,6 +85,7 @@ void k_leaf(const Node* __restrict__ leaves, int nleaves, Scratch S) {
     const int grp = lane / LD, r = lane - (lane / LD) * LD;
     const int li = blockIdx.x * NPW + grp;
     double* __restrict__ Z = Zall + grp * LD * LD;
+    double2* __restrict__ td = tdall + grp * LD;
     double* __restrict__ sd = sdall + grp * LD;
     int* __restrict__ rank = rankall + grp * LD;
     // the group's bits of a wave ballot
@@ -139,8 +130,9 @@ void k_leaf(const Node* __restrict__ leaves, int nleaves, Scratch S) {
     for (int c = 0; c < nl; ++c) Z[c * LD + r] = (c == r) ? 1.0 : 0.0;
 
     // ||T||_inf of the leaf, then an exact power-of-two scale to [1, 2).
-    const double eprev = __shfl_up(ev, 1, LD);
-    double anorm = r < nl ? fabs(dv) + fabs(ev) + (r > 0 ? fabs(eprev) : 0.0) : 0.0;
+    double eprev = __shfl_up(ev, 1, LD);
+    if (r == 0) eprev = 0.0;
+    double anorm = r < nl ? fabs(dv) + fabs(ev) + fabs(eprev) : 0.0;
 #pragma unroll
     for (int o = LD / 2; o > 0; o >>= 1) anorm = fmax(anorm, __shfl_xor(anorm, o, 64));
     double unscale = 1.0;
@@ -150,74 +142,94 @@ void k_leaf(const Node* __restrict__ leaves, int nleaves, Scratch S) {
             const double sc = __longlong_as_double((long long)(1023 - ex) << 52);
             unscale = __longlong_as_double((long long)(1023 + ex) << 52);
             dv *= sc;
-            ev *= sc;
+            eprev *= sc;
             anorm *= sc;
         }
     }
     const double thresh = EPS * anorm;
-    auto set_row = [&](double v, int k, double x) { return r == k ? x : v; };
+    // every pair of the block is written (zeros past the leaf), so reads
+    // ahead of the chase past hi see finite values
+    td[r] = make_double2(eprev, dv);
+    __syncthreads();
 
     int hi = nl - 1;
     int sweeps = 0;
     bool failed = false;
     while (true) {
+        // Pairs written by lane 0 are read by the whole group below: LDS
+        // operations of a wave complete in order, and the fence keeps the
+        // compiler from moving those reads above the writes.
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // deflate at the bottom until the last off-diagonal is not negligible
-        while (hi > 0 && fabs(grp_value<LD>(ev, hi - 1)) <= thresh) {
-            ev = set_row(ev, hi - 1, 0.0);
+        double ehi = hi > 0 ? td[hi].x : 0.0;
+        while (hi > 0 && fabs(ehi) <= thresh) {
+            if (r == 0) td[hi].x = 0.0;
             --hi;
             sweeps = 0;
+            ehi = hi > 0 ? td[hi].x : 0.0;
         }
         if (hi <= 0) break;
-        const double ehi = grp_value<LD>(ev, hi - 1);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // lo: one past the last negligible off-diagonal below hi - 1
-        const unsigned long long small = gbits(__ballot(r < hi - 1 && fabs(ev) <= thresh));
+        bool neg = false;
+        if (r < hi - 1) neg = fabs(td[r + 1].x) <= thresh;
+        const unsigned long long small = gbits(__ballot(neg));
         const int lo = small ? 64 - __builtin_clzll(small) : 0;
-        if (lo > 0) ev = set_row(ev, lo - 1, 0.0);
+        if (lo > 0 && r == 0) td[lo].x = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (++sweeps > MAX_SWEEPS) { failed = true; break; }
-        const double dhi = grp_value<LD>(dv, hi);
-        const double delta = 0.5 * (grp_value<LD>(dv, hi - 1) - dhi);
+        const double dhi = td[hi].y;
+        const double delta = 0.5 * (td[hi - 1].y - dhi);
         const double sgn = delta >= 0.0 ? 1.0 : -1.0;
         const double mu = dhi - ehi * ehi / (delta + sgn * hypot(delta, ehi));
 
-        // Entries ahead of the chase are read from the sweep's starting
-        // values (d0, e0); the chase writes its finished entries into dv, ev.
-        const double d0 = dv, e0 = ev;
-        double a = grp_value<LD>(d0, lo);        // current d[k]
-        double f = grp_value<LD>(e0, lo);        // current e[k]
+        // Step k rotates rows and columns k, k + 1 with the Givens rotation
+        // that maps (x, y) to (rr, 0): with u = s (g - a) + 2 c f, the new
+        // d[k] = a + s u, d[k+1] = g - s u (the trace is kept) and
+        // e[k] = c u - f (using c^2 + s^2 = 1); rr is the new e[k-1], and
+        // the rotation moves the bulge s e[k+1] one row down.  Step k reads
+        // pair k + 2 (d[k+2]) and pair k + 3 (e[k+2]) for the next step,
+        // before this sweep writes them, and writes pair k.  Reads are
+        // clamped inside the block; past hi they feed only values the sweep
+        // never uses (g and zn after the last step, en at it).
+        double a = td[lo].y;                     // current d[k]
+        const double2 p1 = td[lo + 1];
+        double f = p1.x;                         // current e[k]
+        double g = p1.y;                         // d[k+1]
         double x = a - mu, y = f;
+        double en = td[min(lo + 2, LD - 1)].x;   // e[k+1]
         double zc = Z[lo * LD + r];              // current column k, this row
-        double g = grp_value<LD>(d0, lo + 1);
-        // Reads ahead are clamped inside the block.  Past hi they feed only
-        // values the sweep never uses: g and zn after the last step, and en
-        // (the bulge and f) at the last step.
-        double en = grp_value<LD>(e0, min(lo + 1, LD - 1));
         double zn = Z[(lo + 1) * LD + r];
-        for (int k = lo; k < hi; ++k) {
+        auto step = [&](int k, auto first_tag) {
+            constexpr bool FIRST = decltype(first_tag)::value;
             const int k2 = min(k + 2, LD - 1);
-            const double g2 = grp_value<LD>(d0, k2);
-            const double en2 = grp_value<LD>(e0, k2);
+            const double g2 = td[k2].y;
+            const double en2 = td[min(k + 3, LD - 1)].x;
             const double zn2 = Z[k2 * LD + r];
             double c, s, rr;
             givens(x, y, c, s, rr);
-            if (k > lo) ev = set_row(ev, k - 1, rr);
-            const double cc = c * c, ss = s * s, cs = c * s;
-            dv = set_row(dv, k, cc * a + 2.0 * cs * f + ss * g);
-            const double gn = ss * a - 2.0 * cs * f + cc * g;
-            const double fn = cs * (g - a) + (cc - ss) * f;
-            Z[k * LD + r] = c * zc + s * zn;
-            zc = -s * zc + c * zn;
+            const double cf = c * f;
+            const double u = __builtin_fma(s, g - a, cf + cf);
+            const double su = s * u;
+            // the first rotation makes no off-diagonal entry: e[lo-1] stays 0
+            if (r == 0) td[k] = make_double2(FIRST ? 0.0 : rr, a + su);
+            x = __builtin_fma(c, u, -f);
+            a = g - su;
+            Z[k * LD + r] = __builtin_fma(c, zc, s * zn);
+            zc = __builtin_fma(c, zn, -(s * zc));
             y = s * en;                           // the bulge
             f = c * en;
-            x = fn;
-            a = gn;
             g = g2;
             en = en2;
             zn = zn2;
-        }
-        dv = set_row(dv, hi, a);
-        ev = set_row(ev, hi - 1, x);
+        };
+        step(lo, dc_true_type{});
+        for (int k = lo + 1; k < hi; ++k) step(k, dc_false_type{});
+        if (r == 0) td[hi] = make_double2(x, a);
         Z[hi * LD + r] = zc;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    dv = td[r].y;
     if (failed && r == 0) dc_set_info(P.info, 1 + off);
     dv *= unscale;
     if (r < nl) sd[r] = dv;
