@@ -14,9 +14,17 @@
 // poles are formed exactly; when the middle-way iterate leaves the bracket
 // (a weak origin pole, whose fitted weight is mostly that of farther poles),
 // Li's fixed-weight model is tried, which keeps the origin pole's own weight;
-// a bisection safeguard keeps each iterate inside a sign-change bracket.  The
-// last root is bracketed by the last two poles and starts half a pole gap
-// right of the last pole when that is inside its bracket.
+// and the two models take turns whenever an iterate lands on the same side of
+// the root as the one before it with |g| above a quarter of its previous
+// value (near a weak pole the middle way creeps in, the fixed weight closes
+// in; the switch on one-sided slow progress follows LAPACK's dlaed4, which
+// tests for a tenth).  A switch on every slow step, whatever the side, can
+// cycle between one iterate of each model, and one taken where |g| is down
+// to rounding sends a root that the middle way would finish next step into
+// a slow fixed-weight crawl, so neither switches.  A bisection safeguard keeps each iterate
+// inside a sign-change bracket.  The last root is bracketed by the last two
+// poles and starts half a pole gap right of the last pole when that is inside
+// its bracket; it always takes the middle way.
 //
 // Loewner (Gu-Eisenstat): zhat_i^2 = (lam_K - D_i)/rho
 //     * prod_{j<i} (lam_j - D_i)/(D_j - D_i) * prod_{i<=j<K-1} (lam_j - D_i)/(D_{j+1} - D_i).
@@ -158,6 +166,8 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     int org = 0;
     bool done = !valid;
     int iters = 0;
+    double prevg = 0.0;     // g at the previous iterate
+    bool fixed = false;     // next step by the fixed-weight model
     if (w == 0 && valid) {
         De1 = D[e1];
         De0 = e0 >= 0 ? D[e0] : 0.0;
@@ -239,8 +249,17 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
             const double phi = fphi + t1, dphi = fdphi + (valid ? t1 / d2 : 0.0);
             const double aabs = (fphi - fpsi) + fabs(t0) + fabs(t1);   // sum of |terms|
             const double g = 1.0 / rho + psi + phi;
+            const double gtol = 8.0 * EPS * (1.0 / rho + aabs);
             if (!done) {
                 ++iters;
+                // switch models when an iterate stayed on the same side of
+                // the root without shrinking |g| fourfold, unless |g| is
+                // within a small multiple of the tolerance (there its size
+                // and sign are rounding, not progress)
+                if (iters > 1 && g * prevg > 0.0 && fabs(g) > 0.25 * fabs(prevg) &&
+                    fabs(g) > 64.0 * gtol)
+                    fixed = !fixed;
+                prevg = g;
                 if (it == 0 && !last) {
                     // Origin choice from the sign at the midpoint.
                     const double h = 0.5 * (De1 - De0);
@@ -249,10 +268,14 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                     } else {                // root right of it: re-frame at D_{j+1}
                         org = j + 1; lo = -h; hi = 0.0; tau = -h;
                     }
-                    if (g == 0.0) done = true;
+                    // the midpoint itself may pass the test (roots placed
+                    // halfway between poles by symmetry): a model step
+                    // from a zero |g| leaves the bracket and ends in
+                    // bisection at the midpoint's side
+                    if (fabs(g) <= gtol) done = true;
                 } else {
                     if (g > 0.0) hi = tau; else lo = tau;
-                    const bool conv = fabs(g) <= 8.0 * EPS * (1.0 / rho + aabs) ||
+                    const bool conv = fabs(g) <= gtol ||
                                       (hi - lo) <= 4.0 * EPS * fmax(fabs(lo), fabs(hi));
                     if (conv) done = true;
                 }
@@ -265,17 +288,20 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                         const double Dn = (org == j) ? (last ? De1 : De0) : De1;
                         const double ol = e0 >= 0 ? De0 - Dn : 0.0, oh = De1 - Dn;
                         const double q1 = ol - tau, q2 = oh - tau;
-                        double nt;
+                        double nt = lo;     // outside (lo, hi): not yet found
                         if (e0 < 0) {
                             // one pole: c + w1 / (0 - x) = 0 with c = 1/rho
                             nt = rho * w1;
                         } else {
-                            // Middle-way model: both pole sums fitted to
-                            // value and slope by their bracketing pole.
-                            const double s1 = dpsi * q1 * q1;
-                            const double s2 = dphi * q2 * q2;
-                            const double c = 1.0 / rho + (psi - dpsi * q1) + (phi - dphi * q2);
-                            nt = model_root(c, s1, s2, ol, oh, lo, hi);
+                            if (!fixed || last) {
+                                // Middle-way model: both pole sums fitted to
+                                // value and slope by their bracketing pole.
+                                const double s1 = dpsi * q1 * q1;
+                                const double s2 = dphi * q2 * q2;
+                                const double c =
+                                    1.0 / rho + (psi - dpsi * q1) + (phi - dphi * q2);
+                                nt = model_root(c, s1, s2, ol, oh, lo, hi);
+                            }
                             if (!(nt > lo && nt < hi) && !last) {
                                 // Fixed-weight model: the origin pole's own
                                 // term exact, everything else fitted at the
