@@ -21,7 +21,8 @@
 // tests for a tenth).  A switch on every slow step, whatever the side, can
 // cycle between one iterate of each model, and one taken where |g| is down
 // to rounding sends a root that the middle way would finish next step into
-// a slow fixed-weight crawl, so neither switches.  A bisection safeguard keeps each iterate
+// a slow fixed-weight crawl, so neither switches.  When both models leave
+// the bracket a Newton step on g is tried before bisection.  A bisection safeguard keeps each iterate
 // inside a sign-change bracket.  The last root is bracketed by the last two
 // poles and starts half a pole gap right of the last pole when that is inside
 // its bracket; it always takes the middle way.
@@ -101,14 +102,16 @@ __device__ __forceinline__ void chunk_sums(const double* sD, const double* sz2, 
 // itself, so the constant term is a single product and the root next to the
 // origin comes out with full relative accuracy).  Of the quadratic's two
 // roots the one inside (lo, hi) is returned (or the other if neither is).
+// The iterate is only a guess that the next evaluation checks, so its two
+// quotients take the refined reciprocal instead of a division.
 __device__ __forceinline__ double model_root(double c, double s1, double s2, double dl,
                                              double dh, double lo, double hi) {
     const double B = c * (dl + dh) + s1 + s2;
     const double C = c * dl * dh + s1 * dh + s2 * dl;
     const double disc = fmax(B * B - 4.0 * c * C, 0.0);
     const double q = 0.5 * (B + copysign(sqrt(disc), B));
-    const double r1 = q / c;
-    const double r2 = C / q;
+    const double r1 = q * dc_rcp3(c);
+    const double r2 = C * dc_rcp3(q);
     return (r2 > lo && r2 < hi) ? r2 : r1;
 }
 
@@ -129,6 +132,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
     const int j0 = (blockIdx.x - block_start[ti]) * NR;
     if (j0 >= K) return;
     const double rho = T.rho_p ? *T.rho_p : T.rho;
+    const double irho = 1.0 / rho;
     const double* __restrict__ D = T.D;
     const double* __restrict__ z = T.z;
 
@@ -239,17 +243,20 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                 fphi += red[2][q][lane];
                 fdphi += red[3][q][lane];
             }
-            // the bracketing poles' terms, exactly, in the origin frame
+            // the bracketing poles' terms in the origin frame, with the
+            // same refined reciprocal as the far poles' terms
             const double dl = e0 >= 0 ? De0 - Do : 0.0;   // pole offsets from the origin
             const double dh = De1 - Do;
             const double d1 = dl - tau, d2 = dh - tau;    // and from the iterate
-            const double t0 = (valid && e0 >= 0) ? w0 / d1 : 0.0;
-            const double t1 = valid ? w1 / d2 : 0.0;
-            const double psi = fpsi + t0, dpsi = fdpsi + ((valid && e0 >= 0) ? t0 / d1 : 0.0);
-            const double phi = fphi + t1, dphi = fdphi + (valid ? t1 / d2 : 0.0);
+            const double r1 = (valid && e0 >= 0) ? dc_rcp3(d1) : 0.0;
+            const double r2 = valid ? dc_rcp3(d2) : 0.0;
+            const double t0 = w0 * r1, dt0 = t0 * r1;
+            const double t1 = w1 * r2, dt1 = t1 * r2;
+            const double psi = fpsi + t0, dpsi = fdpsi + dt0;
+            const double phi = fphi + t1, dphi = fdphi + dt1;
             const double aabs = (fphi - fpsi) + fabs(t0) + fabs(t1);   // sum of |terms|
-            const double g = 1.0 / rho + psi + phi;
-            const double gtol = 8.0 * EPS * (1.0 / rho + aabs);
+            const double g = irho + psi + phi;
+            const double gtol = 8.0 * EPS * (irho + aabs);
             if (!done) {
                 ++iters;
                 // switch models when an iterate stayed on the same side of
@@ -284,7 +291,11 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                         done = true;
                         dc_set_info(T.info, T.row0 + j + 1);
                     } else {
-                        // Pole offsets in the (possibly new) origin frame.
+                        // Pole offsets in the (possibly new) origin frame;
+                        // their distances from the iterate are d1 and d2
+                        // again (a re-framed midpoint is -h from D_{j+1} as
+                        // it was h from D_j), whose reciprocals r1, r2 the
+                        // fixed-weight model reuses.
                         const double Dn = (org == j) ? (last ? De1 : De0) : De1;
                         const double ol = e0 >= 0 ? De0 - Dn : 0.0, oh = De1 - Dn;
                         const double q1 = ol - tau, q2 = oh - tau;
@@ -299,7 +310,7 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                                 const double s1 = dpsi * q1 * q1;
                                 const double s2 = dphi * q2 * q2;
                                 const double c =
-                                    1.0 / rho + (psi - dpsi * q1) + (phi - dphi * q2);
+                                    irho + (psi - dpsi * q1) + (phi - dphi * q2);
                                 nt = model_root(c, s1, s2, ol, oh, lo, hi);
                             }
                             if (!(nt > lo && nt < hi) && !last) {
@@ -308,8 +319,8 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                                 // other bracketing pole (a weak origin pole
                                 // fools the middle way's fit).
                                 const bool left = org == j;
-                                const double R = 1.0 / rho + fpsi + fphi + (left ? t1 : t0);
-                                const double Rp = fdpsi + fdphi + (left ? t1 / q2 : t0 / q1);
+                                const double R = irho + fpsi + fphi + (left ? t1 : t0);
+                                const double Rp = fdpsi + fdphi + (left ? dt1 : dt0);
                                 const double qo = left ? q2 : q1;
                                 const double sf = Rp * qo * qo;
                                 const double cf = R - Rp * qo;
@@ -317,7 +328,16 @@ void k_secular_roots(const SecTask* __restrict__ tasks, const int* __restrict__ 
                                           : model_root(cf, sf, w1, ol, oh, lo, hi);
                             }
                         }
-                        if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
+                        if (!(nt > lo && nt < hi)) {
+                            // a Newton step on g itself before bisecting:
+                            // when an iterate already sits on the root to
+                            // rounding the models can land just outside the
+                            // bracket, and the midpoint of a bracket whose
+                            // ends are orders of magnitude apart throws the
+                            // root back to where it started
+                            const double nn = tau - g * dc_rcp3(dpsi + dphi);
+                            nt = (nn > lo && nn < hi) ? nn : 0.5 * (lo + hi);
+                        }
                         tau = nt;
                     }
                 }
