@@ -2,17 +2,14 @@
 // at most 64 rows; a wave holds 64 / LD leaves of at most LD rows each.
 //
 // Implicit symmetric tridiagonal QR with a Wilkinson shift (Golub & Van Loan,
-// section 8.3).  The tridiagonal lives in registers, entry i in lane i of the
-// leaf's lane group; the bulge chase is a chain of Givens steps that every
-// lane of the group evaluates identically, reading entries ahead of the chase
-// across the group (readlane for a whole-wave group, a lane permute
-// otherwise) and carrying the entries the chase has touched in registers,
-// while lane r applies each
-// rotation to row r of the eigenvector block (one LDS read and one write per
-// step: the column the chase leaves behind).  The leaf is scaled by a power of
-// two (exact) so that x^2 + y^2 of a rotation neither overflows nor
-// underflows on the usual path; deflation uses the absolute threshold
-// eps * ||T||_inf of the leaf.
+// section 8.3).  The bulge chase is a chain of Givens steps that every lane
+// of the leaf's lane group evaluates identically, reading the entries ahead
+// of the chase from the tridiagonal in LDS and carrying the entries it has
+// touched in registers, while lane r applies each rotation to row r of the
+// eigenvector block (one LDS read and one write per step: the column the
+// chase leaves behind).  The leaf is scaled by a power of two (exact) so that
+// x^2 + y^2 of a rotation neither overflows nor underflows on the usual path;
+// deflation uses the absolute threshold eps * ||T||_inf of the leaf.
 //
 // The leaf's diagonal carries the tear corrections of eq. T2: every boundary
 // between two adjacent leaves is the split point of exactly one merge, whose
