@@ -347,11 +347,29 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     double* cD = S.lamr + base;
     double* cz = S.cbase + base;
     int* cc = S.kbot + base;
-    for (int k = tid; k < Ns; k += NT) {
-        const int i = SI[k];
-        cD[k] = S.Ds[base + i];
-        cz[k] = S.zs[base + i];
-        cc[k] = colof(i);
+    // four entries per thread and pass, loads before stores (the scratch
+    // arrays may alias as far as the compiler knows, which would otherwise
+    // serialise every entry's two dependent loads behind the last store)
+    for (int k0 = tid; k0 < Ns; k0 += 4 * NT) {
+        int ii[4];
+        double dd[4], zz[4];
+        int cl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ii[u] = k0 + u * NT < Ns ? SI[k0 + u * NT] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = max(ii[u], 0);
+            dd[u] = S.Ds[base + i];
+            zz[u] = S.zs[base + i];
+            cl[u] = colof(i);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (ii[u] < 0) continue;
+            cD[k0 + u * NT] = dd[u];
+            cz[k0 + u * NT] = zz[u];
+            cc[k0 + u * NT] = cl[u];
+        }
     }
     __syncthreads();
 
@@ -391,15 +409,31 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
         oorg[tid] = st.orig;
     }
     __syncthreads();
-    // True segment starts, in order.  A segment entered with a rotated
-    // candidate is re-walked until both walks decline a rotation at the same
-    // pair: from there on they coincide.
-    if (tid == 0 && nseg > 0) {
-        WState in = load_orig(0);
-        for (int sg = 0; sg < nseg; ++sg) {
-            iD[sg] = in.D; iz[sg] = in.z; icol[sg] = in.col; ityp[sg] = in.typ;
-            iorg[sg] = in.orig;
-            WState out{oD[sg], oz[sg], ocol[sg], otyp[sg], oorg[sg]};
+    // True segment starts: in_0 is survivor 0 and in_{sg+1} = F_sg(in_sg),
+    // where F_sg keeps the speculative end state when entered with an
+    // unrotated survivor and otherwise re-walks the segment until both walks
+    // decline a rotation at the same pair (from there on they coincide).  The
+    // recurrence is solved by rounds over all segments at once, starting from
+    // in_{sg+1} = speculative end of sg: a round recomputes every F_sg from
+    // the current in_sg, and another round follows only if some in_{sg+1}
+    // changed.  After round r the first r + 1 starts are exact, so the rounds
+    // end; a change passes on only when a re-walk never meets the speculative
+    // walk, so one or two rounds usually settle it (the serial form took one
+    // step per segment: 1024 dependent steps of one thread for a large merge).
+    if (myseg) {
+        WState in = tid == 0 ? load_orig(0)
+                             : WState{oD[tid - 1], oz[tid - 1], ocol[tid - 1], otyp[tid - 1],
+                                      oorg[tid - 1]};
+        iD[tid] = in.D; iz[tid] = in.z; icol[tid] = in.col; ityp[tid] = in.typ;
+        iorg[tid] = in.orig;
+    }
+    for (;;) {
+        __syncthreads();
+        WState out{0.0, 0.0, 0, 0, 1};
+        if (myseg) {
+            const int sg = tid;
+            const WState in{iD[sg], iz[sg], icol[sg], ityp[sg], iorg[sg]};
+            out = WState{oD[sg], oz[sg], ocol[sg], otyp[sg], oorg[sg]};
             if (!in.orig) {
                 const int a = sg * SL, b = min(npairs, a + SL);
                 WState nx;
@@ -416,8 +450,20 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
                 }
                 if (!conv) out = st;
             }
-            in = out;
         }
+        __syncthreads();
+        int changed = 0;
+        if (myseg && tid + 1 < nseg) {
+            const int t = tid + 1;
+            if (__double_as_longlong(out.D) != __double_as_longlong(iD[t]) ||
+                __double_as_longlong(out.z) != __double_as_longlong(iz[t]) ||
+                out.col != icol[t] || out.typ != ityp[t] || out.orig != iorg[t]) {
+                iD[t] = out.D; iz[t] = out.z; icol[t] = out.col; ityp[t] = out.typ;
+                iorg[t] = out.orig;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
     }
     __syncthreads();
 
@@ -565,35 +611,49 @@ void k_deflate(const Node* __restrict__ merges, Scratch S) {
     }
 
     // Order-preserving lists of survivors touching the top / bottom rows
-    // (the survivor panel's columns), and each survivor's place in them.
+    // (the survivor panel's columns), and each survivor's place in them; both
+    // lists in one pass over the survivors.
     const int lane = tid & 63, wv = tid >> 6;
-    for (int half = 0; half < 2; ++half) {
-        const int bit = half ? 2 : 1;
-        int* out = (half ? S.kbot : S.ktop) + base;
-        int* inv = (half ? S.pbot : S.ptop) + base;
-        int running = 0;
-        for (int c0 = 0; c0 < K; c0 += NT) {
-            const int j = c0 + tid;
-            const bool f = j < K && (S.stype[base + j] & bit);
-            const unsigned long long bal = __ballot(f);
-            const int before = __popcll(bal & ((1ull << lane) - 1ull));
-            if (lane == 0) wsum[wv] = __popcll(bal);
-            __syncthreads();
-            int woff = 0;
-            for (int q = 0; q < wv; ++q) woff += wsum[q];
-            int tot = 0;
-            for (int q = 0; q < NT / 64; ++q) tot += wsum[q];
-            if (f) {
-                out[running + woff + before] = j;
-                inv[j] = running + woff + before;
+    __shared__ int wsum2[NT / 64];
+    int run_t = 0, run_b = 0;
+    for (int c0 = 0; c0 < K; c0 += NT) {
+        const int j = c0 + tid;
+        const int ty = j < K ? S.stype[base + j] : 0;
+        const bool ft = ty & 1, fb = ty & 2;
+        const unsigned long long bt = __ballot(ft), bb = __ballot(fb);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        if (lane == 0) {
+            wsum[wv] = __popcll(bt);
+            wsum2[wv] = __popcll(bb);
+        }
+        __syncthreads();
+        int ot = 0, ob = 0, tt = 0, tb = 0;
+        for (int q = 0; q < NT / 64; ++q) {
+            if (q < wv) {
+                ot += wsum[q];
+                ob += wsum2[q];
             }
-            running += tot;
-            __syncthreads();
+            tt += wsum[q];
+            tb += wsum2[q];
         }
-        if (tid == 0) {
-            MergeCnt* cnt = S.cnt + N.slot;
-            if (half) cnt->nbot = running; else cnt->ntop = running;
+        if (ft) {
+            const int at = run_t + ot + __popcll(bt & below);
+            S.ktop[base + at] = j;
+            S.ptop[base + j] = at;
         }
+        if (fb) {
+            const int ab = run_b + ob + __popcll(bb & below);
+            S.kbot[base + ab] = j;
+            S.pbot[base + j] = ab;
+        }
+        run_t += tt;
+        run_b += tb;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        MergeCnt* cnt = S.cnt + N.slot;
+        cnt->ntop = run_t;
+        cnt->nbot = run_b;
     }
 }
 
