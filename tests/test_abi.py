@@ -101,3 +101,34 @@ def test_host_side_argument_checks_need_no_gpu():
     assert lib.dc_autotune_lowrank(1, None, 32, ctypes.byref(bo), ctypes.byref(ko)) == -1
     assert lib.dc_autotune_lowrank(1, n1, 32, None, ctypes.byref(ko)) == -1
     assert lib.dc_autotune_lowrank(1, n1, 32, ctypes.byref(bo), None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"),
+                    reason="HIP headers not installed")
+def test_binding_structs_match_the_header(tmp_path):
+    # The ctypes mirrors of dc_opts and dc_merge_stat against the C compiler's
+    # layout of the header's structs: size and every field's offset.
+    import shutil
+    import subprocess
+    from paper_2008_01990_amd import dcstedc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dcstedc.h"',
+             "int main(void) {"]
+    expect = []
+    for cname, cls in (("dc_opts", dcstedc.DcOpts), ("dc_merge_stat", dcstedc.MergeStat)):
+        lines.append(f'    printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("%zu\\n", offsetof({cname}, {field}));')
+            expect.append(getattr(cls, field).offset)
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == expect

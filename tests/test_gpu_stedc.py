@@ -119,6 +119,28 @@ def test_sht_matrix(lib):
     _check_against_oracle(d, e, lam, Q, 64)
 
 
+def test_merge_records_count_secular_evaluations(lib):
+    # dc_merge_stat's secular counters: every root of a merge is evaluated at
+    # least once and at most max_iter + 1 times, so K <= sum <= K * max and
+    # 1 <= max <= 201 for every merge with survivors; a merge with none
+    # records zeros.  (Random spectra need a few evaluations per root.)
+    announce("stedc merge records: secular evaluation counts")
+    d, e = W.random_tridiag(3000, np.random.default_rng(21))
+    _solve(lib, d, e, leaf=32)
+    stats = lib.last_stats()
+    assert stats
+    total_k = total_it = 0
+    for r in stats:
+        if r["K"] == 0:
+            assert r["sec_iters_sum"] == 0 and r["sec_iters_max"] == 0
+            continue
+        assert 1 <= r["sec_iters_max"] <= 201
+        assert r["K"] <= r["sec_iters_sum"] <= r["K"] * r["sec_iters_max"]
+        total_k += r["K"]
+        total_it += r["sec_iters_sum"]
+    assert 1.0 <= total_it / total_k <= 10.0
+
+
 @pytest.mark.parametrize("nblocks,delta", [(48, 1e-10), (100, 1e-8)])
 def test_glued_wilkinson_rotation_chains(lib, nblocks, delta):
     # Clustered spectra: hundreds of pair rotations per merge, in chains that
