@@ -60,9 +60,10 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
 
 // LD: leaf size bound and row stride of the eigenvector block in LDS (16,
 // 32 or 64).  A wave holds 64 / LD leaves, lane group g = lane / LD solving
-// leaf blockIdx.x * (64 / LD) + g with row r = lane % LD: the chase's scalar
-// chain is then evaluated once per group instead of once per wave (its cost is
-// instruction issue, shared by the waves of a SIMD).  The tridiagonal lives in
+// leaf blockIdx.x * (64 / LD) + g with row r = lane % LD: each group computes
+// its own chase in its own lanes, so one instruction of a chase step advances
+// 64 / LD leaves at once (the chase's cost is instruction issue, shared by the
+// waves of a SIMD).  The tridiagonal lives in
 // LDS as pairs (e[k-1], d[k]): the chase reads entries ahead of it with one
 // broadcast load per step and lane 0 of the group writes each finished pair
 // back, so no register selects or lane permutes sit in the step.  A group that
