@@ -886,6 +886,52 @@ void k_gather(const Node* __restrict__ merges, const int* __restrict__ blk_start
         double* o = G + (long long)t * P.ld2 + r0;
         for (int r = threadIdx.x; r < nr; r += 256) o[r] = r >= lo && r < hi ? a[r] : 0.0;
     };
+    if (stride) {
+        // Small merges: the workgroup's (at most DC_GROUPS_PER_BLOCK) column
+        // groups are resolved first, one thread per (column, half) following
+        // its chain of list, type, survivor, map and row-range loads at once
+        // (one after another per column, those chains were most of the
+        // kernel), then a wave copies each column's few rows.
+        constexpr int NSL = 2 * DC_GATHER_COLS * DC_GROUPS_PER_BLOCK;
+        __shared__ int s_col[NSL], s_lo[NSL], s_hi[NSL], s_t[NSL];
+        const int first = local * DC_GATHER_COLS;
+        const int ng = (ncols - first + step - 1) / step;
+        const int nsl = min(ng, DC_GROUPS_PER_BLOCK) * 2 * DC_GATHER_COLS;
+        for (int i = threadIdx.x; i < nsl; i += 256) {
+            const int q = i / (2 * DC_GATHER_COLS), u = (i >> 1) % DC_GATHER_COLS, h = i & 1;
+            const int t = first + q * step + u;
+            int col = -1, lo = 0, hi = 0;
+            if (t < (h ? C.nbot : C.ntop)) {
+                const int ks = (h ? S.kbot : S.ktop)[base + t];
+                // (survivors that end a rotation chain were written by the rotation)
+                if (!(S.stype[base + ks] & 4)) {
+                    const int c = S.surv[base + ks];
+                    const int2 rg = node_rng(S, N.depth + 1)[base + c];
+                    const int r0 = h ? N.n1 : 0;
+                    col = cmap[c];
+                    lo = rg.x - N.off - r0;
+                    hi = rg.y - N.off - r0;
+                }
+            }
+            s_col[i] = col;
+            s_lo[i] = lo;
+            s_hi[i] = hi;
+            s_t[i] = t;
+        }
+        __syncthreads();
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int i = wv; i < nsl; i += 4) {
+            const int col = s_col[i];
+            if (col < 0) continue;
+            const int h = i & 1;
+            const int r0 = h ? N.n1 : 0, nr = h ? N.n2 : N.n1;
+            const int lo = s_lo[i], hi = s_hi[i];
+            const double* a = Qi + (long long)col * ldi + N.off + r0;
+            double* o = G + (long long)s_t[i] * P.ld2 + r0;
+            for (int r = lane; r < nr; r += 64) o[r] = r >= lo && r < hi ? a[r] : 0.0;
+        }
+        return;
+    }
     for (int t0 = local * DC_GATHER_COLS; t0 < ncols; t0 += step) {
         for (int t = t0; t < t0 + DC_GATHER_COLS; ++t) {
             // (survivors that end a rotation chain were written by the rotation)
