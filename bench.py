@@ -373,15 +373,18 @@ def table_rank(L, torch, n=16384, nprocs=4, tol=1e-12):
     return out
 
 
+BATCH_LEAF = 16   # leaf size of the batched configuration (8 / 12 / 16 / 32 measured)
+
+
 def batched_config(L, torch):
     """Batched configuration: 256 problems, sizes log-uniform in [64, 4096],
-    d, e ~ U(-1, 1), seed 3; default tile rule, bucket-tuned and
+    d, e ~ U(-1, 1), seed 3, leaf 16; default tile rule, bucket-tuned and
     batch-measured tiles, all replayed as graphs."""
     from paper_2008_01990_amd import workloads as W
     res = {}
     probs = W.batched_problems(256, 64, 4096, seed=3)
     sizes = [len(p[0]) for p in probs]
-    B = L.BatchedSolver(sizes, leaf=32)
+    B = L.BatchedSolver(sizes, leaf=BATCH_LEAF)
     B.load_inputs(probs)
 
     def step(graph):
@@ -392,13 +395,13 @@ def batched_config(L, torch):
     table = L.autotune(4096)
     t_tune = time.perf_counter() - t0
     del B
-    B = L.BatchedSolver(sizes, leaf=32)
+    B = L.BatchedSolver(sizes, leaf=BATCH_LEAF)
     B.load_inputs(probs)
     tg_bucket = _time(lambda: step(True), 5, torch)
     L.autotune(0)
     # measured on this batch: every level's product timed under every variant
     del B
-    B = L.BatchedSolver(sizes, leaf=32)
+    B = L.BatchedSolver(sizes, leaf=BATCH_LEAF)
     B.load_inputs(probs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -424,7 +427,7 @@ def batched_config(L, torch):
     leaf_b = 0.0
     for n in sizes:
         nb = float(n)
-        while nb > 32:
+        while nb > BATCH_LEAF:
             nb /= 2.0
         leaf_b += 8.0 * n * nb
     total_b = move_b + prod_b + leaf_b
@@ -435,7 +438,7 @@ def batched_config(L, torch):
         "seconds_graph_bucket_tuned": tg_bucket, "bucket_autotune_seconds": t_tune,
         "bucket_variant_by_size": {f"<={1 << b}": v for b, v in enumerate(table) if 6 <= b <= 12},
         "measured_autotune_seconds": t_meas, "measured_variant_by_level": levels,
-        "problems": len(sizes), "sum_n": int(sum(sizes)),
+        "problems": len(sizes), "sum_n": int(sum(sizes)), "leaf": BATCH_LEAF,
         "status_ok": all(v == 0 for v in B.status()),
         # whole batch against HBM: algorithmic bytes (merge_traffic per merge,
         # plus the leaf blocks) over the graph-replay time
