@@ -698,14 +698,17 @@ hipError_t run_plan(const Plan& P, const LrPlan* LP, const std::vector<Prob>& pr
         DC_TRY(prof_mark(li, MARK_PRODUCT, s));
         if (lr && LP->levels[li].njobs > 0)
             DC_TRY(lowrank_level(*LP, li, lrbase, o.lr_tol, s));
-        if (Lv.stride && Lv.max_m >= 1024 && (Lv.variant == 0 || Lv.variant == 5)) {
-            // Levels of merges from 1024 to 4095 rows (the top of a batch of
-            // random problems, whose K is a few percent of m): the tiles of
-            // the actual K, compacted on the device; the workgroups of the
-            // worst-case grid past their total exit at once instead of
-            // searching the task list first (batched 256 problems: the two
-            // top levels' products 0.37 -> 0.29 ms; on the levels of
-            // smaller merges the scan's own launch cost more than it saved).
+        if ((Lv.stride || Lv.nm >= 16) && Lv.max_m >= 1024 &&
+            (Lv.variant == 0 || Lv.variant == 5)) {
+            // Levels of merges from 1024 to 4095 rows, or of many merges
+            // reaching 4096 and more (the top of a batch of random problems,
+            // whose K is a few percent of m): the tiles of the actual K,
+            // compacted on the device; the workgroups of the worst-case grid
+            // past their total exit at once instead of searching the task
+            // list first (batched 256 problems: the two top levels' products
+            // 0.37 -> 0.29 ms; on the levels of smaller merges the scan's own
+            // launch cost more than it saved, and a level of a few large
+            // merges has little to compact).
             int* act = reinterpret_cast<int*>(work + L.tiles) + 2 * Lv.first + 2 * li;
             DC_TRY(dc_launch_tile_scan(S.gtask + 2 * Lv.first, 2 * Lv.nm, Lv.bn, act,
                                        act + 2 * Lv.nm + 1, s));
