@@ -106,7 +106,9 @@ extern "C" int dc_secular(int K, const double* Dbar, const double* zbar, double 
     if (!scale) return -8;
     if (max_iter <= 0) max_iter = 200;
     const int nblk = (K + DC_ROOTS_PER_BLOCK - 1) / DC_ROOTS_PER_BLOCK;
-    const size_t off_bs = 256, off_cb = 512;
+    // task, block prefix {0, nblk} and block -> task map (all 0), generators
+    const size_t off_bs = 256;
+    const size_t off_cb = (off_bs + (size_t)(2 + nblk) * sizeof(int) + 255) / 256 * 256;
     char* tmp = nullptr;
     hipError_t err = hipMallocAsync((void**)&tmp, off_cb + (size_t)K * sizeof(double), stream);
     if (err != hipSuccess) return (int)err;
@@ -125,6 +127,8 @@ extern "C" int dc_secular(int K, const double* Dbar, const double* zbar, double 
     int bs[2] = {0, nblk};
     err = dc_write_blob(tmp, &T, sizeof(T), stream);
     if (err == hipSuccess) err = dc_write_blob(tmp + off_bs, bs, sizeof(bs), stream);
+    if (err == hipSuccess)
+        err = dc_fill_int(reinterpret_cast<int*>(tmp + off_bs) + 2, nblk, 0, stream);
     if (err == hipSuccess && info_dev) err = dc_fill_int(info_dev, 1, 0, stream);
     if (err == hipSuccess)
         err = dc_launch_secular(reinterpret_cast<SecTask*>(tmp),

@@ -38,13 +38,10 @@ namespace {
 
 constexpr double EPS = 2.220446049250313e-16;
 
+// The merge of workgroup b: blk_start holds the grid's prefix (nm + 1
+// entries) followed by its block -> merge map.
 __device__ __forceinline__ int block_of(const int* blk_start, int nm, int b) {
-    int lo = 0, hi = nm - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (blk_start[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    return blk_start[nm + 1 + b];
 }
 
 // Number of entries of the ascending a[0..n) strictly below x / at most x.

@@ -210,6 +210,13 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
         }
         pre.push_back(acc);
         L.tiles = acc;
+        // Each grid's prefix (nm + 1 entries) is followed by its block -> merge
+        // map (one entry per block), so a workgroup finds its merge with one
+        // load instead of a binary search of dependent loads.
+        auto add_map = [&](int off) {
+            for (int i = 0; i < L.nm; ++i)
+                for (int b = pre[off + i]; b < pre[off + i + 1]; ++b) pre.push_back(i);
+        };
         auto add = [&](int per, int& off, int& total) {
             off = (int)pre.size();
             int a = 0;
@@ -220,6 +227,7 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
             }
             pre.push_back(a);
             total = a;
+            add_map(off);
         };
         add(DC_ROOTS_PER_BLOCK, L.off_sec, L.sec_blocks);
         add(DC_ROWS_PER_BLOCK, L.off_row, L.row_blocks);
@@ -234,6 +242,7 @@ std::unique_ptr<Plan> make_plan(const std::vector<int>& sizes, int leaf, int til
             }
             pre.push_back(a);
             total = a;
+            add_map(off);
         };
         L.stride = L.max_m < DC_STRIDE_MAX_M;
         const bool st = L.stride;

@@ -56,13 +56,10 @@ constexpr int SMALL_K = 256;
 constexpr int SMALL_K_ALWAYS = 128;
 constexpr int ROUND_BLOCKS = 1024;
 
+// The task of workgroup b: block_start holds the prefix (ntasks + 1 entries)
+// followed by the block -> task map.
 __device__ __forceinline__ int task_of(const int* block_start, int ntasks, int b) {
-    int lo = 0, hi = ntasks - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (block_start[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    return block_start[ntasks + 1 + b];
 }
 
 struct Sums {

@@ -24,7 +24,8 @@ struct SecTask {
 };
 
 // block_start: exclusive prefix sum (ntasks + 1 entries, device) of
-// ceil(Kmax / 64) per task; the three kernels run in sequence.  max_k bounds
+// ceil(Kmax / 64) per task, followed by the task of each of the total_blocks
+// workgroups; the three kernels run in sequence.  max_k bounds
 // every task's K (it selects the workgroup shape).
 hipError_t dc_launch_secular(const SecTask* tasks, const int* block_start, int ntasks,
                              int total_blocks, int max_k, int max_iter, hipStream_t s);
