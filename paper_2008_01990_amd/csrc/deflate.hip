@@ -12,10 +12,11 @@
 // and p deflated.  The walk over survivors is sequential in principle (each
 // test involves the last survivor, which a rotation modifies), but only along
 // runs of rotations: the workgroup walks segments of the survivor list in
-// parallel assuming an unrotated start, one lane corrects the segment starts
-// in order (re-walking only until the two walks agree on a pair that does not
-// rotate), and the segments are walked again from their true starts to count
-// and then to write their output.
+// parallel assuming an unrotated start, the true segment starts are settled
+// by parallel rounds (a segment entered with a rotated candidate is re-walked
+// only until the two walks agree on a pair that does not rotate), and the
+// segments are walked again from their true starts to count and then to
+// write their output.
 //
 // Every column of the merge block carries row-type bits: 1 if it may be
 // non-zero in the top rows [0, n1), 2 in the bottom rows [n1, m).  Columns of
